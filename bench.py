@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-grid Helmholtz solve on one MI355X.
+
+A step is one complete solve A u = f to a relative residual of 1e-6 (GMRES
+with the two-grid preconditioner: fine residuals, CSDD smoothing, restriction,
+coarse solve, prolongation, orthogonalisation) on the default workload:
+
+  C2: 2-D unit square, Q4, 200 x 200 cells (801^2 = 641,601 DOF), seeded
+      Gaussian-random-field speed (l = 0.05, 1.5..4.0) with 80 wavelengths at
+      the slowest speed (10 DOF per wavelength there), absorbing boundary, one
+      Gaussian source (sigma = 2h) at the centre, 16x16-cell subdomains,
+      alpha_s = 0.5, complex128 two-grid preconditioner under FP64 GMRES.
+
+value = fine DOF x two-grid cycles / second (setup excluded), summed over the
+right-hand sides; ms_per_step is the time to the 1e-6 residual.  Inputs are in
+HBM before the timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dd_apply_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2509_17494_amd", "csrc", "k_smoother.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C5"])
+    ap.add_argument("--precond", default=None, choices=["c128", "c64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def workload(name):
+    import synthetic as syn
+    cfg = syn.config(name)
+    spec = dict(l_dd=cfg["l_dd"], alpha_s=cfg["alpha_s"], gemm="f64", precond="c128")
+    if name == "C3":
+        spec.update(gemm="f32", precond="c64")
+    return cfg, spec
+
+
+def dd_apply_bytes(info_sub, nrhs, mat_bytes, vec_bytes):
+    """Algorithmic bytes of one batched subdomain apply: every B_i entry once,
+    the gathered patch X_i and the output rows Y_i once per right-hand side."""
+    b = sum(nu * no for nu, no in info_sub) * mat_bytes
+    v = sum(no + nu for nu, no in info_sub) * vec_bytes * nrhs
+    return b + v
+
+
+def subdomain_sizes(N, p, l_dd):
+    import math
+    M = math.ceil(N / l_dd)
+    base, rem = divmod(N, M)
+    sizes = [base + 1] * rem + [base] * (M - rem)
+    starts = [0]
+    for s in sizes:
+        starts.append(starts[-1] + s)
+    out = []
+    for by in range(M):
+        for bx in range(M):
+            ux, uy = sizes[bx], sizes[by]
+            ox = min(starts[bx + 1] + 1, N) - max(starts[bx] - 1, 0)
+            oy = min(starts[by + 1] + 1, N) - max(starts[by] - 1, 0)
+            out.append(((ux * p + 1) * (uy * p + 1), (ox * p + 1) * (oy * p + 1)))
+    return out
+
+
+def traffic_entry(workload_name):
+    """HBM bytes per dd_apply launch from the committed rocprofv3 counter run,
+    or None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+        src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        e = d.get(workload_name)
+        if not e or e.get("kernel_sha256") != src_hash:
+            return None
+        return e.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(cfg_name):
+    """The FP64 oracle timed on this host on a bounded sample: a 96x96-cell
+    window of the same medium, order and k h with the same subdomain size,
+    solved to 1e-6 by the oracle's GMRES; rate = DOF x cycles / solve time."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    import synthetic as syn
+    from oracle.twogrid import TwoGrid
+    cfg = syn.config(cfg_name)
+    n = min(96, cfg["n"])
+    # a physical window of side n/N keeps k h (DOF per wavelength) of the workload
+    k = np.ascontiguousarray(cfg["k"][:n, :n]) * (n / cfg["n"])
+    p = cfg["p"]
+    t0 = time.perf_counter()
+    tg = TwoGrid(p, k, alpha_s=cfg["alpha_s"], l_dd=cfg["l_dd"])
+    t_setup = time.perf_counter() - t0
+    f = syn.gaussian_load(n, p, [[0.5, 0.5]], 2.0 / n)[0]
+    t0 = time.perf_counter()
+    _, its, _ = tg.gmres(f, 1e-6)
+    t_solve = time.perf_counter() - t0
+    ndof = (n * p + 1) ** 2
+    return {"value": ndof * its / t_solve, "unit": "DOF*cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cfg_name} medium, order and k*h on a {n}x{n}-cell window ({ndof} DOF), "
+                      f"l_dd={cfg['l_dd']}, oracle GMRES to 1e-6: {its} cycles in {t_solve:.2f} s "
+                      f"(setup {t_setup:.1f} s excluded), single-threaded numpy/scipy"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synthetic as syn
+    from paper_2509_17494_amd import TwoGridSolver
+
+    cfg, spec = workload(a.workload)
+    precond = a.precond or spec["precond"]
+    N, p = cfg["n"], cfg["p"]
+    f_host = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"])
+    R = f_host.shape[0]
+    t0 = time.perf_counter()
+    s = TwoGridSolver(cfg["k"], order=p, alpha_s=spec["alpha_s"], l_dd=spec["l_dd"],
+                      gemm=spec["gemm"], max_rhs=R)
+    t_setup = time.perf_counter() - t0
+    info = s.info()
+    f = torch.from_numpy(f_host).to("cuda")
+    u = torch.empty_like(f)
+    if a.verbose:
+        print(f"setup {t_setup:.2f} s (fine {info['t_setup_fine_s']:.2f}, coarse "
+              f"{info['t_setup_coarse_s']:.2f}); B {info['b_bytes'] / 1e9:.2f} GB", flush=True)
+    for _ in range(a.warmup):
+        s.solve(f, u, precond=precond)
+    torch.cuda.synchronize()
+    s.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = 0
+    iters = []
+    worst = 0.0
+    for _ in range(a.steps):
+        _, st = s.solve(f, u, precond=precond)
+        cycles += st.n_precond
+        iters.append(st.iters)
+        worst = max(worst, st.rel_res)
+        if st.status != 0:
+            raise RuntimeError(f"solve did not converge: {st}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = s.kernel_times()
+    s.timing(False)
+    elapsed = t1 - t0
+    value = info["n_fine"] * cycles / elapsed
+    ms_step = elapsed / a.steps * 1e3
+
+    mat_bytes = {"f64": 16, "f32": 8, "bf16": 4}[spec["gemm"]]
+    vec_bytes = 16 if precond == "c128" else 8
+    subs = subdomain_sizes(N, p, spec["l_dd"])
+    alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes)
+    dd_ms, dd_n = kt["dd_apply"]
+    avg_ms = dd_ms / max(dd_n, 1)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_entry(a.workload)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_dd_apply", "alg_bytes_per_launch": alg,
+            "avg_launch_ms": round(avg_ms, 4), "launches": dd_n}
+    out = {
+        "metric": "fine DOF*cycles/s and time-to-1e-6 residual, mixed+batched vs FP64, 1 GPU",
+        "value": value,
+        "unit": "DOF*cycles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precond == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: 2-D Q{p}, {N}x{N} cells ({info['n_fine']} DOF), "
+                               f"{R} RHS, l_dd={spec['l_dd']}, alpha_s={spec['alpha_s']}, "
+                               f"B_i {spec['gemm']}, preconditioner {precond}",
+                   "time_to_1e-6_ms": ms_step, "gmres_iters": iters[-1],
+                   "max_rel_res": worst, "setup_s": round(t_setup, 3),
+                   "setup_fine_s": round(info["t_setup_fine_s"], 3),
+                   "setup_coarse_s": round(info["t_setup_coarse_s"], 3),
+                   "b_bytes": info["b_bytes"], "coarse_bytes": info["coarse_bytes"],
+                   "kernel_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in kt.items()}},
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline("C2" if a.workload == "C2" else a.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * th.h -- C ABI of the MI355X two-grid Helmholtz library.
+ *
+ * The library solves the finite-element Helmholtz problem
+ *     -Laplace u - (k(x)^2 + i eps(x)) u = f      on the unit square (cube),
+ * with absorbing (Robin, du/dn - i k u = 0) or Neumann sides (Sec. 2 of
+ * Stolk, "A two-grid method with dispersion matching for finite-element
+ * Helmholtz problems", arXiv 2509.17494, eq. Helmholtz_eq and eq. bilin_form),
+ * discretised with continuous Q_p elements (p even) on N x N cells of size
+ * h = 1/N (Sec. 3.1), and applies the paper's two-grid method (Alg. 1):
+ * complex-shifted domain-decomposition smoothing (Alg. 2), a QSFEM
+ * dispersion-minimising coarse operator on the mesh of spacing 2h/p
+ * (Sec. 3.2-3.3) and Q_{p/2} interpolation between the levels (Sec. 4.2),
+ * used as the preconditioner of an FP64 GMRES.
+ *
+ * Conventions for every call:
+ *   - Every function returns th_status; nothing throws across the ABI.  On a
+ *     failure th_last_error(ctx) holds a message until the next call on ctx.
+ *   - Fine vectors have (pN+1)^d complex entries, one per GLL node of the
+ *     global node grid, lexicographic with x fastest.  Coarse vectors have
+ *     (pN/2+1)^d entries on the coarse vertex grid, x fastest.
+ *   - Vector arguments are DEVICE pointers owned by the caller, holding
+ *     nrhs vectors back to back (layout [nrhs][ndof]), complex interleaved
+ *     (re, im): double pairs for TH_C128, float pairs for TH_C64.  The
+ *     library never allocates, frees or retains caller buffers.
+ *   - Work is ordered on the stream given to th_create (NULL = the default
+ *     stream).  Calls marked "stream-ordered" return before the GPU has
+ *     finished; th_setup_* and th_solve block until their work is done.
+ *   - One context per host thread; a context is not thread safe.
+ */
+#ifndef TH_H
+#define TH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct th_ctx th_ctx;
+
+typedef enum {
+  TH_OK = 0,
+  TH_EINVAL = -1,        /* bad argument: shape, order, NULL pointer, NaN input */
+  TH_ESTATE = -2,        /* call out of order (e.g. smooth before setup) */
+  TH_ENOMEM = -3,        /* device allocation failed */
+  TH_EHIP = -4,          /* HIP runtime error; message in th_last_error */
+  TH_ENOTCONV = -5,      /* th_solve hit maxit; u holds the last iterate */
+  TH_ENUMERIC = -6,      /* NaN/Inf met in a norm or a pivot */
+  TH_EUNSUPPORTED = -7   /* valid request this build does not implement */
+} th_status;
+
+typedef enum { TH_BC_ROBIN = 0, TH_BC_NEUMANN = 1 } th_bc;
+typedef enum { TH_C128 = 0, TH_C64 = 1 } th_dtype;
+
+/* Storage / arithmetic of the dense subdomain operators B_i.
+ * F64: complex128.  F32: complex64.  BF16: planar (re, im) bfloat16 with
+ * FP32 accumulation. */
+typedef enum { TH_GEMM_F64 = 0, TH_GEMM_F32 = 1, TH_GEMM_BF16 = 2 } th_gemm;
+
+typedef enum {
+  TH_COARSE_QSFEM = 0,   /* per-cell QSFEM weights q(h_c k(c)), Sec. 3.3 */
+  TH_COARSE_WEIGHTS = 1  /* caller-supplied per-coarse-cell (q0, q_edge, q_diag) */
+} th_coarse_scheme;
+
+typedef enum {
+  TH_KRYLOV_GMRES = 0,      /* right-preconditioned (flexible) GMRES, x0 = 0 */
+  TH_KRYLOV_STATIONARY = 1  /* u <- TwoGridStep(u, f) repeated */
+} th_krylov;
+
+/* Fine-level problem and smoother parameters (Sec. 2, 3.1, 4.1, 4.4). */
+typedef struct {
+  int dim;              /* 2 (3 is reserved: TH_EUNSUPPORTED) */
+  int n;                /* cells per direction N >= 1 */
+  int order;            /* p in {2, 4, 6, 8} */
+  const double *k;      /* HOST, N^d per-cell wavenumbers > 0, x fastest; copied */
+  const double *eps;    /* HOST, N^d per-cell damping >= 0, or NULL for 0; copied */
+  int bc[6];            /* sides x-, x+, y-, y+, (z-, z+): th_bc */
+  double alpha_s;       /* smoother shift: volume coefficient k^2 + i alpha_s k^2 + i eps */
+  int l_dd;             /* subdomain size in cells (blocks of ceil(N / l_dd) per direction) */
+  int n_dd;             /* DD iterations per smoother step (>= 1) */
+  int n_s;              /* pre- and post-smoothing steps (>= 1) */
+  double omega_c;       /* coarse-grid correction relaxation */
+  th_gemm gemm;         /* storage of the subdomain operators */
+  int max_rhs;          /* largest nrhs of any later call (sizes the workspaces) */
+} th_fine_desc;
+
+typedef struct {
+  th_coarse_scheme scheme;
+  const double *q;      /* HOST, (pN/2)^d x 3 weights, x fastest; TH_COARSE_WEIGHTS only */
+} th_coarse_desc;
+
+typedef struct {
+  th_krylov krylov;
+  double rtol;          /* stop when ||f - A u||_2 / ||f||_2 <= rtol (per RHS) */
+  int maxit;            /* preconditioner applications per RHS */
+  int restart;          /* GMRES restart length (<= 0: maxit) */
+  th_dtype precond_dtype; /* TH_C128: FP64 preconditioner; TH_C64: complex64 */
+} th_solve_opts;
+
+typedef struct {
+  int iters;            /* largest iteration count over the RHS */
+  double rel_res;       /* largest true relative residual ||f - A u|| / ||f|| (FP64) */
+  double t_solve_s;     /* wall time of the solve */
+  long long n_precond;  /* two-grid preconditioner applications (summed over RHS) */
+} th_solve_stats;
+
+typedef struct {
+  long long n_fine;       /* (pN+1)^d */
+  long long n_coarse;     /* (pN/2+1)^d */
+  int n_sub;              /* number of subdomains */
+  long long b_entries;    /* sum over subdomains of n_U * n_Omega */
+  long long b_bytes;      /* device bytes of the stored subdomain operators */
+  long long coarse_bytes; /* device bytes of the coarse factors */
+  double t_setup_fine_s, t_setup_coarse_s;
+} th_info;
+
+/* Create a context on HIP device `hip_device`, ordering work on `hip_stream`
+ * (a hipStream_t, NULL = default stream).  *out receives the context. */
+th_status th_create(th_ctx **out, int hip_device, void *hip_stream);
+void th_destroy(th_ctx *ctx);
+const char *th_last_error(const th_ctx *ctx);
+th_status th_get_info(const th_ctx *ctx, th_info *info);
+
+/* Build the fine operator data and the smoother (Sec. 4.1, Alg. 2): per-cell
+ * coefficients, the subdomains U^(i) and Omega^(i) = U^(i) + one cell layer,
+ * and for every subdomain the dense operator B_i = diag(1/L_j) R_{U_i}
+ * (A_s^(i))^{-1} (n_U x n_Omega), computed on the device in FP64 and stored
+ * in desc->gemm precision.  Blocking.  Errors: TH_EINVAL (odd order, n < 1,
+ * k <= 0 or NaN, l_dd < 1), TH_EUNSUPPORTED (dim 3), TH_ENOMEM, TH_ENUMERIC
+ * (zero pivot). */
+th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *desc);
+
+/* Build the coarse QSFEM quasi-FE matrix (Sec. 3.3, eq. element_wise_qsfem)
+ * on the coarse vertex grid and factorise it once in FP64 on the device
+ * (block-tridiagonal elimination over grid lines with explicit inverses of
+ * the diagonal Schur blocks).  Needs th_setup_fine.  Blocking. */
+th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *desc);
+
+/* r = f - A u (fine Galerkin matrix, eq. bilin_form).  Stream-ordered. */
+th_status th_residual(th_ctx *ctx, const void *u, const void *f, void *r,
+                      int nrhs, th_dtype dt);
+
+/* u <- CSDDSmoother(u, f) (Alg. 2): r = f - A u, n_dd DD steps on the
+ * shifted operator with the averaged update (eq. RAS_like_update), u += v.
+ * Stream-ordered. */
+th_status th_smooth(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt);
+
+/* rc = I_P^T r (adjoint of the Q_{p/2} interpolation, Sec. 4.2).  Stream-ordered. */
+th_status th_restrict(th_ctx *ctx, const void *r, void *rc, int nrhs, th_dtype dt);
+
+/* u += omega_c I_P uc (Sec. 4.2).  Stream-ordered. */
+th_status th_prolong(th_ctx *ctx, const void *uc, void *u, double omega_c,
+                     int nrhs, th_dtype dt);
+
+/* uc = A_c^{-1} rc with the FP64 coarse factors (Alg. 1, coarse solve).
+ * TH_C64 vectors are promoted to FP64 for the sweeps.  Stream-ordered. */
+th_status th_coarse_solve(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt);
+
+/* u <- TwoGridStep(u, f) (Alg. 1).  Stream-ordered. */
+th_status th_twogrid(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt);
+
+/* Solve A u = f for nrhs right-hand sides (TH_C128 device vectors) with the
+ * two-grid preconditioner: GMRES in FP64 (residual, orthogonalisation,
+ * Hessenberg) or the stationary iteration.  Blocking.  Returns TH_ENOTCONV
+ * when maxit is reached (u holds the last iterate, stats filled). */
+th_status th_solve(th_ctx *ctx, const void *f, void *u, int nrhs,
+                   const th_solve_opts *opts, th_solve_stats *stats);
+
+/* Kernel timing for measurement.  While enabled, HIP events are recorded on
+ * the context stream around every launch of the library's kernels, grouped by
+ * the kernel classes below.  th_timing_enable(ctx, 1) clears the totals;
+ * th_timing_get synchronises the stream and returns, for one class, the summed
+ * GPU time in milliseconds and the number of launches since then. */
+typedef enum {
+  TH_KT_DD_APPLY = 0,   /* batched subdomain solves Y_i = B_i X_i */
+  TH_KT_DD_ACCUM = 1,   /* averaged update of the smoother */
+  TH_KT_OPERATOR = 2,   /* matrix-free fine operator (residual / matvec) */
+  TH_KT_RESTRICT = 3,
+  TH_KT_PROLONG = 4,
+  TH_KT_COARSE = 5,     /* coarse forward/backward sweeps */
+  TH_KT_KRYLOV = 6,     /* GMRES vector kernels */
+  TH_KT_COUNT = 7
+} th_kernel_class;
+
+th_status th_timing_enable(th_ctx *ctx, int enable);
+th_status th_timing_get(th_ctx *ctx, int kernel_class, double *total_ms, long long *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TH_H */

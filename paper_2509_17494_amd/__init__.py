@@ -1,0 +1,266 @@
+"""MI355X two-grid solver for finite-element Helmholtz problems.
+
+Thin Python binding over the C ABI of libth.so (include/th.h): it checks
+shapes, dtypes and devices of torch tensors on the host and passes raw device
+pointers and the current HIP stream.  Every step of the method runs in the
+library's HIP kernels; there is no Python or CPU fallback, and importing the
+binding without the built library raises ImportError.
+
+Method: Stolk, "A two-grid method with dispersion matching for finite-element
+Helmholtz problems" (arXiv 2509.17494): Q_p Galerkin fine level (Sec. 3.1),
+complex-shifted DD smoother (Alg. 2), QSFEM coarse level (Sec. 3.2-3.3),
+Q_{p/2} interpolation (Sec. 4.2), two-grid step (Alg. 1) inside FP64 GMRES.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = ["TwoGridSolver", "THError", "SolveStats", "load_library"]
+
+
+class THError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+@dataclass
+class SolveStats:
+    iters: int
+    rel_res: float
+    t_solve_s: float
+    n_precond: int
+    status: int
+
+
+def load_library():
+    return L.load()
+
+
+_BC = {"robin": L.TH_BC_ROBIN, "neumann": L.TH_BC_NEUMANN}
+_GEMM = {"f64": L.TH_GEMM_F64, "f32": L.TH_GEMM_F32, "bf16": L.TH_GEMM_BF16}
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex128:
+        return L.TH_C128
+    if t.dtype == torch.complex64:
+        return L.TH_C64
+    raise TypeError(f"vectors must be complex128 or complex64, got {t.dtype}")
+
+
+class TwoGridSolver:
+    """One fine problem (2-D unit square, N x N cells, order p) on one GPU.
+
+    k, eps: per-cell arrays of shape (N, N) indexed [y][x] (host, float64).
+    Vectors are torch tensors on the solver's device of shape (nrhs, ndof)
+    (or (ndof,) for one right-hand side), complex128 or complex64, contiguous.
+    """
+
+    def __init__(self, k, eps=None, order: int = 2, alpha_s: float = 0.5, l_dd: int = 8,
+                 n_dd: int = 1, n_s: int = 1, omega_c: float = 1.0, bc=("robin",) * 4,
+                 gemm: str = "f64", max_rhs: int = 1, device: int | None = None,
+                 coarse: str | None = "qsfem", coarse_q=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.float64))
+        if k.ndim != 2 or k.shape[0] != k.shape[1]:
+            raise ValueError("k must have shape (N, N)")
+        self.N = k.shape[0]
+        self.p = int(order)
+        self.dim = 2
+        self.n1 = self.N * self.p + 1
+        self.nc1 = self.N * (self.p // 2) + 1
+        self.n_fine = self.n1 ** 2
+        self.n_coarse = self.nc1 ** 2
+        self.max_rhs = int(max_rhs)
+        self.omega_c = float(omega_c)
+        self._k = k
+        self._eps = None if eps is None else np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+        if self._eps is not None and self._eps.shape != k.shape:
+            raise ValueError("eps must have the shape of k")
+        with torch.cuda.device(self.device):
+            self._stream = torch.cuda.current_stream(self.device)
+            h = C.c_void_p()
+            st = self._lib.th_create(C.byref(h), self.device.index, C.c_void_p(self._stream.cuda_stream))
+            if st != 0:
+                raise THError(st, "th_create failed")
+            self._h = h
+            d = L.FineDesc()
+            d.dim, d.n, d.order = 2, self.N, self.p
+            d.k = k.ctypes.data_as(C.POINTER(C.c_double))
+            d.eps = (self._eps.ctypes.data_as(C.POINTER(C.c_double)) if self._eps is not None
+                     else C.POINTER(C.c_double)())
+            for i, b in enumerate(bc):
+                d.bc[i] = _BC[b]
+            d.alpha_s, d.l_dd, d.n_dd, d.n_s, d.omega_c = alpha_s, l_dd, n_dd, n_s, omega_c
+            d.gemm = _GEMM[gemm]
+            d.max_rhs = self.max_rhs
+            self._check(self._lib.th_setup_fine(self._h, C.byref(d)))
+            if coarse is not None:
+                self.setup_coarse(coarse, coarse_q)
+
+    # ------------------------------------------------------------------
+    def _check(self, st: int):
+        if st != 0:
+            msg = self._lib.th_last_error(self._h)
+            raise THError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.th_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def setup_coarse(self, scheme: str = "qsfem", q=None):
+        d = L.CoarseDesc()
+        if scheme == "qsfem":
+            d.scheme = L.TH_COARSE_QSFEM
+            d.q = C.POINTER(C.c_double)()
+        elif scheme == "weights":
+            q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+            nc = self.N * (self.p // 2)
+            if q.shape != (nc, nc, 3):
+                raise ValueError(f"q must have shape ({nc}, {nc}, 3)")
+            self._q = q
+            d.scheme = L.TH_COARSE_WEIGHTS
+            d.q = q.ctypes.data_as(C.POINTER(C.c_double))
+        else:
+            raise ValueError(scheme)
+        with torch.cuda.device(self.device):
+            self._check(self._lib.th_setup_coarse(self._h, C.byref(d)))
+
+    def timing(self, enable: bool):
+        """Start (and clear) or stop per-kernel-class event timing."""
+        self._check(self._lib.th_timing_enable(self._h, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """{class: (total_ms, launches)} since timing was enabled."""
+        out = {}
+        for i, name in enumerate(L.KERNEL_CLASSES):
+            ms, n = C.c_double(), C.c_longlong()
+            self._check(self._lib.th_timing_get(self._h, i, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    def info(self) -> dict:
+        inf = L.Info()
+        self._check(self._lib.th_get_info(self._h, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in L.Info._fields_}
+
+    # ------------------------------------------------------------------
+    def _vec(self, t: torch.Tensor, n: int, name: str, dtype=None):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.shape[-1] != n or t.dim() not in (1, 2):
+            raise ValueError(f"{name} must have shape (nrhs, {n}) or ({n},)")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}")
+        nrhs = 1 if t.dim() == 1 else t.shape[0]
+        if nrhs < 1 or nrhs > self.max_rhs:
+            raise ValueError(f"nrhs={nrhs} outside [1, max_rhs={self.max_rhs}]")
+        return nrhs
+
+    @staticmethod
+    def _p(t):
+        return C.c_void_p(t.data_ptr())
+
+    def empty_fine(self, nrhs=1, dtype=torch.complex128):
+        return torch.zeros((nrhs, self.n_fine), dtype=dtype, device=self.device)
+
+    def empty_coarse(self, nrhs=1, dtype=torch.complex128):
+        return torch.zeros((nrhs, self.n_coarse), dtype=dtype, device=self.device)
+
+    def residual(self, u, f, r=None):
+        """r = f - A u."""
+        nrhs = self._vec(u, self.n_fine, "u")
+        self._vec(f, self.n_fine, "f", u.dtype)
+        if f.shape != u.shape:
+            raise ValueError("u and f must have the same shape")
+        r = torch.empty_like(u) if r is None else r
+        self._vec(r, self.n_fine, "r", u.dtype)
+        self._check(self._lib.th_residual(self._h, self._p(u), self._p(f), self._p(r), nrhs, _dt(u)))
+        return r
+
+    def smooth(self, u, f):
+        """u <- CSDDSmoother(u, f) in place."""
+        nrhs = self._vec(u, self.n_fine, "u")
+        self._vec(f, self.n_fine, "f", u.dtype)
+        if f.shape != u.shape:
+            raise ValueError("u and f must have the same shape")
+        self._check(self._lib.th_smooth(self._h, self._p(u), self._p(f), nrhs, _dt(u)))
+        return u
+
+    def restrict(self, r, rc=None):
+        """rc = I_P^T r."""
+        nrhs = self._vec(r, self.n_fine, "r")
+        shape = (self.n_coarse,) if r.dim() == 1 else (nrhs, self.n_coarse)
+        rc = torch.empty(shape, dtype=r.dtype, device=self.device) if rc is None else rc
+        self._vec(rc, self.n_coarse, "rc", r.dtype)
+        self._check(self._lib.th_restrict(self._h, self._p(r), self._p(rc), nrhs, _dt(r)))
+        return rc
+
+    def prolong(self, uc, u, omega=None):
+        """u += omega I_P uc in place."""
+        nrhs = self._vec(u, self.n_fine, "u")
+        nrc = self._vec(uc, self.n_coarse, "uc", u.dtype)
+        if nrc != nrhs:
+            raise ValueError("uc and u must hold the same number of vectors")
+        om = self.omega_c if omega is None else float(omega)
+        self._check(self._lib.th_prolong(self._h, self._p(uc), self._p(u), om, nrhs, _dt(u)))
+        return u
+
+    def coarse_solve(self, rc, uc=None):
+        """uc = A_c^{-1} rc (FP64 factors)."""
+        nrhs = self._vec(rc, self.n_coarse, "rc")
+        uc = torch.empty_like(rc) if uc is None else uc
+        self._vec(uc, self.n_coarse, "uc", rc.dtype)
+        if uc.data_ptr() == rc.data_ptr():
+            raise ValueError("rc and uc must not alias")
+        self._check(self._lib.th_coarse_solve(self._h, self._p(rc), self._p(uc), nrhs, _dt(rc)))
+        return uc
+
+    def twogrid(self, u, f):
+        """u <- TwoGridStep(u, f) in place."""
+        nrhs = self._vec(u, self.n_fine, "u")
+        self._vec(f, self.n_fine, "f", u.dtype)
+        if f.shape != u.shape:
+            raise ValueError("u and f must have the same shape")
+        self._check(self._lib.th_twogrid(self._h, self._p(u), self._p(f), nrhs, _dt(u)))
+        return u
+
+    def solve(self, f, u=None, rtol=1e-6, maxit=300, restart=0, precond="c128",
+              method="gmres", raise_on_notconv=False):
+        """Solve A u = f (complex128 vectors) with the two-grid preconditioner.
+
+        precond: "c128" (FP64 two-grid step) or "c64" (complex64 step under
+        FP64 flexible GMRES).  Returns (u, SolveStats)."""
+        nrhs = self._vec(f, self.n_fine, "f", torch.complex128)
+        u = torch.empty_like(f) if u is None else u
+        self._vec(u, self.n_fine, "u", torch.complex128)
+        o = L.SolveOpts()
+        o.krylov = L.TH_KRYLOV_GMRES if method == "gmres" else L.TH_KRYLOV_STATIONARY
+        o.rtol, o.maxit, o.restart = float(rtol), int(maxit), int(restart)
+        o.precond_dtype = L.TH_C128 if precond == "c128" else L.TH_C64
+        st = L.SolveStats()
+        status = self._lib.th_solve(self._h, self._p(f), self._p(u), nrhs, C.byref(o), C.byref(st))
+        if status not in (0, L.TH_ENOTCONV) or (status and raise_on_notconv):
+            self._check(status)
+        return u, SolveStats(st.iters, st.rel_res, st.t_solve_s, st.n_precond, status)

@@ -1,0 +1,963 @@
+// Host side of the two-grid library: argument checking, setup orchestration,
+// the two-grid step (Alg. 1) and the outer FP64 GMRES.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace th {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+const std::string &get_error() { return g_err; }
+
+int hip_fail(hipError_t e, const char *expr, const char *file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), expr,
+           file, line);
+  g_err = buf;
+  return TH_EHIP;
+}
+
+static hipEvent_t take_event(th_ctx *c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+KTimer::KTimer(th_ctx *ctx, int k) : c(ctx), cls(k) {
+  if (c->timing) {
+    start = c->ev_used;
+    hipEvent_t e = take_event(c);
+    if (e) (void)hipEventRecord(e, c->stream);
+    else start = (size_t)-1;
+  }
+}
+
+KTimer::~KTimer() {
+  if (c->timing && start != (size_t)-1) {
+    const size_t stop = c->ev_used;
+    hipEvent_t e = take_event(c);
+    if (!e) return;
+    (void)hipEventRecord(e, c->stream);
+    c->ev_marks.push_back({cls, {start, stop}});
+  }
+}
+
+// ---------------------------------------------------------------------------
+// QSFEM weights (Sec. 3.2, eq. P_QSFEM and eq. scaling_factor_QSFEM; Sec. 3.3
+// element-wise q_gamma): eta = h_c k(c) on the coarse mesh.
+static void qsfem_weights(double eta, double q[3]) {
+  const double a1 = M_PI / 16.0, a2 = 3.0 * M_PI / 16.0;
+  const double c1 = std::cos(eta * std::cos(a1)), s1 = std::cos(eta * std::sin(a1));
+  const double c2 = std::cos(eta * std::cos(a2)), s2 = std::cos(eta * std::sin(a2));
+  const double den = c2 * s2 * (c1 + s1) - c1 * s1 * (c2 + s2);
+  const double P0 = 4.0;
+  const double P1 = 2.0 * (c1 * s1 - c2 * s2) / den;
+  const double P2 = (c2 + s2 - c1 - s1) / den;
+  const double sigma0 = P0 + 4.0 * P1 + 4.0 * P2;  // symbol at xi = 0
+  const double Nn = -eta * eta / sigma0;
+  q[0] = Nn * P0 / 4.0;
+  q[1] = Nn * P1 / 2.0;
+  q[2] = Nn * P2;
+}
+
+}  // namespace th
+
+using namespace th;
+
+#define TH_TRY(expr)                   \
+  do {                                 \
+    int _rc = (expr);                  \
+    if (_rc) return finish(ctx, _rc);  \
+  } while (0)
+
+static th_status finish(th_ctx *ctx, int rc) {
+  if (rc && ctx) ctx->err = get_error();
+  return (th_status)rc;
+}
+static th_status fail(th_ctx *ctx, th_status rc, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return rc;
+}
+
+static bool is_f32(th_dtype dt) { return dt == TH_C64; }
+static size_t csize(bool f32) { return f32 ? sizeof(c32) : sizeof(c64); }
+
+static FineOp make_op(const th_ctx *c, bool shifted) {
+  FineOp op;
+  op.N = c->N;
+  op.P = c->P;
+  op.n1 = c->n1;
+  op.nf = c->nf;
+  op.h = c->h;
+  op.robin = 0;
+  for (int sd = 0; sd < 4; ++sd)
+    if (c->desc.bc[sd] == TH_BC_ROBIN) op.robin |= 1 << sd;
+  op.kap = shifted ? c->d_kaps : c->d_kap;
+  op.kr = c->d_k;
+  return op;
+}
+
+static void free_fine(th_ctx *c) {
+  void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,   c->d_subs, c->d_nblk, c->d_B,  c->w_r,
+                  c->w_v,   c->w_rr,   c->w_y,   c->w_rc,   c->w_uc,   c->w_t, c->w_rc32};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  c->d_kap = c->d_kaps = nullptr;
+  c->d_k = nullptr;
+  c->d_subs = nullptr;
+  c->d_nblk = nullptr;
+  c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = c->w_rc32 = nullptr;
+  c->fine_ready = false;
+}
+
+static void free_coarse(th_ctx *c) {
+  void *ptrs[] = {c->coarse.G, c->coarse.st9};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  c->coarse = CoarseData{};
+  c->coarse_ready = false;
+}
+
+static void free_solver(th_ctx *c) {
+  if (c->s_buf) (void)hipFree(c->s_buf);
+  c->s_buf = nullptr;
+  c->s_bytes = 0;
+}
+
+extern "C" {
+
+th_status th_create(th_ctx **out, int hip_device, void *hip_stream) {
+  if (!out) return TH_EINVAL;
+  *out = nullptr;
+  th_ctx *c = new (std::nothrow) th_ctx();
+  if (!c) return TH_ENOMEM;
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipSetDevice(hip_device);
+  if (e != hipSuccess) {
+    delete c;
+    return TH_EHIP;
+  }
+  *out = c;
+  return TH_OK;
+}
+
+void th_destroy(th_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  free_solver(ctx);
+  free_coarse(ctx);
+  free_fine(ctx);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+th_status th_timing_enable(th_ctx *ctx, int enable) {
+  if (!ctx) return TH_EINVAL;
+  ctx->err.clear();
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, TH_EHIP, "synchronisation failed");
+  ctx->ev_used = 0;
+  ctx->ev_marks.clear();
+  ctx->timing = enable != 0;
+  return TH_OK;
+}
+
+th_status th_timing_get(th_ctx *ctx, int kernel_class, double *total_ms, long long *launches) {
+  if (!ctx || !total_ms || !launches) return TH_EINVAL;
+  if (kernel_class < 0 || kernel_class >= TH_KT_COUNT) return fail(ctx, TH_EINVAL, "bad kernel class");
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, TH_EHIP, "synchronisation failed");
+  double tot = 0.0;
+  long long n = 0;
+  for (auto &m : ctx->ev_marks) {
+    if (m.first != kernel_class) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev_pool[m.second.first], ctx->ev_pool[m.second.second]) !=
+        hipSuccess)
+      return fail(ctx, TH_EHIP, "hipEventElapsedTime failed");
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  return TH_OK;
+}
+
+const char *th_last_error(const th_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+th_status th_get_info(const th_ctx *ctx, th_info *info) {
+  if (!ctx || !info) return TH_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->n_fine = ctx->nf;
+  info->n_coarse = ctx->nc;
+  info->n_sub = (int)ctx->subs.size();
+  info->b_entries = ctx->b_entries;
+  info->b_bytes = ctx->b_bytes;
+  info->coarse_bytes = ctx->coarse.bytes;
+  info->t_setup_fine_s = ctx->t_setup_fine;
+  info->t_setup_coarse_s = ctx->t_setup_coarse;
+  return TH_OK;
+}
+
+th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
+  if (!ctx) return TH_EINVAL;
+  ctx->err.clear();
+  if (!d) return fail(ctx, TH_EINVAL, "null descriptor");
+  if (d->dim == 3) return fail(ctx, TH_EUNSUPPORTED, "3-D problems are not built in this library");
+  if (d->dim != 2) return fail(ctx, TH_EINVAL, "dim must be 2");
+  if (d->n < 1) return fail(ctx, TH_EINVAL, "n must be >= 1");
+  if (d->order < 2 || d->order > kMaxP || d->order % 2)
+    return fail(ctx, TH_EINVAL, "order must be 2, 4, 6 or 8");
+  if (!d->k) return fail(ctx, TH_EINVAL, "k is NULL");
+  if (d->l_dd < 1 || d->n_dd < 1 || d->n_s < 1 || d->max_rhs < 1)
+    return fail(ctx, TH_EINVAL, "l_dd, n_dd, n_s and max_rhs must be >= 1");
+  if (!(d->alpha_s >= 0.0) || !std::isfinite(d->alpha_s) || !std::isfinite(d->omega_c))
+    return fail(ctx, TH_EINVAL, "alpha_s must be finite and >= 0, omega_c finite");
+  if (d->gemm != TH_GEMM_F64 && d->gemm != TH_GEMM_F32)
+    return fail(ctx, TH_EUNSUPPORTED, "subdomain operator storage not built");
+  for (int sd = 0; sd < 4; ++sd)
+    if (d->bc[sd] != TH_BC_ROBIN && d->bc[sd] != TH_BC_NEUMANN)
+      return fail(ctx, TH_EINVAL, "boundary condition must be Robin or Neumann");
+  const long long ncell = (long long)d->n * d->n;
+  for (long long i = 0; i < ncell; ++i) {
+    if (!(d->k[i] > 0.0) || !std::isfinite(d->k[i]))
+      return fail(ctx, TH_EINVAL, "k must be finite and > 0 in every cell");
+    if (d->eps && (!(d->eps[i] >= 0.0) || !std::isfinite(d->eps[i])))
+      return fail(ctx, TH_EINVAL, "eps must be finite and >= 0 in every cell");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TH_EHIP, "hipSetDevice failed");
+  auto t0 = std::chrono::steady_clock::now();
+  free_solver(ctx);
+  free_coarse(ctx);
+  free_fine(ctx);
+  th_ctx *c = ctx;
+  c->desc = *d;
+  c->desc.k = nullptr;
+  c->desc.eps = nullptr;
+  c->dim = 2;
+  c->N = d->n;
+  c->P = d->order;
+  c->R = d->order / 2;
+  c->n1 = c->N * c->P + 1;
+  c->nc1 = c->N * c->R + 1;
+  c->nf = (long long)c->n1 * c->n1;
+  c->nc = (long long)c->nc1 * c->nc1;
+  c->h = 1.0 / c->N;
+  make_ref1d(c->P, c->ref);
+  c->h_k.assign(d->k, d->k + ncell);
+  c->h_eps.assign(ncell, 0.0);
+  if (d->eps) c->h_eps.assign(d->eps, d->eps + ncell);
+
+  // per-cell coefficients
+  std::vector<c64> kap(ncell), kaps(ncell);
+  for (long long i = 0; i < ncell; ++i) {
+    const double k2 = c->h_k[i] * c->h_k[i];
+    kap[i] = c64{k2, c->h_eps[i]};
+    kaps[i] = c64{k2, d->alpha_s * k2 + c->h_eps[i]};
+  }
+
+  // subdomains: M balanced blocks per direction (larger ones first)
+  const int N = c->N, P = c->P;
+  const int M = (N + d->l_dd - 1) / d->l_dd;
+  c->M = M;
+  c->blk_start.assign(M + 1, 0);
+  {
+    const int base = N / M, rem = N % M;
+    for (int b = 0; b < M; ++b) c->blk_start[b + 1] = c->blk_start[b] + base + (b < rem ? 1 : 0);
+  }
+  std::vector<int> nblk(2 * c->n1, 0);
+  for (int i = 0; i < c->n1; ++i) {
+    int b = 0;
+    while (c->blk_start[b + 1] * P < i) ++b;
+    const int cnt = (i == c->blk_start[b + 1] * P && b + 1 < M) ? 2 : 1;
+    nblk[2 * i] = b;
+    nblk[2 * i + 1] = cnt;
+  }
+  c->subs.clear();
+  long long boff = 0, yoff = 0;
+  int max_ldb = 0, max_nom = 0;
+  for (int by = 0; by < M; ++by)
+    for (int bx = 0; bx < M; ++bx) {
+      Sub s{};
+      s.u0x = c->blk_start[bx];
+      s.u1x = c->blk_start[bx + 1];
+      s.u0y = c->blk_start[by];
+      s.u1y = c->blk_start[by + 1];
+      s.o0x = std::max(s.u0x - 1, 0);
+      s.o1x = std::min(s.u1x + 1, N);
+      s.o0y = std::max(s.u0y - 1, 0);
+      s.o1y = std::min(s.u1y + 1, N);
+      s.nux = (s.u1x - s.u0x) * P + 1;
+      s.nuy = (s.u1y - s.u0y) * P + 1;
+      s.nox = (s.o1x - s.o0x) * P + 1;
+      s.noy = (s.o1y - s.o0y) * P + 1;
+      s.nU = s.nux * s.nuy;
+      s.nOm = s.nox * s.noy;
+      s.ldb = (s.nU + 63) / 64 * 64;
+      s.robin = 0;
+      const bool inner[4] = {s.o0x > 0, s.o1x < N, s.o0y > 0, s.o1y < N};
+      for (int sd = 0; sd < 4; ++sd)
+        if (inner[sd] || d->bc[sd] == TH_BC_ROBIN) s.robin |= 1 << sd;
+      s.boff = boff;
+      s.yoff = yoff;
+      boff += (long long)s.nOm * s.ldb;
+      yoff += s.nU;
+      max_ldb = std::max(max_ldb, s.ldb);
+      max_nom = std::max(max_nom, s.nOm);
+      c->subs.push_back(s);
+    }
+  c->max_ldb = max_ldb;
+  c->max_nom = max_nom;
+  c->max_rowblocks = (max_ldb + 255) / 256;
+  c->y_rows = yoff;
+  c->b_entries = 0;
+  for (auto &s : c->subs) c->b_entries += (long long)s.nU * s.nOm;
+  const size_t belem = (d->gemm == TH_GEMM_F32) ? sizeof(c32) : sizeof(c64);
+  c->b_bytes = boff * (long long)belem;
+
+  hipStream_t st = c->stream;
+  auto alloc = [&](void **p, size_t bytes) -> bool {
+    if (bytes == 0) bytes = 16;
+    return hipMalloc(p, bytes) == hipSuccess;
+  };
+  const size_t R = (size_t)d->max_rhs;
+  bool ok = alloc((void **)&c->d_kap, ncell * sizeof(c64)) &&
+            alloc((void **)&c->d_kaps, ncell * sizeof(c64)) &&
+            alloc((void **)&c->d_k, ncell * sizeof(double)) &&
+            alloc((void **)&c->d_subs, c->subs.size() * sizeof(Sub)) &&
+            alloc((void **)&c->d_nblk, nblk.size() * sizeof(int)) && alloc(&c->d_B, c->b_bytes) &&
+            alloc(&c->w_r, R * c->nf * sizeof(c64)) &&
+            alloc(&c->w_y, R * c->y_rows * sizeof(c64));
+  if (ok && d->n_dd > 1)
+    ok = alloc(&c->w_v, R * c->nf * sizeof(c64)) && alloc(&c->w_rr, R * c->nf * sizeof(c64));
+  if (!ok) {
+    free_fine(c);
+    return fail(ctx, TH_ENOMEM, "device allocation failed in setup_fine");
+  }
+  if (hipMemcpyAsync(c->d_kap, kap.data(), ncell * sizeof(c64), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(c->d_kaps, kaps.data(), ncell * sizeof(c64), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(c->d_k, c->h_k.data(), ncell * sizeof(double), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(c->d_subs, c->subs.data(), c->subs.size() * sizeof(Sub),
+                     hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(c->d_nblk, nblk.data(), nblk.size() * sizeof(int), hipMemcpyHostToDevice,
+                     st) ||
+      hipMemsetAsync(c->d_B, 0, c->b_bytes, st)) {
+    free_fine(c);
+    return fail(ctx, TH_EHIP, "upload failed in setup_fine");
+  }
+  int rc = setup_subdomain_operators(c);
+  if (rc) {
+    free_fine(c);
+    return finish(ctx, rc);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    free_fine(c);
+    return fail(ctx, TH_EHIP, "synchronisation failed in setup_fine");
+  }
+  c->t_setup_fine = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  c->fine_ready = true;
+  return TH_OK;
+}
+
+th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
+  if (!ctx) return TH_EINVAL;
+  ctx->err.clear();
+  if (!d) return fail(ctx, TH_EINVAL, "null descriptor");
+  if (!ctx->fine_ready) return fail(ctx, TH_ESTATE, "th_setup_fine must succeed first");
+  if (d->scheme != TH_COARSE_QSFEM && d->scheme != TH_COARSE_WEIGHTS)
+    return fail(ctx, TH_EINVAL, "unknown coarse scheme");
+  if (d->scheme == TH_COARSE_WEIGHTS && !d->q) return fail(ctx, TH_EINVAL, "q is NULL");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TH_EHIP, "hipSetDevice failed");
+  auto t0 = std::chrono::steady_clock::now();
+  free_coarse(ctx);
+  th_ctx *c = ctx;
+  const int Nc = c->N * c->R, nc1 = c->nc1;
+  const double hc = 1.0 / Nc;
+  // per coarse cell: k, eps of the fine cell containing it; weights q
+  std::vector<double> qw((size_t)Nc * Nc * 3);
+  for (int cy = 0; cy < Nc; ++cy)
+    for (int cxx = 0; cxx < Nc; ++cxx) {
+      const long long ci = (long long)cy * Nc + cxx;
+      const long long fi = (long long)(cy / c->R) * c->N + cxx / c->R;
+      if (d->scheme == TH_COARSE_QSFEM) {
+        qsfem_weights(hc * c->h_k[fi], &qw[3 * ci]);
+      } else {
+        for (int t = 0; t < 3; ++t) {
+          qw[3 * ci + t] = d->q[3 * ci + t];
+          if (!std::isfinite(qw[3 * ci + t])) return fail(ctx, TH_EINVAL, "non-finite weight q");
+        }
+      }
+    }
+  // 9-point quasi-FE stencil per coarse vertex (eq. element_wise_qsfem with the
+  // -i eps Q1 mass and the absorbing Q1 boundary mass)
+  std::vector<c64> st((size_t)nc1 * nc1 * 9, c64{0, 0});
+  const double m1[2][2] = {{1.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 1.0 / 3.0}};
+  for (int cy = 0; cy < Nc; ++cy)
+    for (int cxx = 0; cxx < Nc; ++cxx) {
+      const long long ci = (long long)cy * Nc + cxx;
+      const long long fi = (long long)(cy / c->R) * c->N + cxx / c->R;
+      const double kk = c->h_k[fi], ee = c->h_eps[fi];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          const int ax = a & 1, ay = a >> 1, bx = b & 1, by = b >> 1;
+          const int diff = (ax != bx) + (ay != by);
+          c64 v = {qw[3 * ci + diff], -ee * hc * hc * m1[ay][by] * m1[ax][bx]};
+          // absorbing sides: x- (cxx==0, ax=bx=0), x+ (ax=bx=1), y- (ay=by=0), y+
+          if (cxx == 0 && ax == 0 && bx == 0 && c->desc.bc[0] == TH_BC_ROBIN)
+            v.im -= kk * hc * m1[ay][by];
+          if (cxx == Nc - 1 && ax == 1 && bx == 1 && c->desc.bc[1] == TH_BC_ROBIN)
+            v.im -= kk * hc * m1[ay][by];
+          if (cy == 0 && ay == 0 && by == 0 && c->desc.bc[2] == TH_BC_ROBIN)
+            v.im -= kk * hc * m1[ax][bx];
+          if (cy == Nc - 1 && ay == 1 && by == 1 && c->desc.bc[3] == TH_BC_ROBIN)
+            v.im -= kk * hc * m1[ax][bx];
+          const long long ga = (long long)(cy + ay) * nc1 + cxx + ax;
+          const int dx = bx - ax, dy = by - ay;
+          c64 &e = st[9 * ga + (dy + 1) * 3 + (dx + 1)];
+          e = e + v;
+        }
+    }
+  int rc = setup_coarse_factors(c, st);
+  if (rc) {
+    free_coarse(c);
+    return finish(ctx, rc);
+  }
+  const size_t R = (size_t)c->desc.max_rhs;
+  if (!c->w_rc) {
+    if (hipMalloc(&c->w_rc, R * c->nc * sizeof(c64)) != hipSuccess ||
+        hipMalloc(&c->w_uc, R * c->nc * sizeof(c64)) != hipSuccess ||
+        hipMalloc(&c->w_rc32, R * c->nc * sizeof(c64)) != hipSuccess) {
+      free_coarse(c);
+      return fail(ctx, TH_ENOMEM, "device allocation failed in setup_coarse");
+    }
+  }
+  c->t_setup_coarse = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  c->coarse_ready = true;
+  return TH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// internal steps (precision selected by f32)
+
+namespace th {
+
+static int add_inplace(th_ctx *c, void *u, const void *v, int nrhs, bool f32) {
+  return launch_add(u, v, (long long)nrhs * c->nf, f32, c->stream);
+}
+
+// u <- CSDDSmoother(u, f) (Alg. 2).  u_zero: u holds zeros on entry (it is
+// then assigned, not read).
+static int smooth_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, bool u_zero) {
+  hipStream_t s = c->stream;
+  const void *r = f;
+  if (!u_zero) {
+    KTimer kt(c, TH_KT_OPERATOR);
+    int rc = launch_apply(make_op(c, false), c->ref, u, f, c->w_r, nrhs, f32, -1.0, s);
+    if (rc) return rc;
+    r = c->w_r;
+  }
+  int rc;
+  {
+    KTimer kt(c, TH_KT_DD_APPLY);
+    rc = launch_dd_apply(c, r, c->w_y, nrhs, f32, s);
+  }
+  if (rc) return rc;
+  if (c->desc.n_dd == 1) {
+    KTimer kt(c, TH_KT_DD_ACCUM);
+    return launch_dd_accumulate(c, c->w_y, u, nrhs, f32, u_zero, s);
+  }
+  // n_dd > 1: v accumulates the DD steps, DDStep(v, r; A_s):
+  // v <- v + avg((A_s^(i))^{-1} R_i (r - A_s v))
+  rc = launch_dd_accumulate(c, c->w_y, c->w_v, nrhs, f32, true, s);
+  for (int it = 1; it < c->desc.n_dd && rc == 0; ++it) {
+    rc = launch_apply(make_op(c, true), c->ref, c->w_v, r, c->w_rr, nrhs, f32, -1.0, s);
+    if (!rc) rc = launch_dd_apply(c, c->w_rr, c->w_y, nrhs, f32, s);
+    if (!rc) rc = launch_dd_accumulate(c, c->w_y, c->w_v, nrhs, f32, false, s);
+  }
+  if (rc) return rc;
+  if (u_zero) {
+    TH_HIP_CHECK_RET(hipMemcpyAsync(u, c->w_v, (size_t)nrhs * c->nf * csize(f32),
+                                    hipMemcpyDeviceToDevice, s));
+    return 0;
+  }
+  return add_inplace(c, u, c->w_v, nrhs, f32);
+}
+
+static int coarse_solve_impl(th_ctx *c, const void *rc_in, void *uc_out, int nrhs, bool f32) {
+  hipStream_t s = c->stream;
+  const c64 *r64 = (const c64 *)rc_in;
+  c64 *u64 = (c64 *)uc_out;
+  if (f32) {
+    int rc = launch_convert(rc_in, c->w_rc, (long long)nrhs * c->nc, true, false, s);
+    if (rc) return rc;
+    r64 = (const c64 *)c->w_rc;
+    u64 = (c64 *)c->w_uc;
+  }
+  int rc;
+  {
+    KTimer kt(c, TH_KT_COARSE);
+    rc = launch_coarse_solve(c, r64, u64, nrhs, s);
+  }
+  if (rc) return rc;
+  if (f32) return launch_convert(u64, uc_out, (long long)nrhs * c->nc, false, true, s);
+  return 0;
+}
+
+// u <- TwoGridStep(u, f) (Alg. 1)
+static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, bool u_zero) {
+  hipStream_t s = c->stream;
+  int rc = 0;
+  for (int i = 0; i < c->desc.n_s && rc == 0; ++i) rc = smooth_impl(c, u, f, nrhs, f32, u_zero && i == 0);
+  if (rc) return rc;
+  {
+    KTimer kt(c, TH_KT_OPERATOR);
+    rc = launch_apply(make_op(c, false), c->ref, u, f, c->w_r, nrhs, f32, -1.0, s);
+  }
+  if (rc) return rc;
+  void *rcv = f32 ? c->w_rc32 : c->w_rc;
+  void *ucv = f32 ? c->w_rc32 : c->w_uc;
+  {
+    KTimer kt(c, TH_KT_RESTRICT);
+    rc = launch_restrict(c->N, c->P, c->ref, c->w_r, rcv, nrhs, f32, s);
+  }
+  if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32);
+  if (!rc) {
+    KTimer kt(c, TH_KT_PROLONG);
+    rc = launch_prolong(c->N, c->P, c->ref, ucv, u, c->desc.omega_c, nrhs, f32, s);
+  }
+  for (int i = 0; i < c->desc.n_s && rc == 0; ++i) rc = smooth_impl(c, u, f, nrhs, f32, false);
+  return rc;
+}
+
+}  // namespace th
+
+extern "C" {
+
+static th_status check_vec_call(th_ctx *ctx, const void *a, const void *b, int nrhs, th_dtype dt,
+                                bool need_coarse) {
+  if (!ctx) return TH_EINVAL;
+  ctx->err.clear();
+  if (!ctx->fine_ready) return fail(ctx, TH_ESTATE, "th_setup_fine must succeed first");
+  if (need_coarse && !ctx->coarse_ready)
+    return fail(ctx, TH_ESTATE, "th_setup_coarse must succeed first");
+  if (!a || !b) return fail(ctx, TH_EINVAL, "null vector pointer");
+  if (nrhs < 1 || nrhs > ctx->desc.max_rhs) return fail(ctx, TH_EINVAL, "nrhs out of range");
+  if (dt != TH_C128 && dt != TH_C64) return fail(ctx, TH_EINVAL, "unknown dtype");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TH_EHIP, "hipSetDevice failed");
+  return TH_OK;
+}
+
+th_status th_residual(th_ctx *ctx, const void *u, const void *f, void *r, int nrhs, th_dtype dt) {
+  th_status st = check_vec_call(ctx, u, f, nrhs, dt, false);
+  if (st) return st;
+  if (!r) return fail(ctx, TH_EINVAL, "null vector pointer");
+  return finish(ctx, launch_apply(make_op(ctx, false), ctx->ref, u, f, r, nrhs, is_f32(dt), -1.0,
+                                  ctx->stream));
+}
+
+th_status th_smooth(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt) {
+  th_status st = check_vec_call(ctx, u, f, nrhs, dt, false);
+  if (st) return st;
+  return finish(ctx, smooth_impl(ctx, u, f, nrhs, is_f32(dt), false));
+}
+
+th_status th_restrict(th_ctx *ctx, const void *r, void *rc, int nrhs, th_dtype dt) {
+  th_status st = check_vec_call(ctx, r, rc, nrhs, dt, false);
+  if (st) return st;
+  return finish(ctx, launch_restrict(ctx->N, ctx->P, ctx->ref, r, rc, nrhs, is_f32(dt), ctx->stream));
+}
+
+th_status th_prolong(th_ctx *ctx, const void *uc, void *u, double omega_c, int nrhs, th_dtype dt) {
+  th_status st = check_vec_call(ctx, uc, u, nrhs, dt, false);
+  if (st) return st;
+  if (!std::isfinite(omega_c)) return fail(ctx, TH_EINVAL, "omega_c must be finite");
+  return finish(ctx, launch_prolong(ctx->N, ctx->P, ctx->ref, uc, u, omega_c, nrhs, is_f32(dt),
+                                    ctx->stream));
+}
+
+th_status th_coarse_solve(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt) {
+  th_status st = check_vec_call(ctx, rc, uc, nrhs, dt, true);
+  if (st) return st;
+  return finish(ctx, coarse_solve_impl(ctx, rc, uc, nrhs, is_f32(dt)));
+}
+
+th_status th_twogrid(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt) {
+  th_status st = check_vec_call(ctx, u, f, nrhs, dt, true);
+  if (st) return st;
+  return finish(ctx, twogrid_impl(ctx, u, f, nrhs, is_f32(dt), false));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Outer Krylov method (FP64)
+
+namespace th {
+
+using zc = std::complex<double>;
+
+struct SolverWS {
+  c64 *V, *Z, *partial, *hd, *tmp32a, *tmp32b, *coef, *fx;
+  double *scal;
+};
+
+static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
+  const size_t vec = (size_t)nrhs * c->nf * sizeof(c64);
+  size_t need = (size_t)(m + 1) * vec + (size_t)m * vec;   // V, Z
+  need += (size_t)nrhs * 256 * sizeof(c64);                 // partial sums
+  need += (size_t)nrhs * sizeof(c64) * 2;                   // dot outputs
+  need += f32 ? 2 * (size_t)nrhs * c->nf * sizeof(c32) : 0;  // precision staging
+  need += (size_t)nrhs * (m + 1) * sizeof(c64);             // lincomb coefficients
+  need += (size_t)nrhs * sizeof(double) * 2;                // scalars
+  need += 4096;
+  if (need > c->s_bytes) {
+    free_solver(c);
+    if (hipMalloc(&c->s_buf, need) != hipSuccess) {
+      set_error("cannot allocate the Krylov work space");
+      return TH_ENOMEM;
+    }
+    c->s_bytes = need;
+  }
+  char *p = (char *)c->s_buf;
+  auto take = [&](size_t bytes) {
+    char *q = p;
+    p += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  w.V = (c64 *)take((size_t)(m + 1) * vec);
+  w.Z = (c64 *)take((size_t)m * vec);
+  w.partial = (c64 *)take((size_t)nrhs * 256 * sizeof(c64));
+  w.hd = (c64 *)take((size_t)nrhs * sizeof(c64) * 2);
+  w.tmp32a = f32 ? (c64 *)take((size_t)nrhs * c->nf * sizeof(c32)) : nullptr;
+  w.tmp32b = f32 ? (c64 *)take((size_t)nrhs * c->nf * sizeof(c32)) : nullptr;
+  w.coef = (c64 *)take((size_t)nrhs * (m + 1) * sizeof(c64));
+  w.scal = (double *)take((size_t)nrhs * sizeof(double) * 2);
+  return 0;
+}
+
+// z = TwoGridStep(0, v) in the requested precision; v, z FP64
+static int precond(th_ctx *c, const c64 *v, c64 *z, int nrhs, bool f32, SolverWS &w) {
+  if (!f32) return twogrid_impl(c, z, v, nrhs, false, true);
+  const long long n = (long long)nrhs * c->nf;
+  int rc = launch_convert(v, w.tmp32a, n, false, true, c->stream);
+  if (!rc) rc = twogrid_impl(c, w.tmp32b, w.tmp32a, nrhs, true, true);
+  if (!rc) rc = launch_convert(w.tmp32b, z, n, true, false, c->stream);
+  return rc;
+}
+
+static int dot_to_host(th_ctx *c, const c64 *x, const c64 *y, int nrhs, SolverWS &w,
+                       std::vector<zc> &out) {
+  int rc = launch_dot(x, y, c->nf, nrhs, c->nf, c->nf, w.hd, w.partial, c->stream);
+  if (rc) return rc;
+  std::vector<c64> h(nrhs);
+  TH_HIP_CHECK_RET(hipMemcpyAsync(h.data(), w.hd, nrhs * sizeof(c64), hipMemcpyDeviceToHost,
+                                  c->stream));
+  TH_HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+  out.resize(nrhs);
+  for (int r = 0; r < nrhs; ++r) out[r] = zc(h[r].re, h[r].im);
+  return 0;
+}
+
+static void givens(zc a, zc b, zc &cs, zc &sn, zc &rr) {
+  if (b == 0.0) {
+    cs = 1.0;
+    sn = 0.0;
+    rr = a;
+    return;
+  }
+  if (a == 0.0) {
+    cs = 0.0;
+    sn = std::conj(b) / std::abs(b);
+    rr = std::abs(b);
+    return;
+  }
+  const double t = std::sqrt(std::norm(a) + std::norm(b));
+  const zc ph = a / std::abs(a);
+  cs = std::abs(a) / t;
+  sn = ph * std::conj(b) / t;
+  rr = ph * t;
+}
+
+static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve_opts *o,
+                       th_solve_stats *stats) {
+  hipStream_t s = c->stream;
+  const bool f32 = o->precond_dtype == TH_C64;
+  const int maxit = o->maxit;
+  const int m = (o->restart > 0) ? std::min(o->restart, maxit) : maxit;
+  SolverWS w;
+  int rc = ensure_solver_ws(c, m, nrhs, f32, w);
+  if (rc) return rc;
+  const size_t vbytes = (size_t)nrhs * c->nf * sizeof(c64);
+  const long long nf = c->nf;
+  auto Vj = [&](int j) { return w.V + (size_t)j * nrhs * nf; };
+  auto Zj = [&](int j) { return w.Z + (size_t)j * nrhs * nf; };
+
+  std::vector<zc> fn2;
+  rc = dot_to_host(c, f, f, nrhs, w, fn2);
+  if (rc) return rc;
+  std::vector<double> fnorm(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    fnorm[r] = std::sqrt(std::max(fn2[r].real(), 0.0));
+    if (!std::isfinite(fnorm[r])) {
+      set_error("right-hand side contains NaN or Inf");
+      return TH_ENUMERIC;
+    }
+  }
+  TH_HIP_CHECK_RET(hipMemsetAsync(u, 0, vbytes, s));
+  std::vector<int> conv(nrhs, 0), it_r(nrhs, 0);
+  for (int r = 0; r < nrhs; ++r)
+    if (fnorm[r] == 0.0) conv[r] = 1;
+  int total = 0;
+  long long nprec = 0;
+  bool first_cycle = true;
+  std::vector<double> hscal(nrhs);
+  while (true) {
+    // r0 = f - A x into V_0
+    if (first_cycle) {
+      TH_HIP_CHECK_RET(hipMemcpyAsync(Vj(0), f, vbytes, hipMemcpyDeviceToDevice, s));
+    } else {
+      rc = launch_apply(make_op(c, false), c->ref, u, f, Vj(0), nrhs, false, -1.0, s);
+      if (rc) return rc;
+    }
+    std::vector<zc> bb;
+    rc = dot_to_host(c, Vj(0), Vj(0), nrhs, w, bb);
+    if (rc) return rc;
+    std::vector<double> beta(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      beta[r] = std::sqrt(std::max(bb[r].real(), 0.0));
+      hscal[r] = (beta[r] > 0.0) ? 1.0 / beta[r] : 0.0;
+    }
+    TH_HIP_CHECK_RET(hipMemcpyAsync(w.scal, hscal.data(), nrhs * sizeof(double),
+                                    hipMemcpyHostToDevice, s));
+    rc = launch_scale_dev(Vj(0), Vj(0), w.scal, nf, nrhs, nf, nf, s);
+    if (rc) return rc;
+    std::vector<std::vector<zc>> H(nrhs, std::vector<zc>((size_t)(m + 1) * m, 0.0));
+    std::vector<std::vector<zc>> g(nrhs, std::vector<zc>(m + 1, 0.0)), cs(nrhs, std::vector<zc>(m)),
+        sn(nrhs, std::vector<zc>(m));
+    std::vector<int> jend(nrhs, 0), active(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      g[r][0] = beta[r];
+      active[r] = !conv[r];
+      if (beta[r] == 0.0 && !conv[r]) {
+        conv[r] = 1;
+        active[r] = 0;
+      }
+    }
+    int j = 0;
+    bool cycle_done = false;
+    for (j = 0; j < m && !cycle_done; ++j) {
+      rc = precond(c, Vj(j), Zj(j), nrhs, f32, w);
+      if (rc) return rc;
+      nprec += nrhs;
+      {
+        KTimer kt(c, TH_KT_OPERATOR);
+        rc = launch_apply(make_op(c, false), c->ref, Zj(j), nullptr, Vj(j + 1), nrhs, false, 1.0, s);
+      }
+      if (rc) return rc;
+      // modified Gram-Schmidt
+      std::vector<std::vector<zc>> hcol(nrhs, std::vector<zc>(j + 2, 0.0));
+      std::vector<c64> hh((size_t)nrhs * (j + 1));
+      for (int i = 0; i <= j; ++i) {
+        {
+          KTimer kt(c, TH_KT_KRYLOV);
+          rc = launch_dot(Vj(i), Vj(j + 1), nf, nrhs, nf, nf, w.hd, w.partial, s);
+          if (!rc) rc = launch_axpy_dev(Vj(j + 1), Vj(i), w.hd, -1.0, nf, nrhs, nf, nf, s);
+        }
+        if (rc) return rc;
+        TH_HIP_CHECK_RET(hipMemcpyAsync(hh.data() + (size_t)i * nrhs, w.hd, nrhs * sizeof(c64),
+                                        hipMemcpyDeviceToHost, s));
+      }
+      std::vector<zc> ww;
+      rc = dot_to_host(c, Vj(j + 1), Vj(j + 1), nrhs, w, ww);  // synchronises
+      if (rc) return rc;
+      for (int r = 0; r < nrhs; ++r) {
+        for (int i = 0; i <= j; ++i) hcol[r][i] = zc(hh[(size_t)i * nrhs + r].re, hh[(size_t)i * nrhs + r].im);
+        const double hn = std::sqrt(std::max(ww[r].real(), 0.0));
+        hcol[r][j + 1] = hn;
+        hscal[r] = (hn > 0.0 && std::isfinite(hn)) ? 1.0 / hn : 0.0;
+      }
+      TH_HIP_CHECK_RET(hipMemcpyAsync(w.scal, hscal.data(), nrhs * sizeof(double),
+                                      hipMemcpyHostToDevice, s));
+      rc = launch_scale_dev(Vj(j + 1), Vj(j + 1), w.scal, nf, nrhs, nf, nf, s);
+      if (rc) return rc;
+      ++total;
+      bool all_done = true;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!active[r]) continue;
+        std::vector<zc> &h = hcol[r];
+        const double hsub = std::abs(h[j + 1]);  // before the rotation zeroes it
+        if (!std::isfinite(hsub)) {
+          set_error("NaN or Inf in the Arnoldi process");
+          return TH_ENUMERIC;
+        }
+        for (int i = 0; i < j; ++i) {
+          zc t = cs[r][i] * h[i] + sn[r][i] * h[i + 1];
+          h[i + 1] = -std::conj(sn[r][i]) * h[i] + std::conj(cs[r][i]) * h[i + 1];
+          h[i] = t;
+        }
+        zc rr;
+        givens(h[j], h[j + 1], cs[r][j], sn[r][j], rr);
+        h[j] = rr;
+        h[j + 1] = 0.0;
+        g[r][j + 1] = -std::conj(sn[r][j]) * g[r][j];
+        g[r][j] = cs[r][j] * g[r][j];
+        for (int i = 0; i <= j; ++i) H[r][(size_t)i * m + j] = h[i];
+        jend[r] = j + 1;
+        it_r[r] = total;
+        const double rel = std::abs(g[r][j + 1]) / fnorm[r];
+        if (rel <= o->rtol || hsub == 0.0) {
+          conv[r] = 1;
+          active[r] = 0;
+        } else {
+          all_done = false;
+        }
+      }
+      if (all_done || total >= maxit) cycle_done = true;
+    }
+    // x += Z y for every RHS
+    std::vector<c64> coef((size_t)nrhs * m, c64{0, 0});
+    for (int r = 0; r < nrhs; ++r) {
+      const int je = jend[r];
+      std::vector<zc> y(je, 0.0);
+      for (int i = je - 1; i >= 0; --i) {
+        zc acc = g[r][i];
+        for (int q = i + 1; q < je; ++q) acc -= H[r][(size_t)i * m + q] * y[q];
+        y[i] = acc / H[r][(size_t)i * m + i];
+      }
+      for (int i = 0; i < je; ++i) coef[(size_t)r * m + i] = c64{y[i].real(), y[i].imag()};
+    }
+    TH_HIP_CHECK_RET(hipMemcpyAsync(w.coef, coef.data(), coef.size() * sizeof(c64),
+                                    hipMemcpyHostToDevice, s));
+    rc = launch_lincomb(u, w.Z, w.coef, j, m, nf, nrhs, (long long)nrhs * nf, nf, s);
+    if (rc) return rc;
+    TH_HIP_CHECK_RET(hipStreamSynchronize(s));
+    first_cycle = false;
+    bool all_conv = true;
+    for (int r = 0; r < nrhs; ++r) all_conv &= conv[r] != 0;
+    if (all_conv || total >= maxit) break;
+  }
+  // true FP64 residual
+  rc = launch_apply(make_op(c, false), c->ref, u, f, w.V, nrhs, false, -1.0, s);
+  if (rc) return rc;
+  std::vector<zc> rn;
+  rc = dot_to_host(c, w.V, w.V, nrhs, w, rn);
+  if (rc) return rc;
+  double worst = 0.0;
+  int maxits = 0;
+  bool all_conv = true;
+  for (int r = 0; r < nrhs; ++r) {
+    const double rel = (fnorm[r] > 0) ? std::sqrt(std::max(rn[r].real(), 0.0)) / fnorm[r] : 0.0;
+    worst = std::max(worst, rel);
+    maxits = std::max(maxits, it_r[r]);
+    all_conv &= conv[r] != 0;
+  }
+  if (stats) {
+    stats->iters = maxits;
+    stats->rel_res = worst;
+    stats->n_precond = nprec;
+  }
+  if (!all_conv) {
+    set_error("GMRES reached maxit before the tolerance");
+    return TH_ENOTCONV;
+  }
+  return 0;
+}
+
+static int solve_stationary(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve_opts *o,
+                            th_solve_stats *stats) {
+  hipStream_t s = c->stream;
+  const bool f32 = o->precond_dtype == TH_C64;
+  SolverWS w;
+  int rc = ensure_solver_ws(c, 1, nrhs, f32, w);
+  if (rc) return rc;
+  const long long nf = c->nf;
+  const size_t vbytes = (size_t)nrhs * nf * sizeof(c64);
+  std::vector<zc> fn2;
+  rc = dot_to_host(c, f, f, nrhs, w, fn2);
+  if (rc) return rc;
+  std::vector<double> fnorm(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    fnorm[r] = std::sqrt(std::max(fn2[r].real(), 0.0));
+    if (!std::isfinite(fnorm[r])) {
+      set_error("right-hand side contains NaN or Inf");
+      return TH_ENUMERIC;
+    }
+  }
+  TH_HIP_CHECK_RET(hipMemsetAsync(u, 0, vbytes, s));
+  int it = 0;
+  double worst = 0.0;
+  while (it < o->maxit) {
+    // u <- u + B (f - A u)  (= TwoGridStep(u, f) for the linear two-grid map)
+    rc = launch_apply(make_op(c, false), c->ref, u, f, w.V, nrhs, false, -1.0, s);
+    if (!rc) rc = precond(c, w.V, w.Z, nrhs, f32, w);
+    if (rc) return rc;
+    c64 one = {1.0, 0.0};
+    std::vector<c64> ones(nrhs, one);
+    TH_HIP_CHECK_RET(hipMemcpyAsync(w.hd, ones.data(), nrhs * sizeof(c64), hipMemcpyHostToDevice, s));
+    rc = launch_axpy_dev(u, w.Z, w.hd, 1.0, nf, nrhs, nf, nf, s);
+    if (rc) return rc;
+    ++it;
+    rc = launch_apply(make_op(c, false), c->ref, u, f, w.V, nrhs, false, -1.0, s);
+    if (rc) return rc;
+    std::vector<zc> rn;
+    rc = dot_to_host(c, w.V, w.V, nrhs, w, rn);
+    if (rc) return rc;
+    worst = 0.0;
+    for (int r = 0; r < nrhs; ++r)
+      worst = std::max(worst, fnorm[r] > 0 ? std::sqrt(std::max(rn[r].real(), 0.0)) / fnorm[r] : 0.0);
+    if (!std::isfinite(worst)) {
+      set_error("stationary iteration diverged to NaN/Inf");
+      return TH_ENUMERIC;
+    }
+    if (worst <= o->rtol) break;
+  }
+  if (stats) {
+    stats->iters = it;
+    stats->rel_res = worst;
+    stats->n_precond = (long long)it * nrhs;
+  }
+  if (worst > o->rtol) {
+    set_error("stationary iteration reached maxit before the tolerance");
+    return TH_ENOTCONV;
+  }
+  return 0;
+}
+
+}  // namespace th
+
+extern "C" th_status th_solve(th_ctx *ctx, const void *f, void *u, int nrhs,
+                              const th_solve_opts *opts, th_solve_stats *stats) {
+  th_status st = check_vec_call(ctx, f, u, nrhs, TH_C128, true);
+  if (st) return st;
+  if (!opts) return fail(ctx, TH_EINVAL, "null options");
+  if (!(opts->rtol > 0.0) || opts->maxit < 1) return fail(ctx, TH_EINVAL, "rtol > 0 and maxit >= 1 required");
+  if (opts->precond_dtype != TH_C128 && opts->precond_dtype != TH_C64)
+    return fail(ctx, TH_EINVAL, "unknown preconditioner dtype");
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if (opts->krylov == TH_KRYLOV_GMRES)
+    rc = solve_gmres(ctx, (const c64 *)f, (c64 *)u, nrhs, opts, stats);
+  else if (opts->krylov == TH_KRYLOV_STATIONARY)
+    rc = solve_stationary(ctx, (const c64 *)f, (c64 *)u, nrhs, opts, stats);
+  else
+    return fail(ctx, TH_EINVAL, "unknown Krylov method");
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == 0) rc = TH_EHIP;
+  if (stats)
+    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return finish(ctx, rc);
+}

@@ -1,0 +1,162 @@
+// Library context and internal interfaces between the host code and the
+// kernel launchers.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/th.h"
+#include "common.hpp"
+
+namespace th {
+
+// One subdomain: U = non-overlapping cell box, Om = U plus one cell layer
+// clipped to the domain (Sec. 4.1, 4.4).  Boxes are half-open cell ranges.
+struct Sub {
+  int u0x, u1x, u0y, u1y;     // U cell box
+  int o0x, o1x, o0y, o1y;     // Omega cell box
+  int nux, nuy, nox, noy;     // node counts of closed U / Omega per direction
+  int nU, nOm;                // nodes of closed U / Omega
+  int ldb;                    // leading dimension (padded n_U) of stored B_i^T
+  int robin;                  // bit s set: absorbing term on side s of Omega (x-,x+,y-,y+)
+  long long boff;             // element offset of B_i in the operator store
+  long long yoff;             // offset of this subdomain's rows in the Y scratch
+};
+
+// Geometry and coefficients of the fine operator, passed to kernels by value.
+struct FineOp {
+  int N, P, n1;               // cells/dir, order, nodes/dir
+  long long nf;               // nodes
+  double h;
+  int robin;                  // bit s: Robin on global side s (x-,x+,y-,y+)
+  const c64 *kap;             // per cell volume coefficient (k^2 + i eps) or shifted
+  const double *kr;           // per cell k for the absorbing term
+};
+
+struct CoarseData {
+  int nx = 0, ny = 0;         // coarse vertices per line / lines
+  int nblk = 0;               // super-blocks of consecutive lines
+  int rc_chunk = 1;           // right-hand sides per sweep pass
+  std::vector<int> line0;     // first line of every super-block (nblk + 1 entries)
+  std::vector<int> ld;        // padded leading dimension of G_J
+  std::vector<long long> goff;  // element offset of G_J
+  c64 *G = nullptr;           // inverses of the Schur blocks S_J (symmetric), row-major
+  c64 *st9 = nullptr;         // per coarse vertex the 9 stencil couplings [dy+1][dx+1]
+  long long bytes = 0;
+};
+
+}  // namespace th
+
+struct th_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  bool fine_ready = false, coarse_ready = false;
+  th_fine_desc desc{};
+  int dim = 2, N = 0, P = 0, R = 0, n1 = 0, nc1 = 0;
+  long long nf = 0, nc = 0;
+  double h = 0;
+  th::Ref1D ref{};
+
+  // per-cell data
+  th::c64 *d_kap = nullptr;    // k^2 + i eps
+  th::c64 *d_kaps = nullptr;   // k^2 (1 + i alpha_s) + i eps
+  double *d_k = nullptr;       // k
+  std::vector<double> h_k, h_eps;
+
+  // subdomains
+  int M = 0;                   // blocks per direction
+  std::vector<int> blk_start;  // M+1 cell starts
+  std::vector<th::Sub> subs;
+  th::Sub *d_subs = nullptr;
+  int *d_nblk = nullptr;       // per node index along an axis: first block, count (2 ints)
+  void *d_B = nullptr;         // operator store (layout depends on gemm)
+  long long b_entries = 0, b_bytes = 0, y_rows = 0;
+  int max_ldb = 0, max_nom = 0, max_rowblocks = 0;
+
+  // workspaces (fine vectors of max_rhs, both precisions as needed)
+  void *w_r = nullptr;         // residual
+  void *w_v = nullptr;         // DD update accumulator (n_dd > 1)
+  void *w_rr = nullptr;        // shifted residual (n_dd > 1)
+  void *w_y = nullptr;         // Y scratch [rhs][y_rows]
+  void *w_rc = nullptr;        // coarse rhs (FP64)
+  void *w_uc = nullptr;        // coarse solution (FP64)
+  void *w_t = nullptr;         // coarse sweep temporaries
+  void *w_rc32 = nullptr;      // coarse rhs in working precision
+  size_t ws_bytes = 0;
+
+  th::CoarseData coarse;
+
+  // solver workspaces (allocated lazily by th_solve)
+  void *s_buf = nullptr;
+  size_t s_bytes = 0;
+
+  double t_setup_fine = 0, t_setup_coarse = 0;
+
+  // kernel timing (measurement only)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;                  // reusable events
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_marks;  // class, (start, stop)
+};
+
+namespace th {
+// Records events around a launch sequence of one kernel class while timing is on.
+struct KTimer {
+  th_ctx *c;
+  int cls;
+  size_t start = (size_t)-1;
+  KTimer(th_ctx *ctx, int k);
+  ~KTimer();
+};
+}  // namespace th
+
+namespace th {
+
+// thread-local error text written by internal functions
+void set_error(const std::string &msg);
+const std::string &get_error();
+
+// ref1d.cpp
+void make_ref1d(int p, Ref1D &ref);
+void gll_points(int p, std::vector<double> &x, std::vector<double> &w);
+
+// k_operator.hip: out = f + sgn * (A u)   (f may be null)
+int launch_apply(const FineOp &op, const Ref1D &ref, const void *u, const void *f, void *out,
+                 int nrhs, bool f32, double sgn, hipStream_t s);
+
+// k_transfer.hip
+int launch_restrict(int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs, bool f32,
+                    hipStream_t s);
+int launch_prolong(int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
+                   int nrhs, bool f32, hipStream_t s);
+
+// k_smoother.hip
+int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);
+int launch_dd_accumulate(const th_ctx *c, const void *y, void *u, int nrhs, bool f32, bool assign,
+                         hipStream_t s);
+
+// k_dense.hip (setup)
+int setup_subdomain_operators(th_ctx *c);
+
+// k_coarse.hip
+int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);
+int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s);
+int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStream_t s,
+                      c64 *pbuf);
+
+// k_blas.hip
+int launch_convert(const void *in, void *out, long long n, bool in_f32, bool out_f32, hipStream_t s);
+int launch_dot(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx, long long ldy,
+               c64 *out, c64 *partial, hipStream_t s);
+int launch_axpy_dev(c64 *y, const c64 *x, const c64 *coef, double sign, long long n, int nrhs,
+                    long long ldy, long long ldx, hipStream_t s);
+int launch_scale_dev(c64 *y, const c64 *x, const double *inv_norm, long long n, int nrhs,
+                     long long ldy, long long ldx, hipStream_t s);
+int launch_lincomb(c64 *x, const c64 *Z, const c64 *coef, int mcount, int cstride, long long n,
+                   int nrhs, long long ldz_j, long long ldz_r, hipStream_t s);
+int launch_add(void *u, const void *v, long long n_complex, bool f32, hipStream_t s);
+int launch_nan_check(const c64 *x, long long n, int *flag, hipStream_t s);
+
+}  // namespace th

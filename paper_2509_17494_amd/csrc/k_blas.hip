@@ -1,0 +1,192 @@
+// Vector kernels of the outer FP64 Krylov method and precision conversions.
+// Reductions are two-pass with a fixed tree, so every result is bitwise
+// reproducible (no atomics).
+#include "ctx.hpp"
+
+namespace th {
+
+constexpr int RED_BLOCKS = 256;
+
+__device__ __forceinline__ void block_reduce(c64 *sh, c64 v) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
+    __syncthreads();
+  }
+}
+
+// partial[rhs][block] = sum over the block's slice of conj(x) y
+__global__ __launch_bounds__(256) void k_dot_partial(const c64 *__restrict__ x,
+                                                     const c64 *__restrict__ y, long long n,
+                                                     long long ldx, long long ldy,
+                                                     c64 *__restrict__ partial) {
+  __shared__ c64 sh[256];
+  const long long rhs = blockIdx.y;
+  x += rhs * ldx;
+  y += rhs * ldy;
+  c64 acc = {0, 0};
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const c64 a = x[i], b = y[i];
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+  }
+  block_reduce(sh, acc);
+  if (threadIdx.x == 0) partial[rhs * RED_BLOCKS + blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const c64 *__restrict__ partial,
+                                                   c64 *__restrict__ out) {
+  __shared__ c64 sh[256];
+  block_reduce(sh, partial[blockIdx.x * RED_BLOCKS + threadIdx.x]);
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+int launch_dot(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx, long long ldy,
+               c64 *out, c64 *partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS, nrhs), dim3(256), 0, s, x, y, n, ldx, ldy,
+                     partial);
+  hipLaunchKernelGGL(k_dot_final, dim3(nrhs), dim3(RED_BLOCKS), 0, s, (const c64 *)partial, out);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// y[rhs] += sign * coef[rhs] * x[rhs]
+__global__ __launch_bounds__(256) void k_axpy_dev(c64 *__restrict__ y, const c64 *__restrict__ x,
+                                                  const c64 *__restrict__ coef, double sign,
+                                                  long long n, long long ldy, long long ldx) {
+  const long long rhs = blockIdx.y;
+  const c64 a = coef[rhs];
+  const c64 sa = {sign * a.re, sign * a.im};
+  y += rhs * ldy;
+  x += rhs * ldx;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    c64 v = y[i];
+    cmac(v, sa, x[i]);
+    y[i] = v;
+  }
+}
+
+int launch_axpy_dev(c64 *y, const c64 *x, const c64 *coef, double sign, long long n, int nrhs,
+                    long long ldy, long long ldx, hipStream_t s) {
+  int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 4096);
+  hipLaunchKernelGGL(k_axpy_dev, dim3(blocks, nrhs), dim3(256), 0, s, y, x, coef, sign, n, ldy,
+                     ldx);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// y[rhs] = x[rhs] * s[rhs]  (s real, from a device array)
+__global__ __launch_bounds__(256) void k_scale_dev(c64 *__restrict__ y, const c64 *__restrict__ x,
+                                                   const double *__restrict__ sc, long long n,
+                                                   long long ldy, long long ldx) {
+  const long long rhs = blockIdx.y;
+  const double a = sc[rhs];
+  y += rhs * ldy;
+  x += rhs * ldx;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const c64 v = x[i];
+    y[i] = c64{a * v.re, a * v.im};
+  }
+}
+
+int launch_scale_dev(c64 *y, const c64 *x, const double *inv_norm, long long n, int nrhs,
+                     long long ldy, long long ldx, hipStream_t s) {
+  int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 4096);
+  hipLaunchKernelGGL(k_scale_dev, dim3(blocks, nrhs), dim3(256), 0, s, y, x, inv_norm, n, ldy, ldx);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// x[rhs] += sum_j coef[rhs][j] Z[j][rhs]   (Z block j at Z + j*ldz_j + rhs*ldz_r)
+__global__ __launch_bounds__(256) void k_lincomb(c64 *__restrict__ x, const c64 *__restrict__ Z,
+                                                 const c64 *__restrict__ coef, int m, int cstride,
+                                                 long long n, long long ldz_j, long long ldz_r) {
+  const long long rhs = blockIdx.y;
+  x += rhs * n;
+  const c64 *cf = coef + rhs * cstride;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    c64 acc = x[i];
+    for (int j = 0; j < m; ++j) cmac(acc, cf[j], Z[j * ldz_j + rhs * ldz_r + i]);
+    x[i] = acc;
+  }
+}
+
+int launch_lincomb(c64 *x, const c64 *Z, const c64 *coef, int mcount, int cstride, long long n,
+                   int nrhs, long long ldz_j, long long ldz_r, hipStream_t s) {
+  int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 4096);
+  hipLaunchKernelGGL(k_lincomb, dim3(blocks, nrhs), dim3(256), 0, s, x, Z, coef, mcount, cstride,
+                     n, ldz_j, ldz_r);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_convert(const Ti *__restrict__ in, To *__restrict__ out,
+                                                 long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    out[i] = (To)in[i];
+}
+
+int launch_convert(const void *in, void *out, long long n_complex, bool in_f32, bool out_f32,
+                   hipStream_t s) {
+  const long long n = 2 * n_complex;
+  int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 8192);
+  if (in_f32 && !out_f32)
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks), dim3(256), 0, s,
+                       (const float *)in, (double *)out, n);
+  else if (!in_f32 && out_f32)
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks), dim3(256), 0, s,
+                       (const double *)in, (float *)out, n);
+  else if (in_f32)
+    hipLaunchKernelGGL((k_convert<float, float>), dim3(blocks), dim3(256), 0, s,
+                       (const float *)in, (float *)out, n);
+  else
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(blocks), dim3(256), 0, s,
+                       (const double *)in, (double *)out, n);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// u += v (complex, either precision)
+template <typename T>
+__global__ __launch_bounds__(256) void k_add(T *__restrict__ u, const T *__restrict__ v,
+                                             long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    u[i] += v[i];
+}
+
+int launch_add(void *u, const void *v, long long n_complex, bool f32, hipStream_t s) {
+  const long long n = 2 * n_complex;
+  int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 8192);
+  if (f32)
+    hipLaunchKernelGGL((k_add<float>), dim3(blocks), dim3(256), 0, s, (float *)u,
+                       (const float *)v, n);
+  else
+    hipLaunchKernelGGL((k_add<double>), dim3(blocks), dim3(256), 0, s, (double *)u,
+                       (const double *)v, n);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// flag = 1 if any entry is not finite
+__global__ __launch_bounds__(256) void k_nan_check(const c64 *__restrict__ x, long long n,
+                                                   int *flag) {
+  bool bad = false;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const c64 v = x[i];
+    bad |= !isfinite(v.re) || !isfinite(v.im);
+  }
+  if (bad) flag[0] = 1;
+}
+
+int launch_nan_check(const c64 *x, long long n, int *flag, hipStream_t s) {
+  int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 1024);
+  hipLaunchKernelGGL(k_nan_check, dim3(blocks), dim3(256), 0, s, x, n, flag);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+}  // namespace th

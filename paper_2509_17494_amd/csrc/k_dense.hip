@@ -1,0 +1,337 @@
+// Setup of the smoother's subdomain operators on the device (FP64).
+//
+// For every subdomain (Sec. 4.1): assemble the dense Galerkin matrix
+// A_s^(i) of a(u, v; Omega^(i), Gamma) with the shifted coefficient
+// k^2 (1 + i alpha_s) + i eps and the absorbing term -i k on the sides of
+// Omega^(i) that are internal or inherit an absorbing boundary; invert it by
+// blocked Gauss-Jordan elimination; store B_i = diag(1/L_j) R_{U_i} A^{-1}
+// transposed (column-major, ld = n_U rounded up to 64) in the working
+// precision.
+//
+// Gauss-Jordan runs without pivoting.  A_s^(i) = H - i S with S = alpha_s k^2 M
+// + k M_Gamma (plus eps M) symmetric positive definite, so i A_s^(i) has a
+// positive definite Hermitian part; that property passes to every leading
+// block and every Schur complement, so all pivots are nonzero.  The blocked
+// in-place sweep over 32-wide block columns k is
+//   P = A_kk^{-1};  A_kj <- P A_kj (j != k);  A_ij <- A_ij - A_ik A_kj;
+//   A_ik <- -A_ik P (i != k);  A_kk <- P,
+// and after the last block A holds A^{-1}.  Matrices are padded with an
+// identity block to a multiple of 32, which leaves the inverse unchanged on
+// the leading block.
+#include <algorithm>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace th {
+
+constexpr int GJ_BS = 32;   // block width of the elimination
+constexpr int GJ_T = 64;    // tile edge of the panel / update kernels
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan kernels.  Matrix b of the batch starts at A + b * stride and is
+// row-major with leading dimension ld; n is a multiple of GJ_BS.
+
+__global__ __launch_bounds__(256) void k_gj_diag(c64 *A, int ld, long long stride, int kb,
+                                                 c64 *pbuf, int *flag) {
+  __shared__ c64 a[GJ_BS][GJ_BS + 1];
+  c64 *Ab = A + blockIdx.x * stride + (long long)kb * GJ_BS * ld + kb * GJ_BS;
+  for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) {
+    int i = t / GJ_BS, j = t % GJ_BS;
+    a[i][j] = Ab[(long long)i * ld + j];
+  }
+  __syncthreads();
+  for (int kk = 0; kk < GJ_BS; ++kk) {
+    const c64 d = a[kk][kk];
+    const double den = d.re * d.re + d.im * d.im;
+    if (!(den > 0.0) || !isfinite(den)) {
+      if (threadIdx.x == 0) flag[0] = 1;
+    }
+    const c64 piv = {d.re / den, -d.im / den};
+    __syncthreads();
+    // scale pivot row
+    for (int j = threadIdx.x; j < GJ_BS; j += blockDim.x)
+      if (j != kk) a[kk][j] = piv * a[kk][j];
+    __syncthreads();
+    // eliminate other rows (pivot column still holds the old values)
+    for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) {
+      int i = t / GJ_BS, j = t % GJ_BS;
+      if (i != kk && j != kk) a[i][j] = a[i][j] - a[i][kk] * a[kk][j];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < GJ_BS; i += blockDim.x)
+      if (i != kk) a[i][kk] = cx<double>{0, 0} - a[i][kk] * piv;
+    if (threadIdx.x == 0) a[kk][kk] = piv;
+    __syncthreads();
+  }
+  c64 *pb = pbuf + (long long)blockIdx.x * GJ_BS * GJ_BS;
+  for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) {
+    int i = t / GJ_BS, j = t % GJ_BS;
+    Ab[(long long)i * ld + j] = a[i][j];
+    pb[t] = a[i][j];
+  }
+}
+
+// A_kj <- P A_kj for the 64-column tile blockIdx.x (columns of block k skipped)
+__global__ __launch_bounds__(256) void k_gj_rowpanel(c64 *A, int ld, long long stride, int n, int kb,
+                                                     const c64 *pbuf) {
+  __shared__ c64 Ps[GJ_BS][GJ_BS + 1];
+  __shared__ c64 Ts[GJ_BS][GJ_T + 1];
+  const int j0 = blockIdx.x * GJ_T;
+  c64 *Ab = A + blockIdx.y * stride + (long long)kb * GJ_BS * ld;
+  const c64 *pb = pbuf + (long long)blockIdx.y * GJ_BS * GJ_BS;
+  for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) Ps[t / GJ_BS][t % GJ_BS] = pb[t];
+  for (int t = threadIdx.x; t < GJ_BS * GJ_T; t += blockDim.x) {
+    int i = t / GJ_T, j = t % GJ_T;
+    Ts[i][j] = (j0 + j < n) ? Ab[(long long)i * ld + j0 + j] : c64{0, 0};
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < GJ_BS * GJ_T; t += blockDim.x) {
+    int i = t / GJ_T, j = t % GJ_T;
+    int col = j0 + j;
+    if (col >= n || (col / GJ_BS) == kb) continue;
+    c64 acc = {0, 0};
+#pragma unroll 8
+    for (int q = 0; q < GJ_BS; ++q) cmac(acc, Ps[i][q], Ts[q][j]);
+    Ab[(long long)i * ld + col] = acc;
+  }
+}
+
+// A_ik <- -A_ik P for the 64-row tile blockIdx.x (rows of block k skipped)
+__global__ __launch_bounds__(256) void k_gj_colpanel(c64 *A, int ld, long long stride, int n, int kb,
+                                                     const c64 *pbuf) {
+  __shared__ c64 Ps[GJ_BS][GJ_BS + 1];
+  __shared__ c64 Ts[GJ_T][GJ_BS + 1];
+  const int i0 = blockIdx.x * GJ_T;
+  c64 *Ab = A + blockIdx.y * stride + kb * GJ_BS;
+  const c64 *pb = pbuf + (long long)blockIdx.y * GJ_BS * GJ_BS;
+  for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) Ps[t / GJ_BS][t % GJ_BS] = pb[t];
+  for (int t = threadIdx.x; t < GJ_T * GJ_BS; t += blockDim.x) {
+    int i = t / GJ_BS, j = t % GJ_BS;
+    Ts[i][j] = (i0 + i < n) ? Ab[(long long)(i0 + i) * ld + j] : c64{0, 0};
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < GJ_T * GJ_BS; t += blockDim.x) {
+    int i = t / GJ_BS, j = t % GJ_BS;
+    int row = i0 + i;
+    if (row >= n || (row / GJ_BS) == kb) continue;
+    c64 acc = {0, 0};
+#pragma unroll 8
+    for (int q = 0; q < GJ_BS; ++q) cmac(acc, Ts[i][q], Ps[q][j]);
+    Ab[(long long)row * ld + j] = c64{-acc.re, -acc.im};
+  }
+}
+
+// A_ij <- A_ij - A_ik A_kj on the 64x64 tile (blockIdx.x, blockIdx.y), entries
+// in block row k or block column k left untouched.
+__global__ __launch_bounds__(256) void k_gj_update(c64 *A, int ld, long long stride, int n, int kb) {
+  __shared__ c64 As[GJ_T][GJ_BS + 1];
+  __shared__ c64 Bs[GJ_BS][GJ_T + 1];
+  const int j0 = blockIdx.x * GJ_T, i0 = blockIdx.y * GJ_T;
+  c64 *Ab = A + blockIdx.z * stride;
+  const int k0 = kb * GJ_BS;
+  for (int t = threadIdx.x; t < GJ_T * GJ_BS; t += blockDim.x) {
+    int i = t / GJ_BS, q = t % GJ_BS;
+    As[i][q] = (i0 + i < n) ? Ab[(long long)(i0 + i) * ld + k0 + q] : c64{0, 0};
+  }
+  for (int t = threadIdx.x; t < GJ_BS * GJ_T; t += blockDim.x) {
+    int q = t / GJ_T, j = t % GJ_T;
+    Bs[q][j] = (j0 + j < n) ? Ab[(long long)(k0 + q) * ld + j0 + j] : c64{0, 0};
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  c64 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = {0, 0};
+#pragma unroll 4
+  for (int q = 0; q < GJ_BS; ++q) {
+    c64 av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = As[ty + 16 * a][q];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = Bs[q][tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cmac(acc[a][b], av[a], bv[b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = i0 + ty + 16 * a;
+    if (row >= n || (row / GJ_BS) == kb) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = j0 + tx + 16 * b;
+      if (col >= n || (col / GJ_BS) == kb) continue;
+      c64 *p = Ab + (long long)row * ld + col;
+      *p = *p - acc[a][b];
+    }
+  }
+}
+
+int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStream_t s,
+                      c64 *pbuf_flag_ws) {
+  // pbuf_flag_ws: batch * 32 * 32 complex for the inverted diagonal blocks,
+  // followed by one int flag (zeroed by the caller)
+  if (n % GJ_BS) {
+    set_error("gauss-jordan size must be a multiple of 32");
+    return TH_EINVAL;
+  }
+  c64 *pbuf = pbuf_flag_ws;
+  int *flag = (int *)(pbuf + (long long)batch * GJ_BS * GJ_BS);
+  const int nbk = n / GJ_BS;
+  const int nt = ceil_div(n, GJ_T);
+  for (int kb = 0; kb < nbk; ++kb) {
+    hipLaunchKernelGGL(k_gj_diag, dim3(batch), dim3(256), 0, s, A, ld, stride, kb, pbuf, flag);
+    hipLaunchKernelGGL(k_gj_rowpanel, dim3(nt, batch), dim3(256), 0, s, A, ld, stride, n, kb,
+                       (const c64 *)pbuf);
+    hipLaunchKernelGGL(k_gj_update, dim3(nt, nt, batch), dim3(256), 0, s, A, ld, stride, n, kb);
+    hipLaunchKernelGGL(k_gj_colpanel, dim3(nt, batch), dim3(256), 0, s, A, ld, stride, n, kb,
+                       (const c64 *)pbuf);
+    TH_HIP_CHECK_RET(hipGetLastError());
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Dense subdomain assembly: one thread per row (local Omega node); every
+// thread writes only its own row, summing its cells in a fixed order.
+
+template <int P>
+__global__ __launch_bounds__(256) void k_assemble_sub(const Sub *__restrict__ subs, int s0,
+                                                      c64 *A, int ld, long long stride,
+                                                      const c64 *__restrict__ kaps,
+                                                      const double *__restrict__ kr, Ref1D ref,
+                                                      double h, int N) {
+  constexpr int NP = P + 1;
+  const Sub s = subs[s0 + blockIdx.y];
+  c64 *Ab = A + blockIdx.y * stride;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= ld) return;
+  c64 *row = Ab + (long long)a * ld;
+  if (a >= s.nOm) {
+    row[a] = c64{1.0, 0.0};
+    return;
+  }
+  const int ncx = s.o1x - s.o0x, ncy = s.o1y - s.o0y;
+  const int ax = a % s.nox, ay = a / s.nox;
+  const int chx = min(ax / P, ncx - 1), chy = min(ay / P, ncy - 1);
+  const int nxc = (ax % P == 0 && ax > 0 && ax < ncx * P) ? 2 : 1;
+  const int nyc = (ay % P == 0 && ay > 0 && ay < ncy * P) ? 2 : 1;
+  const double h2 = h * h;
+  for (int qy = nyc - 1; qy >= 0; --qy) {
+    const int lcy = chy - qy, ly = ay - lcy * P;
+    for (int qx = nxc - 1; qx >= 0; --qx) {
+      const int lcx = chx - qx, lx = ax - lcx * P;
+      const long long gc = (long long)(s.o0y + lcy) * N + (s.o0x + lcx);
+      const c64 kap = kaps[gc];
+      const double kk = kr[gc];
+      const bool rxl = (s.robin & 1) && lcx == 0 && lx == 0;
+      const bool rxh = (s.robin & 2) && lcx == ncx - 1 && lx == P;
+      const bool ryl = (s.robin & 4) && lcy == 0 && ly == 0;
+      const bool ryh = (s.robin & 8) && lcy == ncy - 1 && ly == P;
+      for (int by = 0; by < NP; ++by) {
+        const double Ky = ref.K[ly * NP + by], My = ref.M[ly * NP + by];
+        for (int bx = 0; bx < NP; ++bx) {
+          const double Kx = ref.K[lx * NP + bx], Mx = ref.M[lx * NP + bx];
+          const double mm = h2 * My * Mx;
+          c64 v = {Ky * Mx + My * Kx - kap.re * mm, -kap.im * mm};
+          if ((rxl && bx == 0) || (rxh && bx == P)) v.im -= kk * h * My;
+          if ((ryl && by == 0) || (ryh && by == P)) v.im -= kk * h * Mx;
+          const int col = (lcy * P + by) * s.nox + lcx * P + bx;
+          row[col] = row[col] + v;
+        }
+      }
+    }
+  }
+}
+
+// B_i^T[k][j] = (A^{-1})[u_j][k] / L_{u_j} in the storage precision.
+template <typename TB>
+__global__ __launch_bounds__(256) void k_extract_b(const Sub *__restrict__ subs, int s0,
+                                                   const c64 *__restrict__ A, int ld,
+                                                   long long stride, const int *__restrict__ nblk,
+                                                   cx<TB> *__restrict__ B, int P) {
+  const Sub s = subs[s0 + blockIdx.z];
+  const c64 *Ab = A + blockIdx.z * stride;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s.nU) return;
+  const int jx = j % s.nux, jy = j / s.nux;
+  const int gx = s.u0x * P + jx, gy = s.u0y * P + jy;
+  const double invL = 1.0 / (double)(nblk[2 * gx + 1] * nblk[2 * gy + 1]);
+  const int ox = (s.u0x - s.o0x) * P + jx, oy = (s.u0y - s.o0y) * P + jy;
+  const int uj = oy * s.nox + ox;
+  const c64 *arow = Ab + (long long)uj * ld;
+  for (int k = blockIdx.y; k < s.nOm; k += gridDim.y) {
+    const c64 v = arow[k];
+    B[s.boff + (long long)k * s.ldb + j] = cx<TB>{(TB)(v.re * invL), (TB)(v.im * invL)};
+  }
+}
+
+int setup_subdomain_operators(th_ctx *c) {
+  hipStream_t s = c->stream;
+  const int nsub = (int)c->subs.size();
+  const int npad = ceil_div(c->max_nom, GJ_BS) * GJ_BS;
+  const long long mat = (long long)npad * npad;
+  // batch: bounded by ~8 GiB of work space and by free memory
+  size_t free_b = 0, total_b = 0;
+  TH_HIP_CHECK_RET(hipMemGetInfo(&free_b, &total_b));
+  long long budget = std::min<long long>(8LL << 30, (long long)(free_b / 3));
+  int batch = (int)std::max<long long>(1, std::min<long long>(nsub, budget / (mat * 16)));
+  c64 *work = nullptr, *pws = nullptr;
+  if (hipMalloc(&work, (size_t)batch * mat * sizeof(c64)) != hipSuccess) {
+    set_error("cannot allocate the subdomain work space");
+    return TH_ENOMEM;
+  }
+  size_t pws_bytes = (size_t)batch * GJ_BS * GJ_BS * sizeof(c64) + 64;
+  if (hipMalloc(&pws, pws_bytes) != hipSuccess) {
+    (void)hipFree(work);
+    set_error("cannot allocate the pivot work space");
+    return TH_ENOMEM;
+  }
+  int *flag = (int *)(pws + (long long)batch * GJ_BS * GJ_BS);
+  int rc = 0;
+  TH_HIP_CHECK_RET(hipMemsetAsync(flag, 0, sizeof(int), s));
+  for (int s0 = 0; s0 < nsub && rc == 0; s0 += batch) {
+    const int nb = std::min(batch, nsub - s0);
+    TH_HIP_CHECK_RET(hipMemsetAsync(work, 0, (size_t)nb * mat * sizeof(c64), s));
+    dim3 ga(ceil_div(npad, 256), nb);
+    switch (c->P) {
+#define TH_ASM(PP)                                                                              \
+  case PP:                                                                                      \
+    hipLaunchKernelGGL((k_assemble_sub<PP>), ga, dim3(256), 0, s, c->d_subs, s0, work, npad,    \
+                       mat, (const c64 *)c->d_kaps, (const double *)c->d_k, c->ref, c->h, c->N); \
+    break;
+      TH_ASM(2) TH_ASM(4) TH_ASM(6) TH_ASM(8)
+#undef TH_ASM
+    }
+    TH_HIP_CHECK_RET(hipGetLastError());
+    rc = gj_invert_batched(work, npad, npad, mat, nb, s, pws);
+    if (rc) break;
+    dim3 ge(ceil_div(c->max_ldb, 256), 64, nb);
+    if (c->desc.gemm == TH_GEMM_F32)
+      hipLaunchKernelGGL((k_extract_b<float>), ge, dim3(256), 0, s, c->d_subs, s0,
+                         (const c64 *)work, npad, mat, c->d_nblk, (cx<float> *)c->d_B, c->P);
+    else
+      hipLaunchKernelGGL((k_extract_b<double>), ge, dim3(256), 0, s, c->d_subs, s0,
+                         (const c64 *)work, npad, mat, c->d_nblk, (cx<double> *)c->d_B, c->P);
+    TH_HIP_CHECK_RET(hipGetLastError());
+  }
+  int hflag = 0;
+  if (rc == 0) {
+    TH_HIP_CHECK_RET(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    TH_HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
+  (void)hipFree(work);
+  (void)hipFree(pws);
+  if (rc) return rc;
+  if (hflag) {
+    set_error("zero or non-finite pivot in a subdomain inverse");
+    return TH_ENUMERIC;
+  }
+  return 0;
+}
+
+}  // namespace th

@@ -1,0 +1,148 @@
+// Inter-grid transfers (Sec. 4.2): prolongation I_P = Q_{p/2} interpolation
+// from the coarse vertex grid (spacing 2h/p) to the fine GLL nodes, and the
+// restriction I_P^T of Alg. 1.
+//
+// On each fine cell the interpolant is a tensor product of 1-D degree-p/2
+// Lagrange interpolants through the r+1 = p/2+1 coarse points of the cell, so
+// the global operator is P1 (x) P1 with P1 the (pN+1) x (rN+1) 1-D matrix
+// P1[i][J] = L[a][b], (c, a) = cell and local index of fine node i, b = J - c r
+// (cell-edge nodes get the same value from either cell: they coincide with
+// coarse points).  Both kernels are gathers (no atomics): prolongation per
+// fine node over the (r+1)^2 coarse points of its cell, restriction per
+// coarse point over the fine nodes of the cells around it, every fine node
+// counted once.
+#include "ctx.hpp"
+
+namespace th {
+
+template <int P>
+__device__ __forceinline__ double p1w(const double *L, int N, int i, int J) {
+  constexpr int R = P / 2;
+  const int c = min(i / P, N - 1);
+  const int a = i - c * P, b = J - c * R;
+  return (b >= 0 && b <= R) ? L[a * (R + 1) + b] : 0.0;
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_prolong2d(int N, Ref1D ref, const cx<T> *__restrict__ uc,
+                                                   cx<T> *__restrict__ u, T omega, long long nf,
+                                                   long long ncn) {
+  constexpr int R = P / 2;
+  const int n1 = N * P + 1, nc1 = N * R + 1;
+  const long long rhs = blockIdx.y;
+  uc += rhs * ncn;
+  u += rhs * nf;
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < nf;
+       g += (long long)gridDim.x * blockDim.x) {
+    const int iy = (int)(g / n1), ix = (int)(g - (long long)iy * n1);
+    const int cxq = min(ix / P, N - 1), cyq = min(iy / P, N - 1);
+    const int ax = ix - cxq * P, ay = iy - cyq * P;
+    cx<T> acc = {0, 0};
+#pragma unroll
+    for (int by = 0; by <= R; ++by) {
+      const T wy = (T)ref.L[ay * (R + 1) + by];
+      if (wy == (T)0) continue;
+      cx<T> row = {0, 0};
+#pragma unroll
+      for (int bx = 0; bx <= R; ++bx) {
+        const T wx = (T)ref.L[ax * (R + 1) + bx];
+        if (wx == (T)0) continue;
+        rmac(row, wx, uc[(long long)(cyq * R + by) * nc1 + cxq * R + bx]);
+      }
+      rmac(acc, wy, row);
+    }
+    cx<T> o = u[g];
+    o.re = fma(omega, acc.re, o.re);
+    o.im = fma(omega, acc.im, o.im);
+    u[g] = o;
+  }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_restrict2d(int N, Ref1D ref, const cx<T> *__restrict__ r,
+                                                    cx<T> *__restrict__ rc, long long nf,
+                                                    long long ncn) {
+  constexpr int R = P / 2;
+  const int n1 = N * P + 1, nc1 = N * R + 1;
+  const long long rhs = blockIdx.y;
+  r += rhs * nf;
+  rc += rhs * ncn;
+  for (long long G = blockIdx.x * (long long)blockDim.x + threadIdx.x; G < ncn;
+       G += (long long)gridDim.x * blockDim.x) {
+    const int Jy = (int)(G / nc1), Jx = (int)(G - (long long)Jy * nc1);
+    // cells whose coarse points include J: c R <= J <= c R + R
+    const int clx = max((Jx % R == 0) ? Jx / R - 1 : Jx / R, 0), chx = min(Jx / R, N - 1);
+    const int cly = max((Jy % R == 0) ? Jy / R - 1 : Jy / R, 0), chy = min(Jy / R, N - 1);
+    const int ixs = clx * P, ixe = (chx + 1) * P;  // inclusive range of fine nodes
+    const int iys = cly * P, iye = (chy + 1) * P;
+    cx<T> acc = {0, 0};
+    for (int iy = iys; iy <= iye; ++iy) {
+      const T wy = (T)p1w<P>(ref.L, N, iy, Jy);
+      if (wy == (T)0) continue;
+      cx<T> row = {0, 0};
+      const cx<T> *rr = r + (long long)iy * n1;
+      for (int ix = ixs; ix <= ixe; ++ix) {
+        const T wx = (T)p1w<P>(ref.L, N, ix, Jx);
+        if (wx == (T)0) continue;
+        rmac(row, wx, rr[ix]);
+      }
+      rmac(acc, wy, row);
+    }
+    rc[G] = acc;
+  }
+}
+
+template <int P, typename T>
+static int prolong_t(int N, const Ref1D &ref, const void *uc, void *u, double omega, int nrhs,
+                     hipStream_t s) {
+  const long long nf = (long long)(N * P + 1) * (N * P + 1);
+  const long long ncn = (long long)(N * (P / 2) + 1) * (N * (P / 2) + 1);
+  int blocks = (int)std::min<long long>(ceil_div_ll(nf, 256), 65535);
+  hipLaunchKernelGGL((k_prolong2d<P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
+                     (const cx<T> *)uc, (cx<T> *)u, (T)omega, nf, ncn);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+template <int P, typename T>
+static int restrict_t(int N, const Ref1D &ref, const void *r, void *rc, int nrhs, hipStream_t s) {
+  const long long nf = (long long)(N * P + 1) * (N * P + 1);
+  const long long ncn = (long long)(N * (P / 2) + 1) * (N * (P / 2) + 1);
+  int blocks = (int)std::min<long long>(ceil_div_ll(ncn, 256), 65535);
+  hipLaunchKernelGGL((k_restrict2d<P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
+                     (const cx<T> *)r, (cx<T> *)rc, nf, ncn);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+#define TH_DISPATCH_P(P_, F32_, CALL_F, CALL_D)   \
+  switch (P_) {                                   \
+    case 2: return F32_ ? CALL_F(2) : CALL_D(2);  \
+    case 4: return F32_ ? CALL_F(4) : CALL_D(4);  \
+    case 6: return F32_ ? CALL_F(6) : CALL_D(6);  \
+    case 8: return F32_ ? CALL_F(8) : CALL_D(8);  \
+  }
+
+int launch_prolong(int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
+                   int nrhs, bool f32, hipStream_t s) {
+#define CF(p) prolong_t<p, float>(N, ref, uc, u, omega, nrhs, s)
+#define CD(p) prolong_t<p, double>(N, ref, uc, u, omega, nrhs, s)
+  TH_DISPATCH_P(P, f32, CF, CD)
+#undef CF
+#undef CD
+  set_error("unsupported order");
+  return TH_EUNSUPPORTED;
+}
+
+int launch_restrict(int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs, bool f32,
+                    hipStream_t s) {
+#define CF(p) restrict_t<p, float>(N, ref, r, rc, nrhs, s)
+#define CD(p) restrict_t<p, double>(N, ref, r, rc, nrhs, s)
+  TH_DISPATCH_P(P, f32, CF, CD)
+#undef CF
+#undef CD
+  set_error("unsupported order");
+  return TH_EUNSUPPORTED;
+}
+
+}  // namespace th

@@ -1,0 +1,162 @@
+"""GPU parity: every C-ABI step against the FP64 CPU oracle on the same seeded
+inputs.  FP64 steps must agree to a relative L2 error of 1e-12 (single
+operator applications; the bound leaves room for summation-order and
+explicit-inverse-versus-LU rounding, ~cond * 1e-16) and the full two-grid GMRES
+solve to 1e-10 after the same iteration count.  Complex64 steps are checked
+to 1e-5 (about 100 ulp of FP32)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synthetic as syn
+from oracle.fem import helmholtz_matrix
+from oracle.qsfem import coarse_cell_values, coarse_matrix
+from oracle.smoother import CSDDSmoother
+from oracle.transfer import prolongation
+from oracle.twogrid import TwoGrid
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def to_dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda")
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def hetero_k(N, p, seed, ppw=8.0):
+    c = syn.grf_speed(N, 2, 0.2, 1.5, 4.0, seed=seed)
+    return syn.wavenumber_from_speed(c, p * N / ppw)
+
+
+CASES = [  # (N, p, l_dd): several tiles of the operator kernel and ragged tails
+    (37, 2, 8),
+    (19, 4, 6),
+    (7, 6, 3),
+    (5, 8, 2),
+]
+
+
+def make_solver(k, p, l_dd, **kw):
+    from paper_2509_17494_amd import TwoGridSolver
+    return TwoGridSolver(k, order=p, l_dd=l_dd, **kw)
+
+
+@pytest.mark.parametrize("N,p,l_dd", CASES)
+def test_residual(N, p, l_dd):
+    print(f"case residual N={N} p={p}", flush=True)
+    k = hetero_k(N, p, seed=N)
+    A = helmholtz_matrix(p, k)
+    s = make_solver(k, p, l_dd, max_rhs=2, coarse=None)
+    n = A.shape[0]
+    u = syn.random_complex((2, n), seed=1)
+    f = syn.random_complex((2, n), seed=2)
+    ref = np.stack([f[i] - A @ u[i] for i in range(2)])
+    r = s.residual(to_dev(u), to_dev(f))
+    assert rel(to_np(r), ref) < 1e-12
+    r32 = s.residual(to_dev(u, torch.complex64), to_dev(f, torch.complex64))
+    assert rel(to_np(r32), ref) < 1e-5
+
+
+@pytest.mark.parametrize("N,p,l_dd", CASES)
+def test_transfers(N, p, l_dd):
+    print(f"case transfers N={N} p={p}", flush=True)
+    k = hetero_k(N, p, seed=3)
+    s = make_solver(k, p, l_dd, max_rhs=2, coarse=None)
+    IP = prolongation(N, p)
+    r = syn.random_complex((2, IP.shape[0]), seed=4)
+    uc = syn.random_complex((2, IP.shape[1]), seed=5)
+    u0 = syn.random_complex((2, IP.shape[0]), seed=6)
+    rc = s.restrict(to_dev(r))
+    assert rel(to_np(rc), np.stack([IP.T @ x for x in r])) < 1e-13
+    u = to_dev(u0)
+    s.prolong(to_dev(uc), u, omega=0.7)
+    assert rel(to_np(u), np.stack([u0[i] + 0.7 * (IP @ uc[i]) for i in range(2)])) < 1e-13
+
+
+@pytest.mark.parametrize("N,p,l_dd", CASES)
+def test_smooth(N, p, l_dd):
+    print(f"case smooth N={N} p={p} l_dd={l_dd}", flush=True)
+    k = hetero_k(N, p, seed=7)
+    sm = CSDDSmoother(p, k, None, 0.5, l_dd)
+    s = make_solver(k, p, l_dd, max_rhs=2, coarse=None)
+    n = sm.n_nodes
+    u0 = syn.random_complex((2, n), seed=8)
+    f = syn.random_complex((2, n), seed=9)
+    ref = np.stack([sm.apply(u0[i], f[i]) for i in range(2)])
+    u = to_dev(u0)
+    s.smooth(u, to_dev(f))
+    assert rel(to_np(u), ref) < 1e-12
+
+
+def test_smooth_ndd2_neumann():
+    N, p, l_dd = 18, 2, 5
+    k = hetero_k(N, p, seed=10)
+    robin = (True, False, True, False)
+    sm = CSDDSmoother(p, k, None, 0.3, l_dd, robin=robin, n_dd=2)
+    s = make_solver(k, p, l_dd, alpha_s=0.3, n_dd=2, max_rhs=1, coarse=None,
+                    bc=("robin", "neumann", "robin", "neumann"))
+    u0 = syn.random_complex(sm.n_nodes, seed=11)
+    f = syn.random_complex(sm.n_nodes, seed=12)
+    ref = sm.apply(u0, f)
+    u = to_dev(u0[None])
+    s.smooth(u, to_dev(f[None]))
+    assert rel(to_np(u)[0], ref) < 1e-12
+
+
+@pytest.mark.parametrize("N,p,l_dd", CASES)
+def test_coarse_solve(N, p, l_dd):
+    print(f"case coarse N={N} p={p}", flush=True)
+    k = hetero_k(N, p, seed=13)
+    Ac = coarse_matrix(coarse_cell_values(k, p))
+    s = make_solver(k, p, l_dd, max_rhs=2)
+    rc = syn.random_complex((2, Ac.shape[0]), seed=14)
+    lu = spla.splu(Ac.tocsc())
+    ref = np.stack([lu.solve(x) for x in rc])
+    uc = s.coarse_solve(to_dev(rc))
+    assert rel(to_np(uc), ref) < 1e-11
+
+
+@pytest.mark.parametrize("N,p,l_dd", CASES)
+def test_twogrid_step(N, p, l_dd):
+    print(f"case twogrid N={N} p={p}", flush=True)
+    k = hetero_k(N, p, seed=15)
+    tg = TwoGrid(p, k, alpha_s=0.5, l_dd=l_dd)
+    s = make_solver(k, p, l_dd, max_rhs=1)
+    n = tg.A.shape[0]
+    u0 = syn.random_complex(n, seed=16)
+    f = syn.random_complex(n, seed=17)
+    ref = tg.twogrid_step(u0, f)
+    u = to_dev(u0[None])
+    s.twogrid(u, to_dev(f[None]))
+    assert rel(to_np(u)[0], ref) < 1e-11
+
+
+def test_solve_c1_fp64():
+    """Full C1 workload: same GMRES iteration count, solutions within 1e-10."""
+    cfg = syn.config("C1")
+    p, N = cfg["p"], cfg["n"]
+    f = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"])
+    tg = TwoGrid(p, cfg["k"], alpha_s=cfg["alpha_s"], l_dd=cfg["l_dd"])
+    x_ref, it_ref, _ = tg.gmres(f[0], 1e-6)
+    s = make_solver(cfg["k"], p, cfg["l_dd"], alpha_s=cfg["alpha_s"], max_rhs=1)
+    u, st = s.solve(to_dev(f))
+    print(f"C1 oracle iters {it_ref}, gpu iters {st.iters}, rel_res {st.rel_res:.3e}", flush=True)
+    assert st.status == 0
+    assert st.iters == it_ref
+    assert rel(to_np(u)[0], x_ref) < 1e-10
+    assert st.rel_res <= 1e-6
