@@ -113,6 +113,9 @@ typedef struct {
   long long b_bytes;      /* device bytes of the stored subdomain operators */
   long long coarse_bytes; /* device bytes of the coarse factors */
   double t_setup_fine_s, t_setup_coarse_s;
+  int smoother_cfg;       /* matrix-core smoother configuration chosen by the autotuner */
+  int smoother_grid;      /* its persistent grid size (0: one workgroup per work item) */
+  int coarse_lines;       /* grid lines per coarse super-block */
 } th_info;
 
 /* Create a context on HIP device `hip_device`, ordering work on `hip_stream`

@@ -47,7 +47,8 @@ class Info(C.Structure):
     _fields_ = [("n_fine", C.c_longlong), ("n_coarse", C.c_longlong), ("n_sub", C.c_int),
                 ("b_entries", C.c_longlong), ("b_bytes", C.c_longlong),
                 ("coarse_bytes", C.c_longlong), ("t_setup_fine_s", C.c_double),
-                ("t_setup_coarse_s", C.c_double)]
+                ("t_setup_coarse_s", C.c_double), ("smoother_cfg", C.c_int),
+                ("smoother_grid", C.c_int), ("coarse_lines", C.c_int)]
 
 
 _lib = None

@@ -208,6 +208,9 @@ th_status th_get_info(const th_ctx *ctx, th_info *info) {
   info->coarse_bytes = ctx->coarse.bytes;
   info->t_setup_fine_s = ctx->t_setup_fine;
   info->t_setup_coarse_s = ctx->t_setup_coarse;
+  info->smoother_cfg = ctx->mfma_cfg;
+  info->smoother_grid = ctx->mfma_grid;
+  info->coarse_lines = ctx->coarse.nblk > 0 ? ctx->coarse.line0[1] - ctx->coarse.line0[0] : 0;
   return TH_OK;
 }
 
@@ -225,8 +228,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return fail(ctx, TH_EINVAL, "l_dd, n_dd, n_s and max_rhs must be >= 1");
   if (!(d->alpha_s >= 0.0) || !std::isfinite(d->alpha_s) || !std::isfinite(d->omega_c))
     return fail(ctx, TH_EINVAL, "alpha_s must be finite and >= 0, omega_c finite");
-  if (d->gemm != TH_GEMM_F64 && d->gemm != TH_GEMM_F32)
-    return fail(ctx, TH_EUNSUPPORTED, "subdomain operator storage not built");
+  if (d->gemm != TH_GEMM_F64 && d->gemm != TH_GEMM_F32 && d->gemm != TH_GEMM_BF16)
+    return fail(ctx, TH_EINVAL, "unknown subdomain operator storage");
   for (int sd = 0; sd < 4; ++sd)
     if (d->bc[sd] != TH_BC_ROBIN && d->bc[sd] != TH_BC_NEUMANN)
       return fail(ctx, TH_EINVAL, "boundary condition must be Robin or Neumann");
@@ -312,7 +315,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
         if (inner[sd] || d->bc[sd] == TH_BC_ROBIN) s.robin |= 1 << sd;
       s.boff = boff;
       s.yoff = yoff;
-      boff += (long long)s.nOm * s.ldb;
+      // element offsets: complex entries (F64/F32) or bf16 values (MFMA layout)
+      boff += (d->gemm == TH_GEMM_BF16) ? mfma_store_elems(s) : (long long)s.nOm * s.ldb;
       yoff += s.nU;
       max_ldb = std::max(max_ldb, s.ldb);
       max_nom = std::max(max_nom, s.nOm);
@@ -324,7 +328,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   c->y_rows = yoff;
   c->b_entries = 0;
   for (auto &s : c->subs) c->b_entries += (long long)s.nU * s.nOm;
-  const size_t belem = (d->gemm == TH_GEMM_F32) ? sizeof(c32) : sizeof(c64);
+  const size_t belem = (d->gemm == TH_GEMM_BF16) ? 2 : (d->gemm == TH_GEMM_F32) ? sizeof(c32)
+                                                                                : sizeof(c64);
   c->b_bytes = boff * (long long)belem;
 
   hipStream_t st = c->stream;
@@ -358,6 +363,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return fail(ctx, TH_EHIP, "upload failed in setup_fine");
   }
   int rc = setup_subdomain_operators(c);
+  if (rc == 0 && d->gemm == TH_GEMM_BF16) rc = autotune_mfma(c);
   if (rc) {
     free_fine(c);
     return finish(ctx, rc);

@@ -94,6 +94,10 @@ struct th_ctx {
 
   double t_setup_fine = 0, t_setup_coarse = 0;
 
+  // matrix-core smoother tunables (chosen by the setup autotuner)
+  int mfma_cfg = 0, mfma_grid = 0;
+  std::string tune_report;
+
   // kernel timing (measurement only)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;                  // reusable events
@@ -139,6 +143,17 @@ int launch_dd_accumulate(const th_ctx *c, const void *y, void *u, int nrhs, bool
 
 // k_dense.hip (setup)
 int setup_subdomain_operators(th_ctx *c);
+
+// k_smoother_mfma.hip
+int launch_extract_b_mfma(const th_ctx *c, int s0, int nb, const c64 *work, int ld,
+                          long long stride, hipStream_t s);
+long long mfma_store_elems(const Sub &s);
+int mfma_num_configs();
+int launch_dd_mfma(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, int cfg, int grid,
+                   hipStream_t s);
+
+// autotune.cpp
+int autotune_mfma(th_ctx *c);
 
 // k_coarse.hip
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);

@@ -311,7 +311,10 @@ int setup_subdomain_operators(th_ctx *c) {
     rc = gj_invert_batched(work, npad, npad, mat, nb, s, pws);
     if (rc) break;
     dim3 ge(ceil_div(c->max_ldb, 256), 64, nb);
-    if (c->desc.gemm == TH_GEMM_F32)
+    if (c->desc.gemm == TH_GEMM_BF16) {
+      rc = launch_extract_b_mfma(c, s0, nb, work, npad, mat, s);
+      if (rc) break;
+    } else if (c->desc.gemm == TH_GEMM_F32)
       hipLaunchKernelGGL((k_extract_b<float>), ge, dim3(256), 0, s, c->d_subs, s0,
                          (const c64 *)work, npad, mat, c->d_nblk, (cx<float> *)c->d_B, c->P);
     else

@@ -115,6 +115,8 @@ static int dd_apply_t(const th_ctx *c, const void *r, void *y, int nrhs, hipStre
 
 int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s) {
   switch (c->desc.gemm) {
+    case TH_GEMM_BF16:
+      return launch_dd_mfma(c, r, y, nrhs, f32, c->mfma_cfg, c->mfma_grid, s);
     case TH_GEMM_F64:
       return f32 ? dd_apply_t<double, float>(c, r, y, nrhs, s)
                  : dd_apply_t<double, double>(c, r, y, nrhs, s);

@@ -160,3 +160,90 @@ def test_solve_c1_fp64():
     assert st.iters == it_ref
     assert rel(to_np(u)[0], x_ref) < 1e-10
     assert st.rel_res <= 1e-6
+
+
+# ------------------------------------------------------------ mixed precision
+def bf16_round(x):
+    """Round float64 values to bfloat16 (nearest even) via float32, back to float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_complex(z):
+    return bf16_round(np.real(z)) + 1j * bf16_round(np.imag(z))
+
+
+def bf16_smoother(sm, u, f):
+    """CSDDSmoother (n_dd = 1) with B_i = diag(1/L) R_U (A_s^(i))^{-1} and
+    X_i = R_Omega r rounded to bfloat16, products and sums exact (FP64)."""
+    r = f - sm.A @ u
+    v = np.zeros_like(u)
+    for i, s in enumerate(sm.subs):
+        B = bf16_complex(sm.subdomain_inverse_rows(i))
+        v[s.u_nodes] += B @ bf16_complex(r[s.om_nodes])
+    return u + v
+
+
+@pytest.mark.parametrize("N,p,l_dd,nrhs", [(37, 2, 8, 20), (19, 4, 6, 3), (16, 2, 8, 64)])
+def test_smooth_bf16_matrix_cores(N, p, l_dd, nrhs):
+    """BF16-stored subdomain operators on MFMA with FP32 accumulation: the
+    smoother output against the FP64 oracle within BF16 accuracy."""
+    print(f"case smooth bf16 N={N} p={p} nrhs={nrhs}", flush=True)
+    k = hetero_k(N, p, seed=21)
+    sm = CSDDSmoother(p, k, None, 0.5, l_dd)
+    s = make_solver(k, p, l_dd, max_rhs=nrhs, coarse=None, gemm="bf16")
+    n = sm.n_nodes
+    u0 = syn.random_complex((nrhs, n), seed=22)
+    f = syn.random_complex((nrhs, n), seed=23)
+    ref = np.stack([sm.apply(u0[i], f[i]) for i in range(nrhs)])
+    emu = np.stack([bf16_smoother(sm, u0[i], f[i]) for i in range(nrhs)])
+    for dt in (torch.complex64, torch.complex128):
+        u = to_dev(u0, dt)
+        s.smooth(u, to_dev(f, dt))
+        got = to_np(u)
+        err, err_emu = rel(got, ref), rel(got - u0, emu - u0)
+        print(f"  {dt}: rel err vs FP64 {err:.2e}, vs BF16-operand emulation {err_emu:.2e}",
+              flush=True)
+        # the kernel is exact arithmetic on BF16-rounded B_i and X_i up to FP32
+        # accumulation (and rare BF16 rounding flips of the complex64 residual)
+        assert err_emu < 2e-3
+        # cost of the precision choice (BF16 unit roundoff 2^-8 on both operands)
+        assert err < 5e-2
+
+
+def test_smooth_f32_storage():
+    N, p, l_dd = 21, 4, 8
+    k = hetero_k(N, p, seed=24)
+    sm = CSDDSmoother(p, k, None, 0.5, l_dd)
+    s = make_solver(k, p, l_dd, max_rhs=2, coarse=None, gemm="f32")
+    u0 = syn.random_complex((2, sm.n_nodes), seed=25)
+    f = syn.random_complex((2, sm.n_nodes), seed=26)
+    ref = np.stack([sm.apply(u0[i], f[i]) for i in range(2)])
+    u = to_dev(u0, torch.complex64)
+    s.smooth(u, to_dev(f, torch.complex64))
+    assert rel(to_np(u), ref) < 1e-5
+
+
+def test_solve_c3_mixed_batched():
+    """C3: 64 Gaussian sources, complex64 preconditioner with BF16 subdomain
+    operators under FP64 flexible GMRES: every RHS reaches a true relative
+    residual <= 1e-6 and the solution error against the FP64 direct solve is
+    <= 1e-5."""
+    cfg = syn.config("C3")
+    p, N = cfg["p"], cfg["n"]
+    f = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"])
+    A = helmholtz_matrix(p, cfg["k"])
+    lu = spla.splu(A.tocsc())
+    x_ref = np.stack([lu.solve(x) for x in f])
+    s = make_solver(cfg["k"], p, cfg["l_dd"], alpha_s=cfg["alpha_s"], max_rhs=64, gemm="bf16")
+    print("autotune:", s.info(), flush=True)
+    u, st = s.solve(to_dev(f), precond="c64")
+    x = to_np(u)
+    errs = [np.linalg.norm(x[i] - x_ref[i]) / np.linalg.norm(x_ref[i]) for i in range(64)]
+    print(f"C3 mixed: iters {st.iters} max rel res {st.rel_res:.2e} max err {max(errs):.2e}",
+          flush=True)
+    assert st.status == 0
+    assert st.rel_res <= 1e-6
+    assert max(errs) <= 1e-5
