@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C5"])
     ap.add_argument("--precond", default=None, choices=["c128", "c64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -51,7 +52,7 @@ def workload(name):
     cfg = syn.config(name)
     spec = dict(l_dd=cfg["l_dd"], alpha_s=cfg["alpha_s"], gemm="f64", precond="c128")
     if name == "C3":
-        spec.update(gemm="f32", precond="c64")
+        spec.update(gemm="bf16", precond="c64")
     return cfg, spec
 
 
@@ -124,92 +125,140 @@ def cpu_baseline(cfg_name):
                       f"(setup {t_setup:.1f} s excluded), single-threaded numpy/scipy"}
 
 
+def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, verbose=False,
+                 gemm=None):
+    """Set up one workload, then time `steps` solves to 1e-6 after `warmup`
+    untimed ones.  With timing, HIP events record every kernel class over the
+    timed region (graph replay is off then); without it a separate one-solve
+    timing pass follows the timed region."""
+    import torch
+    import synthetic as syn
+    from paper_2509_17494_amd import TwoGridSolver
+
+    cfg, spec = workload(name)
+    precond = precond or spec["precond"]
+    if gemm:
+        spec["gemm"] = gemm
+    N, p = cfg["n"], cfg["p"]
+    f_host = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"])
+    R = f_host.shape[0]
+    stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        s = TwoGridSolver(cfg["k"], order=p, alpha_s=spec["alpha_s"], l_dd=spec["l_dd"],
+                          gemm=spec["gemm"], max_rhs=R)
+        t_setup = time.perf_counter() - t0
+        info = s.info()
+        f = torch.from_numpy(f_host).to("cuda")
+        u = torch.empty_like(f)
+        if verbose:
+            print(f"{name}: setup {t_setup:.2f} s (fine {info['t_setup_fine_s']:.2f}, coarse "
+                  f"{info['t_setup_coarse_s']:.2f}); B {info['b_bytes'] / 1e9:.3f} GB",
+                  flush=True)
+        for _ in range(warmup):
+            s.solve(f, u, precond=precond, graph=graph)
+        torch.cuda.synchronize()
+        if timing:
+            s.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cycles, iters, worst = 0, [], 0.0
+        for _ in range(steps):
+            _, st = s.solve(f, u, precond=precond, graph=graph)
+            cycles += st.n_precond
+            iters.append(st.iters)
+            worst = max(worst, st.rel_res)
+            if st.status != 0:
+                raise RuntimeError(f"{name}: solve did not converge: {st}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if not timing:
+            s.timing(True)
+            s.solve(f, u, precond=precond, graph=False)
+            torch.cuda.synchronize()
+        kt = s.kernel_times()
+        s.timing(False)
+        ksteps = steps if timing else 1
+    elapsed = t1 - t0
+    mat_bytes = {"f64": 16, "f32": 8, "bf16": 4}[spec["gemm"]]
+    vec_bytes = 16 if precond == "c128" else 8
+    subs = subdomain_sizes(N, p, spec["l_dd"])
+    alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes)
+    flops = 8.0 * sum(nu * no for nu, no in subs) * R
+    dd_ms, dd_n = kt["dd_apply"]
+    avg_ms = dd_ms / max(dd_n, 1)
+    res = {
+        "name": name, "precond": precond, "gemm": spec["gemm"], "graph": graph, "R": R,
+        "n_fine": info["n_fine"], "value": info["n_fine"] * cycles / elapsed,
+        "ms_per_step": elapsed / steps * 1e3, "gmres_iters": iters[-1], "max_rel_res": worst,
+        "setup_s": t_setup, "info": info,
+        "kernel_ms_per_step": {k: round(v[0] / ksteps, 4) for k, v in kt.items()},
+        "dd": {"alg_bytes": alg, "flops": flops, "avg_ms": avg_ms, "launches": dd_n,
+               "gbs": alg / (avg_ms * 1e-3) / 1e9, "tflops": flops / (avg_ms * 1e-3) / 1e12},
+        "desc": f"{name}: 2-D Q{p}, {N}x{N} cells ({info['n_fine']} DOF), {R} RHS, "
+                f"l_dd={spec['l_dd']}, alpha_s={spec['alpha_s']}, B_i {spec['gemm']}, "
+                f"preconditioner {precond}" + (", HIP-graph replay" if graph else ""),
+    }
+    del s
+    torch.cuda.synchronize()
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
-    import torch
-    import synthetic as syn
-    from paper_2509_17494_amd import TwoGridSolver
-
-    cfg, spec = workload(a.workload)
-    precond = a.precond or spec["precond"]
-    N, p = cfg["n"], cfg["p"]
-    f_host = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"])
-    R = f_host.shape[0]
-    t0 = time.perf_counter()
-    s = TwoGridSolver(cfg["k"], order=p, alpha_s=spec["alpha_s"], l_dd=spec["l_dd"],
-                      gemm=spec["gemm"], max_rhs=R)
-    t_setup = time.perf_counter() - t0
-    info = s.info()
-    f = torch.from_numpy(f_host).to("cuda")
-    u = torch.empty_like(f)
-    if a.verbose:
-        print(f"setup {t_setup:.2f} s (fine {info['t_setup_fine_s']:.2f}, coarse "
-              f"{info['t_setup_coarse_s']:.2f}); B {info['b_bytes'] / 1e9:.2f} GB", flush=True)
-    for _ in range(a.warmup):
-        s.solve(f, u, precond=precond)
-    torch.cuda.synchronize()
-    s.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cycles = 0
-    iters = []
-    worst = 0.0
-    for _ in range(a.steps):
-        _, st = s.solve(f, u, precond=precond)
-        cycles += st.n_precond
-        iters.append(st.iters)
-        worst = max(worst, st.rel_res)
-        if st.status != 0:
-            raise RuntimeError(f"solve did not converge: {st}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = s.kernel_times()
-    s.timing(False)
-    elapsed = t1 - t0
-    value = info["n_fine"] * cycles / elapsed
-    ms_step = elapsed / a.steps * 1e3
-
-    mat_bytes = {"f64": 16, "f32": 8, "bf16": 4}[spec["gemm"]]
-    vec_bytes = 16 if precond == "c128" else 8
-    subs = subdomain_sizes(N, p, spec["l_dd"])
-    alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes)
-    dd_ms, dd_n = kt["dd_apply"]
-    avg_ms = dd_ms / max(dd_n, 1)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
+    mixed = a.workload == "C3"
+    prim = run_workload(a.workload, a.steps, a.warmup, precond=a.precond, graph=mixed,
+                        timing=not mixed, verbose=a.verbose)
+    d = prim["dd"]
     traffic = traffic_entry(a.workload)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_dd_apply", "alg_bytes_per_launch": alg,
-            "avg_launch_ms": round(avg_ms, 4), "launches": dd_n}
+    roof = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_dd_apply" if prim["gemm"] != "bf16" else "k_dd_mfma",
+            "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": round(d["avg_ms"], 4),
+            "launches": d["launches"]}
+    info = prim["info"]
     out = {
         "metric": "fine DOF*cycles/s and time-to-1e-6 residual, mixed+batched vs FP64, 1 GPU",
-        "value": value,
+        "value": prim["value"],
         "unit": "DOF*cycles/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precond == "c128" else "f32",
+        "dtype": "f64" if prim["precond"] == "c128" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload}: 2-D Q{p}, {N}x{N} cells ({info['n_fine']} DOF), "
-                               f"{R} RHS, l_dd={spec['l_dd']}, alpha_s={spec['alpha_s']}, "
-                               f"B_i {spec['gemm']}, preconditioner {precond}",
-                   "time_to_1e-6_ms": ms_step, "gmres_iters": iters[-1],
-                   "max_rel_res": worst, "setup_s": round(t_setup, 3),
+        "config": {"workload": prim["desc"],
+                   "time_to_1e-6_ms": prim["ms_per_step"], "gmres_iters": prim["gmres_iters"],
+                   "max_rel_res": prim["max_rel_res"], "setup_s": round(prim["setup_s"], 3),
                    "setup_fine_s": round(info["t_setup_fine_s"], 3),
                    "setup_coarse_s": round(info["t_setup_coarse_s"], 3),
                    "b_bytes": info["b_bytes"], "coarse_bytes": info["coarse_bytes"],
-                   "kernel_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in kt.items()}},
+                   "coarse_lines_per_block": info["coarse_lines"],
+                   "kernel_ms_per_step": prim["kernel_ms_per_step"]},
         "roofline": roof,
     }
+    if not a.no_variants and a.workload == "C2":
+        variants = {}
+        for key, kw in [("C3_mixed_bf16_batched64_graph", dict(name="C3", graph=True, timing=False)),
+                        ("C3_fp64_batched64_control", dict(name="C3", precond="c128", gemm="f64",
+                                                           graph=False, timing=True)),
+                        ("C1_fp64", dict(name="C1", graph=False, timing=True))]:
+            v = run_workload(steps=max(3, a.steps), warmup=1, verbose=a.verbose, **kw)
+            variants[key] = {"workload": v["desc"], "value": v["value"],
+                             "unit": "DOF*cycles/s", "time_to_1e-6_ms": v["ms_per_step"],
+                             "gmres_iters": v["gmres_iters"], "max_rel_res": v["max_rel_res"],
+                             "smoother_kernel_ms": round(v["dd"]["avg_ms"], 4),
+                             "smoother_alg_GBps": round(v["dd"]["gbs"], 1),
+                             "smoother_TFLOPs": round(v["dd"]["tflops"], 3),
+                             "kernel_ms_per_step": v["kernel_ms_per_step"]}
+        out["config"]["variants"] = variants
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline("C2" if a.workload == "C2" else a.workload)
     print(json.dumps(out), flush=True)

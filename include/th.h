@@ -59,9 +59,13 @@ typedef enum { TH_C128 = 0, TH_C64 = 1 } th_dtype;
 typedef enum { TH_GEMM_F64 = 0, TH_GEMM_F32 = 1, TH_GEMM_BF16 = 2 } th_gemm;
 
 typedef enum {
-  TH_COARSE_QSFEM = 0,   /* per-cell QSFEM weights q(h_c k(c)), Sec. 3.3 */
-  TH_COARSE_WEIGHTS = 1  /* caller-supplied per-coarse-cell (q0, q_edge, q_diag) */
+  TH_COARSE_QSFEM = 0,    /* per-cell QSFEM weights q(h_c k(c)), Sec. 3.3 */
+  TH_COARSE_WEIGHTS = 1,  /* caller-supplied per-coarse-cell (q0, q_edge, q_diag) */
+  TH_COARSE_PLAINFIT = 2, /* per-cell plain dispersion-matching fit (see th_plain_fit) */
+  TH_COARSE_MLP = 3       /* per-cell surrogate network with fallback to the plain fit */
 } th_coarse_scheme;
+
+typedef struct th_mlp th_mlp;
 
 typedef enum {
   TH_KRYLOV_GMRES = 0,      /* right-preconditioned (flexible) GMRES, x0 = 0 */
@@ -88,6 +92,10 @@ typedef struct {
 typedef struct {
   th_coarse_scheme scheme;
   const double *q;      /* HOST, (pN/2)^d x 3 weights, x fastest; TH_COARSE_WEIGHTS only */
+  const th_mlp *mlp;    /* trained surrogate; TH_COARSE_MLP only */
+  double fallback_tau;  /* TH_COARSE_MLP: a cell falls back to the plain fit when the
+                           network's dispersion errors differ from the fine ones by more
+                           than this (relative wavenumber); 0 = every cell falls back */
 } th_coarse_desc;
 
 typedef struct {
@@ -96,6 +104,9 @@ typedef struct {
   int maxit;            /* preconditioner applications per RHS */
   int restart;          /* GMRES restart length (<= 0: maxit) */
   th_dtype precond_dtype; /* TH_C128: FP64 preconditioner; TH_C64: complex64 */
+  int use_graph;        /* 1: capture the two-grid preconditioner once in a HIP graph and
+                           replay it every iteration (needs a non-NULL stream; ignored
+                           while kernel timing is enabled) */
 } th_solve_opts;
 
 typedef struct {
@@ -116,6 +127,8 @@ typedef struct {
   int smoother_cfg;       /* matrix-core smoother configuration chosen by the autotuner */
   int smoother_grid;      /* its persistent grid size (0: one workgroup per work item) */
   int coarse_lines;       /* grid lines per coarse super-block */
+  int n_fallback_cells;   /* TH_COARSE_MLP: coarse cells that fell back to the plain fit */
+  double t_stencil_s;     /* time spent computing the per-cell coarse weights */
 } th_info;
 
 /* Create a context on HIP device `hip_device`, ordering work on `hip_stream`
@@ -188,6 +201,61 @@ typedef enum {
 
 th_status th_timing_enable(th_ctx *ctx, int enable);
 th_status th_timing_get(th_ctx *ctx, int kernel_class, double *total_ms, long long *launches);
+
+/* ------------------------------------------------------------------------
+ * Dispersion-matched coarse stencils (a project addition motivated by the
+ * footnote of Sec. 1: the coarse level should match the fine, not the true,
+ * dispersion relation).  A sample is (eta_c, p, shift): eta_c = h_c k of a
+ * coarse cell (h_c = 2h/p), the order p, and shift = eps / k^2.
+ *
+ * Plain fit: e_m = r(t_m) / kh - 1, the relative error of the fine Q_p
+ * discrete wavenumber (Sec. 6.2) along t_1 = pi/16 and t_2 = 3 pi/16, and the
+ * 9-point weights (q0, q_edge, q_diag) of the QSFEM family (Sec. 3.2) whose
+ * zero set passes through those fine wave vectors, scaled so that the symbol
+ * at 0 is -eta^2.  Valid for kh = eta_c p / 2 < pi.  Host computation.
+ *   samples: HOST n x 3; e_out: HOST n x 2 or NULL; q_out: HOST n x 3 or NULL. */
+th_status th_plain_fit(const double *samples, int n, double *e_out, double *q_out);
+
+/* Surrogate network 3 -> 64 -> 64 -> 2 (SiLU), inputs standardised samples,
+ * outputs standardised log(max(-e_m, 0) + 1e-13); FP32 master weights with a
+ * BF16 copy, FP32 accumulation.  Weight layout (n_params = 4546 floats):
+ * W1 (64 x 3 row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2). */
+typedef struct {
+  int epochs;           /* passes over the samples */
+  int batch;            /* samples per step (multiple of 64) */
+  double lr;            /* Adam learning rate */
+  int bf16;             /* 1: forward/backward with the BF16 weight copy */
+} th_mlp_train_opts;
+
+typedef struct {
+  double loss_first, loss_last;  /* mean squared error of the first / last step */
+  int steps;
+  double t_targets_s, t_train_s;  /* plain-fit targets on the host / training on the device */
+} th_mlp_train_stats;
+
+th_status th_mlp_create(th_mlp **out, int hip_device, void *hip_stream);
+void th_mlp_destroy(th_mlp *m);
+const char *th_mlp_last_error(const th_mlp *m);
+th_status th_mlp_num_params(int *n_params);
+/* theta: HOST FP32 weights in the layout above (the BF16 copy is refreshed) */
+th_status th_mlp_set_weights(th_mlp *m, const float *theta, int n_params);
+th_status th_mlp_get_weights(const th_mlp *m, float *theta, int n_params);
+/* standardisation: x_std = (x - in_mean) / in_std, y_std = (y - out_mean) / out_std */
+th_status th_mlp_set_scaling(th_mlp *m, const double in_mean[3], const double in_std[3],
+                             const double out_mean[2], const double out_std[2]);
+th_status th_mlp_get_scaling(const th_mlp *m, double in_mean[3], double in_std[3],
+                             double out_mean[2], double out_std[2]);
+/* Loss (mean squared error) and gradient for HOST standardised data
+ * x_std (n x 3) and y_std (n x 2), computed by the device kernels; bf16 selects
+ * the BF16 weight copy.  grad: HOST n_params floats. */
+th_status th_mlp_loss_grad(th_mlp *m, const float *x_std, const float *y_std, int n, int bf16,
+                           double *loss, float *grad);
+/* Train on n HOST samples: plain-fit targets on the host, standardisation
+ * from the samples, Adam steps on the device from the current weights. */
+th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_train_opts *opts,
+                       th_mlp_train_stats *stats);
+/* Device inference for n HOST samples: e_out (HOST n x 2) = predicted e_m. */
+th_status th_mlp_predict(th_mlp *m, const double *samples, int n, int bf16, double *e_out);
 
 #ifdef __cplusplus
 }

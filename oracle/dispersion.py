@@ -1,0 +1,119 @@
+"""Discrete dispersion of the fine Q_p scheme and the plain dispersion-matching
+fit of the coarse 9-point stencil.
+
+Fine dispersion (Sec. 6.1-6.2 and the appendix): Bloch waves of the
+finite-element matrix on the infinite square mesh exist for the wave vectors
+theta with det A^(theta) = 0, where A^(theta) = sum_beta e^{i theta.beta}
+A_{0,beta} is the p^2 x p^2 symbol on the unit cell (lower-left vertex, left
+and lower edges, face).  Along a direction t the radius r with
+theta = r (cos t, sin t) (mesh size h = 1) is found as in the appendix: sample
+the eigenvalue of A^(theta) closest to zero (A^ is Hermitian for real k), find
+the sign change near r = kh, and zoom in (Brent's method).  Only the regime
+kh < pi (a single closed dispersion curve) is handled.
+
+Plain fit (a project definition; the paper's footnote in Sec. 1 notes that the
+coarse level should match the fine rather than the true dispersion): the same
+9-point family as QSFEM (P0 = 4), with P1, P2 chosen so that the coarse symbol
+vanishes at the fine discrete wave vectors of the two QSFEM directions
+t = pi/16 and 3 pi/16, i.e. the printed QSFEM formulas evaluated with
+c_m = cos(zeta_m cos t_m), s_m = cos(zeta_m sin t_m), zeta_m = h_c xi_f(t_m);
+the scaling N keeps sigma(0) = -eta^2 (eq. scaling_factor_QSFEM).  Reading of
+the "shift" input: the damping ratio delta = eps / k^2, entering through the
+real wavenumber of the damped medium, k Re sqrt(1 + i delta).  With
+xi_f = k the fit is exactly QSFEM.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.optimize import brentq
+
+from .fem import ref_matrices
+from .qsfem import stencil_P
+
+T1, T2 = math.pi / 16.0, 3.0 * math.pi / 16.0
+
+
+def bloch_symbol(p: int, kh: float, theta) -> np.ndarray:
+    """A^(theta) on the unit cell of the Q_p GLL space (h = 1): element matrix
+    K1 x M1 + M1 x K1 - (kh)^2 M1 x M1, element node (ax, ay) -> cell dof
+    (ax mod p, ay mod p) with lattice shift (ax // p, ay // p)."""
+    K1, M1 = ref_matrices(p)
+    Ae = np.kron(K1, M1) + np.kron(M1, K1) - kh * kh * np.kron(M1, M1)
+    n = p * p
+    S = np.zeros((n, n), dtype=complex)
+    loc = [(ay, ax) for ay in range(p + 1) for ax in range(p + 1)]
+    dof = [(ay % p) * p + (ax % p) for ay, ax in loc]
+    shift = [np.array([ax // p, ay // p]) for ay, ax in loc]
+    th = np.asarray(theta, dtype=float)
+    for a in range(len(loc)):
+        for b in range(len(loc)):
+            S[dof[a], dof[b]] += Ae[a, b] * np.exp(1j * th @ (shift[b] - shift[a]))
+    return S
+
+
+def _nearest_zero_eig(p, kh, r, t):
+    ev = np.linalg.eigvalsh(bloch_symbol(p, kh, (r * math.cos(t), r * math.sin(t))))
+    return ev[np.argmin(np.abs(ev))]
+
+
+def fine_radius(p: int, kh: float, t: float, rel_window: float = 0.08, samples: int = 9) -> float:
+    """Radius r (units of 1/h) of the fine discrete dispersion curve along t."""
+    if not kh < math.pi:
+        raise ValueError("only kh < pi is supported")
+    rs = np.linspace(kh * (1 - rel_window), kh * (1 + rel_window), samples)
+    vals = [_nearest_zero_eig(p, kh, r, t) for r in rs]
+    for i in range(samples - 1):
+        if vals[i] == 0.0:
+            return float(rs[i])
+        if vals[i] * vals[i + 1] < 0:
+            return brentq(lambda r: _nearest_zero_eig(p, kh, r, t), rs[i], rs[i + 1],
+                          xtol=1e-15, rtol=1e-15, maxiter=200)
+    raise RuntimeError("no sign change of the symbol near r = kh")
+
+
+def fit_from_radii(eta: float, zeta1: float, zeta2: float):
+    """(q0, q_edge, q_diag) of the 9-point stencil whose symbol vanishes at
+    zeta_m (cos t_m, sin t_m), scaled so that sigma(0) = -eta^2."""
+    c1, s1 = math.cos(zeta1 * math.cos(T1)), math.cos(zeta1 * math.sin(T1))
+    c2, s2 = math.cos(zeta2 * math.cos(T2)), math.cos(zeta2 * math.sin(T2))
+    den = c2 * s2 * (c1 + s1) - c1 * s1 * (c2 + s2)
+    P0 = 4.0
+    P1 = 2.0 * (c1 * s1 - c2 * s2) / den
+    P2 = (c2 + s2 - c1 - s1) / den
+    N = -eta * eta / (P0 + 4.0 * P1 + 4.0 * P2)
+    return N * P0 / 4.0, N * P1 / 2.0, N * P2
+
+
+def plain_fit(eta_c: float, p: int, shift: float = 0.0):
+    """Plain dispersion-matching coarse weights for one coarse cell with
+    eta_c = h_c k (h_c = 2h/p), order p and damping ratio `shift`."""
+    eta = eta_c * (1.0 + 1j * shift) ** 0.5
+    eta = float(eta.real)
+    kh = eta * p / 2.0                      # fine cell: h = h_c p / 2
+    z1 = fine_radius(p, kh, T1) * 2.0 / p   # coarse-normalised radii
+    z2 = fine_radius(p, kh, T2) * 2.0 / p
+    return fit_from_radii(eta, z1, z2)
+
+
+def coarse_radius(q, t: float, eta: float) -> float:
+    """Radius zeta of the zero set of the 9-point symbol with weights q along t."""
+    q0, qe, qd = q
+    N = q0  # q0 = N P0 / 4 = N
+    P1, P2 = 2.0 * qe / N, qd / N
+    f = lambda z: 4.0 + 2.0 * P1 * (math.cos(z * math.cos(t)) + math.cos(z * math.sin(t))) + \
+        4.0 * P2 * math.cos(z * math.cos(t)) * math.cos(z * math.sin(t))
+    a, b = 0.7 * eta, 1.3 * eta
+    return brentq(f, a, b, xtol=1e-15, rtol=1e-15, maxiter=200)
+
+
+def dispersion_mismatch(q, eta_c: float, p: int, n_dir: int = 16) -> float:
+    """max over directions t in [0, pi/4] of |zeta_c(t) - zeta_f(t)| / eta."""
+    kh = eta_c * p / 2.0
+    worst = 0.0
+    for t in np.linspace(0.0, math.pi / 4, n_dir):
+        zf = fine_radius(p, kh, t) * 2.0 / p
+        zc = coarse_radius(q, t, eta_c)
+        worst = max(worst, abs(zc - zf) / eta_c)
+    return worst

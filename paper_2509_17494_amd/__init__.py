@@ -21,7 +21,7 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["TwoGridSolver", "THError", "SolveStats", "load_library"]
+__all__ = ["TwoGridSolver", "THError", "SolveStats", "load_library", "CoarseStencilMLP", "plain_fit"]
 
 
 class THError(RuntimeError):
@@ -130,6 +130,16 @@ class TwoGridSolver:
         if scheme == "qsfem":
             d.scheme = L.TH_COARSE_QSFEM
             d.q = C.POINTER(C.c_double)()
+        elif scheme == "plainfit":
+            d.scheme = L.TH_COARSE_PLAINFIT
+            d.q = C.POINTER(C.c_double)()
+        elif scheme == "mlp":
+            net, tau = q
+            d.scheme = L.TH_COARSE_MLP
+            d.q = C.POINTER(C.c_double)()
+            d.mlp = net._h
+            d.fallback_tau = float(tau)
+            self._mlp_ref = net
         elif scheme == "weights":
             q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
             nc = self.N * (self.p // 2)
@@ -178,6 +188,17 @@ class TwoGridSolver:
             raise ValueError(f"nrhs={nrhs} outside [1, max_rhs={self.max_rhs}]")
         return nrhs
 
+    def _ordered(self, fn, *args):
+        """Run a stream-ordered library call on the solver's stream, ordered
+        after the caller's current stream and before its later work."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self._stream:
+            self._stream.wait_stream(cur)
+        st = fn(*args)
+        if cur != self._stream:
+            cur.wait_stream(self._stream)
+        return st
+
     @staticmethod
     def _p(t):
         return C.c_void_p(t.data_ptr())
@@ -196,7 +217,7 @@ class TwoGridSolver:
             raise ValueError("u and f must have the same shape")
         r = torch.empty_like(u) if r is None else r
         self._vec(r, self.n_fine, "r", u.dtype)
-        self._check(self._lib.th_residual(self._h, self._p(u), self._p(f), self._p(r), nrhs, _dt(u)))
+        self._check(self._ordered(self._lib.th_residual, self._h, self._p(u), self._p(f), self._p(r), nrhs, _dt(u)))
         return r
 
     def smooth(self, u, f):
@@ -205,7 +226,7 @@ class TwoGridSolver:
         self._vec(f, self.n_fine, "f", u.dtype)
         if f.shape != u.shape:
             raise ValueError("u and f must have the same shape")
-        self._check(self._lib.th_smooth(self._h, self._p(u), self._p(f), nrhs, _dt(u)))
+        self._check(self._ordered(self._lib.th_smooth, self._h, self._p(u), self._p(f), nrhs, _dt(u)))
         return u
 
     def restrict(self, r, rc=None):
@@ -214,7 +235,7 @@ class TwoGridSolver:
         shape = (self.n_coarse,) if r.dim() == 1 else (nrhs, self.n_coarse)
         rc = torch.empty(shape, dtype=r.dtype, device=self.device) if rc is None else rc
         self._vec(rc, self.n_coarse, "rc", r.dtype)
-        self._check(self._lib.th_restrict(self._h, self._p(r), self._p(rc), nrhs, _dt(r)))
+        self._check(self._ordered(self._lib.th_restrict, self._h, self._p(r), self._p(rc), nrhs, _dt(r)))
         return rc
 
     def prolong(self, uc, u, omega=None):
@@ -224,7 +245,7 @@ class TwoGridSolver:
         if nrc != nrhs:
             raise ValueError("uc and u must hold the same number of vectors")
         om = self.omega_c if omega is None else float(omega)
-        self._check(self._lib.th_prolong(self._h, self._p(uc), self._p(u), om, nrhs, _dt(u)))
+        self._check(self._ordered(self._lib.th_prolong, self._h, self._p(uc), self._p(u), om, nrhs, _dt(u)))
         return u
 
     def coarse_solve(self, rc, uc=None):
@@ -234,7 +255,7 @@ class TwoGridSolver:
         self._vec(uc, self.n_coarse, "uc", rc.dtype)
         if uc.data_ptr() == rc.data_ptr():
             raise ValueError("rc and uc must not alias")
-        self._check(self._lib.th_coarse_solve(self._h, self._p(rc), self._p(uc), nrhs, _dt(rc)))
+        self._check(self._ordered(self._lib.th_coarse_solve, self._h, self._p(rc), self._p(uc), nrhs, _dt(rc)))
         return uc
 
     def twogrid(self, u, f):
@@ -243,15 +264,17 @@ class TwoGridSolver:
         self._vec(f, self.n_fine, "f", u.dtype)
         if f.shape != u.shape:
             raise ValueError("u and f must have the same shape")
-        self._check(self._lib.th_twogrid(self._h, self._p(u), self._p(f), nrhs, _dt(u)))
+        self._check(self._ordered(self._lib.th_twogrid, self._h, self._p(u), self._p(f), nrhs, _dt(u)))
         return u
 
     def solve(self, f, u=None, rtol=1e-6, maxit=300, restart=0, precond="c128",
-              method="gmres", raise_on_notconv=False):
+              method="gmres", raise_on_notconv=False, graph=False):
         """Solve A u = f (complex128 vectors) with the two-grid preconditioner.
 
         precond: "c128" (FP64 two-grid step) or "c64" (complex64 step under
-        FP64 flexible GMRES).  Returns (u, SolveStats)."""
+        FP64 flexible GMRES).  graph: replay the preconditioner from a HIP
+        graph (needs the solver to run on a non-default stream).
+        Returns (u, SolveStats)."""
         nrhs = self._vec(f, self.n_fine, "f", torch.complex128)
         u = torch.empty_like(f) if u is None else u
         self._vec(u, self.n_fine, "u", torch.complex128)
@@ -259,8 +282,118 @@ class TwoGridSolver:
         o.krylov = L.TH_KRYLOV_GMRES if method == "gmres" else L.TH_KRYLOV_STATIONARY
         o.rtol, o.maxit, o.restart = float(rtol), int(maxit), int(restart)
         o.precond_dtype = L.TH_C128 if precond == "c128" else L.TH_C64
+        o.use_graph = 1 if graph else 0
         st = L.SolveStats()
-        status = self._lib.th_solve(self._h, self._p(f), self._p(u), nrhs, C.byref(o), C.byref(st))
+        status = self._ordered(self._lib.th_solve, self._h, self._p(f), self._p(u), nrhs, C.byref(o), C.byref(st))
         if status not in (0, L.TH_ENOTCONV) or (status and raise_on_notconv):
             self._check(status)
         return u, SolveStats(st.iters, st.rel_res, st.t_solve_s, st.n_precond, status)
+
+
+def plain_fit(samples):
+    """Plain dispersion-matching fit (host, through the C ABI): samples (n, 3)
+    rows (eta_c, p, shift) -> (e (n, 2) fine dispersion errors at pi/16 and
+    3 pi/16, q (n, 3) coarse weights)."""
+    lib = L.load()
+    x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64).reshape(-1, 3))
+    n = x.shape[0]
+    e = np.zeros((n, 2))
+    q = np.zeros((n, 3))
+    st = lib.th_plain_fit(x.ctypes.data, n, e.ctypes.data, q.ctypes.data)
+    if st != 0:
+        raise THError(st, "th_plain_fit rejected the samples (eta_c > 0, p in 1..8, kh < pi)")
+    return e, q
+
+
+@dataclass
+class TrainStats:
+    loss_first: float
+    loss_last: float
+    steps: int
+    t_targets_s: float
+    t_train_s: float
+
+
+class CoarseStencilMLP:
+    """Surrogate network for the per-cell dispersion errors of the fine scheme
+    (3 -> 64 -> 64 -> 2, SiLU), trained and evaluated by the library's HIP
+    kernels (FP32 master weights, BF16 copy, FP32 accumulation)."""
+
+    def __init__(self, weights=None, device: int | None = None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        n = C.c_int()
+        self._lib.th_mlp_num_params(C.byref(n))
+        self.n_params = n.value
+        with torch.cuda.device(self.device):
+            self._stream = torch.cuda.current_stream(self.device)
+            h = C.c_void_p()
+            st = self._lib.th_mlp_create(C.byref(h), self.device.index,
+                                         C.c_void_p(self._stream.cuda_stream))
+            if st != 0:
+                raise THError(st, "th_mlp_create failed")
+            self._h = h
+        if weights is not None:
+            self.set_weights(weights)
+
+    def _check(self, st):
+        if st != 0:
+            msg = self._lib.th_mlp_last_error(self._h)
+            raise THError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.th_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, theta):
+        w = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        self._check(self._lib.th_mlp_set_weights(self._h, w.ctypes.data, w.size))
+
+    def weights(self):
+        w = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self._lib.th_mlp_get_weights(self._h, w.ctypes.data, w.size))
+        return w
+
+    def set_scaling(self, in_mean, in_std, out_mean, out_std):
+        a = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in
+             (in_mean, in_std, out_mean, out_std)]
+        self._check(self._lib.th_mlp_set_scaling(self._h, *[v.ctypes.data for v in a]))
+        self._keep = a
+
+    def scaling(self):
+        a = [np.zeros(3), np.zeros(3), np.zeros(2), np.zeros(2)]
+        self._check(self._lib.th_mlp_get_scaling(self._h, *[v.ctypes.data for v in a]))
+        return a
+
+    def loss_grad(self, x_std, y_std, bf16=False):
+        x = np.ascontiguousarray(np.asarray(x_std, dtype=np.float32))
+        y = np.ascontiguousarray(np.asarray(y_std, dtype=np.float32))
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        self._check(self._lib.th_mlp_loss_grad(self._h, x.ctypes.data, y.ctypes.data, x.shape[0],
+                                               1 if bf16 else 0, C.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train(self, samples, epochs=20, batch=1024, lr=2e-3, bf16=True) -> TrainStats:
+        x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64))
+        o = L.MlpTrainOpts(epochs, batch, lr, 1 if bf16 else 0)
+        st = L.MlpTrainStats()
+        self._check(self._lib.th_mlp_train(self._h, x.ctypes.data, x.shape[0], C.byref(o),
+                                           C.byref(st)))
+        return TrainStats(st.loss_first, st.loss_last, st.steps, st.t_targets_s, st.t_train_s)
+
+    def predict(self, samples, bf16=True):
+        x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64))
+        e = np.zeros((x.shape[0], 2))
+        self._check(self._lib.th_mlp_predict(self._h, x.ctypes.data, x.shape[0],
+                                             1 if bf16 else 0, e.ctypes.data))
+        return e

@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "TH_OK", -1: "TH_EINVAL", -2: "TH_ESTATE", -3: "TH_ENOMEM", -
 TH_BC_ROBIN, TH_BC_NEUMANN = 0, 1
 TH_C128, TH_C64 = 0, 1
 TH_GEMM_F64, TH_GEMM_F32, TH_GEMM_BF16 = 0, 1, 2
-TH_COARSE_QSFEM, TH_COARSE_WEIGHTS = 0, 1
+TH_COARSE_QSFEM, TH_COARSE_WEIGHTS, TH_COARSE_PLAINFIT, TH_COARSE_MLP = 0, 1, 2, 3
 TH_KRYLOV_GMRES, TH_KRYLOV_STATIONARY = 0, 1
 KERNEL_CLASSES = ["dd_apply", "dd_accum", "operator", "restrict", "prolong", "coarse", "krylov"]
 
@@ -30,12 +30,13 @@ class FineDesc(C.Structure):
 
 
 class CoarseDesc(C.Structure):
-    _fields_ = [("scheme", C.c_int), ("q", C.POINTER(C.c_double))]
+    _fields_ = [("scheme", C.c_int), ("q", C.POINTER(C.c_double)), ("mlp", C.c_void_p),
+                ("fallback_tau", C.c_double)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("krylov", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int),
-                ("restart", C.c_int), ("precond_dtype", C.c_int)]
+                ("restart", C.c_int), ("precond_dtype", C.c_int), ("use_graph", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -48,7 +49,8 @@ class Info(C.Structure):
                 ("b_entries", C.c_longlong), ("b_bytes", C.c_longlong),
                 ("coarse_bytes", C.c_longlong), ("t_setup_fine_s", C.c_double),
                 ("t_setup_coarse_s", C.c_double), ("smoother_cfg", C.c_int),
-                ("smoother_grid", C.c_int), ("coarse_lines", C.c_int)]
+                ("smoother_grid", C.c_int), ("coarse_lines", C.c_int),
+                ("n_fallback_cells", C.c_int), ("t_stencil_s", C.c_double)]
 
 
 _lib = None
@@ -92,5 +94,39 @@ def load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
+    load_mlp(lib)
     _lib = lib
+    return lib
+
+
+class MlpTrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("bf16", C.c_int)]
+
+
+class MlpTrainStats(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("steps", C.c_int),
+                ("t_targets_s", C.c_double), ("t_train_s", C.c_double)]
+
+
+def load_mlp(lib):
+    """Declare the surrogate-network entry points on an already loaded library."""
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    sig = {
+        "th_plain_fit": ([vp, i, vp, vp], i),
+        "th_mlp_num_params": ([C.POINTER(i)], i),
+        "th_mlp_create": ([C.POINTER(vp), i, vp], i),
+        "th_mlp_destroy": ([vp], None),
+        "th_mlp_last_error": ([vp], C.c_char_p),
+        "th_mlp_set_weights": ([vp, vp, i], i),
+        "th_mlp_get_weights": ([vp, vp, i], i),
+        "th_mlp_set_scaling": ([vp, vp, vp, vp, vp], i),
+        "th_mlp_get_scaling": ([vp, vp, vp, vp, vp], i),
+        "th_mlp_loss_grad": ([vp, vp, vp, i, i, C.POINTER(d), vp], i),
+        "th_mlp_train": ([vp, vp, i, C.POINTER(MlpTrainOpts), C.POINTER(MlpTrainStats)], i),
+        "th_mlp_predict": ([vp, vp, i, i, vp], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
     return lib

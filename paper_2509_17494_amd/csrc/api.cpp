@@ -108,6 +108,11 @@ static FineOp make_op(const th_ctx *c, bool shifted) {
   return op;
 }
 
+static void free_graphs(th_ctx *c) {
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
 static void free_fine(th_ctx *c) {
   void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,   c->d_subs, c->d_nblk, c->d_B,  c->w_r,
                   c->w_v,   c->w_rr,   c->w_y,   c->w_rc,   c->w_uc,   c->w_t, c->w_rc32};
@@ -122,6 +127,7 @@ static void free_fine(th_ctx *c) {
 }
 
 static void free_coarse(th_ctx *c) {
+  free_graphs(c);  // graphs reference the coarse factors and workspaces
   void *ptrs[] = {c->coarse.G, c->coarse.st9};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -130,6 +136,7 @@ static void free_coarse(th_ctx *c) {
 }
 
 static void free_solver(th_ctx *c) {
+  free_graphs(c);  // graphs reference the solver's staging buffers
   if (c->s_buf) (void)hipFree(c->s_buf);
   c->s_buf = nullptr;
   c->s_bytes = 0;
@@ -162,6 +169,7 @@ void th_destroy(th_ctx *ctx) {
   free_coarse(ctx);
   free_fine(ctx);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
 }
 
@@ -211,6 +219,8 @@ th_status th_get_info(const th_ctx *ctx, th_info *info) {
   info->smoother_cfg = ctx->mfma_cfg;
   info->smoother_grid = ctx->mfma_grid;
   info->coarse_lines = ctx->coarse.nblk > 0 ? ctx->coarse.line0[1] - ctx->coarse.line0[0] : 0;
+  info->n_fallback_cells = ctx->n_fallback;
+  info->t_stencil_s = ctx->t_stencil;
   return TH_OK;
 }
 
@@ -382,9 +392,13 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
   ctx->err.clear();
   if (!d) return fail(ctx, TH_EINVAL, "null descriptor");
   if (!ctx->fine_ready) return fail(ctx, TH_ESTATE, "th_setup_fine must succeed first");
-  if (d->scheme != TH_COARSE_QSFEM && d->scheme != TH_COARSE_WEIGHTS)
+  if (d->scheme != TH_COARSE_QSFEM && d->scheme != TH_COARSE_WEIGHTS &&
+      d->scheme != TH_COARSE_PLAINFIT && d->scheme != TH_COARSE_MLP)
     return fail(ctx, TH_EINVAL, "unknown coarse scheme");
   if (d->scheme == TH_COARSE_WEIGHTS && !d->q) return fail(ctx, TH_EINVAL, "q is NULL");
+  if (d->scheme == TH_COARSE_MLP && !d->mlp) return fail(ctx, TH_EINVAL, "mlp is NULL");
+  if (d->scheme == TH_COARSE_MLP && !(d->fallback_tau >= 0.0))
+    return fail(ctx, TH_EINVAL, "fallback_tau must be >= 0");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TH_EHIP, "hipSetDevice failed");
   auto t0 = std::chrono::steady_clock::now();
   free_coarse(ctx);
@@ -393,19 +407,41 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
   const double hc = 1.0 / Nc;
   // per coarse cell: k, eps of the fine cell containing it; weights q
   std::vector<double> qw((size_t)Nc * Nc * 3);
-  for (int cy = 0; cy < Nc; ++cy)
-    for (int cxx = 0; cxx < Nc; ++cxx) {
-      const long long ci = (long long)cy * Nc + cxx;
-      const long long fi = (long long)(cy / c->R) * c->N + cxx / c->R;
-      if (d->scheme == TH_COARSE_QSFEM) {
-        qsfem_weights(hc * c->h_k[fi], &qw[3 * ci]);
-      } else {
-        for (int t = 0; t < 3; ++t) {
-          qw[3 * ci + t] = d->q[3 * ci + t];
-          if (!std::isfinite(qw[3 * ci + t])) return fail(ctx, TH_EINVAL, "non-finite weight q");
+  const auto ts0 = std::chrono::steady_clock::now();
+  c->n_fallback = 0;
+  if (d->scheme == TH_COARSE_PLAINFIT || d->scheme == TH_COARSE_MLP) {
+    // per-cell samples (eta_c = h_c k, p, eps / k^2)
+    std::vector<double> smp((size_t)Nc * Nc * 3);
+    for (int cy = 0; cy < Nc; ++cy)
+      for (int cxx = 0; cxx < Nc; ++cxx) {
+        const long long ci = (long long)cy * Nc + cxx;
+        const long long fi = (long long)(cy / c->R) * c->N + cxx / c->R;
+        const double kk = c->h_k[fi];
+        smp[3 * ci] = hc * kk;
+        smp[3 * ci + 1] = c->P;
+        smp[3 * ci + 2] = c->h_eps[fi] / (kk * kk);
+        if (!(smp[3 * ci] * c->P / 2.0 < M_PI))
+          return fail(ctx, TH_EINVAL, "dispersion fit needs fine k h < pi in every cell");
+      }
+    int rc = coarse_weights(d->scheme, d->mlp, d->fallback_tau, smp.data(), Nc * Nc, qw.data(),
+                            &c->n_fallback);
+    if (rc) return finish(ctx, rc);
+  } else {
+    for (int cy = 0; cy < Nc; ++cy)
+      for (int cxx = 0; cxx < Nc; ++cxx) {
+        const long long ci = (long long)cy * Nc + cxx;
+        const long long fi = (long long)(cy / c->R) * c->N + cxx / c->R;
+        if (d->scheme == TH_COARSE_QSFEM) {
+          qsfem_weights(hc * c->h_k[fi], &qw[3 * ci]);
+        } else {
+          for (int t = 0; t < 3; ++t) {
+            qw[3 * ci + t] = d->q[3 * ci + t];
+            if (!std::isfinite(qw[3 * ci + t])) return fail(ctx, TH_EINVAL, "non-finite weight q");
+          }
         }
       }
-    }
+  }
+  c->t_stencil = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts0).count();
   // 9-point quasi-FE stencil per coarse vertex (eq. element_wise_qsfem with the
   // -i eps Q1 mass and the absorbing Q1 boundary mass)
   std::vector<c64> st((size_t)nc1 * nc1 * 9, c64{0, 0});
@@ -619,6 +655,8 @@ using zc = std::complex<double>;
 struct SolverWS {
   c64 *V, *Z, *partial, *hd, *tmp32a, *tmp32b, *coef, *fx;
   double *scal;
+  c64 *hcol;    // device: one Hessenberg column, (m + 2) x nrhs
+  c64 *hcol_h;  // pinned host copy of it
 };
 
 static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
@@ -626,9 +664,21 @@ static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
   size_t need = (size_t)(m + 1) * vec + (size_t)m * vec;   // V, Z
   need += (size_t)nrhs * 256 * sizeof(c64);                 // partial sums
   need += (size_t)nrhs * sizeof(c64) * 2;                   // dot outputs
-  need += f32 ? 2 * (size_t)nrhs * c->nf * sizeof(c32) : 0;  // precision staging
+  need += 2 * (size_t)nrhs * c->nf * sizeof(c64);          // preconditioner staging
   need += (size_t)nrhs * (m + 1) * sizeof(c64);             // lincomb coefficients
   need += (size_t)nrhs * sizeof(double) * 2;                // scalars
+  need += (size_t)nrhs * (m + 2) * sizeof(c64);             // Hessenberg column
+  const size_t pinned = (size_t)nrhs * (m + 2) * sizeof(c64);
+  if (pinned > c->h_pinned_bytes) {
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    c->h_pinned = nullptr;
+    c->h_pinned_bytes = 0;
+    if (hipHostMalloc(&c->h_pinned, pinned, hipHostMallocDefault) != hipSuccess) {
+      set_error("cannot allocate pinned host memory for the Krylov work space");
+      return TH_ENOMEM;
+    }
+    c->h_pinned_bytes = pinned;
+  }
   need += 4096;
   if (need > c->s_bytes) {
     free_solver(c);
@@ -648,19 +698,62 @@ static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
   w.Z = (c64 *)take((size_t)m * vec);
   w.partial = (c64 *)take((size_t)nrhs * 256 * sizeof(c64));
   w.hd = (c64 *)take((size_t)nrhs * sizeof(c64) * 2);
-  w.tmp32a = f32 ? (c64 *)take((size_t)nrhs * c->nf * sizeof(c32)) : nullptr;
-  w.tmp32b = f32 ? (c64 *)take((size_t)nrhs * c->nf * sizeof(c32)) : nullptr;
+  // staging of the preconditioner input/output (complex64 copies, or FP64
+  // copies at fixed addresses for graph replay)
+  w.tmp32a = (c64 *)take((size_t)nrhs * c->nf * sizeof(c64));
+  w.tmp32b = (c64 *)take((size_t)nrhs * c->nf * sizeof(c64));
+  (void)f32;
   w.coef = (c64 *)take((size_t)nrhs * (m + 1) * sizeof(c64));
   w.scal = (double *)take((size_t)nrhs * sizeof(double) * 2);
+  w.hcol = (c64 *)take((size_t)nrhs * (m + 2) * sizeof(c64));
+  w.hcol_h = (c64 *)c->h_pinned;
   return 0;
 }
 
 // z = TwoGridStep(0, v) in the requested precision; v, z FP64
-static int precond(th_ctx *c, const c64 *v, c64 *z, int nrhs, bool f32, SolverWS &w) {
-  if (!f32) return twogrid_impl(c, z, v, nrhs, false, true);
+// out = TwoGridStep(0, in) replayed from a HIP graph captured on first use for
+// this (nrhs, precision, in, out); the graph holds every kernel of the step.
+static int twogrid_graph(th_ctx *c, void *out, const void *in, int nrhs, bool f32) {
+  for (auto &g : c->graphs)
+    if (g.nrhs == nrhs && g.f32 == f32 && g.in == in && g.out == out) {
+      TH_HIP_CHECK_RET(hipGraphLaunch(g.exec, c->stream));
+      ++c->graph_launches;
+      return 0;
+    }
+  hipGraph_t graph = nullptr;
+  TH_HIP_CHECK_RET(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+  int rc = twogrid_impl(c, out, in, nrhs, f32, true);
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate", __FILE__, __LINE__);
+  c->graphs.push_back({nrhs, f32, in, out, exec});
+  TH_HIP_CHECK_RET(hipGraphLaunch(exec, c->stream));
+  ++c->graph_launches;
+  return 0;
+}
+
+static int precond(th_ctx *c, const c64 *v, c64 *z, int nrhs, bool f32, SolverWS &w,
+                   bool use_graph) {
+  const bool graph = use_graph && c->stream != nullptr && !c->timing;
   const long long n = (long long)nrhs * c->nf;
+  if (!f32) {
+    if (!graph) return twogrid_impl(c, z, v, nrhs, false, true);
+    TH_HIP_CHECK_RET(hipMemcpyAsync(w.tmp32a, v, n * sizeof(c64), hipMemcpyDeviceToDevice, c->stream));
+    int rc = twogrid_graph(c, w.tmp32b, w.tmp32a, nrhs, false);
+    if (rc) return rc;
+    TH_HIP_CHECK_RET(hipMemcpyAsync(z, w.tmp32b, n * sizeof(c64), hipMemcpyDeviceToDevice, c->stream));
+    return 0;
+  }
   int rc = launch_convert(v, w.tmp32a, n, false, true, c->stream);
-  if (!rc) rc = twogrid_impl(c, w.tmp32b, w.tmp32a, nrhs, true, true);
+  if (!rc) rc = graph ? twogrid_graph(c, w.tmp32b, w.tmp32a, nrhs, true)
+                      : twogrid_impl(c, w.tmp32b, w.tmp32a, nrhs, true, true);
   if (!rc) rc = launch_convert(w.tmp32b, z, n, true, false, c->stream);
   return rc;
 }
@@ -751,7 +844,9 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
                                     hipMemcpyHostToDevice, s));
     rc = launch_scale_dev(Vj(0), Vj(0), w.scal, nf, nrhs, nf, nf, s);
     if (rc) return rc;
-    std::vector<std::vector<zc>> H(nrhs, std::vector<zc>((size_t)(m + 1) * m, 0.0));
+    // rotated Hessenberg (upper triangular R) stored by columns as they grow:
+    // H[r][q][i] = R(i, q), i <= q
+    std::vector<std::vector<std::vector<zc>>> H(nrhs);
     std::vector<std::vector<zc>> g(nrhs, std::vector<zc>(m + 1, 0.0)), cs(nrhs, std::vector<zc>(m)),
         sn(nrhs, std::vector<zc>(m));
     std::vector<int> jend(nrhs, 0), active(nrhs);
@@ -766,7 +861,7 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
     int j = 0;
     bool cycle_done = false;
     for (j = 0; j < m && !cycle_done; ++j) {
-      rc = precond(c, Vj(j), Zj(j), nrhs, f32, w);
+      rc = precond(c, Vj(j), Zj(j), nrhs, f32, w, o->use_graph != 0);
       if (rc) return rc;
       nprec += nrhs;
       {
@@ -774,32 +869,36 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
         rc = launch_apply(make_op(c, false), c->ref, Zj(j), nullptr, Vj(j + 1), nrhs, false, 1.0, s);
       }
       if (rc) return rc;
-      // modified Gram-Schmidt
+      // modified Gram-Schmidt: coefficients stay on the device (column j of
+      // the Hessenberg matrix in w.hcol), the new vector is normalised by a
+      // device-computed 1/norm, and one copy brings the column to the host
       std::vector<std::vector<zc>> hcol(nrhs, std::vector<zc>(j + 2, 0.0));
-      std::vector<c64> hh((size_t)nrhs * (j + 1));
-      for (int i = 0; i <= j; ++i) {
-        {
-          KTimer kt(c, TH_KT_KRYLOV);
-          rc = launch_dot(Vj(i), Vj(j + 1), nf, nrhs, nf, nf, w.hd, w.partial, s);
-          if (!rc) rc = launch_axpy_dev(Vj(j + 1), Vj(i), w.hd, -1.0, nf, nrhs, nf, nf, s);
+      {
+        KTimer kt(c, TH_KT_KRYLOV);
+        for (int i = 0; i <= j && rc == 0; ++i) {
+          rc = launch_dot(Vj(i), Vj(j + 1), nf, nrhs, nf, nf, w.hcol + (size_t)i * nrhs,
+                          w.partial, s);
+          if (!rc)
+            rc = launch_axpy_dev(Vj(j + 1), Vj(i), w.hcol + (size_t)i * nrhs, -1.0, nf, nrhs, nf,
+                                 nf, s);
         }
-        if (rc) return rc;
-        TH_HIP_CHECK_RET(hipMemcpyAsync(hh.data() + (size_t)i * nrhs, w.hd, nrhs * sizeof(c64),
-                                        hipMemcpyDeviceToHost, s));
+        if (!rc)
+          rc = launch_dot(Vj(j + 1), Vj(j + 1), nf, nrhs, nf, nf, w.hcol + (size_t)(j + 1) * nrhs,
+                          w.partial, s);
+        if (!rc) rc = launch_inv_norm(w.hcol + (size_t)(j + 1) * nrhs, w.scal, nrhs, s);
+        if (!rc) rc = launch_scale_dev(Vj(j + 1), Vj(j + 1), w.scal, nf, nrhs, nf, nf, s);
       }
-      std::vector<zc> ww;
-      rc = dot_to_host(c, Vj(j + 1), Vj(j + 1), nrhs, w, ww);  // synchronises
       if (rc) return rc;
+      TH_HIP_CHECK_RET(hipMemcpyAsync(w.hcol_h, w.hcol, (size_t)(j + 2) * nrhs * sizeof(c64),
+                                      hipMemcpyDeviceToHost, s));
+      TH_HIP_CHECK_RET(hipStreamSynchronize(s));
       for (int r = 0; r < nrhs; ++r) {
-        for (int i = 0; i <= j; ++i) hcol[r][i] = zc(hh[(size_t)i * nrhs + r].re, hh[(size_t)i * nrhs + r].im);
-        const double hn = std::sqrt(std::max(ww[r].real(), 0.0));
-        hcol[r][j + 1] = hn;
-        hscal[r] = (hn > 0.0 && std::isfinite(hn)) ? 1.0 / hn : 0.0;
+        for (int i = 0; i <= j; ++i) {
+          const c64 v = w.hcol_h[(size_t)i * nrhs + r];
+          hcol[r][i] = zc(v.re, v.im);
+        }
+        hcol[r][j + 1] = std::sqrt(std::max(w.hcol_h[(size_t)(j + 1) * nrhs + r].re, 0.0));
       }
-      TH_HIP_CHECK_RET(hipMemcpyAsync(w.scal, hscal.data(), nrhs * sizeof(double),
-                                      hipMemcpyHostToDevice, s));
-      rc = launch_scale_dev(Vj(j + 1), Vj(j + 1), w.scal, nf, nrhs, nf, nf, s);
-      if (rc) return rc;
       ++total;
       bool all_done = true;
       for (int r = 0; r < nrhs; ++r) {
@@ -821,7 +920,7 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
         h[j + 1] = 0.0;
         g[r][j + 1] = -std::conj(sn[r][j]) * g[r][j];
         g[r][j] = cs[r][j] * g[r][j];
-        for (int i = 0; i <= j; ++i) H[r][(size_t)i * m + j] = h[i];
+        H[r].emplace_back(h.begin(), h.begin() + j + 1);
         jend[r] = j + 1;
         it_r[r] = total;
         const double rel = std::abs(g[r][j + 1]) / fnorm[r];
@@ -841,8 +940,8 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
       std::vector<zc> y(je, 0.0);
       for (int i = je - 1; i >= 0; --i) {
         zc acc = g[r][i];
-        for (int q = i + 1; q < je; ++q) acc -= H[r][(size_t)i * m + q] * y[q];
-        y[i] = acc / H[r][(size_t)i * m + i];
+        for (int q = i + 1; q < je; ++q) acc -= H[r][q][i] * y[q];
+        y[i] = acc / H[r][i][i];
       }
       for (int i = 0; i < je; ++i) coef[(size_t)r * m + i] = c64{y[i].real(), y[i].imag()};
     }
@@ -909,7 +1008,7 @@ static int solve_stationary(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_
   while (it < o->maxit) {
     // u <- u + B (f - A u)  (= TwoGridStep(u, f) for the linear two-grid map)
     rc = launch_apply(make_op(c, false), c->ref, u, f, w.V, nrhs, false, -1.0, s);
-    if (!rc) rc = precond(c, w.V, w.Z, nrhs, f32, w);
+    if (!rc) rc = precond(c, w.V, w.Z, nrhs, f32, w, o->use_graph != 0);
     if (rc) return rc;
     c64 one = {1.0, 0.0};
     std::vector<c64> ones(nrhs, one);

@@ -91,8 +91,22 @@ struct th_ctx {
   // solver workspaces (allocated lazily by th_solve)
   void *s_buf = nullptr;
   size_t s_bytes = 0;
+  void *h_pinned = nullptr;    // pinned host staging of the Hessenberg column
+  size_t h_pinned_bytes = 0;
 
-  double t_setup_fine = 0, t_setup_coarse = 0;
+  // captured preconditioner graphs: (nrhs, f32, input, output) -> executable
+  struct PrecGraph {
+    int nrhs;
+    bool f32;
+    const void *in;
+    void *out;
+    hipGraphExec_t exec;
+  };
+  std::vector<PrecGraph> graphs;
+  long long graph_launches = 0;
+
+  double t_setup_fine = 0, t_setup_coarse = 0, t_stencil = 0;
+  int n_fallback = 0;
 
   // matrix-core smoother tunables (chosen by the setup autotuner)
   int mfma_cfg = 0, mfma_grid = 0;
@@ -155,6 +169,10 @@ int launch_dd_mfma(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, 
 // autotune.cpp
 int autotune_mfma(th_ctx *c);
 
+// mlp_api.cpp
+int coarse_weights(int scheme, const th_mlp *m, double tau, const double *samples, int n,
+                   double *q_out, int *n_fallback);
+
 // k_coarse.hip
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);
 int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s);
@@ -172,6 +190,7 @@ int launch_scale_dev(c64 *y, const c64 *x, const double *inv_norm, long long n, 
 int launch_lincomb(c64 *x, const c64 *Z, const c64 *coef, int mcount, int cstride, long long n,
                    int nrhs, long long ldz_j, long long ldz_r, hipStream_t s);
 int launch_add(void *u, const void *v, long long n_complex, bool f32, hipStream_t s);
+int launch_inv_norm(const c64 *dots, double *inv, int n, hipStream_t s);
 int launch_nan_check(const c64 *x, long long n, int *flag, hipStream_t s);
 
 }  // namespace th

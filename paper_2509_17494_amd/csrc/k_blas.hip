@@ -171,6 +171,22 @@ int launch_add(void *u, const void *v, long long n_complex, bool f32, hipStream_
   return 0;
 }
 
+// inv[r] = 1 / sqrt(Re dots[r]) (0 when the norm is zero or not finite)
+__global__ void k_inv_norm(const c64 *__restrict__ dots, double *__restrict__ inv, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) {
+    const double v = dots[r].re;
+    const double nrm = sqrt(v > 0.0 ? v : 0.0);
+    inv[r] = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+  }
+}
+
+int launch_inv_norm(const c64 *dots, double *inv, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_inv_norm, dim3(ceil_div(n, 64)), dim3(64), 0, s, dots, inv, n);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
 // flag = 1 if any entry is not finite
 __global__ __launch_bounds__(256) void k_nan_check(const c64 *__restrict__ x, long long n,
                                                    int *flag) {

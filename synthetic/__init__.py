@@ -132,6 +132,31 @@ def gaussian_load(n_cells: int, p: int, centres, sigma: float,
     return out
 
 
+def mlp_samples(n: int, seed: int = 1, orders=(2, 4, 6, 8), eta_min: float = 0.3,
+                eta_max: float = 2.1, shift_max: float = 0.05) -> np.ndarray:
+    """Training inputs of the coarse-stencil surrogate: rows (eta_c, p, shift)
+    with p uniform over `orders`, eta_c uniform on [eta_min, min(eta_max,
+    0.95 * 2 pi / p)] (fine k h below 0.95 pi) and shift uniform on
+    [0, shift_max]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = rng.choice(np.asarray(orders, dtype=np.float64), size=n)
+    hi = np.minimum(eta_max, 0.95 * 2.0 * math.pi / p)
+    eta = eta_min + (hi - eta_min) * rng.random(n)
+    shift = shift_max * rng.random(n)
+    return np.ascontiguousarray(np.stack([eta, p, shift], axis=1))
+
+
+def mlp_init(seed: int = 2, n_in: int = 3, width: int = 64, n_out: int = 2) -> np.ndarray:
+    """Initial weights (float32, layout W1, b1, W2, b2, W3, b3): normal with
+    standard deviation sqrt(1 / fan_in) for the matrices, zero biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fan_in, fan_out in [(n_in, width), (width, width), (width, n_out)]:
+        parts.append(rng.standard_normal(fan_out * fan_in) * math.sqrt(1.0 / fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def random_complex(shape, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)

@@ -247,3 +247,27 @@ def test_solve_c3_mixed_batched():
     assert st.status == 0
     assert st.rel_res <= 1e-6
     assert max(errs) <= 1e-5
+
+
+@pytest.mark.parametrize("precond,gemm", [("c128", "f64"), ("c64", "bf16")])
+def test_graph_replay_matches_eager(precond, gemm):
+    """The preconditioner captured in a HIP graph (replayed once per GMRES
+    iteration, with the eager Krylov kernels and host synchronisations in
+    between) gives bitwise the eager result, solve after solve."""
+    cfg = syn.config("C1")
+    p, N = cfg["p"], cfg["n"]
+    f = syn.gaussian_load(N, p, syn.gaussian_centres_grid(2, 2), cfg["sigma"])
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = make_solver(cfg["k"], p, cfg["l_dd"], max_rhs=4, gemm=gemm)
+        fd = to_dev(f)
+        u_e, st_e = s.solve(fd, precond=precond, graph=False)
+        ref = to_np(u_e)
+        for rep in range(3):
+            u_g, st_g = s.solve(fd, precond=precond, graph=True)
+            got = to_np(u_g)
+            print(f"{precond}/{gemm} replay {rep}: iters {st_g.iters} vs {st_e.iters}, "
+                  f"max |diff| {np.max(np.abs(got - ref)):.1e}", flush=True)
+            assert st_g.iters == st_e.iters
+            assert np.array_equal(got, ref)
+    torch.cuda.synchronize()
