@@ -79,3 +79,120 @@ def toy_rho(k, h, D, alpha_s, n_theta=4001, **kw):
     th = np.linspace(-math.pi / 2, math.pi / 2, n_theta, endpoint=False)
     return max(np.max(np.abs(np.linalg.eigvals(toy_two_grid_symbol(t, k, h, D, alpha_s, **kw))))
                for t in th)
+
+
+# ---------------------------------------------------------------------------
+# Bloch-wave LFA of the finite-element two-grid method (Sec. 6.1)
+#
+# Operators on the N x N periodic mesh (constant k, eps = D k^2 / pi): fine A,
+# shifted A_s (exact smoother S = I - A_s^{-1} A), coarse QSFEM quasi-FE A_c on
+# the periodic coarse mesh of spacing 2h/p, interpolation I_P and restriction
+# I_P^T.  Their symbols use eq. symbol_sum, sigma(P)(theta) = sum_beta
+# e^{i theta . beta} P_{0,beta}, with the unit cell of p^2 fine and (p/2)^2
+# coarse dofs; S^ = I - A_s^-1 A^, K^ = I - omega_c I_P^ A_c^-1 I_P^H A^,
+# M^ = S^{n_s} K^ S^{n_s}.  Reading: the printed K^ omits omega_c, which
+# Fig. 4 varies; it is included.
+
+def periodic_fine_matrix(p, N, kappa):
+    """Periodic Q_p matrix (h = 1/N) of int grad.grad - kappa int u v."""
+    from .fem import element_matrices
+    h = 1.0 / N
+    S, M = element_matrices(p, h, 2)
+    Ae = S - kappa * M
+    n1 = N * p
+    A = np.zeros((n1 * n1, n1 * n1), dtype=complex)
+    for cy in range(N):
+        for cx in range(N):
+            nodes = [((cy * p + ay) % n1) * n1 + (cx * p + ax) % n1
+                     for ay in range(p + 1) for ax in range(p + 1)]
+            A[np.ix_(nodes, nodes)] += Ae
+    return A
+
+
+def periodic_coarse_matrix(p, N, k, eps):
+    """Periodic quasi-FE QSFEM matrix on the coarse mesh (spacing 2h/p)."""
+    from .qsfem import cell_q_matrix, q_weights
+    r = p // 2
+    Nc = N * r
+    hc = 1.0 / Nc
+    q0, qe, qd = q_weights(hc * k)
+    m1 = np.array([[1 / 3, 1 / 6], [1 / 6, 1 / 3]])
+    E = cell_q_matrix(q0, qe, qd).astype(complex) - 1j * eps * np.kron(m1, m1) * hc * hc
+    A = np.zeros((Nc * Nc, Nc * Nc), dtype=complex)
+    for cy in range(Nc):
+        for cx in range(Nc):
+            nodes = [((cy + ay) % Nc) * Nc + (cx + ax) % Nc for ay in (0, 1) for ax in (0, 1)]
+            A[np.ix_(nodes, nodes)] += E
+    return A
+
+
+def periodic_prolongation(p, N):
+    from .fem import gll, lagrange
+    r = p // 2
+    xf, _ = gll(p)
+    L, _ = lagrange(np.linspace(0, 1, r + 1), xf)
+    n1, nc = N * p, N * r
+    P1 = np.zeros((n1, nc))
+    for c in range(N):
+        for a in range(p):  # node c p + a (a = p belongs to the next cell)
+            for b in range(r + 1):
+                P1[c * p + a, (c * r + b) % nc] = L[a, b]
+    return np.kron(P1, P1)
+
+
+def _lattice(n1, per_cell):
+    idx = np.arange(n1 * n1)
+    ix, iy = idx % n1, idx // n1
+    return ix // per_cell, iy // per_cell, (iy % per_cell) * per_cell + ix % per_cell
+
+
+def symbol_of(P, N, rows_per, cols_per, theta):
+    """sigma(P)(theta) from a periodic matrix: rows = dofs of the unit cell at
+    the origin, phases of the minimal-image lattice offsets of the columns."""
+    nr, nc = N * rows_per, N * cols_per
+    ax_r, ay_r, j_r = _lattice(nr, rows_per)
+    ax_c, ay_c, j_c = _lattice(nc, cols_per)
+    out = np.zeros((rows_per * rows_per, cols_per * cols_per), dtype=complex)
+    origin = np.nonzero((ax_r == 0) & (ay_r == 0))[0]
+    bx = ((ax_c + N // 2) % N) - N // 2
+    by = ((ay_c + N // 2) % N) - N // 2
+    ph = np.exp(1j * (theta[0] * bx + theta[1] * by))
+    for row in origin:
+        np.add.at(out[j_r[row]], j_c, P[row] * ph)
+    return out
+
+
+class BlochTwoGrid:
+    """Symbols and the periodic brute-force operators of the two-grid cycle."""
+
+    def __init__(self, p, N, kh, D=0.01, alpha_s=0.2, n_s=1, omega_c=1.0):
+        self.p, self.N, self.n_s, self.omega_c = p, N, n_s, omega_c
+        k = kh * N  # h = 1 / N
+        eps = k * k * D / math.pi
+        self.A = periodic_fine_matrix(p, N, k * k + 1j * eps)
+        self.As = periodic_fine_matrix(p, N, k * k * (1 + 1j * alpha_s) + 1j * eps)
+        self.Ac = periodic_coarse_matrix(p, N, k, eps)
+        self.IP = periodic_prolongation(p, N)
+
+    def brute_force(self):
+        n = self.A.shape[0]
+        S = np.eye(n) - np.linalg.solve(self.As, self.A)
+        K = np.eye(n) - self.omega_c * self.IP @ np.linalg.solve(self.Ac, self.IP.T @ self.A)
+        Sn = np.linalg.matrix_power(S, self.n_s)
+        return Sn @ K @ Sn
+
+    def symbol(self, theta):
+        p, N, r = self.p, self.N, self.p // 2
+        Ah = symbol_of(self.A, N, p, p, theta)
+        Ash = symbol_of(self.As, N, p, p, theta)
+        Ach = symbol_of(self.Ac, N, r, r, theta)
+        IPh = symbol_of(self.IP, N, p, r, theta)
+        n = p * p
+        S = np.eye(n) - np.linalg.solve(Ash, Ah)
+        K = np.eye(n) - self.omega_c * IPh @ np.linalg.solve(Ach, IPh.conj().T @ Ah)
+        Sn = np.linalg.matrix_power(S, self.n_s)
+        return Sn @ K @ Sn
+
+    def rho(self, n_theta=32):
+        ts = np.linspace(-math.pi, math.pi, n_theta, endpoint=False)
+        return max(np.max(np.abs(np.linalg.eigvals(self.symbol((a, b))))) for a in ts for b in ts)

@@ -113,3 +113,32 @@ def test_adam_first_step_is_lr_times_sign():
 def test_target_transform_round_trip():
     e = np.array([-1e-3, -4e-7, -2e-12])
     assert np.allclose(mlp.errors_from_targets(mlp.targets_from_errors(e)), e, rtol=1e-12)
+
+
+# ------------------------------------------------- Bloch LFA of the two-grid --
+@pytest.mark.parametrize("p,N", [(2, 4), (4, 3)])
+def test_two_grid_symbols_match_periodic_brute_force(p, N):
+    """eig(M) on the periodic mesh = union over theta in (2 pi / N) Z^2 of
+    eig(M^(theta)) (Sec. 6.1: the symbols block-diagonalise the cycle)."""
+    from oracle.lfa import BlochTwoGrid
+    lfa = BlochTwoGrid(p, N, kh=2 * math.pi * p / 10 * 1.0, D=0.01, alpha_s=0.2)
+    ev = np.linalg.eigvals(lfa.brute_force())
+    sym = np.concatenate([np.linalg.eigvals(lfa.symbol((2 * math.pi * jx / N, 2 * math.pi * jy / N)))
+                          for jy in range(N) for jx in range(N)])
+    # match every brute-force eigenvalue to a distinct symbol eigenvalue
+    used = np.zeros(len(sym), dtype=bool)
+    for z in ev:
+        d_ = np.abs(sym - z) + used * 1e9
+        i = int(np.argmin(d_))
+        assert d_[i] < 1e-8 * max(1.0, abs(z)), (z, sym[i])
+        used[i] = True
+
+
+def test_lfa_convergence_factor_p4_at_10_dof_per_wavelength():
+    """Sec. 6.3: for order 4 the method converges above 8 DOF per wavelength
+    (alpha_s = 0.2, D = 0.01, n_s = 1, omega_c = 1)."""
+    from oracle.lfa import BlochTwoGrid
+    lfa = BlochTwoGrid(4, 5, kh=2 * math.pi * 4 / 10, D=0.01, alpha_s=0.2)
+    rho = lfa.rho(24)
+    print("rho p=4, 10 DOF/wavelength:", rho)
+    assert rho < 1.0
