@@ -20,6 +20,7 @@ import scipy.sparse.linalg as spla
 
 from .fem import helmholtz_matrix
 from .qsfem import coarse_cell_values, coarse_matrix
+from .qsfem3d import coarse_matrix_3d
 from .smoother import CSDDSmoother
 from .transfer import prolongation
 
@@ -41,7 +42,10 @@ class TwoGrid:
         self.I_P = prolongation(self.N, p, self.dim)
         kc = coarse_cell_values(k, p)
         epsc = coarse_cell_values(eps, p)
-        self.A_c = coarse_matrix(kc, epsc, robin, q=coarse_q)
+        if self.dim == 3:
+            self.A_c = coarse_matrix_3d(kc, epsc, robin, q=coarse_q)
+        else:
+            self.A_c = coarse_matrix(kc, epsc, robin, q=coarse_q)
         self.coarse_lu = spla.splu(self.A_c.tocsc())
         self.n_s = n_s
         self.omega_c = omega_c
