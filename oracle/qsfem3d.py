@@ -14,11 +14,22 @@ distribution follows Sec. 3.3: a vertex pair of one coarse cell gets N P0 / 8
 (same vertex), N P1 / 4 (edge), N P2 / 2 (face diagonal), N P3 (body
 diagonal).  Parity of this stencil is unpinned beyond its defining zeros, the
 consistency limit and the assembly invariants.
+
+Plain fit in 3-D (project definition, as the 2-D plain fit): the zeros are put
+at the fine Q_p discrete wave vectors along the same three directions, found
+from the p^3 x p^3 Bloch symbol of the fine element (Sec. 6.1 in three
+dimensions) by a sign change of its eigenvalue nearest to zero and Brent's
+method, as in the 2-D oracle.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import scipy.sparse as sp
+from scipy.optimize import brentq
+
+from .fem import ref_matrices
 
 DIRS = np.array([[1.0, 0.2, 0.1], [1.0, 0.6, 0.3], [1.0, 0.9, 0.7]])
 DIRS = DIRS / np.linalg.norm(DIRS, axis=1)[:, None]
@@ -87,3 +98,49 @@ def coarse_matrix_3d(kc: np.ndarray, epsc=None, robin=None, q=None) -> sp.csr_ma
                       shape=(n, n)).tocsr()
     A.sum_duplicates()
     return A
+
+
+def bloch_symbol_3d(p: int, kh: float, theta) -> np.ndarray:
+    """A^(theta) on the unit cell of the 3-D Q_p space (h = 1): element matrix
+    K M M + M K M + M M K - (kh)^2 M M M (kron order z, y, x), element node
+    (az, ay, ax) -> cell dof (a mod p) with lattice shift (a // p)."""
+    K1, M1 = ref_matrices(p)
+    kr = lambda a, b, c: np.kron(a, np.kron(b, c))
+    Ae = kr(K1, M1, M1) + kr(M1, K1, M1) + kr(M1, M1, K1) - kh * kh * kr(M1, M1, M1)
+    n = p ** 3
+    loc = [(az, ay, ax) for az in range(p + 1) for ay in range(p + 1) for ax in range(p + 1)]
+    dof = np.array([((az % p) * p + ay % p) * p + ax % p for az, ay, ax in loc])
+    shift = np.array([[ax // p, ay // p, az // p] for az, ay, ax in loc], dtype=float)
+    ph = np.exp(1j * shift @ np.asarray(theta, dtype=float))
+    S = np.zeros((n, n), dtype=complex)
+    np.add.at(S, (dof[:, None], dof[None, :]), Ae * np.conj(ph)[:, None] * ph[None, :])
+    return S
+
+
+def _nearest_zero_eig_3d(p, kh, r, d):
+    ev = np.linalg.eigvalsh(bloch_symbol_3d(p, kh, r * np.asarray(d)))
+    return ev[np.argmin(np.abs(ev))]
+
+
+def fine_radius_3d(p: int, kh: float, d, rel_window: float = 0.08, samples: int = 9) -> float:
+    """Radius r (units of 1/h) of the fine discrete dispersion surface along d."""
+    if not kh < math.pi:
+        raise ValueError("only kh < pi is supported")
+    rs = np.linspace(kh * (1 - rel_window), kh * (1 + rel_window), samples)
+    vals = [_nearest_zero_eig_3d(p, kh, r, d) for r in rs]
+    for i in range(samples - 1):
+        if vals[i] == 0.0:
+            return float(rs[i])
+        if vals[i] * vals[i + 1] < 0:
+            return brentq(lambda r: _nearest_zero_eig_3d(p, kh, r, d), rs[i], rs[i + 1],
+                          xtol=1e-15, rtol=1e-15, maxiter=200)
+    raise RuntimeError("no sign change of the symbol near r = kh")
+
+
+def plain_fit_3d(eta_c: float, p: int, shift: float = 0.0):
+    """(q0, q_face, q_edge, q_corner) matched to the fine dispersion of one
+    coarse cell (eta_c = h_c k, h_c = 2h/p; shift = eps / k^2 as in 2-D)."""
+    eta = float(((1.0 + 1j * shift) ** 0.5).real * eta_c)
+    kh = eta * p / 2.0
+    radii = [fine_radius_3d(p, kh, DIRS[m]) * 2.0 / p for m in range(3)]
+    return q_weights(eta, radii)

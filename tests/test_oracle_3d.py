@@ -191,3 +191,69 @@ def test_3d_twogrid_fixed_point():
     f = syn.random_complex(tg.A.shape[0], seed=10)
     x = spla.spsolve(tg.A.tocsc(), f)
     assert np.linalg.norm(tg.twogrid_step(x, f) - x) / np.linalg.norm(x) < 1e-11
+
+
+# ------------------------------------------------ fine dispersion in 3-D ----
+@pytest.mark.parametrize("p,N", [(1, 3), (2, 2)])
+def test_3d_bloch_symbol_by_periodic_brute_force(p, N):
+    """eig of the assembled periodic 3-D FE matrix = union over
+    theta in (2 pi / N) Z^3 of eig(A^(theta))."""
+    kh = 0.7
+    K1, M1 = fem.ref_matrices(p)
+    kr = lambda a, b, c: np.kron(a, np.kron(b, c))
+    Ae = kr(K1, M1, M1) + kr(M1, K1, M1) + kr(M1, M1, K1) - kh * kh * kr(M1, M1, M1)
+    n1 = N * p
+    A = np.zeros((n1 ** 3, n1 ** 3))
+    for cz in range(N):
+        for cy in range(N):
+            for cx in range(N):
+                nodes = [(((cz * p + az) % n1) * n1 + (cy * p + ay) % n1) * n1 + (cx * p + ax) % n1
+                         for az in range(p + 1) for ay in range(p + 1) for ax in range(p + 1)]
+                A[np.ix_(nodes, nodes)] += Ae
+    ev = np.sort(np.linalg.eigvalsh(A))
+    sym = []
+    for j in np.ndindex(N, N, N):
+        sym.extend(np.linalg.eigvalsh(qsfem3d.bloch_symbol_3d(p, kh, 2 * math.pi * np.array(j) / N)))
+    assert np.allclose(ev, np.sort(sym), atol=1e-11)
+
+
+def test_3d_fine_radius_p1_is_the_trilinear_closed_form():
+    kh = 0.8
+    d = qsfem3d.DIRS[1]
+    r = qsfem3d.fine_radius_3d(1, kh, d)
+    c = np.cos(r * d)
+    s_ = (2 - 2 * c) * 1.0
+    m = (2 + c) / 3
+    sigma = s_[0] * m[1] * m[2] + m[0] * s_[1] * m[2] + m[0] * m[1] * s_[2] - kh ** 2 * m.prod()
+    assert abs(sigma) < 1e-13
+
+
+def test_3d_fine_radius_converges_to_k_with_order():
+    kh = 2 * math.pi * 4 / 10
+    d = qsfem3d.DIRS[2]
+    errs = [abs(qsfem3d.fine_radius_3d(p, kh * p / 4, d) / (kh * p / 4) - 1) for p in (2, 4)]
+    assert errs[1] < errs[0] * 1e-1
+
+
+def test_3d_plain_fit_tracks_the_fine_dispersion_better_than_the_exact_k_stencil():
+    eta, p = 0.9, 2
+    kh = eta * p / 2
+    qf = qsfem3d.plain_fit_3d(eta, p)
+    qe = qsfem3d.q_weights(eta)
+    rng = np.random.default_rng(4)
+    dirs = np.abs(rng.standard_normal((12, 3)))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+
+    def P_of(q):
+        N = q[0]  # q0 = N P0 / 8 = N
+        return 8.0, 4 * q[1] / N, 2 * q[2] / N, q[3] / N
+
+    def mismatch(q):
+        P = P_of(q)
+        out = 0.0
+        for d in dirs:
+            zc = _radius(lambda r: qsfem3d.symbol(P, r * d), eta)
+            zf = qsfem3d.fine_radius_3d(p, kh, d) * 2 / p
+            out = max(out, abs(zc - zf) / eta)
+        return out
+    assert mismatch(qf) < mismatch(qe) / 5, (mismatch(qf), mismatch(qe))
