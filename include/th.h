@@ -59,10 +59,14 @@ typedef enum { TH_C128 = 0, TH_C64 = 1 } th_dtype;
 typedef enum { TH_GEMM_F64 = 0, TH_GEMM_F32 = 1, TH_GEMM_BF16 = 2 } th_gemm;
 
 typedef enum {
-  TH_COARSE_QSFEM = 0,    /* per-cell QSFEM weights q(h_c k(c)), Sec. 3.3 */
-  TH_COARSE_WEIGHTS = 1,  /* caller-supplied per-coarse-cell (q0, q_edge, q_diag) */
-  TH_COARSE_PLAINFIT = 2, /* per-cell plain dispersion-matching fit (see th_plain_fit) */
-  TH_COARSE_MLP = 3       /* per-cell surrogate network with fallback to the plain fit */
+  TH_COARSE_QSFEM = 0,    /* per-cell QSFEM weights q(h_c k(c)), Sec. 3.3; in 3-D the
+                             27-point stencil exact at k (see th_plain_fit3d) */
+  TH_COARSE_WEIGHTS = 1,  /* caller-supplied per-coarse-cell (q0, q_edge, q_diag), or
+                             (q0, q_face, q_edge, q_corner) in 3-D */
+  TH_COARSE_PLAINFIT = 2, /* per-cell plain dispersion-matching fit (th_plain_fit, or
+                             th_plain_fit3d in 3-D) */
+  TH_COARSE_MLP = 3       /* per-cell surrogate network with fallback to the plain fit
+                             (2-D only) */
 } th_coarse_scheme;
 
 typedef struct th_mlp th_mlp;
@@ -74,7 +78,7 @@ typedef enum {
 
 /* Fine-level problem and smoother parameters (Sec. 2, 3.1, 4.1, 4.4). */
 typedef struct {
-  int dim;              /* 2 (3 is reserved: TH_EUNSUPPORTED) */
+  int dim;              /* 2 or 3 (3-D: orders 2 and 4) */
   int n;                /* cells per direction N >= 1 */
   int order;            /* p in {2, 4, 6, 8} */
   const double *k;      /* HOST, N^d per-cell wavenumbers > 0, x fastest; copied */
@@ -91,7 +95,8 @@ typedef struct {
 
 typedef struct {
   th_coarse_scheme scheme;
-  const double *q;      /* HOST, (pN/2)^d x 3 weights, x fastest; TH_COARSE_WEIGHTS only */
+  const double *q;      /* HOST, (pN/2)^d x 3 (2-D) or x 4 (3-D) weights, x fastest;
+                           TH_COARSE_WEIGHTS only */
   const th_mlp *mlp;    /* trained surrogate; TH_COARSE_MLP only */
   double fallback_tau;  /* TH_COARSE_MLP: a cell falls back to the plain fit when the
                            network's dispersion errors differ from the fine ones by more
@@ -126,7 +131,7 @@ typedef struct {
   double t_setup_fine_s, t_setup_coarse_s;
   int smoother_cfg;       /* matrix-core smoother configuration chosen by the autotuner */
   int smoother_grid;      /* its persistent grid size (0: one workgroup per work item) */
-  int coarse_lines;       /* grid lines per coarse super-block */
+  int coarse_lines;       /* grid lines (2-D) or planes (3-D) per coarse super-block */
   int n_fallback_cells;   /* TH_COARSE_MLP: coarse cells that fell back to the plain fit */
   double t_stencil_s;     /* time spent computing the per-cell coarse weights */
 } th_info;
@@ -143,14 +148,16 @@ th_status th_get_info(const th_ctx *ctx, th_info *info);
  * and for every subdomain the dense operator B_i = diag(1/L_j) R_{U_i}
  * (A_s^(i))^{-1} (n_U x n_Omega), computed on the device in FP64 and stored
  * in desc->gemm precision.  Blocking.  Errors: TH_EINVAL (odd order, n < 1,
- * k <= 0 or NaN, l_dd < 1), TH_EUNSUPPORTED (dim 3), TH_ENOMEM, TH_ENUMERIC
- * (zero pivot). */
+ * k <= 0 or NaN, l_dd < 1, dim not 2 or 3), TH_EUNSUPPORTED (3-D order above
+ * 4), TH_ENOMEM, TH_ENUMERIC (zero pivot). */
 th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *desc);
 
-/* Build the coarse QSFEM quasi-FE matrix (Sec. 3.3, eq. element_wise_qsfem)
- * on the coarse vertex grid and factorise it once in FP64 on the device
- * (block-tridiagonal elimination over grid lines with explicit inverses of
- * the diagonal Schur blocks).  Needs th_setup_fine.  Blocking. */
+/* Build the coarse QSFEM quasi-FE matrix (Sec. 3.3, eq. element_wise_qsfem;
+ * 27-point in 3-D) on the coarse vertex grid and factorise it once in FP64 on
+ * the device (block-tridiagonal elimination over grid lines, or planes in
+ * 3-D, with explicit inverses of the diagonal Schur blocks).  Needs
+ * th_setup_fine.  Blocking.  Errors: TH_EINVAL, TH_EUNSUPPORTED (surrogate
+ * scheme in 3-D), TH_ENOMEM, TH_ENUMERIC. */
 th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *desc);
 
 /* r = f - A u (fine Galerkin matrix, eq. bilin_form).  Stream-ordered. */
@@ -215,6 +222,16 @@ th_status th_timing_get(th_ctx *ctx, int kernel_class, double *total_ms, long lo
  * at 0 is -eta^2.  Valid for kh = eta_c p / 2 < pi.  Host computation.
  *   samples: HOST n x 3; e_out: HOST n x 2 or NULL; q_out: HOST n x 3 or NULL. */
 th_status th_plain_fit(const double *samples, int n, double *e_out, double *q_out);
+
+/* 3-D analogue (project definition; the paper treats 2-D): the compact
+ * 27-point family with classes centre P0 = 8, face P1, edge P2, corner P3,
+ *   sigma(xi) = P0 + 2 P1 sum c_i + 4 P2 sum_{i<j} c_i c_j + 8 P3 c_1 c_2 c_3,
+ * c_i = cos(h_c xi_i), whose zero set passes through the fine Q_p discrete
+ * wave vectors along the normalised directions (1, .2, .1), (1, .6, .3),
+ * (1, .9, .7), scaled so that sigma(0) = -eta^2; quasi-FE weights
+ * (q0, q_face, q_edge, q_corner) = N (P0 / 8, P1 / 4, P2 / 2, P3).
+ *   samples: HOST n x 3; e_out: HOST n x 3 or NULL; q_out: HOST n x 4 or NULL. */
+th_status th_plain_fit3d(const double *samples, int n, double *e_out, double *q_out);
 
 /* Surrogate network 3 -> 64 -> 64 -> 2 (SiLU), inputs standardised samples,
  * outputs standardised log(max(-e_m, 0) + 1e-13); FP32 master weights with a

@@ -21,7 +21,8 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["TwoGridSolver", "THError", "SolveStats", "load_library", "CoarseStencilMLP", "plain_fit"]
+__all__ = ["TwoGridSolver", "THError", "SolveStats", "load_library", "CoarseStencilMLP", "plain_fit",
+           "plain_fit3d"]
 
 
 class THError(RuntimeError):
@@ -56,15 +57,16 @@ def _dt(t: torch.Tensor) -> int:
 
 
 class TwoGridSolver:
-    """One fine problem (2-D unit square, N x N cells, order p) on one GPU.
+    """One fine problem (unit square or cube, N^d cells, order p) on one GPU.
 
-    k, eps: per-cell arrays of shape (N, N) indexed [y][x] (host, float64).
+    k, eps: per-cell arrays of shape (N, N) indexed [y][x], or (N, N, N)
+    indexed [z][y][x] (host, float64); bc lists the sides x-, x+, y-, y+(, z-, z+).
     Vectors are torch tensors on the solver's device of shape (nrhs, ndof)
     (or (ndof,) for one right-hand side), complex128 or complex64, contiguous.
     """
 
     def __init__(self, k, eps=None, order: int = 2, alpha_s: float = 0.5, l_dd: int = 8,
-                 n_dd: int = 1, n_s: int = 1, omega_c: float = 1.0, bc=("robin",) * 4,
+                 n_dd: int = 1, n_s: int = 1, omega_c: float = 1.0, bc=None,
                  gemm: str = "f64", max_rhs: int = 1, device: int | None = None,
                  coarse: str | None = "qsfem", coarse_q=None):
         self._lib = L.load()
@@ -72,15 +74,19 @@ class TwoGridSolver:
             raise RuntimeError("a HIP device is required")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         k = np.ascontiguousarray(np.asarray(k, dtype=np.float64))
-        if k.ndim != 2 or k.shape[0] != k.shape[1]:
-            raise ValueError("k must have shape (N, N)")
+        if k.ndim not in (2, 3) or len(set(k.shape)) != 1:
+            raise ValueError("k must have shape (N, N) or (N, N, N)")
         self.N = k.shape[0]
         self.p = int(order)
-        self.dim = 2
+        self.dim = k.ndim
         self.n1 = self.N * self.p + 1
         self.nc1 = self.N * (self.p // 2) + 1
-        self.n_fine = self.n1 ** 2
-        self.n_coarse = self.nc1 ** 2
+        self.n_fine = self.n1 ** self.dim
+        self.n_coarse = self.nc1 ** self.dim
+        if bc is None:
+            bc = ("robin",) * (2 * self.dim)
+        if len(bc) != 2 * self.dim:
+            raise ValueError(f"bc needs {2 * self.dim} entries")
         self.max_rhs = int(max_rhs)
         self.omega_c = float(omega_c)
         self._k = k
@@ -95,7 +101,7 @@ class TwoGridSolver:
                 raise THError(st, "th_create failed")
             self._h = h
             d = L.FineDesc()
-            d.dim, d.n, d.order = 2, self.N, self.p
+            d.dim, d.n, d.order = self.dim, self.N, self.p
             d.k = k.ctypes.data_as(C.POINTER(C.c_double))
             d.eps = (self._eps.ctypes.data_as(C.POINTER(C.c_double)) if self._eps is not None
                      else C.POINTER(C.c_double)())
@@ -143,8 +149,9 @@ class TwoGridSolver:
         elif scheme == "weights":
             q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
             nc = self.N * (self.p // 2)
-            if q.shape != (nc, nc, 3):
-                raise ValueError(f"q must have shape ({nc}, {nc}, 3)")
+            want = (nc,) * self.dim + (3 if self.dim == 2 else 4,)
+            if q.shape != want:
+                raise ValueError(f"q must have shape {want}")
             self._q = q
             d.scheme = L.TH_COARSE_WEIGHTS
             d.q = q.ctypes.data_as(C.POINTER(C.c_double))
@@ -302,6 +309,21 @@ def plain_fit(samples):
     st = lib.th_plain_fit(x.ctypes.data, n, e.ctypes.data, q.ctypes.data)
     if st != 0:
         raise THError(st, "th_plain_fit rejected the samples (eta_c > 0, p in 1..8, kh < pi)")
+    return e, q
+
+
+def plain_fit3d(samples):
+    """3-D compact 27-point plain fit (host, through the C ABI): samples (n, 3)
+    rows (eta_c, p, shift) -> (e (n, 3) fine dispersion errors along the three
+    fit directions, q (n, 4) weights (q0, q_face, q_edge, q_corner))."""
+    lib = L.load()
+    x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64).reshape(-1, 3))
+    n = x.shape[0]
+    e = np.zeros((n, 3))
+    q = np.zeros((n, 4))
+    st = lib.th_plain_fit3d(x.ctypes.data, n, e.ctypes.data, q.ctypes.data)
+    if st != 0:
+        raise THError(st, "th_plain_fit3d rejected the samples (eta_c > 0, p in 1..8, kh < pi)")
     return e, q
 
 

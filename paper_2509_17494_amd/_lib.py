@@ -113,6 +113,7 @@ def load_mlp(lib):
     vp, i, d = C.c_void_p, C.c_int, C.c_double
     sig = {
         "th_plain_fit": ([vp, i, vp, vp], i),
+        "th_plain_fit3d": ([vp, i, vp, vp], i),
         "th_mlp_num_params": ([C.POINTER(i)], i),
         "th_mlp_create": ([C.POINTER(vp), i, vp], i),
         "th_mlp_destroy": ([vp], None),

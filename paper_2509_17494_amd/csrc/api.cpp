@@ -95,13 +95,14 @@ static size_t csize(bool f32) { return f32 ? sizeof(c32) : sizeof(c64); }
 
 static FineOp make_op(const th_ctx *c, bool shifted) {
   FineOp op;
+  op.dim = c->dim;
   op.N = c->N;
   op.P = c->P;
   op.n1 = c->n1;
   op.nf = c->nf;
   op.h = c->h;
   op.robin = 0;
-  for (int sd = 0; sd < 4; ++sd)
+  for (int sd = 0; sd < 2 * c->dim; ++sd)
     if (c->desc.bc[sd] == TH_BC_ROBIN) op.robin |= 1 << sd;
   op.kap = shifted ? c->d_kaps : c->d_kap;
   op.kr = c->d_k;
@@ -128,7 +129,7 @@ static void free_fine(th_ctx *c) {
 
 static void free_coarse(th_ctx *c) {
   free_graphs(c);  // graphs reference the coarse factors and workspaces
-  void *ptrs[] = {c->coarse.G, c->coarse.st9};
+  void *ptrs[] = {c->coarse.G, c->coarse.st, c->coarse.tbuf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->coarse = CoarseData{};
@@ -228,11 +229,12 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   if (!ctx) return TH_EINVAL;
   ctx->err.clear();
   if (!d) return fail(ctx, TH_EINVAL, "null descriptor");
-  if (d->dim == 3) return fail(ctx, TH_EUNSUPPORTED, "3-D problems are not built in this library");
-  if (d->dim != 2) return fail(ctx, TH_EINVAL, "dim must be 2");
+  if (d->dim != 2 && d->dim != 3) return fail(ctx, TH_EINVAL, "dim must be 2 or 3");
   if (d->n < 1) return fail(ctx, TH_EINVAL, "n must be >= 1");
   if (d->order < 2 || d->order > kMaxP || d->order % 2)
     return fail(ctx, TH_EINVAL, "order must be 2, 4, 6 or 8");
+  if (d->dim == 3 && d->order > 4)
+    return fail(ctx, TH_EUNSUPPORTED, "3-D problems support orders 2 and 4");
   if (!d->k) return fail(ctx, TH_EINVAL, "k is NULL");
   if (d->l_dd < 1 || d->n_dd < 1 || d->n_s < 1 || d->max_rhs < 1)
     return fail(ctx, TH_EINVAL, "l_dd, n_dd, n_s and max_rhs must be >= 1");
@@ -240,10 +242,10 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return fail(ctx, TH_EINVAL, "alpha_s must be finite and >= 0, omega_c finite");
   if (d->gemm != TH_GEMM_F64 && d->gemm != TH_GEMM_F32 && d->gemm != TH_GEMM_BF16)
     return fail(ctx, TH_EINVAL, "unknown subdomain operator storage");
-  for (int sd = 0; sd < 4; ++sd)
+  for (int sd = 0; sd < 2 * d->dim; ++sd)
     if (d->bc[sd] != TH_BC_ROBIN && d->bc[sd] != TH_BC_NEUMANN)
       return fail(ctx, TH_EINVAL, "boundary condition must be Robin or Neumann");
-  const long long ncell = (long long)d->n * d->n;
+  const long long ncell = (long long)d->n * d->n * (d->dim == 3 ? d->n : 1);
   for (long long i = 0; i < ncell; ++i) {
     if (!(d->k[i] > 0.0) || !std::isfinite(d->k[i]))
       return fail(ctx, TH_EINVAL, "k must be finite and > 0 in every cell");
@@ -259,14 +261,14 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   c->desc = *d;
   c->desc.k = nullptr;
   c->desc.eps = nullptr;
-  c->dim = 2;
+  c->dim = d->dim;
   c->N = d->n;
   c->P = d->order;
   c->R = d->order / 2;
   c->n1 = c->N * c->P + 1;
   c->nc1 = c->N * c->R + 1;
-  c->nf = (long long)c->n1 * c->n1;
-  c->nc = (long long)c->nc1 * c->nc1;
+  c->nf = (long long)c->n1 * c->n1 * (c->dim == 3 ? c->n1 : 1);
+  c->nc = (long long)c->nc1 * c->nc1 * (c->dim == 3 ? c->nc1 : 1);
   c->h = 1.0 / c->N;
   make_ref1d(c->P, c->ref);
   c->h_k.assign(d->k, d->k + ncell);
@@ -301,37 +303,47 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   c->subs.clear();
   long long boff = 0, yoff = 0;
   int max_ldb = 0, max_nom = 0;
-  for (int by = 0; by < M; ++by)
-    for (int bx = 0; bx < M; ++bx) {
-      Sub s{};
-      s.u0x = c->blk_start[bx];
-      s.u1x = c->blk_start[bx + 1];
-      s.u0y = c->blk_start[by];
-      s.u1y = c->blk_start[by + 1];
-      s.o0x = std::max(s.u0x - 1, 0);
-      s.o1x = std::min(s.u1x + 1, N);
-      s.o0y = std::max(s.u0y - 1, 0);
-      s.o1y = std::min(s.u1y + 1, N);
-      s.nux = (s.u1x - s.u0x) * P + 1;
-      s.nuy = (s.u1y - s.u0y) * P + 1;
-      s.nox = (s.o1x - s.o0x) * P + 1;
-      s.noy = (s.o1y - s.o0y) * P + 1;
-      s.nU = s.nux * s.nuy;
-      s.nOm = s.nox * s.noy;
-      s.ldb = (s.nU + 63) / 64 * 64;
-      s.robin = 0;
-      const bool inner[4] = {s.o0x > 0, s.o1x < N, s.o0y > 0, s.o1y < N};
-      for (int sd = 0; sd < 4; ++sd)
-        if (inner[sd] || d->bc[sd] == TH_BC_ROBIN) s.robin |= 1 << sd;
-      s.boff = boff;
-      s.yoff = yoff;
-      // element offsets: complex entries (F64/F32) or bf16 values (MFMA layout)
-      boff += (d->gemm == TH_GEMM_BF16) ? mfma_store_elems(s) : (long long)s.nOm * s.ldb;
-      yoff += s.nU;
-      max_ldb = std::max(max_ldb, s.ldb);
-      max_nom = std::max(max_nom, s.nOm);
-      c->subs.push_back(s);
-    }
+  const int Mz = c->dim == 3 ? M : 1;
+  for (int bz = 0; bz < Mz; ++bz)
+    for (int by = 0; by < M; ++by)
+      for (int bx = 0; bx < M; ++bx) {
+        Sub s{};
+        s.u0x = c->blk_start[bx];
+        s.u1x = c->blk_start[bx + 1];
+        s.u0y = c->blk_start[by];
+        s.u1y = c->blk_start[by + 1];
+        s.o0x = std::max(s.u0x - 1, 0);
+        s.o1x = std::min(s.u1x + 1, N);
+        s.o0y = std::max(s.u0y - 1, 0);
+        s.o1y = std::min(s.u1y + 1, N);
+        if (c->dim == 3) {
+          s.u0z = c->blk_start[bz];
+          s.u1z = c->blk_start[bz + 1];
+          s.o0z = std::max(s.u0z - 1, 0);
+          s.o1z = std::min(s.u1z + 1, N);
+        }
+        s.nux = (s.u1x - s.u0x) * P + 1;
+        s.nuy = (s.u1y - s.u0y) * P + 1;
+        s.nuz = (s.u1z - s.u0z) * P + 1;  // 1 in 2-D
+        s.nox = (s.o1x - s.o0x) * P + 1;
+        s.noy = (s.o1y - s.o0y) * P + 1;
+        s.noz = (s.o1z - s.o0z) * P + 1;
+        s.nU = s.nux * s.nuy * s.nuz;
+        s.nOm = s.nox * s.noy * s.noz;
+        s.ldb = (s.nU + 63) / 64 * 64;
+        s.robin = 0;
+        const bool inner[6] = {s.o0x > 0, s.o1x < N, s.o0y > 0, s.o1y < N, s.o0z > 0, s.o1z < N};
+        for (int sd = 0; sd < 2 * c->dim; ++sd)
+          if (inner[sd] || d->bc[sd] == TH_BC_ROBIN) s.robin |= 1 << sd;
+        s.boff = boff;
+        s.yoff = yoff;
+        // element offsets: complex entries (F64/F32) or bf16 values (MFMA layout)
+        boff += (d->gemm == TH_GEMM_BF16) ? mfma_store_elems(s) : (long long)s.nOm * s.ldb;
+        yoff += s.nU;
+        max_ldb = std::max(max_ldb, s.ldb);
+        max_nom = std::max(max_nom, s.nOm);
+        c->subs.push_back(s);
+      }
   c->max_ldb = max_ldb;
   c->max_nom = max_nom;
   c->max_rowblocks = (max_ldb + 255) / 256;
@@ -387,22 +399,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   return TH_OK;
 }
 
-th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
-  if (!ctx) return TH_EINVAL;
-  ctx->err.clear();
-  if (!d) return fail(ctx, TH_EINVAL, "null descriptor");
-  if (!ctx->fine_ready) return fail(ctx, TH_ESTATE, "th_setup_fine must succeed first");
-  if (d->scheme != TH_COARSE_QSFEM && d->scheme != TH_COARSE_WEIGHTS &&
-      d->scheme != TH_COARSE_PLAINFIT && d->scheme != TH_COARSE_MLP)
-    return fail(ctx, TH_EINVAL, "unknown coarse scheme");
-  if (d->scheme == TH_COARSE_WEIGHTS && !d->q) return fail(ctx, TH_EINVAL, "q is NULL");
-  if (d->scheme == TH_COARSE_MLP && !d->mlp) return fail(ctx, TH_EINVAL, "mlp is NULL");
-  if (d->scheme == TH_COARSE_MLP && !(d->fallback_tau >= 0.0))
-    return fail(ctx, TH_EINVAL, "fallback_tau must be >= 0");
-  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TH_EHIP, "hipSetDevice failed");
-  auto t0 = std::chrono::steady_clock::now();
-  free_coarse(ctx);
-  th_ctx *c = ctx;
+// Per-cell weights and the 9-point quasi-FE stencil on the 2-D coarse grid.
+static th_status coarse_stencil_2d(th_ctx *c, const th_coarse_desc *d, std::vector<c64> &st) {
   const int Nc = c->N * c->R, nc1 = c->nc1;
   const double hc = 1.0 / Nc;
   // per coarse cell: k, eps of the fine cell containing it; weights q
@@ -421,11 +419,11 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
         smp[3 * ci + 1] = c->P;
         smp[3 * ci + 2] = c->h_eps[fi] / (kk * kk);
         if (!(smp[3 * ci] * c->P / 2.0 < M_PI))
-          return fail(ctx, TH_EINVAL, "dispersion fit needs fine k h < pi in every cell");
+          return fail(c, TH_EINVAL, "dispersion fit needs fine k h < pi in every cell");
       }
     int rc = coarse_weights(d->scheme, d->mlp, d->fallback_tau, smp.data(), Nc * Nc, qw.data(),
                             &c->n_fallback);
-    if (rc) return finish(ctx, rc);
+    if (rc) return finish(c, rc);
   } else {
     for (int cy = 0; cy < Nc; ++cy)
       for (int cxx = 0; cxx < Nc; ++cxx) {
@@ -436,7 +434,7 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
         } else {
           for (int t = 0; t < 3; ++t) {
             qw[3 * ci + t] = d->q[3 * ci + t];
-            if (!std::isfinite(qw[3 * ci + t])) return fail(ctx, TH_EINVAL, "non-finite weight q");
+            if (!std::isfinite(qw[3 * ci + t])) return fail(c, TH_EINVAL, "non-finite weight q");
           }
         }
       }
@@ -444,7 +442,7 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
   c->t_stencil = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts0).count();
   // 9-point quasi-FE stencil per coarse vertex (eq. element_wise_qsfem with the
   // -i eps Q1 mass and the absorbing Q1 boundary mass)
-  std::vector<c64> st((size_t)nc1 * nc1 * 9, c64{0, 0});
+  st.assign((size_t)nc1 * nc1 * 9, c64{0, 0});
   const double m1[2][2] = {{1.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 1.0 / 3.0}};
   for (int cy = 0; cy < Nc; ++cy)
     for (int cxx = 0; cxx < Nc; ++cxx) {
@@ -471,6 +469,108 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
           e = e + v;
         }
     }
+  return TH_OK;
+}
+
+// Per-cell weights (q0, q_face, q_edge, q_corner) and the 27-point quasi-FE
+// stencil on the 3-D coarse grid: the -i eps Q1 mass and the absorbing Q1
+// face mass are added per coarse cell as in 2-D.
+static th_status coarse_stencil_3d(th_ctx *c, const th_coarse_desc *d, std::vector<c64> &st) {
+  const int Nc = c->N * c->R, nc1 = c->nc1, R = c->R, N = c->N;
+  const double hc = 1.0 / Nc;
+  const long long ncc = (long long)Nc * Nc * Nc;
+  auto fine_of = [&](long long cz, long long cy, long long cxx) {
+    return ((cz / R) * N + cy / R) * N + cxx / R;
+  };
+  if (d->scheme == TH_COARSE_MLP)
+    return fail(c, TH_EUNSUPPORTED, "the surrogate network covers the 2-D stencil family only");
+  std::vector<double> qw((size_t)ncc * 4);
+  const auto ts0 = std::chrono::steady_clock::now();
+  c->n_fallback = 0;
+  if (d->scheme == TH_COARSE_PLAINFIT) {
+    std::vector<double> smp((size_t)ncc * 3);
+    for (long long ci = 0; ci < ncc; ++ci) {
+      const long long fi = fine_of(ci / ((long long)Nc * Nc), (ci / Nc) % Nc, ci % Nc);
+      const double kk = c->h_k[fi];
+      smp[3 * ci] = hc * kk;
+      smp[3 * ci + 1] = c->P;
+      smp[3 * ci + 2] = c->h_eps[fi] / (kk * kk);
+      if (!(smp[3 * ci] * c->P / 2.0 < M_PI))
+        return fail(c, TH_EINVAL, "dispersion fit needs fine k h < pi in every cell");
+    }
+    plain_fit27_batch(smp.data(), (int)ncc, nullptr, qw.data());
+  } else {
+    for (long long ci = 0; ci < ncc; ++ci) {
+      if (d->scheme == TH_COARSE_QSFEM) {
+        const long long fi = fine_of(ci / ((long long)Nc * Nc), (ci / Nc) % Nc, ci % Nc);
+        const double eta = hc * c->h_k[fi];
+        const double z[3] = {eta, eta, eta};
+        fit27_from_radii(eta, z, &qw[4 * ci]);
+      } else {
+        for (int t = 0; t < 4; ++t) {
+          qw[4 * ci + t] = d->q[4 * ci + t];
+          if (!std::isfinite(qw[4 * ci + t])) return fail(c, TH_EINVAL, "non-finite weight q");
+        }
+      }
+    }
+  }
+  c->t_stencil = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts0).count();
+  st.assign((size_t)nc1 * nc1 * nc1 * 27, c64{0, 0});
+  const double m1[2][2] = {{1.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 1.0 / 3.0}};
+  const double hc2 = hc * hc, hc3 = hc2 * hc;
+  const bool rb[6] = {c->desc.bc[0] == TH_BC_ROBIN, c->desc.bc[1] == TH_BC_ROBIN,
+                      c->desc.bc[2] == TH_BC_ROBIN, c->desc.bc[3] == TH_BC_ROBIN,
+                      c->desc.bc[4] == TH_BC_ROBIN, c->desc.bc[5] == TH_BC_ROBIN};
+  for (int cz = 0; cz < Nc; ++cz)
+    for (int cy = 0; cy < Nc; ++cy)
+      for (int cxx = 0; cxx < Nc; ++cxx) {
+        const long long ci = ((long long)cz * Nc + cy) * Nc + cxx;
+        const long long fi = fine_of(cz, cy, cxx);
+        const double kk = c->h_k[fi], ee = c->h_eps[fi];
+        for (int a = 0; a < 8; ++a)
+          for (int b = 0; b < 8; ++b) {
+            const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+            const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+            const int diff = (ax != bx) + (ay != by) + (az != bz);
+            c64 v = {qw[4 * ci + diff], -ee * hc3 * m1[az][bz] * m1[ay][by] * m1[ax][bx]};
+            const double fx = kk * hc2 * m1[ay][by] * m1[az][bz];
+            const double fy = kk * hc2 * m1[ax][bx] * m1[az][bz];
+            const double fz = kk * hc2 * m1[ax][bx] * m1[ay][by];
+            if (rb[0] && cxx == 0 && ax == 0 && bx == 0) v.im -= fx;
+            if (rb[1] && cxx == Nc - 1 && ax == 1 && bx == 1) v.im -= fx;
+            if (rb[2] && cy == 0 && ay == 0 && by == 0) v.im -= fy;
+            if (rb[3] && cy == Nc - 1 && ay == 1 && by == 1) v.im -= fy;
+            if (rb[4] && cz == 0 && az == 0 && bz == 0) v.im -= fz;
+            if (rb[5] && cz == Nc - 1 && az == 1 && bz == 1) v.im -= fz;
+            const long long ga = ((long long)(cz + az) * nc1 + cy + ay) * nc1 + cxx + ax;
+            c64 &e = st[27 * ga + ((bz - az + 1) * 3 + (by - ay + 1)) * 3 + (bx - ax + 1)];
+            e = e + v;
+          }
+      }
+  return TH_OK;
+}
+
+th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
+  if (!ctx) return TH_EINVAL;
+  ctx->err.clear();
+  if (!d) return fail(ctx, TH_EINVAL, "null descriptor");
+  if (!ctx->fine_ready) return fail(ctx, TH_ESTATE, "th_setup_fine must succeed first");
+  if (d->scheme != TH_COARSE_QSFEM && d->scheme != TH_COARSE_WEIGHTS &&
+      d->scheme != TH_COARSE_PLAINFIT && d->scheme != TH_COARSE_MLP)
+    return fail(ctx, TH_EINVAL, "unknown coarse scheme");
+  if (d->scheme == TH_COARSE_WEIGHTS && !d->q) return fail(ctx, TH_EINVAL, "q is NULL");
+  if (d->scheme == TH_COARSE_MLP && !d->mlp) return fail(ctx, TH_EINVAL, "mlp is NULL");
+  if (d->scheme == TH_COARSE_MLP && !(d->fallback_tau >= 0.0))
+    return fail(ctx, TH_EINVAL, "fallback_tau must be >= 0");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TH_EHIP, "hipSetDevice failed");
+  auto t0 = std::chrono::steady_clock::now();
+  free_coarse(ctx);
+  th_ctx *c = ctx;
+  std::vector<c64> st;
+  {
+    const th_status sc = c->dim == 3 ? coarse_stencil_3d(c, d, st) : coarse_stencil_2d(c, d, st);
+    if (sc) return sc;
+  }
   int rc = setup_coarse_factors(c, st);
   if (rc) {
     free_coarse(c);
@@ -574,12 +674,12 @@ static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, b
   void *ucv = f32 ? c->w_rc32 : c->w_uc;
   {
     KTimer kt(c, TH_KT_RESTRICT);
-    rc = launch_restrict(c->N, c->P, c->ref, c->w_r, rcv, nrhs, f32, s);
+    rc = launch_restrict(c->dim, c->N, c->P, c->ref, c->w_r, rcv, nrhs, f32, s);
   }
   if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32);
   if (!rc) {
     KTimer kt(c, TH_KT_PROLONG);
-    rc = launch_prolong(c->N, c->P, c->ref, ucv, u, c->desc.omega_c, nrhs, f32, s);
+    rc = launch_prolong(c->dim, c->N, c->P, c->ref, ucv, u, c->desc.omega_c, nrhs, f32, s);
   }
   for (int i = 0; i < c->desc.n_s && rc == 0; ++i) rc = smooth_impl(c, u, f, nrhs, f32, false);
   return rc;
@@ -620,14 +720,16 @@ th_status th_smooth(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt) 
 th_status th_restrict(th_ctx *ctx, const void *r, void *rc, int nrhs, th_dtype dt) {
   th_status st = check_vec_call(ctx, r, rc, nrhs, dt, false);
   if (st) return st;
-  return finish(ctx, launch_restrict(ctx->N, ctx->P, ctx->ref, r, rc, nrhs, is_f32(dt), ctx->stream));
+  return finish(ctx, launch_restrict(ctx->dim, ctx->N, ctx->P, ctx->ref, r, rc, nrhs, is_f32(dt),
+                                     ctx->stream));
 }
 
 th_status th_prolong(th_ctx *ctx, const void *uc, void *u, double omega_c, int nrhs, th_dtype dt) {
   th_status st = check_vec_call(ctx, uc, u, nrhs, dt, false);
   if (st) return st;
   if (!std::isfinite(omega_c)) return fail(ctx, TH_EINVAL, "omega_c must be finite");
-  return finish(ctx, launch_prolong(ctx->N, ctx->P, ctx->ref, uc, u, omega_c, nrhs, is_f32(dt),
+  return finish(ctx, launch_prolong(ctx->dim, ctx->N, ctx->P, ctx->ref, uc, u, omega_c, nrhs,
+                                    is_f32(dt),
                                     ctx->stream));
 }
 

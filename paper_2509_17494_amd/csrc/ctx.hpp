@@ -12,36 +12,66 @@ namespace th {
 
 // One subdomain: U = non-overlapping cell box, Om = U plus one cell layer
 // clipped to the domain (Sec. 4.1, 4.4).  Boxes are half-open cell ranges.
+// In 2-D the z extents are a single node layer (u0z = o0z = 0, nuz = noz = 1),
+// so every index formula below serves both dimensions.
 struct Sub {
-  int u0x, u1x, u0y, u1y;     // U cell box
-  int o0x, o1x, o0y, o1y;     // Omega cell box
-  int nux, nuy, nox, noy;     // node counts of closed U / Omega per direction
+  int u0x, u1x, u0y, u1y, u0z, u1z;  // U cell box
+  int o0x, o1x, o0y, o1y, o0z, o1z;  // Omega cell box
+  int nux, nuy, nuz, nox, noy, noz;  // node counts of closed U / Omega per direction
   int nU, nOm;                // nodes of closed U / Omega
   int ldb;                    // leading dimension (padded n_U) of stored B_i^T
-  int robin;                  // bit s set: absorbing term on side s of Omega (x-,x+,y-,y+)
+  int robin;                  // bit s set: absorbing term on side s of Omega (x-,x+,y-,y+,z-,z+)
   long long boff;             // element offset of B_i in the operator store
   long long yoff;             // offset of this subdomain's rows in the Y scratch
 };
 
+// global node index of local Omega node k of subdomain s
+__host__ __device__ __forceinline__ long long om_node(const Sub &s, int k, int P, int n1) {
+  const int kx = k % s.nox, t = k / s.nox;
+  const int ky = t % s.noy, kz = t / s.noy;
+  return ((long long)(s.o0z * P + kz) * n1 + (s.o0y * P + ky)) * n1 + s.o0x * P + kx;
+}
+
+// Local node j of closed U (x fastest): global node coordinates g[] and the
+// position uj of the same node in the Omega numbering.
+__host__ __device__ __forceinline__ void u_node(const Sub &s, int j, int P, int g[3], int &uj) {
+  const int jx = j % s.nux, t = j / s.nux;
+  const int jy = t % s.nuy, jz = t / s.nuy;
+  g[0] = s.u0x * P + jx;
+  g[1] = s.u0y * P + jy;
+  g[2] = s.u0z * P + jz;
+  uj = (((s.u0z - s.o0z) * P + jz) * s.noy + (s.u0y - s.o0y) * P + jy) * s.nox +
+       (s.u0x - s.o0x) * P + jx;
+}
+
 // Geometry and coefficients of the fine operator, passed to kernels by value.
 struct FineOp {
+  int dim;
   int N, P, n1;               // cells/dir, order, nodes/dir
   long long nf;               // nodes
   double h;
-  int robin;                  // bit s: Robin on global side s (x-,x+,y-,y+)
+  int robin;                  // bit s: Robin on global side s (x-,x+,y-,y+,z-,z+)
   const c64 *kap;             // per cell volume coefficient (k^2 + i eps) or shifted
   const double *kr;           // per cell k for the absorbing term
 };
 
+// The coarse grid is ordered in slabs along the slowest axis (lines of
+// constant y in 2-D, planes of constant z in 3-D).  Every vertex couples to
+// the previous / same / next slab through C = 3^(d-1) in-slab offsets.
 struct CoarseData {
-  int nx = 0, ny = 0;         // coarse vertices per line / lines
-  int nblk = 0;               // super-blocks of consecutive lines
+  int dim = 2;
+  int nx = 0;                 // vertices per grid direction
+  int L = 0;                  // vertices per slab (nx or nx^2)
+  int ny = 0;                 // slabs
+  int C = 3;                  // in-slab couplings per vertex (3 or 9)
+  int nblk = 0;               // super-blocks of consecutive slabs
   int rc_chunk = 1;           // right-hand sides per sweep pass
-  std::vector<int> line0;     // first line of every super-block (nblk + 1 entries)
+  std::vector<int> line0;     // first slab of every super-block (nblk + 1 entries)
   std::vector<int> ld;        // padded leading dimension of G_J
   std::vector<long long> goff;  // element offset of G_J
   c64 *G = nullptr;           // inverses of the Schur blocks S_J (symmetric), row-major
-  c64 *st9 = nullptr;         // per coarse vertex the 9 stencil couplings [dy+1][dx+1]
+  c64 *st = nullptr;          // per vertex 3 x C couplings [slab offset + 1][in-slab code]
+  c64 *tbuf = nullptr;        // staging of slab right-hand sides for large slabs
   long long bytes = 0;
 };
 
@@ -145,9 +175,9 @@ int launch_apply(const FineOp &op, const Ref1D &ref, const void *u, const void *
                  int nrhs, bool f32, double sgn, hipStream_t s);
 
 // k_transfer.hip
-int launch_restrict(int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs, bool f32,
-                    hipStream_t s);
-int launch_prolong(int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
+int launch_restrict(int dim, int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs,
+                    bool f32, hipStream_t s);
+int launch_prolong(int dim, int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
                    int nrhs, bool f32, hipStream_t s);
 
 // k_smoother.hip
@@ -168,6 +198,10 @@ int launch_dd_mfma(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, 
 
 // autotune.cpp
 int autotune_mfma(th_ctx *c);
+
+// dispersion.cpp (3-D compact stencil)
+void fit27_from_radii(double eta, const double z[3], double qw[4]);
+void plain_fit27_batch(const double *x, int n, double *e_out, double *q_out);
 
 // mlp_api.cpp
 int coarse_weights(int scheme, const th_mlp *m, double tau, const double *samples, int n,

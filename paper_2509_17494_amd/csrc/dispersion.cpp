@@ -219,4 +219,114 @@ void plain_fit_batch(const double *x, int n, double *e_out, double *q_out) {
   for (auto &t : ts) t.join();
 }
 
+// ---------------------------------------------------------------------------
+// 3-D: the compact 27-point family with classes P0 = 8 (centre), P1 (face),
+// P2 (edge), P3 (corner),
+//   sigma(xi) = P0 + 2 P1 sum c_i + 4 P2 sum_{i<j} c_i c_j + 8 P3 c_1 c_2 c_3,
+// c_i = cos(h_c xi_i), whose zero set is put through three points along fixed
+// directions of the symmetry sector (normalised (1, .2, .1), (1, .6, .3),
+// (1, .9, .7)); N = -eta^2 / sigma(0); element weights N P0 / 8, N P1 / 4,
+// N P2 / 2, N P3 for vertex pairs at Hamming distance 0..3 (the quasi-FE
+// distribution of Sec. 3.3 in three dimensions).  The fine 3-D Q_p dispersion
+// separates as mu(theta_x) + mu(theta_y) + mu(theta_z) = (kh)^2.
+
+static void dirs27(double d[3][3]) {
+  const double raw[3][3] = {{1.0, 0.2, 0.1}, {1.0, 0.6, 0.3}, {1.0, 0.9, 0.7}};
+  for (int m = 0; m < 3; ++m) {
+    const double n = std::sqrt(raw[m][0] * raw[m][0] + raw[m][1] * raw[m][1] + raw[m][2] * raw[m][2]);
+    for (int i = 0; i < 3; ++i) d[m][i] = raw[m][i] / n;
+  }
+}
+
+// Weights (q0, q_face, q_edge, q_corner) with zeros at radius z[m] along the
+// m-th direction (z[m] = eta gives the exact-wavenumber stencil).
+void fit27_from_radii(double eta, const double z[3], double qw[4]) {
+  double d[3][3];
+  dirs27(d);
+  double A[3][4];
+  for (int m = 0; m < 3; ++m) {
+    const double c0 = std::cos(z[m] * d[m][0]), c1 = std::cos(z[m] * d[m][1]),
+                 c2 = std::cos(z[m] * d[m][2]);
+    A[m][0] = 2.0 * (c0 + c1 + c2);
+    A[m][1] = 4.0 * (c0 * c1 + c0 * c2 + c1 * c2);
+    A[m][2] = 8.0 * c0 * c1 * c2;
+    A[m][3] = -8.0;
+  }
+  // Gaussian elimination with partial pivoting
+  for (int k = 0; k < 3; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < 3; ++i)
+      if (std::fabs(A[i][k]) > std::fabs(A[piv][k])) piv = i;
+    if (piv != k)
+      for (int j = 0; j < 4; ++j) std::swap(A[k][j], A[piv][j]);
+    for (int i = k + 1; i < 3; ++i) {
+      const double f = A[i][k] / A[k][k];
+      for (int j = k; j < 4; ++j) A[i][j] -= f * A[k][j];
+    }
+  }
+  double P[3];
+  for (int i = 2; i >= 0; --i) {
+    double t = A[i][3];
+    for (int j = i + 1; j < 3; ++j) t -= A[i][j] * P[j];
+    P[i] = t / A[i][i];
+  }
+  const double P0 = 8.0;
+  const double Nn = -eta * eta / (P0 + 6.0 * P[0] + 12.0 * P[1] + 8.0 * P[2]);
+  qw[0] = Nn * P0 / 8.0;
+  qw[1] = Nn * P[0] / 4.0;
+  qw[2] = Nn * P[1] / 2.0;
+  qw[3] = Nn * P[2];
+}
+
+// Radius (h = 1) of the fine 3-D Q_p dispersion surface along unit vector d.
+static double fine_radius3(const Pencil1D &q, double kh, const double d[3]) {
+  const double a0 = std::fabs(d[0]), a1 = std::fabs(d[1]), a2 = std::fabs(d[2]);
+  const double k2 = kh * kh;
+  auto g = [&](double r) {
+    return k2 - (mu_acoustic(q, r * a0) + mu_acoustic(q, r * a1) + mu_acoustic(q, r * a2));
+  };
+  const double rmax = 0.999 * M_PI / std::max(a0, std::max(a1, a2));
+  double a = 0.5 * kh, b = std::min(1.5 * kh, rmax);
+  double ga = g(a), gb = g(b);
+  if (!(ga > 0.0 && gb < 0.0)) return kh;  // outside the supported regime
+  return illinois(g, a, ga, b, gb, 1e-15);
+}
+
+// Plain 3-D fit for n cells (inputs eta_c, p, shift per cell): q_out[4 i ...],
+// and the relative fine errors e_out[3 i ...] when requested.
+void plain_fit27_batch(const double *x, int n, double *e_out, double *q_out) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nt = std::min<unsigned>(nt, (unsigned)std::max(1, n / 64));
+  double d[3][3];
+  dirs27(d);
+  auto work = [&](int i0, int i1) {
+    int last_p = -1;
+    Pencil1D q;
+    for (int i = i0; i < i1; ++i) {
+      const double eta_c = x[3 * i], shift = x[3 * i + 2];
+      const int p = (int)std::lround(x[3 * i + 1]);
+      if (p != last_p) {
+        make_pencil(p, q);
+        last_p = p;
+      }
+      const double eta = effective_eta(eta_c, shift);
+      const double kh = eta * p / 2.0;
+      double z[3];
+      for (int m = 0; m < 3; ++m) {
+        const double e = fine_radius3(q, kh, d[m]) / kh - 1.0;
+        if (e_out) e_out[3 * i + m] = e;
+        z[m] = eta * (1.0 + e);
+      }
+      if (q_out) fit27_from_radii(eta, z, q_out + 4 * i);
+    }
+  };
+  std::vector<std::thread> ts;
+  const int chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int i0 = t * chunk, i1 = std::min(n, (int)(t + 1) * chunk);
+    if (i0 < i1) ts.emplace_back(work, i0, i1);
+  }
+  for (auto &t : ts) t.join();
+}
+
 }  // namespace th

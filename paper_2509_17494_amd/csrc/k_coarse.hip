@@ -1,23 +1,25 @@
 // Coarse-level direct solve in FP64 (Alg. 1, "solve A_c u_c = r_c"; the paper
 // uses a direct solver and notes that approximate ones may be used).
 //
-// The quasi-FE QSFEM matrix (Sec. 3.3) is a 9-point stencil on the coarse
-// vertex grid.  Grouping K consecutive grid lines (constant y) into a
-// super-block makes it block tridiagonal, and the coupling between
-// super-blocks J-1 and J only links the last line of J-1 with the first line
-// of J (tridiagonal in x).  Setup (once, timed separately) runs the block
+// The quasi-FE QSFEM matrix (Sec. 3.3) is a 9-point (2-D) or 27-point (3-D)
+// stencil on the coarse vertex grid.  Grouping K consecutive slabs (grid
+// lines of constant y in 2-D, planes of constant z in 3-D) into a super-block
+// makes it block tridiagonal, and the coupling between super-blocks J-1 and J
+// only links the last slab of J-1 with the first slab of J (3 or 9 in-slab
+// neighbours per vertex).  Setup (once, timed separately) runs the block
 // elimination in natural order
 //   S_0 = T_0,   S_J = T_J - L_J S_{J-1}^{-1} U_{J-1},   G_J = S_J^{-1},
-// where L_J S_{J-1}^{-1} U_{J-1} only touches the first-line block of S_J and
-// only needs the last-line block of G_{J-1}.  Every S_J is inverted by the
+// where L_J S_{J-1}^{-1} U_{J-1} only touches the first-slab block of S_J and
+// only needs the last-slab block of G_{J-1}.  Every S_J is inverted by the
 // same Gauss-Jordan kernels as the subdomain operators (no pivoting: natural
 // order elimination of these matrices is stable, checked against pivoted
 // sparse LU).  The solve is
 //   forward   y_J = G_J (r_J - L_J y_{J-1})
-//   backward  x_J = y_J - G_J[:, last line] (U_J x_{J+1}[first line]),
+//   backward  x_J = y_J - G_J[:, last slab] (U_J x_{J+1}[first slab]),
 // two launches per super-block, each a bandwidth-bound GEMV with one
 // wavefront per output row (coalesced row reads of G_J, the right-hand side
-// staged in LDS, fixed-order wavefront reductions).  K trades the bytes of G
+// staged in LDS, or in global memory when a 3-D slab is too large for it;
+// fixed-order wavefront reductions).  K trades the bytes of G
 // (proportional to K) against the number of sequential launches (~2 ny / K).
 #include <algorithm>
 #include <cmath>
@@ -29,33 +31,62 @@ namespace th {
 
 constexpr int CW = 8;  // wavefronts (rows) per workgroup in the sweeps
 
+// In-slab neighbourhood: C = 3 codes dx + 1 along a line (2-D), C = 9 codes
+// (dy + 1) 3 + dx + 1 in a plane (3-D).  The code from b back to a is C - 1 - code.
+__device__ __forceinline__ int slab_nbr(int a, int code, int nx, int C) {
+  if (C == 3) {
+    const int x = a + code - 1;
+    return (x >= 0 && x < nx) ? x : -1;
+  }
+  const int y = a / nx + code / 3 - 1, x = a % nx + code % 3 - 1;
+  return (x >= 0 && x < nx && y >= 0 && y < nx) ? y * nx + x : -1;
+}
+
+__device__ __forceinline__ int slab_code(int a, int b, int nx, int C) {
+  if (C == 3) {
+    const int d = b - a;
+    return (d >= -1 && d <= 1) ? d + 1 : -1;
+  }
+  const int dy = b / nx - a / nx, dx = b % nx - a % nx;
+  return (dy >= -1 && dy <= 1 && dx >= -1 && dx <= 1) ? (dy + 1) * 3 + dx + 1 : -1;
+}
+
 // S_J (ld x ld, identity padding) written over the G_J slot.
 __global__ __launch_bounds__(256) void k_build_s(c64 *__restrict__ S, int ld, int nb, int nx,
-                                                 int line0, const c64 *__restrict__ st9,
+                                                 int L, int C, int line0,
+                                                 const c64 *__restrict__ st,
                                                  const c64 *__restrict__ Gp, int ldp, int kp) {
   const long long t = blockIdx.x * 256LL + threadIdx.x;
   if (t >= (long long)ld * ld) return;
   const int a = (int)(t / ld), b = (int)(t % ld);
+  const int SC = 3 * C;
   c64 v = {0, 0};
   if (a >= nb || b >= nb) {
     v = (a == b) ? c64{1.0, 0.0} : c64{0, 0};
   } else {
-    const int la = a / nx, ca = a - la * nx, lb = b / nx, cb = b - lb * nx;
-    const int dy = lb - la, dx = cb - ca;
-    const long long ga = (long long)(line0 + la) * nx + ca;
-    if (dy >= -1 && dy <= 1 && dx >= -1 && dx <= 1) v = st9[9 * ga + (dy + 1) * 3 + dx + 1];
+    const int la = a / L, ca = a - la * L, lb = b / L, cb = b - lb * L;
+    const int ds = lb - la;
+    const long long ga = (long long)(line0 + la) * L + ca;
+    if (ds >= -1 && ds <= 1) {
+      const int code = slab_code(ca, cb, nx, C);
+      if (code >= 0) v = st[SC * ga + (ds + 1) * C + code];
+    }
     if (Gp && la == 0 && lb == 0) {
       // - sum_{c,d} L[ca][c] G_{J-1}[last c][last d] U[d][cb]
-      const long long off = (long long)(kp - 1) * nx;
-      for (int c = max(ca - 1, 0); c <= min(ca + 1, nx - 1); ++c) {
-        const c64 l = st9[9 * ga + 0 * 3 + (c - ca) + 1];
-        c64 s = {0, 0};
-        for (int d = max(cb - 1, 0); d <= min(cb + 1, nx - 1); ++d) {
-          const long long gd = (long long)(line0 - 1) * nx + d;
-          const c64 u = st9[9 * gd + 2 * 3 + (cb - d) + 1];
-          cmac(s, Gp[(off + c) * ldp + off + d], u);
+      const long long off = (long long)(kp - 1) * L;
+      for (int c1 = 0; c1 < C; ++c1) {
+        const int c = slab_nbr(ca, c1, nx, C);
+        if (c < 0) continue;
+        const c64 l = st[SC * ga + c1];
+        c64 sum = {0, 0};
+        for (int c2 = 0; c2 < C; ++c2) {
+          const int d = slab_nbr(cb, c2, nx, C);
+          if (d < 0) continue;
+          const long long gd = (long long)(line0 - 1) * L + d;
+          const c64 u = st[SC * gd + 2 * C + (C - 1 - c2)];
+          cmac(sum, Gp[(off + c) * ldp + off + d], u);
         }
-        v = v - l * s;
+        v = v - l * sum;
       }
     }
   }
@@ -71,30 +102,78 @@ __device__ __forceinline__ c64 wave_sum(c64 v) {
   return v;
 }
 
-// forward step of super-block J: y_J = G_J (r_J - L_J y_{J-1})
+// right-hand side of the forward step of super-block J: r_J - L_J y_{J-1}
+__device__ __forceinline__ c64 fwd_rhs(int a, int r, int nx, int L, int C, int line0,
+                                       const c64 *__restrict__ st, const c64 *__restrict__ rc,
+                                       const c64 *__restrict__ uc, long long ncn, int has_prev) {
+  const long long g = (long long)line0 * L + a;
+  c64 v = rc[r * ncn + g];
+  if (has_prev && a < L) {
+    const c64 *s = st + 3 * C * g;
+    for (int code = 0; code < C; ++code) {
+      const int c = slab_nbr(a, code, nx, C);
+      if (c >= 0) v = v - s[code] * uc[r * ncn + (long long)(line0 - 1) * L + c];
+    }
+  }
+  return v;
+}
+
+// U_J x_{J+1}[first slab] at position c of the last slab of J (lend = first slab of J+1)
+__device__ __forceinline__ c64 bwd_rhs(int c, int r, int nx, int L, int C, int lend,
+                                       const c64 *__restrict__ st, const c64 *__restrict__ uc,
+                                       long long ncn) {
+  const long long gc = (long long)(lend - 1) * L + c;
+  const c64 *s = st + 3 * C * gc + 2 * C;
+  c64 v = {0, 0};
+  for (int code = 0; code < C; ++code) {
+    const int d = slab_nbr(c, code, nx, C);
+    if (d >= 0) cmac(v, s[code], uc[r * ncn + (long long)lend * L + d]);
+  }
+  return v;
+}
+
+// Staging in global memory for slabs whose right-hand side does not fit in
+// LDS: xg[(chunk RC + q) n + i], n = nb (forward) or L (backward).
 template <int RC>
-__global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int ld, int nb,
-                                                  int nx, int line0, const c64 *__restrict__ st9,
-                                                  const c64 *__restrict__ rc, c64 *__restrict__ uc,
-                                                  int nrhs, long long ncn, int has_prev) {
-  extern __shared__ c64 tsh[];  // RC x nb
+__global__ __launch_bounds__(256) void k_cstage(int fwd, int n, int nx, int L, int C, int slab,
+                                                const c64 *__restrict__ st,
+                                                const c64 *__restrict__ rc,
+                                                const c64 *__restrict__ uc, c64 *__restrict__ xg,
+                                                int nrhs, long long ncn, int has_prev) {
   const int r0 = blockIdx.y * RC;
-  for (int i = threadIdx.x; i < nb * RC; i += blockDim.x) {
-    const int q = i / nb, a = i - q * nb;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n * RC; i += gridDim.x * 256) {
+    const int q = i / n, a = i - q * n;
     const int r = r0 + q;
     c64 v = {0, 0};
-    if (r < nrhs) {
-      const long long g = (long long)line0 * nx + a;
-      v = rc[r * ncn + g];
-      if (has_prev && a < nx) {
-        const c64 *s = st9 + 9 * g;
-        for (int c = max(a - 1, 0); c <= min(a + 1, nx - 1); ++c)
-          v = v - s[(c - a) + 1] * uc[r * ncn + (long long)(line0 - 1) * nx + c];
-      }
-    }
-    tsh[q * nb + a] = v;
+    if (r < nrhs)
+      v = fwd ? fwd_rhs(a, r, nx, L, C, slab, st, rc, uc, ncn, has_prev)
+              : bwd_rhs(a, r, nx, L, C, slab, st, uc, ncn);
+    xg[(long long)r0 * n + i] = v;
   }
-  __syncthreads();
+}
+
+// forward step of super-block J: y_J = G_J (r_J - L_J y_{J-1})
+template <int RC, bool GS>
+__global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int ld, int nb,
+                                                  int nx, int L, int C, int line0,
+                                                  const c64 *__restrict__ st,
+                                                  const c64 *__restrict__ rc, c64 *__restrict__ uc,
+                                                  int nrhs, long long ncn, int has_prev,
+                                                  const c64 *__restrict__ xg) {
+  extern __shared__ c64 tsh[];  // RC x nb
+  const int r0 = blockIdx.y * RC;
+  const c64 *xs = tsh;
+  if (GS) {
+    xs = xg + (long long)r0 * nb;
+  } else {
+    for (int i = threadIdx.x; i < nb * RC; i += blockDim.x) {
+      const int q = i / nb, a = i - q * nb;
+      const int r = r0 + q;
+      tsh[q * nb + a] =
+          r < nrhs ? fwd_rhs(a, r, nx, L, C, line0, st, rc, uc, ncn, has_prev) : c64{0, 0};
+    }
+    __syncthreads();
+  }
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int a = blockIdx.x * CW + wave;
   if (a >= nb) return;
@@ -106,72 +185,71 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int
   for (int b = lane; b < nb; b += 64) {
     const c64 g = row[b];
 #pragma unroll
-    for (int q = 0; q < RC; ++q) cmac(acc[q], g, tsh[q * nb + b]);
+    for (int q = 0; q < RC; ++q) cmac(acc[q], g, xs[q * nb + b]);
   }
 #pragma unroll
   for (int q = 0; q < RC; ++q) {
     const c64 s = wave_sum(acc[q]);
-    if (lane == 0 && r0 + q < nrhs) uc[(r0 + q) * ncn + (long long)line0 * nx + a] = s;
+    if (lane == 0 && r0 + q < nrhs) uc[(r0 + q) * ncn + (long long)line0 * L + a] = s;
   }
 }
 
 // backward step of super-block J (not the last): x_J = y_J - G_J[:, last] w,
-// w = U_J x_{J+1}[first line]
-template <int RC>
+// w = U_J x_{J+1}[first slab]
+template <int RC, bool GS>
 __global__ __launch_bounds__(64 * CW) void k_cbwd(const c64 *__restrict__ G, int ld, int nb,
-                                                  int nx, int line0, int kJ,
-                                                  const c64 *__restrict__ st9,
-                                                  c64 *__restrict__ uc, int nrhs, long long ncn) {
-  extern __shared__ c64 wsh[];  // RC x nx
+                                                  int nx, int L, int C, int line0, int kJ,
+                                                  const c64 *__restrict__ st,
+                                                  c64 *__restrict__ uc, int nrhs, long long ncn,
+                                                  const c64 *__restrict__ xg) {
+  extern __shared__ c64 wsh[];  // RC x L
   const int r0 = blockIdx.y * RC;
-  const int lend = line0 + kJ;  // first line of J+1
-  for (int i = threadIdx.x; i < nx * RC; i += blockDim.x) {
-    const int q = i / nx, c = i - q * nx;
-    const int r = r0 + q;
-    c64 v = {0, 0};
-    if (r < nrhs) {
-      const long long gc = (long long)(lend - 1) * nx + c;
-      const c64 *s = st9 + 9 * gc + 6;
-      for (int d = max(c - 1, 0); d <= min(c + 1, nx - 1); ++d)
-        cmac(v, s[(d - c) + 1], uc[r * ncn + (long long)lend * nx + d]);
+  const int lend = line0 + kJ;  // first slab of J+1
+  const c64 *ws = wsh;
+  if (GS) {
+    ws = xg + (long long)r0 * L;
+  } else {
+    for (int i = threadIdx.x; i < L * RC; i += blockDim.x) {
+      const int q = i / L, c = i - q * L;
+      const int r = r0 + q;
+      wsh[q * L + c] = r < nrhs ? bwd_rhs(c, r, nx, L, C, lend, st, uc, ncn) : c64{0, 0};
     }
-    wsh[q * nx + c] = v;
+    __syncthreads();
   }
-  __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int a = blockIdx.x * CW + wave;
   if (a >= nb) return;
-  const c64 *row = G + (long long)a * ld + (long long)(kJ - 1) * nx;
+  const c64 *row = G + (long long)a * ld + (long long)(kJ - 1) * L;
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-  for (int c = lane; c < nx; c += 64) {
+  for (int c = lane; c < L; c += 64) {
     const c64 g = row[c];
 #pragma unroll
-    for (int q = 0; q < RC; ++q) cmac(acc[q], g, wsh[q * nx + c]);
+    for (int q = 0; q < RC; ++q) cmac(acc[q], g, ws[q * L + c]);
   }
 #pragma unroll
   for (int q = 0; q < RC; ++q) {
     const c64 s = wave_sum(acc[q]);
     if (lane == 0 && r0 + q < nrhs) {
-      c64 *p = uc + (r0 + q) * ncn + (long long)line0 * nx + a;
+      c64 *p = uc + (r0 + q) * ncn + (long long)line0 * L + a;
       *p = *p - s;
     }
   }
 }
 
-// Number of lines per super-block: minimise the modelled solve time
-// (K + 1) ny nx^2 16 B / BW  +  2 ceil(ny / K) launches x latency, with the
-// staged right-hand side within 64 KiB of LDS and G within a memory budget.
-static int choose_lines(int nx, int ny, int rc_chunk, int passes) {
+// Number of slabs per super-block: minimise the modelled solve time
+// (K + 1) ny L^2 16 B / BW  +  2 ceil(ny / K) launches x latency, with G
+// within a memory budget; slab right-hand sides up to 64 KiB are staged in LDS.
+static int choose_lines(int L, int ny, int rc_chunk, int passes) {
   const double bw = 4.0e12, lat = 8.0e-6;
   const int nb_max = std::min(4096, 65536 / (16 * rc_chunk));
-  const int kmax = std::max(1, std::min(ny, nb_max / nx));
+  const int kmax = std::max(1, std::min(ny, nb_max / L));
   int best = 1;
   double best_t = 1e300;
   for (int K = 1; K <= kmax; ++K) {
-    const double bytes = (double)(K + 1) * ny * nx * (double)nx * 16.0 * passes;
-    if ((double)ny * K * nx * (double)nx * 16.0 > 24e9) break;
+    const double bytes = (double)(K + 1) * ny * L * (double)L * 16.0 * passes;
+    if (K > 1 && (double)ny * K * L * (double)L * 16.0 > 24e9) break;
     const double t = bytes / bw + 2.0 * std::ceil((double)ny / K) * lat;
     if (t < best_t) {
       best_t = t;
@@ -184,13 +262,17 @@ static int choose_lines(int nx, int ny, int rc_chunk, int passes) {
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   hipStream_t s = c->stream;
   CoarseData &cd = c->coarse;
-  const int nx = c->nc1, ny = c->nc1;
+  const int nx = c->nc1;
+  cd.dim = c->dim;
   cd.nx = nx;
-  cd.ny = ny;
+  cd.L = c->dim == 3 ? nx * nx : nx;
+  cd.ny = nx;
+  cd.C = c->dim == 3 ? 9 : 3;
+  const int L = cd.L, ny = cd.ny, C = cd.C;
   const int R = c->desc.max_rhs;
   cd.rc_chunk = (R >= 4) ? 4 : (R >= 2 ? 2 : 1);
   const int passes = (R + cd.rc_chunk - 1) / cd.rc_chunk;
-  const int K = choose_lines(nx, ny, cd.rc_chunk, passes);
+  const int K = choose_lines(L, ny, cd.rc_chunk, passes);
   // balanced super-blocks of about K lines
   const int nblk = (ny + K - 1) / K;
   cd.nblk = nblk;
@@ -203,33 +285,41 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   cd.goff.resize(nblk + 1);
   cd.goff[0] = 0;
   for (int J = 0; J < nblk; ++J) {
-    const int nb = (cd.line0[J + 1] - cd.line0[J]) * nx;
+    const int nb = (cd.line0[J + 1] - cd.line0[J]) * L;
     cd.ld[J] = ceil_div(nb, 32) * 32;
     cd.goff[J + 1] = cd.goff[J] + (long long)cd.ld[J] * cd.ld[J];
   }
-  const size_t st_bytes = (size_t)nx * ny * 9 * sizeof(c64);
+  const size_t st_bytes = (size_t)L * ny * 3 * C * sizeof(c64);
+  if (st.size() * sizeof(c64) != st_bytes) {
+    set_error("coarse stencil has the wrong size");
+    return TH_EINVAL;
+  }
+  int max_nb = 0;
+  for (int J = 0; J < nblk; ++J) max_nb = std::max(max_nb, (cd.line0[J + 1] - cd.line0[J]) * L);
+  const size_t t_bytes = (size_t)max_nb * ceil_div(R, cd.rc_chunk) * cd.rc_chunk * sizeof(c64);
   cd.bytes = cd.goff[nblk] * (long long)sizeof(c64) + (long long)st_bytes;
   c64 *pws = nullptr;
   if (hipMalloc(&cd.G, (size_t)cd.goff[nblk] * sizeof(c64)) != hipSuccess ||
-      hipMalloc(&cd.st9, st_bytes) != hipSuccess ||
+      hipMalloc(&cd.st, st_bytes) != hipSuccess ||
+      hipMalloc(&cd.tbuf, t_bytes) != hipSuccess ||
       hipMalloc(&pws, 32 * 32 * sizeof(c64) + 64) != hipSuccess) {
     if (pws) (void)hipFree(pws);
     set_error("cannot allocate the coarse factors");
     return TH_ENOMEM;
   }
-  TH_HIP_CHECK_RET(hipMemcpyAsync(cd.st9, st.data(), st_bytes, hipMemcpyHostToDevice, s));
+  TH_HIP_CHECK_RET(hipMemcpyAsync(cd.st, st.data(), st_bytes, hipMemcpyHostToDevice, s));
   int *flag = (int *)(pws + 32 * 32);
   TH_HIP_CHECK_RET(hipMemsetAsync(flag, 0, sizeof(int), s));
   int rc = 0;
   for (int J = 0; J < nblk && rc == 0; ++J) {
-    const int ld = cd.ld[J], nb = (cd.line0[J + 1] - cd.line0[J]) * nx;
+    const int ld = cd.ld[J], nb = (cd.line0[J + 1] - cd.line0[J]) * L;
     c64 *GJ = cd.G + cd.goff[J];
     const c64 *Gp = J > 0 ? cd.G + cd.goff[J - 1] : nullptr;
     const int ldp = J > 0 ? cd.ld[J - 1] : 0;
     const int kp = J > 0 ? cd.line0[J] - cd.line0[J - 1] : 0;
     const long long tot = (long long)ld * ld;
     hipLaunchKernelGGL(k_build_s, dim3((unsigned)ceil_div_ll(tot, 256)), dim3(256), 0, s, GJ, ld,
-                       nb, nx, cd.line0[J], (const c64 *)cd.st9, Gp, ldp, kp);
+                       nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, Gp, ldp, kp);
     TH_HIP_CHECK_RET(hipGetLastError());
     rc = gj_invert_batched(GJ, ld, ld, tot, 1, s, pws);
   }
@@ -248,22 +338,44 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
 template <int RC>
 static int sweep_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
   const CoarseData &cd = c->coarse;
-  const long long ncn = (long long)cd.nx * cd.ny;
+  const int nx = cd.nx, L = cd.L, C = cd.C;
+  const long long ncn = (long long)L * cd.ny;
   const unsigned ychunks = (unsigned)ceil_div(nrhs, RC);
+  const size_t lds_max = 64 * 1024;
   for (int J = 0; J < cd.nblk; ++J) {
-    const int nb = (cd.line0[J + 1] - cd.line0[J]) * cd.nx;
+    const int nb = (cd.line0[J + 1] - cd.line0[J]) * L;
     const size_t shm = (size_t)nb * RC * sizeof(c64);
-    hipLaunchKernelGGL((k_cfwd<RC>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm, s,
-                       (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, cd.nx, cd.line0[J],
-                       (const c64 *)cd.st9, rcv, uc, nrhs, ncn, J > 0 ? 1 : 0);
+    const c64 *GJ = cd.G + cd.goff[J];
+    if (shm <= lds_max) {
+      hipLaunchKernelGGL((k_cfwd<RC, false>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm,
+                         s, GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, rcv, uc,
+                         nrhs, ncn, J > 0 ? 1 : 0, (const c64 *)nullptr);
+    } else {
+      hipLaunchKernelGGL((k_cstage<RC>), dim3(std::min(ceil_div(nb * RC, 256), 1024), ychunks),
+                         dim3(256), 0, s, 1, nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, rcv,
+                         (const c64 *)uc, cd.tbuf, nrhs, ncn, J > 0 ? 1 : 0);
+      hipLaunchKernelGGL((k_cfwd<RC, true>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), 0, s,
+                         GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, rcv, uc,
+                         nrhs, ncn, J > 0 ? 1 : 0, (const c64 *)cd.tbuf);
+    }
   }
   for (int J = cd.nblk - 2; J >= 0; --J) {
     const int kJ = cd.line0[J + 1] - cd.line0[J];
-    const int nb = kJ * cd.nx;
-    const size_t shm = (size_t)cd.nx * RC * sizeof(c64);
-    hipLaunchKernelGGL((k_cbwd<RC>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm, s,
-                       (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, cd.nx, cd.line0[J], kJ,
-                       (const c64 *)cd.st9, uc, nrhs, ncn);
+    const int nb = kJ * L;
+    const size_t shm = (size_t)L * RC * sizeof(c64);
+    const c64 *GJ = cd.G + cd.goff[J];
+    if (shm <= lds_max) {
+      hipLaunchKernelGGL((k_cbwd<RC, false>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm,
+                         s, GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], kJ, (const c64 *)cd.st, uc,
+                         nrhs, ncn, (const c64 *)nullptr);
+    } else {
+      hipLaunchKernelGGL((k_cstage<RC>), dim3(std::min(ceil_div(L * RC, 256), 1024), ychunks),
+                         dim3(256), 0, s, 0, L, nx, L, C, cd.line0[J] + kJ, (const c64 *)cd.st,
+                         (const c64 *)nullptr, (const c64 *)uc, cd.tbuf, nrhs, ncn, 0);
+      hipLaunchKernelGGL((k_cbwd<RC, true>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), 0, s,
+                         GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], kJ, (const c64 *)cd.st, uc, nrhs,
+                         ncn, (const c64 *)cd.tbuf);
+    }
   }
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;

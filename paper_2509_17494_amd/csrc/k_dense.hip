@@ -248,6 +248,69 @@ __global__ __launch_bounds__(256) void k_assemble_sub(const Sub *__restrict__ su
   }
 }
 
+// 3-D: per cell h (Kz My Mx + Mz Ky Mx + Mz My Kx) - kappa h^3 Mz My Mx, and
+// -i k h^2 (M (x) M over the face) on faces of Omega carrying the absorbing term.
+template <int P>
+__global__ __launch_bounds__(256) void k_assemble_sub3(const Sub *__restrict__ subs, int s0,
+                                                       c64 *A, int ld, long long stride,
+                                                       const c64 *__restrict__ kaps,
+                                                       const double *__restrict__ kr, Ref1D ref,
+                                                       double h, int N) {
+  constexpr int NP = P + 1;
+  const Sub s = subs[s0 + blockIdx.y];
+  c64 *Ab = A + blockIdx.y * stride;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= ld) return;
+  c64 *row = Ab + (long long)a * ld;
+  if (a >= s.nOm) {
+    row[a] = c64{1.0, 0.0};
+    return;
+  }
+  const int nc[3] = {s.o1x - s.o0x, s.o1y - s.o0y, s.o1z - s.o0z};
+  const int al[3] = {a % s.nox, (a / s.nox) % s.noy, a / (s.nox * s.noy)};
+  int ch[3], nq[3];
+  for (int d = 0; d < 3; ++d) {
+    ch[d] = min(al[d] / P, nc[d] - 1);
+    nq[d] = (al[d] % P == 0 && al[d] > 0 && al[d] < nc[d] * P) ? 2 : 1;
+  }
+  const double h2 = h * h, h3 = h2 * h;
+  for (int qz = nq[2] - 1; qz >= 0; --qz) {
+    const int lcz = ch[2] - qz, lz = al[2] - lcz * P;
+    for (int qy = nq[1] - 1; qy >= 0; --qy) {
+      const int lcy = ch[1] - qy, ly = al[1] - lcy * P;
+      for (int qx = nq[0] - 1; qx >= 0; --qx) {
+        const int lcx = ch[0] - qx, lx = al[0] - lcx * P;
+        const long long gc = ((long long)(s.o0z + lcz) * N + (s.o0y + lcy)) * N + (s.o0x + lcx);
+        const c64 kap = kaps[gc];
+        const double kk = kr[gc];
+        const bool rxl = (s.robin & 1) && lcx == 0 && lx == 0;
+        const bool rxh = (s.robin & 2) && lcx == nc[0] - 1 && lx == P;
+        const bool ryl = (s.robin & 4) && lcy == 0 && ly == 0;
+        const bool ryh = (s.robin & 8) && lcy == nc[1] - 1 && ly == P;
+        const bool rzl = (s.robin & 16) && lcz == 0 && lz == 0;
+        const bool rzh = (s.robin & 32) && lcz == nc[2] - 1 && lz == P;
+        for (int bz = 0; bz < NP; ++bz) {
+          const double Kz = ref.K[lz * NP + bz], Mz = ref.M[lz * NP + bz];
+          for (int by = 0; by < NP; ++by) {
+            const double Ky = ref.K[ly * NP + by], My = ref.M[ly * NP + by];
+            for (int bx = 0; bx < NP; ++bx) {
+              const double Kx = ref.K[lx * NP + bx], Mx = ref.M[lx * NP + bx];
+              const double mmm = h3 * Mz * My * Mx;
+              c64 v = {h * (Kz * My * Mx + Mz * Ky * Mx + Mz * My * Kx) - kap.re * mmm,
+                       -kap.im * mmm};
+              if ((rxl && bx == 0) || (rxh && bx == P)) v.im -= kk * h2 * Mz * My;
+              if ((ryl && by == 0) || (ryh && by == P)) v.im -= kk * h2 * Mz * Mx;
+              if ((rzl && bz == 0) || (rzh && bz == P)) v.im -= kk * h2 * My * Mx;
+              const int col = ((lcz * P + bz) * s.noy + lcy * P + by) * s.nox + lcx * P + bx;
+              row[col] = row[col] + v;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // B_i^T[k][j] = (A^{-1})[u_j][k] / L_{u_j} in the storage precision.
 template <typename TB>
 __global__ __launch_bounds__(256) void k_extract_b(const Sub *__restrict__ subs, int s0,
@@ -258,11 +321,10 @@ __global__ __launch_bounds__(256) void k_extract_b(const Sub *__restrict__ subs,
   const c64 *Ab = A + blockIdx.z * stride;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= s.nU) return;
-  const int jx = j % s.nux, jy = j / s.nux;
-  const int gx = s.u0x * P + jx, gy = s.u0y * P + jy;
-  const double invL = 1.0 / (double)(nblk[2 * gx + 1] * nblk[2 * gy + 1]);
-  const int ox = (s.u0x - s.o0x) * P + jx, oy = (s.u0y - s.o0y) * P + jy;
-  const int uj = oy * s.nox + ox;
+  int gn[3], uj;
+  u_node(s, j, P, gn, uj);
+  const double invL =
+      1.0 / (double)(nblk[2 * gn[0] + 1] * nblk[2 * gn[1] + 1] * nblk[2 * gn[2] + 1]);
   const c64 *arow = Ab + (long long)uj * ld;
   for (int k = blockIdx.y; k < s.nOm; k += gridDim.y) {
     const c64 v = arow[k];
@@ -298,7 +360,14 @@ int setup_subdomain_operators(th_ctx *c) {
     const int nb = std::min(batch, nsub - s0);
     TH_HIP_CHECK_RET(hipMemsetAsync(work, 0, (size_t)nb * mat * sizeof(c64), s));
     dim3 ga(ceil_div(npad, 256), nb);
-    switch (c->P) {
+    if (c->dim == 3) {
+      if (c->P == 2)
+        hipLaunchKernelGGL((k_assemble_sub3<2>), ga, dim3(256), 0, s, c->d_subs, s0, work, npad,
+                           mat, (const c64 *)c->d_kaps, (const double *)c->d_k, c->ref, c->h, c->N);
+      else
+        hipLaunchKernelGGL((k_assemble_sub3<4>), ga, dim3(256), 0, s, c->d_subs, s0, work, npad,
+                           mat, (const c64 *)c->d_kaps, (const double *)c->d_k, c->ref, c->h, c->N);
+    } else switch (c->P) {
 #define TH_ASM(PP)                                                                              \
   case PP:                                                                                      \
     hipLaunchKernelGGL((k_assemble_sub<PP>), ga, dim3(256), 0, s, c->d_subs, s0, work, npad,    \

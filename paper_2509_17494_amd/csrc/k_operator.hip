@@ -1,7 +1,7 @@
 // Matrix-free fine operator: out = f + sgn * (A u) for the Q_p Galerkin matrix
 // of a(u, v) = int grad u . grad v - int kappa u v - int_{Gamma_abs} i k u v
 // (eq. bilin_form; kappa = k^2 + i eps, or the shifted coefficient of A_s,
-// Sec. 4.1) on the 2-D N x N mesh.
+// Sec. 4.1) on the N x N (2-D) or N x N x N (3-D) mesh.
 //
 // Per cell of size h the operator is  K1 (x) M1 + M1 (x) K1 - kappa_c h^2 M1 (x) M1
 // (1-D reference matrices on [0,1]; the 2-D stiffness does not scale with h),
@@ -148,6 +148,203 @@ __global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3-D: per cell of size h the operator is
+//   h (K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1 + M1 (x) M1 (x) K1) - kappa_c h^3 M1 (x) M1 (x) M1
+// (z (x) y (x) x), plus -i k_c h^2 M1 (x) M1 on cell faces lying on an absorbing
+// side.  A workgroup owns the nodes of a TC^3 cell tile (low faces included)
+// and stages the nodes of the tile grown by one cell on the low sides in LDS.
+//   pass 1: per cell, node line (bz, ay): the x and y contractions
+//           A1 = (My (x) Mx) u,  G = h (My (x) Kx + Ky (x) Mx) u
+//   pass 2: every owned node sums, over the (at most 8) cells containing it,
+//           the z contraction  Mz (G - kappa h^3 A1) + h Kz A1,
+// again a fixed-order gather.  Orders 2 and 4 are provided in 3-D.
+template <int P> struct Tile3Of;
+template <> struct Tile3Of<2> { static constexpr int TC = 4; };
+template <> struct Tile3Of<4> { static constexpr int TC = 2; };
+
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_apply3d(FineOp op, Ref1D ref, const cx<T> *__restrict__ u,
+                                                 const cx<T> *__restrict__ f,
+                                                 cx<T> *__restrict__ out, T sgn, int ntile) {
+  constexpr int TC = Tile3Of<P>::TC;
+  constexpr int NP = P + 1;
+  constexpr int NC = TC + 1;          // staged cells per direction
+  constexpr int NN = NC * P + 1;      // staged nodes per direction
+  constexpr int CL = NP * NP * NP;    // partials per cell
+  __shared__ cx<T> Us[NN * NN * NN];
+  __shared__ cx<T> A1s[NC * NC * NC * CL];
+  __shared__ cx<T> Gs[NC * NC * NC * CL];
+  __shared__ T sK[NP * NP], sM[NP * NP];
+
+  const int N = op.N, n1 = op.n1;
+  const long long rb = (long long)blockIdx.y * op.nf;
+  u += rb;
+  out += rb;
+  if (f) f += rb;
+
+  const int tx = blockIdx.x % ntile, tt = blockIdx.x / ntile;
+  const int ty = tt % ntile, tz = tt / ntile;
+  const int cx0 = tx * TC, cy0 = ty * TC, cz0 = tz * TC;
+  const int cxs = max(cx0 - 1, 0), cxe = min(cx0 + TC, N);
+  const int cys = max(cy0 - 1, 0), cye = min(cy0 + TC, N);
+  const int czs = max(cz0 - 1, 0), cze = min(cz0 + TC, N);
+  const int ncx = cxe - cxs, ncy = cye - cys, ncz = cze - czs;
+  const int nnx = ncx * P + 1, nny = ncy * P + 1, nnz = ncz * P + 1;
+
+  for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) {
+    sK[i] = (T)ref.K[i];
+    sM[i] = (T)ref.M[i];
+  }
+  for (int i = threadIdx.x; i < nnx * nny * nnz; i += blockDim.x) {
+    const int jx = i % nnx, t = i / nnx;
+    const int jy = t % nny, jz = t / nny;
+    Us[(jz * NN + jy) * NN + jx] =
+        u[((long long)(czs * P + jz) * n1 + cys * P + jy) * n1 + cxs * P + jx];
+  }
+  __syncthreads();
+
+  const T h = (T)op.h;
+  // pass 1: items (cell, bz, ay)
+  const int ncell = ncx * ncy * ncz;
+  for (int it = threadIdx.x; it < ncell * NP * NP; it += blockDim.x) {
+    const int ay = it % NP, t1 = it / NP;
+    const int bz = t1 % NP, cl = t1 / NP;
+    const int lx = cl % ncx, t2 = cl / ncx;
+    const int ly = t2 % ncy, lz = t2 / ncy;
+    cx<T> a1[NP], b1[NP], c1[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) a1[a] = b1[a] = c1[a] = cx<T>{0, 0};
+    const cx<T> *ub = Us + ((lz * P + bz) * NN + ly * P) * NN + lx * P;
+#pragma unroll
+    for (int by = 0; by < NP; ++by) {
+      cx<T> uv[NP];
+#pragma unroll
+      for (int bx = 0; bx < NP; ++bx) uv[bx] = ub[by * NN + bx];
+      const T my = sM[ay * NP + by], ky = sK[ay * NP + by];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        cx<T> wm = {0, 0}, wk = {0, 0};
+#pragma unroll
+        for (int bx = 0; bx < NP; ++bx) {
+          rmac(wm, sM[a * NP + bx], uv[bx]);
+          rmac(wk, sK[a * NP + bx], uv[bx]);
+        }
+        rmac(a1[a], my, wm);
+        rmac(b1[a], my, wk);
+        rmac(c1[a], ky, wm);
+      }
+    }
+    const int cell = (lz * NC + ly) * NC + lx;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      const int o = cell * CL + (bz * NP + ay) * NP + a;
+      A1s[o] = a1[a];
+      cx<T> g = b1[a] + c1[a];
+      Gs[o] = cx<T>{h * g.re, h * g.im};
+    }
+  }
+  __syncthreads();
+
+  // pass 2 over owned nodes
+  const int NPn = N * P;
+  const int ix0 = cx0 * P, iy0 = cy0 * P, iz0 = cz0 * P;
+  const int ix1 = (cx0 + TC >= N) ? NPn + 1 : (cx0 + TC) * P;
+  const int iy1 = (cy0 + TC >= N) ? NPn + 1 : (cy0 + TC) * P;
+  const int iz1 = (cz0 + TC >= N) ? NPn + 1 : (cz0 + TC) * P;
+  const int nox = ix1 - ix0, noy = iy1 - iy0, noz = iz1 - iz0;
+  const T h3 = (T)(op.h * op.h * op.h), h2 = (T)(op.h * op.h);
+
+  for (int it = threadIdx.x; it < nox * noy * noz; it += blockDim.x) {
+    const int jx = it % nox, t = it / nox;
+    const int jy = t % noy, jz = t / noy;
+    const int ix = ix0 + jx, iy = iy0 + jy, iz = iz0 + jz;
+    const int chx = min(ix / P, N - 1), chy = min(iy / P, N - 1), chz = min(iz / P, N - 1);
+    const int ncellx = (ix % P == 0 && ix > 0 && ix < NPn) ? 2 : 1;
+    const int ncelly = (iy % P == 0 && iy > 0 && iy < NPn) ? 2 : 1;
+    const int ncellz = (iz % P == 0 && iz > 0 && iz < NPn) ? 2 : 1;
+    cx<T> acc = {0, 0};
+    for (int qz = ncellz - 1; qz >= 0; --qz) {
+      const int czq = chz - qz, az = iz - czq * P;
+      for (int qy = ncelly - 1; qy >= 0; --qy) {
+        const int cyq = chy - qy, ay = iy - cyq * P;
+        for (int qx = ncellx - 1; qx >= 0; --qx) {
+          const int cxq = chx - qx, ax = ix - cxq * P;
+          const c64 kd = op.kap[((long long)czq * N + cyq) * N + cxq];
+          const cx<T> kh = {(T)kd.re * h3, (T)kd.im * h3};
+          const int cell = ((czq - czs) * NC + (cyq - cys)) * NC + (cxq - cxs);
+#pragma unroll
+          for (int bz = 0; bz < NP; ++bz) {
+            const int o = cell * CL + (bz * NP + ay) * NP + ax;
+            const cx<T> a1 = A1s[o], g = Gs[o];
+            const T mz = sM[az * NP + bz], kz = sK[az * NP + bz];
+            rmac(acc, mz, g - kh * a1);
+            rmac(acc, h * kz, a1);
+          }
+        }
+      }
+    }
+    // absorbing faces: -i h^2 k_c (M1 (x) M1 over the face) u
+    if (op.robin) {
+      cx<T> s = {0, 0};
+      const int idx[3] = {ix, iy, iz};
+      const int ch[3] = {chx, chy, chz};
+      const int nq[3] = {ncellx, ncelly, ncellz};
+      const int cs[3] = {cxs, cys, czs};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const bool lo = idx[d] == 0 && (op.robin & (1 << (2 * d)));
+        const bool hi = idx[d] == NPn && (op.robin & (2 << (2 * d)));
+        if (!lo && !hi) continue;
+        const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+        int cc[3];
+        cc[d] = lo ? 0 : N - 1;
+        for (int q2 = nq[e2] - 1; q2 >= 0; --q2) {
+          cc[e2] = ch[e2] - q2;
+          const int a2 = idx[e2] - cc[e2] * P;
+          for (int q1 = nq[e1] - 1; q1 >= 0; --q1) {
+            cc[e1] = ch[e1] - q1;
+            const int a1 = idx[e1] - cc[e1] * P;
+            const T kk = (T)op.kr[((long long)cc[2] * N + cc[1]) * N + cc[0]];
+            cx<T> m = {0, 0};
+            for (int b2 = 0; b2 < NP; ++b2) {
+              cx<T> m1 = {0, 0};
+              for (int b1 = 0; b1 < NP; ++b1) {
+                int l[3];
+                l[d] = idx[d] - cs[d] * P;
+                l[e1] = (cc[e1] - cs[e1]) * P + b1;
+                l[e2] = (cc[e2] - cs[e2]) * P + b2;
+                rmac(m1, sM[a1 * NP + b1], Us[(l[2] * NN + l[1]) * NN + l[0]]);
+              }
+              rmac(m, sM[a2 * NP + b2], m1);
+            }
+            rmac(s, kk, m);
+          }
+        }
+      }
+      acc.re += h2 * s.im;
+      acc.im -= h2 * s.re;
+    }
+    const long long g = ((long long)iz * n1 + iy) * n1 + ix;
+    cx<T> o = f ? f[g] : cx<T>{0, 0};
+    o.re = fma(sgn, acc.re, o.re);
+    o.im = fma(sgn, acc.im, o.im);
+    out[g] = o;
+  }
+}
+
+template <int P, typename T>
+static int launch_apply3_t(const FineOp &op, const Ref1D &ref, const void *u, const void *f,
+                           void *out, int nrhs, double sgn, hipStream_t s) {
+  constexpr int TC = Tile3Of<P>::TC;
+  const int nt = ceil_div(op.N, TC);
+  dim3 grid(nt * nt * nt, nrhs);
+  hipLaunchKernelGGL((k_apply3d<P, T>), grid, dim3(256), 0, s, op, ref, (const cx<T> *)u,
+                     (const cx<T> *)f, (cx<T> *)out, (T)sgn, nt);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
 template <int P, typename T>
 static int launch_apply_t(const FineOp &op, const Ref1D &ref, const void *u, const void *f,
                           void *out, int nrhs, double sgn, hipStream_t s) {
@@ -161,6 +358,16 @@ static int launch_apply_t(const FineOp &op, const Ref1D &ref, const void *u, con
 
 int launch_apply(const FineOp &op, const Ref1D &ref, const void *u, const void *f, void *out,
                  int nrhs, bool f32, double sgn, hipStream_t s) {
+  if (op.dim == 3) {
+    switch (op.P) {
+      case 2: return f32 ? launch_apply3_t<2, float>(op, ref, u, f, out, nrhs, sgn, s)
+                         : launch_apply3_t<2, double>(op, ref, u, f, out, nrhs, sgn, s);
+      case 4: return f32 ? launch_apply3_t<4, float>(op, ref, u, f, out, nrhs, sgn, s)
+                         : launch_apply3_t<4, double>(op, ref, u, f, out, nrhs, sgn, s);
+    }
+    set_error("3-D problems support orders 2 and 4");
+    return TH_EUNSUPPORTED;
+  }
   switch (op.P) {
     case 2: return f32 ? launch_apply_t<2, float>(op, ref, u, f, out, nrhs, sgn, s)
                        : launch_apply_t<2, double>(op, ref, u, f, out, nrhs, sgn, s);

@@ -4,7 +4,7 @@
 // subdomain, and the averaged update (eq. RAS_like_update) sets
 //   v_j = (1/L_j) sum_{i : j in Dofs(U^(i))} (w_i)_j .
 // Setup stores B_i = diag(1/L_j) R_{U_i} (A_s^(i))^{-1} (n_U x n_Omega; the
-// weights 1/L_j in {1, 1/2, 1/4} are exact powers of two), so the apply is
+// weights 1/L_j in {1, 1/2, 1/4, 1/8} are exact powers of two), so the apply is
 //   gather  X_i = R_{Omega_i} r            (structured box, no index maps)
 //   GEMV    Y_i = B_i X_i                  (k_dd_apply: streams B_i once)
 //   gather  v_j = sum_i (Y_i)_j            (k_dd_accumulate: fixed order)
@@ -41,8 +41,7 @@ __global__ __launch_bounds__(256) void k_dd_apply(const Sub *__restrict__ subs,
       for (int t = threadIdx.x; t < kc * NR; t += 256) {
         const int kk = t / NR, q = t - kk * NR;
         const int k = k0 + kk;
-        const int ky = k / s.nox, kx = k - ky * s.nox;
-        const long long g = (long long)(s.o0y * P + ky) * n1 + s.o0x * P + kx;
+        const long long g = om_node(s, k, P, n1);
         Xs[t] = (r0 + q < nrhs) ? r[(long long)(r0 + q) * nf + g] : cx<T>{0, 0};
       }
       __syncthreads();
@@ -77,16 +76,20 @@ __global__ __launch_bounds__(256) void k_dd_accumulate(const Sub *__restrict__ s
   u += rhs * nf;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < nf;
        g += (long long)gridDim.x * blockDim.x) {
-    const int iy = (int)(g / n1), ix = (int)(g - (long long)iy * n1);
+    const int ix = (int)(g % n1);
+    const long long t = g / n1;
+    const int iy = (int)(t % n1), iz = (int)(t / n1);  // iz = 0 in 2-D
     const int bx0 = nblk[2 * ix], nbx = nblk[2 * ix + 1];
     const int by0 = nblk[2 * iy], nby = nblk[2 * iy + 1];
+    const int bz0 = nblk[2 * iz], nbz = nblk[2 * iz + 1];
     cx<T> acc = {0, 0};
-    for (int by = by0; by < by0 + nby; ++by)
-      for (int bx = bx0; bx < bx0 + nbx; ++bx) {
-        const Sub &s = subs[by * M + bx];
-        const int lx = ix - s.u0x * P, ly = iy - s.u0y * P;
-        acc = acc + Y[s.yoff + (long long)ly * s.nux + lx];
-      }
+    for (int bz = bz0; bz < bz0 + nbz; ++bz)
+      for (int by = by0; by < by0 + nby; ++by)
+        for (int bx = bx0; bx < bx0 + nbx; ++bx) {
+          const Sub &s = subs[(bz * M + by) * M + bx];
+          const int lx = ix - s.u0x * P, ly = iy - s.u0y * P, lz = iz - s.u0z * P;
+          acc = acc + Y[s.yoff + ((long long)lz * s.nuy + ly) * s.nux + lx];
+        }
     u[g] = assign ? acc : u[g] + acc;
   }
 }

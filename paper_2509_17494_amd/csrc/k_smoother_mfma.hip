@@ -80,8 +80,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_dd_mfma(const Sub *__restrict__ 
           const int k = k0 + kk;
           unsigned short vr = 0, vi = 0;
           if (q < nr && k < s.nOm) {
-            const int ky = k / s.nox, kx = k - ky * s.nox;
-            const long long g = (long long)(s.o0y * P + ky) * n1 + s.o0x * P + kx;
+            const long long g = om_node(s, k, P, n1);
             const cx<T> v = r[(long long)(r0 + q) * nf + g];
             vr = f2bf((float)v.re);
             vi = f2bf((float)v.im);
@@ -156,10 +155,10 @@ __global__ __launch_bounds__(256) void k_extract_b_mfma(const Sub *__restrict__ 
       const int k = kb * MF_KB + (lane / 16) * 8 + e;
       vr[e] = vi[e] = 0;
       if (row < s.nU && k < s.nOm) {
-        const int jx = row % s.nux, jy = row / s.nux;
-        const int gx = s.u0x * P + jx, gy = s.u0y * P + jy;
-        const double invL = 1.0 / (double)(nblk[2 * gx + 1] * nblk[2 * gy + 1]);
-        const int uj = ((s.u0y - s.o0y) * P + jy) * s.nox + (s.u0x - s.o0x) * P + jx;
+        int gn[3], uj;
+        u_node(s, row, P, gn, uj);
+        const double invL =
+            1.0 / (double)(nblk[2 * gn[0] + 1] * nblk[2 * gn[1] + 1] * nblk[2 * gn[2] + 1]);
         const c64 v = Ab[(long long)uj * ld + k];
         vr[e] = f2bf((float)(v.re * invL));
         vi[e] = f2bf((float)(v.im * invL));

@@ -4,11 +4,11 @@
 //
 // On each fine cell the interpolant is a tensor product of 1-D degree-p/2
 // Lagrange interpolants through the r+1 = p/2+1 coarse points of the cell, so
-// the global operator is P1 (x) P1 with P1 the (pN+1) x (rN+1) 1-D matrix
+// the global operator is P1 (x) P1 (x P1 in 3-D) with P1 the (pN+1) x (rN+1) 1-D matrix
 // P1[i][J] = L[a][b], (c, a) = cell and local index of fine node i, b = J - c r
 // (cell-edge nodes get the same value from either cell: they coincide with
 // coarse points).  Both kernels are gathers (no atomics): prolongation per
-// fine node over the (r+1)^2 coarse points of its cell, restriction per
+// fine node over the (r+1)^d coarse points of its cell, restriction per
 // coarse point over the fine nodes of the cells around it, every fine node
 // counted once.
 #include "ctx.hpp"
@@ -23,33 +23,48 @@ __device__ __forceinline__ double p1w(const double *L, int N, int i, int J) {
   return (b >= 0 && b <= R) ? L[a * (R + 1) + b] : 0.0;
 }
 
-template <int P, typename T>
-__global__ __launch_bounds__(256) void k_prolong2d(int N, Ref1D ref, const cx<T> *__restrict__ uc,
-                                                   cx<T> *__restrict__ u, T omega, long long nf,
-                                                   long long ncn) {
+// The grids are n1^DIM (fine) and nc1^DIM (coarse), x fastest; in 2-D the z
+// loops collapse to one iteration with unit weight.
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(256) void k_prolong(int N, Ref1D ref, const cx<T> *__restrict__ uc,
+                                                 cx<T> *__restrict__ u, T omega, long long nf,
+                                                 long long ncn) {
   constexpr int R = P / 2;
+  constexpr int RZ = DIM == 3 ? R : 0;
   const int n1 = N * P + 1, nc1 = N * R + 1;
   const long long rhs = blockIdx.y;
   uc += rhs * ncn;
   u += rhs * nf;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < nf;
        g += (long long)gridDim.x * blockDim.x) {
-    const int iy = (int)(g / n1), ix = (int)(g - (long long)iy * n1);
+    const int ix = (int)(g % n1);
+    const long long t = g / n1;
+    const int iy = (int)(t % n1), iz = (int)(t / n1);
     const int cxq = min(ix / P, N - 1), cyq = min(iy / P, N - 1);
-    const int ax = ix - cxq * P, ay = iy - cyq * P;
+    const int czq = DIM == 3 ? min(iz / P, N - 1) : 0;
+    const int ax = ix - cxq * P, ay = iy - cyq * P, az = iz - czq * P;
     cx<T> acc = {0, 0};
 #pragma unroll
-    for (int by = 0; by <= R; ++by) {
-      const T wy = (T)ref.L[ay * (R + 1) + by];
-      if (wy == (T)0) continue;
-      cx<T> row = {0, 0};
+    for (int bz = 0; bz <= RZ; ++bz) {
+      const T wz = DIM == 3 ? (T)ref.L[az * (R + 1) + bz] : (T)1;
+      if (wz == (T)0) continue;
+      cx<T> pl = {0, 0};
 #pragma unroll
-      for (int bx = 0; bx <= R; ++bx) {
-        const T wx = (T)ref.L[ax * (R + 1) + bx];
-        if (wx == (T)0) continue;
-        rmac(row, wx, uc[(long long)(cyq * R + by) * nc1 + cxq * R + bx]);
+      for (int by = 0; by <= R; ++by) {
+        const T wy = (T)ref.L[ay * (R + 1) + by];
+        if (wy == (T)0) continue;
+        cx<T> row = {0, 0};
+        const cx<T> *ucr = uc + ((long long)(czq * R + bz) * nc1 + cyq * R + by) * nc1 + cxq * R;
+#pragma unroll
+        for (int bx = 0; bx <= R; ++bx) {
+          const T wx = (T)ref.L[ax * (R + 1) + bx];
+          if (wx == (T)0) continue;
+          rmac(row, wx, ucr[bx]);
+        }
+        rmac(pl, wy, row);
       }
-      rmac(acc, wy, row);
+      if (DIM == 3) rmac(acc, wz, pl);
+      else acc = pl;
     }
     cx<T> o = u[g];
     o.re = fma(omega, acc.re, o.re);
@@ -58,10 +73,10 @@ __global__ __launch_bounds__(256) void k_prolong2d(int N, Ref1D ref, const cx<T>
   }
 }
 
-template <int P, typename T>
-__global__ __launch_bounds__(256) void k_restrict2d(int N, Ref1D ref, const cx<T> *__restrict__ r,
-                                                    cx<T> *__restrict__ rc, long long nf,
-                                                    long long ncn) {
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(256) void k_restrict(int N, Ref1D ref, const cx<T> *__restrict__ r,
+                                                  cx<T> *__restrict__ rc, long long nf,
+                                                  long long ncn) {
   constexpr int R = P / 2;
   const int n1 = N * P + 1, nc1 = N * R + 1;
   const long long rhs = blockIdx.y;
@@ -69,47 +84,62 @@ __global__ __launch_bounds__(256) void k_restrict2d(int N, Ref1D ref, const cx<T
   rc += rhs * ncn;
   for (long long G = blockIdx.x * (long long)blockDim.x + threadIdx.x; G < ncn;
        G += (long long)gridDim.x * blockDim.x) {
-    const int Jy = (int)(G / nc1), Jx = (int)(G - (long long)Jy * nc1);
-    // cells whose coarse points include J: c R <= J <= c R + R
-    const int clx = max((Jx % R == 0) ? Jx / R - 1 : Jx / R, 0), chx = min(Jx / R, N - 1);
-    const int cly = max((Jy % R == 0) ? Jy / R - 1 : Jy / R, 0), chy = min(Jy / R, N - 1);
-    const int ixs = clx * P, ixe = (chx + 1) * P;  // inclusive range of fine nodes
-    const int iys = cly * P, iye = (chy + 1) * P;
+    const int Jx = (int)(G % nc1);
+    const long long t = G / nc1;
+    const int Jy = (int)(t % nc1), Jz = (int)(t / nc1);
+    // cells whose coarse points include J: c R <= J <= c R + R; fine node range of those cells
+    const int ixs = max((Jx % R == 0) ? Jx / R - 1 : Jx / R, 0) * P;
+    const int ixe = (min(Jx / R, N - 1) + 1) * P;
+    const int iys = max((Jy % R == 0) ? Jy / R - 1 : Jy / R, 0) * P;
+    const int iye = (min(Jy / R, N - 1) + 1) * P;
+    const int izs = DIM == 3 ? max((Jz % R == 0) ? Jz / R - 1 : Jz / R, 0) * P : 0;
+    const int ize = DIM == 3 ? (min(Jz / R, N - 1) + 1) * P : 0;
     cx<T> acc = {0, 0};
-    for (int iy = iys; iy <= iye; ++iy) {
-      const T wy = (T)p1w<P>(ref.L, N, iy, Jy);
-      if (wy == (T)0) continue;
-      cx<T> row = {0, 0};
-      const cx<T> *rr = r + (long long)iy * n1;
-      for (int ix = ixs; ix <= ixe; ++ix) {
-        const T wx = (T)p1w<P>(ref.L, N, ix, Jx);
-        if (wx == (T)0) continue;
-        rmac(row, wx, rr[ix]);
+    for (int iz = izs; iz <= ize; ++iz) {
+      const T wz = DIM == 3 ? (T)p1w<P>(ref.L, N, iz, Jz) : (T)1;
+      if (wz == (T)0) continue;
+      cx<T> pl = {0, 0};
+      for (int iy = iys; iy <= iye; ++iy) {
+        const T wy = (T)p1w<P>(ref.L, N, iy, Jy);
+        if (wy == (T)0) continue;
+        cx<T> row = {0, 0};
+        const cx<T> *rr = r + ((long long)iz * n1 + iy) * n1;
+        for (int ix = ixs; ix <= ixe; ++ix) {
+          const T wx = (T)p1w<P>(ref.L, N, ix, Jx);
+          if (wx == (T)0) continue;
+          rmac(row, wx, rr[ix]);
+        }
+        rmac(pl, wy, row);
       }
-      rmac(acc, wy, row);
+      if (DIM == 3) rmac(acc, wz, pl);
+      else acc = pl;
     }
     rc[G] = acc;
   }
 }
 
-template <int P, typename T>
+static long long ipow(long long b, int e) {
+  long long r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+template <int DIM, int P, typename T>
 static int prolong_t(int N, const Ref1D &ref, const void *uc, void *u, double omega, int nrhs,
                      hipStream_t s) {
-  const long long nf = (long long)(N * P + 1) * (N * P + 1);
-  const long long ncn = (long long)(N * (P / 2) + 1) * (N * (P / 2) + 1);
+  const long long nf = ipow(N * P + 1, DIM), ncn = ipow(N * (P / 2) + 1, DIM);
   int blocks = (int)std::min<long long>(ceil_div_ll(nf, 256), 65535);
-  hipLaunchKernelGGL((k_prolong2d<P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
+  hipLaunchKernelGGL((k_prolong<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
                      (const cx<T> *)uc, (cx<T> *)u, (T)omega, nf, ncn);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
 
-template <int P, typename T>
+template <int DIM, int P, typename T>
 static int restrict_t(int N, const Ref1D &ref, const void *r, void *rc, int nrhs, hipStream_t s) {
-  const long long nf = (long long)(N * P + 1) * (N * P + 1);
-  const long long ncn = (long long)(N * (P / 2) + 1) * (N * (P / 2) + 1);
+  const long long nf = ipow(N * P + 1, DIM), ncn = ipow(N * (P / 2) + 1, DIM);
   int blocks = (int)std::min<long long>(ceil_div_ll(ncn, 256), 65535);
-  hipLaunchKernelGGL((k_restrict2d<P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
+  hipLaunchKernelGGL((k_restrict<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
                      (const cx<T> *)r, (cx<T> *)rc, nf, ncn);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
@@ -123,24 +153,40 @@ static int restrict_t(int N, const Ref1D &ref, const void *r, void *rc, int nrhs
     case 8: return F32_ ? CALL_F(8) : CALL_D(8);  \
   }
 
-int launch_prolong(int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
+int launch_prolong(int dim, int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
                    int nrhs, bool f32, hipStream_t s) {
-#define CF(p) prolong_t<p, float>(N, ref, uc, u, omega, nrhs, s)
-#define CD(p) prolong_t<p, double>(N, ref, uc, u, omega, nrhs, s)
-  TH_DISPATCH_P(P, f32, CF, CD)
+  if (dim == 3) {
+#define CF(p) prolong_t<3, p, float>(N, ref, uc, u, omega, nrhs, s)
+#define CD(p) prolong_t<3, p, double>(N, ref, uc, u, omega, nrhs, s)
+    TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
+  } else {
+#define CF(p) prolong_t<2, p, float>(N, ref, uc, u, omega, nrhs, s)
+#define CD(p) prolong_t<2, p, double>(N, ref, uc, u, omega, nrhs, s)
+    TH_DISPATCH_P(P, f32, CF, CD)
+#undef CF
+#undef CD
+  }
   set_error("unsupported order");
   return TH_EUNSUPPORTED;
 }
 
-int launch_restrict(int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs, bool f32,
-                    hipStream_t s) {
-#define CF(p) restrict_t<p, float>(N, ref, r, rc, nrhs, s)
-#define CD(p) restrict_t<p, double>(N, ref, r, rc, nrhs, s)
-  TH_DISPATCH_P(P, f32, CF, CD)
+int launch_restrict(int dim, int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs,
+                    bool f32, hipStream_t s) {
+  if (dim == 3) {
+#define CF(p) restrict_t<3, p, float>(N, ref, r, rc, nrhs, s)
+#define CD(p) restrict_t<3, p, double>(N, ref, r, rc, nrhs, s)
+    TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
+  } else {
+#define CF(p) restrict_t<2, p, float>(N, ref, r, rc, nrhs, s)
+#define CD(p) restrict_t<2, p, double>(N, ref, r, rc, nrhs, s)
+    TH_DISPATCH_P(P, f32, CF, CD)
+#undef CF
+#undef CD
+  }
   set_error("unsupported order");
   return TH_EUNSUPPORTED;
 }

@@ -92,6 +92,13 @@ th_status th_plain_fit(const double *samples, int n, double *e_out, double *q_ou
   return TH_OK;
 }
 
+th_status th_plain_fit3d(const double *samples, int n, double *e_out, double *q_out) {
+  std::string msg;
+  if (check_samples(samples, n, msg) != TH_OK) return TH_EINVAL;
+  plain_fit27_batch(samples, n, e_out, q_out);
+  return TH_OK;
+}
+
 th_status th_mlp_num_params(int *n_params) {
   if (!n_params) return TH_EINVAL;
   *n_params = mlp_num_params();
