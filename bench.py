@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C5"])
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
     ap.add_argument("--precond", default=None, choices=["c128", "c64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -50,9 +50,13 @@ def parse():
 def workload(name):
     import synthetic as syn
     cfg = syn.config(name)
-    spec = dict(l_dd=cfg["l_dd"], alpha_s=cfg["alpha_s"], gemm="f64", precond="c128")
+    spec = dict(l_dd=cfg["l_dd"], alpha_s=cfg["alpha_s"], gemm="f64", precond="c128",
+                coarse="qsfem")
     if name == "C3":
         spec.update(gemm="bf16", precond="c64")
+    if name == "C4":  # BF16 operators, complex64 preconditioner, dispersion-matched 27-point
+        # restarted GMRES bounds the Krylov basis (2 x 81 x 8 RHS x 3.4M DOF x 16 B = 71 GB)
+        spec.update(gemm="bf16", precond="c64", coarse="plainfit", restart=80, maxit=400)
     return cfg, spec
 
 
@@ -64,7 +68,10 @@ def dd_apply_bytes(info_sub, nrhs, mat_bytes, vec_bytes):
     return b + v
 
 
-def subdomain_sizes(N, p, l_dd):
+def subdomain_sizes(N, p, l_dd, dim=2):
+    """(n_U, n_Omega) of every subdomain: balanced blocks of about l_dd cells,
+    Omega = U grown by one cell layer clipped to the domain."""
+    import itertools
     import math
     M = math.ceil(N / l_dd)
     base, rem = divmod(N, M)
@@ -72,13 +79,11 @@ def subdomain_sizes(N, p, l_dd):
     starts = [0]
     for s in sizes:
         starts.append(starts[-1] + s)
+    nu1 = [sizes[b] * p + 1 for b in range(M)]
+    no1 = [(min(starts[b + 1] + 1, N) - max(starts[b] - 1, 0)) * p + 1 for b in range(M)]
     out = []
-    for by in range(M):
-        for bx in range(M):
-            ux, uy = sizes[bx], sizes[by]
-            ox = min(starts[bx + 1] + 1, N) - max(starts[bx] - 1, 0)
-            oy = min(starts[by + 1] + 1, N) - max(starts[by] - 1, 0)
-            out.append(((ux * p + 1) * (uy * p + 1), (ox * p + 1) * (oy * p + 1)))
+    for idx in itertools.product(range(M), repeat=dim):
+        out.append((math.prod(nu1[b] for b in idx), math.prod(no1[b] for b in idx)))
     return out
 
 
@@ -98,10 +103,37 @@ def traffic_entry(workload_name):
         return None
 
 
+def cpu_baseline_3d():
+    """The oracle on the reduced 3-D cube: C4's recipe (GRF correlation 0.1,
+    speeds 1.5..4, 10 points per minimum wavelength, Q2, 8-cell subdomains,
+    8 sources at {1/4, 3/4}^3) on 16^3 cells, one source, solved to 1e-6."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    import synthetic as syn
+    from oracle.twogrid import TwoGrid
+    n, p = 16, 2
+    k = syn.wavenumber_from_speed(syn.grf_speed(n, 3, 0.1, 1.5, 4.0, seed=0), n * p / 10.0)
+    t0 = time.perf_counter()
+    tg = TwoGrid(p, k, alpha_s=0.5, l_dd=8)
+    t_setup = time.perf_counter() - t0
+    f = syn.gaussian_load(n, p, [[0.25, 0.25, 0.25]], 2.0 / n, dim=3)[0]
+    t0 = time.perf_counter()
+    _, its, _ = tg.gmres(f, 1e-6)
+    t_solve = time.perf_counter() - t0
+    ndof = (n * p + 1) ** 3
+    return {"value": ndof * its / t_solve, "unit": "DOF*cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"C4 recipe on a 16^3-cell cube ({ndof} DOF), Q2, l_dd=8, one source, "
+                      f"exact-wavenumber 27-point coarse stencil, oracle GMRES to 1e-6: {its} "
+                      f"cycles in {t_solve:.2f} s (setup {t_setup:.1f} s excluded), "
+                      f"single-threaded numpy/scipy"}
+
+
 def cpu_baseline(cfg_name):
     """The FP64 oracle timed on this host on a bounded sample: a 96x96-cell
     window of the same medium, order and k h with the same subdomain size,
     solved to 1e-6 by the oracle's GMRES; rate = DOF x cycles / solve time."""
+    if cfg_name == "C4":
+        return cpu_baseline_3d()
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import numpy as np
     import synthetic as syn
@@ -137,16 +169,17 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
 
     cfg, spec = workload(name)
     precond = precond or spec["precond"]
+    kry = {k: spec[k] for k in ("restart", "maxit") if k in spec}
     if gemm:
         spec["gemm"] = gemm
-    N, p = cfg["n"], cfg["p"]
-    f_host = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"])
+    N, p, dim = cfg["n"], cfg["p"], cfg.get("dim", 2)
+    f_host = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"], dim=dim)
     R = f_host.shape[0]
     stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
     with torch.cuda.stream(stream):
         t0 = time.perf_counter()
         s = TwoGridSolver(cfg["k"], order=p, alpha_s=spec["alpha_s"], l_dd=spec["l_dd"],
-                          gemm=spec["gemm"], max_rhs=R)
+                          gemm=spec["gemm"], max_rhs=R, coarse=spec["coarse"])
         t_setup = time.perf_counter() - t0
         info = s.info()
         f = torch.from_numpy(f_host).to("cuda")
@@ -156,7 +189,7 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
                   f"{info['t_setup_coarse_s']:.2f}); B {info['b_bytes'] / 1e9:.3f} GB",
                   flush=True)
         for _ in range(warmup):
-            s.solve(f, u, precond=precond, graph=graph)
+            s.solve(f, u, precond=precond, graph=graph, **kry)
         torch.cuda.synchronize()
         if timing:
             s.timing(True)
@@ -164,7 +197,7 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         t0 = time.perf_counter()
         cycles, iters, worst = 0, [], 0.0
         for _ in range(steps):
-            _, st = s.solve(f, u, precond=precond, graph=graph)
+            _, st = s.solve(f, u, precond=precond, graph=graph, **kry)
             cycles += st.n_precond
             iters.append(st.iters)
             worst = max(worst, st.rel_res)
@@ -174,7 +207,7 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         t1 = time.perf_counter()
         if not timing:
             s.timing(True)
-            s.solve(f, u, precond=precond, graph=False)
+            s.solve(f, u, precond=precond, graph=False, **kry)
             torch.cuda.synchronize()
         kt = s.kernel_times()
         s.timing(False)
@@ -182,7 +215,7 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
     elapsed = t1 - t0
     mat_bytes = {"f64": 16, "f32": 8, "bf16": 4}[spec["gemm"]]
     vec_bytes = 16 if precond == "c128" else 8
-    subs = subdomain_sizes(N, p, spec["l_dd"])
+    subs = subdomain_sizes(N, p, spec["l_dd"], dim)
     alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes)
     flops = 8.0 * sum(nu * no for nu, no in subs) * R
     dd_ms, dd_n = kt["dd_apply"]
@@ -195,9 +228,10 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         "kernel_ms_per_step": {k: round(v[0] / ksteps, 4) for k, v in kt.items()},
         "dd": {"alg_bytes": alg, "flops": flops, "avg_ms": avg_ms, "launches": dd_n,
                "gbs": alg / (avg_ms * 1e-3) / 1e9, "tflops": flops / (avg_ms * 1e-3) / 1e12},
-        "desc": f"{name}: 2-D Q{p}, {N}x{N} cells ({info['n_fine']} DOF), {R} RHS, "
+        "desc": f"{name}: {dim}-D Q{p}, {N}^{dim} cells ({info['n_fine']} DOF), {R} RHS, "
                 f"l_dd={spec['l_dd']}, alpha_s={spec['alpha_s']}, B_i {spec['gemm']}, "
-                f"preconditioner {precond}" + (", HIP-graph replay" if graph else ""),
+                f"preconditioner {precond}, coarse {spec['coarse']}"
+                + (", HIP-graph replay" if graph else ""),
     }
     del s
     torch.cuda.synchronize()
@@ -206,11 +240,13 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
 
 def main():
     a = parse()
+    if a.verbose:
+        os.environ.setdefault("TH_PROGRESS", "1")  # library progress lines during long setups
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
-    mixed = a.workload == "C3"
+    mixed = a.workload in ("C3", "C4")
     prim = run_workload(a.workload, a.steps, a.warmup, precond=a.precond, graph=mixed,
                         timing=not mixed, verbose=a.verbose)
     d = prim["dd"]

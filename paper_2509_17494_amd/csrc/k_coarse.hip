@@ -132,48 +132,100 @@ __device__ __forceinline__ c64 bwd_rhs(int c, int r, int nx, int L, int C, int l
   return v;
 }
 
-// Staging in global memory for slabs whose right-hand side does not fit in
-// LDS: xg[(chunk RC + q) n + i], n = nb (forward) or L (backward).
-template <int RC>
+// Staging in global memory for slabs whose right-hand sides do not fit in
+// LDS: xg[r n + i] for r < nrhs, n = nb (forward) or L (backward).
 __global__ __launch_bounds__(256) void k_cstage(int fwd, int n, int nx, int L, int C, int slab,
                                                 const c64 *__restrict__ st,
                                                 const c64 *__restrict__ rc,
                                                 const c64 *__restrict__ uc, c64 *__restrict__ xg,
                                                 int nrhs, long long ncn, int has_prev) {
-  const int r0 = blockIdx.y * RC;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n * RC; i += gridDim.x * 256) {
-    const int q = i / n, a = i - q * n;
-    const int r = r0 + q;
-    c64 v = {0, 0};
-    if (r < nrhs)
-      v = fwd ? fwd_rhs(a, r, nx, L, C, slab, st, rc, uc, ncn, has_prev)
-              : bwd_rhs(a, r, nx, L, C, slab, st, uc, ncn);
-    xg[(long long)r0 * n + i] = v;
+  const long long tot = (long long)n * nrhs;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < tot; i += (long long)gridDim.x * 256) {
+    const int r = (int)(i / n), a = (int)(i - (long long)r * n);
+    xg[i] = fwd ? fwd_rhs(a, r, nx, L, C, slab, st, rc, uc, ncn, has_prev)
+                : bwd_rhs(a, r, nx, L, C, slab, st, uc, ncn);
   }
 }
 
+// Sweep GEMV for large slabs: y_a = sum_b G[a][col0 + b] x[b] for the rows a
+// of one super-block and RC right-hand sides, x staged from xg (above) through
+// LDS in chunks of columns; every wavefront owns RPW rows, so each staged
+// value is reused RPW times from registers and G streams once per RC
+// right-hand sides.  sub = 0: uc[a] = y_a (forward), sub = 1: uc[a] -= y_a
+// (backward).
+template <int RC, int RPW>
+__global__ __launch_bounds__(256) void k_cgemv(const c64 *__restrict__ G, int ld, int nrows,
+                                               int col0, int ncols, const c64 *__restrict__ xg,
+                                               c64 *__restrict__ uc, long long row0, long long ncn,
+                                               int nrhs, int sub) {
+  constexpr int CK = 256;
+  __shared__ c64 Ts[RC][CK];
+  const int r0 = blockIdx.y * RC;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int a0 = (blockIdx.x * 4 + wave) * RPW;
+  c64 acc[RPW][RC];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int q = 0; q < RC; ++q) acc[i][q] = {0, 0};
+  for (int c0 = 0; c0 < ncols; c0 += CK) {
+    const int ck = min(CK, ncols - c0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < RC * CK; t += 256) {
+      const int q = t / CK, b = t - q * CK;
+      Ts[q][b] = (b < ck && r0 + q < nrhs) ? xg[(long long)(r0 + q) * ncols + c0 + b] : c64{0, 0};
+    }
+    __syncthreads();
+    // fixed trip count: all CK / 64 x RPW loads of G are issued before use
+    c64 g[CK / 64][RPW];
+#pragma unroll
+    for (int u = 0; u < CK / 64; ++u) {
+      const int b = u * 64 + lane;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+        g[u][i] = (b < ck && a0 + i < nrows) ? G[(long long)(a0 + i) * ld + col0 + c0 + b]
+                                             : c64{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < CK / 64; ++u) {
+      const int b = u * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < RC; ++q) {
+        const c64 x = Ts[q][b];  // zero beyond ck
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) cmac(acc[i][q], g[u][i], x);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int q = 0; q < RC; ++q) {
+      const c64 sm = wave_sum(acc[i][q]);
+      if (lane == 0 && a0 + i < nrows && r0 + q < nrhs) {
+        c64 *p = uc + (r0 + q) * ncn + row0 + a0 + i;
+        *p = sub ? *p - sm : sm;
+      }
+    }
+}
+
 // forward step of super-block J: y_J = G_J (r_J - L_J y_{J-1})
-template <int RC, bool GS>
+template <int RC>
 __global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int ld, int nb,
                                                   int nx, int L, int C, int line0,
                                                   const c64 *__restrict__ st,
                                                   const c64 *__restrict__ rc, c64 *__restrict__ uc,
-                                                  int nrhs, long long ncn, int has_prev,
-                                                  const c64 *__restrict__ xg) {
+                                                  int nrhs, long long ncn, int has_prev) {
   extern __shared__ c64 tsh[];  // RC x nb
   const int r0 = blockIdx.y * RC;
   const c64 *xs = tsh;
-  if (GS) {
-    xs = xg + (long long)r0 * nb;
-  } else {
-    for (int i = threadIdx.x; i < nb * RC; i += blockDim.x) {
-      const int q = i / nb, a = i - q * nb;
-      const int r = r0 + q;
-      tsh[q * nb + a] =
-          r < nrhs ? fwd_rhs(a, r, nx, L, C, line0, st, rc, uc, ncn, has_prev) : c64{0, 0};
-    }
-    __syncthreads();
+  for (int i = threadIdx.x; i < nb * RC; i += blockDim.x) {
+    const int q = i / nb, a = i - q * nb;
+    const int r = r0 + q;
+    tsh[q * nb + a] =
+        r < nrhs ? fwd_rhs(a, r, nx, L, C, line0, st, rc, uc, ncn, has_prev) : c64{0, 0};
   }
+  __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int a = blockIdx.x * CW + wave;
   if (a >= nb) return;
@@ -196,26 +248,21 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int
 
 // backward step of super-block J (not the last): x_J = y_J - G_J[:, last] w,
 // w = U_J x_{J+1}[first slab]
-template <int RC, bool GS>
+template <int RC>
 __global__ __launch_bounds__(64 * CW) void k_cbwd(const c64 *__restrict__ G, int ld, int nb,
                                                   int nx, int L, int C, int line0, int kJ,
                                                   const c64 *__restrict__ st,
-                                                  c64 *__restrict__ uc, int nrhs, long long ncn,
-                                                  const c64 *__restrict__ xg) {
+                                                  c64 *__restrict__ uc, int nrhs, long long ncn) {
   extern __shared__ c64 wsh[];  // RC x L
   const int r0 = blockIdx.y * RC;
   const int lend = line0 + kJ;  // first slab of J+1
   const c64 *ws = wsh;
-  if (GS) {
-    ws = xg + (long long)r0 * L;
-  } else {
-    for (int i = threadIdx.x; i < L * RC; i += blockDim.x) {
-      const int q = i / L, c = i - q * L;
-      const int r = r0 + q;
-      wsh[q * L + c] = r < nrhs ? bwd_rhs(c, r, nx, L, C, lend, st, uc, ncn) : c64{0, 0};
-    }
-    __syncthreads();
+  for (int i = threadIdx.x; i < L * RC; i += blockDim.x) {
+    const int q = i / L, c = i - q * L;
+    const int r = r0 + q;
+    wsh[q * L + c] = r < nrhs ? bwd_rhs(c, r, nx, L, C, lend, st, uc, ncn) : c64{0, 0};
   }
+  __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int a = blockIdx.x * CW + wave;
   if (a >= nb) return;
@@ -296,7 +343,7 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   }
   int max_nb = 0;
   for (int J = 0; J < nblk; ++J) max_nb = std::max(max_nb, (cd.line0[J + 1] - cd.line0[J]) * L);
-  const size_t t_bytes = (size_t)max_nb * ceil_div(R, cd.rc_chunk) * cd.rc_chunk * sizeof(c64);
+  const size_t t_bytes = (size_t)max_nb * R * sizeof(c64);
   cd.bytes = cd.goff[nblk] * (long long)sizeof(c64) + (long long)st_bytes;
   c64 *pws = nullptr;
   if (hipMalloc(&cd.G, (size_t)cd.goff[nblk] * sizeof(c64)) != hipSuccess ||
@@ -335,53 +382,81 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   return 0;
 }
 
+// Large slabs: one staging launch and one chunked GEMV per step, G streamed
+// once per RCG right-hand sides.
+template <int RCG>
+static int sweep_large_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+  const CoarseData &cd = c->coarse;
+  const int nx = cd.nx, L = cd.L, C = cd.C;
+  const long long ncn = (long long)L * cd.ny;
+  constexpr int RPW = RCG >= 8 ? 2 : 4;
+  const unsigned ychunks = (unsigned)ceil_div(nrhs, RCG);
+  for (int J = 0; J < cd.nblk; ++J) {
+    const int nb = (cd.line0[J + 1] - cd.line0[J]) * L;
+    const unsigned sb = (unsigned)std::min<long long>(ceil_div_ll((long long)nb * nrhs, 256), 2048);
+    hipLaunchKernelGGL(k_cstage, dim3(sb), dim3(256), 0, s, 1, nb, nx, L, C, cd.line0[J],
+                       (const c64 *)cd.st, rcv, (const c64 *)uc, cd.tbuf, nrhs, ncn,
+                       J > 0 ? 1 : 0);
+    hipLaunchKernelGGL((k_cgemv<RCG, RPW>), dim3(ceil_div(nb, 4 * RPW), ychunks), dim3(256), 0,
+                       s, (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, 0, nb,
+                       (const c64 *)cd.tbuf, uc, (long long)cd.line0[J] * L, ncn, nrhs, 0);
+  }
+  for (int J = cd.nblk - 2; J >= 0; --J) {
+    const int kJ = cd.line0[J + 1] - cd.line0[J];
+    const int nb = kJ * L;
+    const unsigned sb = (unsigned)std::min<long long>(ceil_div_ll((long long)L * nrhs, 256), 2048);
+    hipLaunchKernelGGL(k_cstage, dim3(sb), dim3(256), 0, s, 0, L, nx, L, C, cd.line0[J] + kJ,
+                       (const c64 *)cd.st, (const c64 *)nullptr, (const c64 *)uc, cd.tbuf, nrhs,
+                       ncn, 0);
+    hipLaunchKernelGGL((k_cgemv<RCG, RPW>), dim3(ceil_div(nb, 4 * RPW), ychunks), dim3(256), 0,
+                       s, (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, (kJ - 1) * L, L,
+                       (const c64 *)cd.tbuf, uc, (long long)cd.line0[J] * L, ncn, nrhs, 1);
+  }
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// Small slabs: the right-hand side of a step is formed in LDS by the GEMV
+// launch itself (one launch per step).
 template <int RC>
 static int sweep_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
   const CoarseData &cd = c->coarse;
   const int nx = cd.nx, L = cd.L, C = cd.C;
   const long long ncn = (long long)L * cd.ny;
   const unsigned ychunks = (unsigned)ceil_div(nrhs, RC);
-  const size_t lds_max = 64 * 1024;
   for (int J = 0; J < cd.nblk; ++J) {
     const int nb = (cd.line0[J + 1] - cd.line0[J]) * L;
     const size_t shm = (size_t)nb * RC * sizeof(c64);
-    const c64 *GJ = cd.G + cd.goff[J];
-    if (shm <= lds_max) {
-      hipLaunchKernelGGL((k_cfwd<RC, false>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm,
-                         s, GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, rcv, uc,
-                         nrhs, ncn, J > 0 ? 1 : 0, (const c64 *)nullptr);
-    } else {
-      hipLaunchKernelGGL((k_cstage<RC>), dim3(std::min(ceil_div(nb * RC, 256), 1024), ychunks),
-                         dim3(256), 0, s, 1, nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, rcv,
-                         (const c64 *)uc, cd.tbuf, nrhs, ncn, J > 0 ? 1 : 0);
-      hipLaunchKernelGGL((k_cfwd<RC, true>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), 0, s,
-                         GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, rcv, uc,
-                         nrhs, ncn, J > 0 ? 1 : 0, (const c64 *)cd.tbuf);
-    }
+    hipLaunchKernelGGL((k_cfwd<RC>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm, s,
+                       (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, nx, L, C, cd.line0[J],
+                       (const c64 *)cd.st, rcv, uc, nrhs, ncn, J > 0 ? 1 : 0);
   }
   for (int J = cd.nblk - 2; J >= 0; --J) {
     const int kJ = cd.line0[J + 1] - cd.line0[J];
     const int nb = kJ * L;
     const size_t shm = (size_t)L * RC * sizeof(c64);
-    const c64 *GJ = cd.G + cd.goff[J];
-    if (shm <= lds_max) {
-      hipLaunchKernelGGL((k_cbwd<RC, false>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm,
-                         s, GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], kJ, (const c64 *)cd.st, uc,
-                         nrhs, ncn, (const c64 *)nullptr);
-    } else {
-      hipLaunchKernelGGL((k_cstage<RC>), dim3(std::min(ceil_div(L * RC, 256), 1024), ychunks),
-                         dim3(256), 0, s, 0, L, nx, L, C, cd.line0[J] + kJ, (const c64 *)cd.st,
-                         (const c64 *)nullptr, (const c64 *)uc, cd.tbuf, nrhs, ncn, 0);
-      hipLaunchKernelGGL((k_cbwd<RC, true>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), 0, s,
-                         GJ, cd.ld[J], nb, nx, L, C, cd.line0[J], kJ, (const c64 *)cd.st, uc, nrhs,
-                         ncn, (const c64 *)cd.tbuf);
-    }
+    hipLaunchKernelGGL((k_cbwd<RC>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm, s,
+                       (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, nx, L, C, cd.line0[J], kJ,
+                       (const c64 *)cd.st, uc, nrhs, ncn);
   }
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
 
+// LDS bytes the small-slab path needs for RC right-hand sides
+static bool small_slabs_fit(const CoarseData &cd, int RC) {
+  int max_nb = 0;
+  for (int J = 0; J < cd.nblk; ++J) max_nb = std::max(max_nb, (cd.line0[J + 1] - cd.line0[J]) * cd.L);
+  return (size_t)max_nb * RC * sizeof(c64) <= 64 * 1024;
+}
+
 int launch_coarse_solve(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+  if (!small_slabs_fit(c->coarse, c->coarse.rc_chunk)) {
+    if (nrhs >= 8) return sweep_large_t<8>(c, rcv, uc, nrhs, s);
+    if (nrhs >= 4) return sweep_large_t<4>(c, rcv, uc, nrhs, s);
+    if (nrhs >= 2) return sweep_large_t<2>(c, rcv, uc, nrhs, s);
+    return sweep_large_t<1>(c, rcv, uc, nrhs, s);
+  }
   switch (c->coarse.rc_chunk) {
     case 4: return sweep_t<4>(c, rcv, uc, nrhs, s);
     case 2: return sweep_t<2>(c, rcv, uc, nrhs, s);

@@ -19,6 +19,9 @@
 // identity block to a multiple of 32, which leaves the inverse unchanged on
 // the leading block.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "ctx.hpp"
@@ -356,7 +359,20 @@ int setup_subdomain_operators(th_ctx *c) {
   int *flag = (int *)(pws + (long long)batch * GJ_BS * GJ_BS);
   int rc = 0;
   TH_HIP_CHECK_RET(hipMemsetAsync(flag, 0, sizeof(int), s));
+  // optional progress lines on stderr for long setups (environment TH_PROGRESS
+  // set): the stream is synchronised after a batch at most every 10 s
+  const bool progress = std::getenv("TH_PROGRESS") != nullptr;
+  auto t_last = std::chrono::steady_clock::now();
+  const auto t_begin = t_last;
   for (int s0 = 0; s0 < nsub && rc == 0; s0 += batch) {
+    if (progress && s0 > 0 &&
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_last).count() > 10.0) {
+      TH_HIP_CHECK_RET(hipStreamSynchronize(s));
+      t_last = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "setup: %d / %d subdomain operators, %.1f s\n", s0, nsub,
+                   std::chrono::duration<double>(t_last - t_begin).count());
+      std::fflush(stderr);
+    }
     const int nb = std::min(batch, nsub - s0);
     TH_HIP_CHECK_RET(hipMemsetAsync(work, 0, (size_t)nb * mat * sizeof(c64), s));
     dim3 ga(ceil_div(npad, 256), nb);

@@ -74,19 +74,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_dd_mfma(const Sub *__restrict__ 
       for (int kb0 = 0; kb0 < nkb; kb0 += KCH) {
         const int k0 = kb0 * MF_KB;
         __syncthreads();
-        // stage X chunk: columns [k0, k0 + KC) for right-hand sides [r0, r0 + 64)
-        for (int t = threadIdx.x; t < MF_RHS_GROUP * KC; t += 64 * WAVES) {
-          const int q = t / KC, kk = t - q * KC;
+        // stage X chunk: columns [k0, k0 + KC) for the right-hand sides of the
+        // ntile MFMA tiles in use; a thread keeps one column (its patch node
+        // index computed once) and steps over right-hand sides, consecutive
+        // threads take consecutive columns (coalesced loads)
+        constexpr int NT = 64 * WAVES;
+        constexpr int QG = NT >= KC ? NT / KC : 1;
+        const int nrp = ntile * MF_NT;
+        for (int t = threadIdx.x; t < KC * QG; t += NT) {
+          const int kk = t % KC, qg = t / KC;
           const int k = k0 + kk;
-          unsigned short vr = 0, vi = 0;
-          if (q < nr && k < s.nOm) {
-            const long long g = om_node(s, k, P, n1);
-            const cx<T> v = r[(long long)(r0 + q) * nf + g];
-            vr = f2bf((float)v.re);
-            vi = f2bf((float)v.im);
+          const bool valid = k < s.nOm;
+          const long long g = valid ? om_node(s, k, P, n1) : 0;
+          for (int q = qg; q < nrp; q += QG) {
+            unsigned short vr = 0, vi = 0;
+            if (valid && q < nr) {
+              const cx<T> v = r[(long long)(r0 + q) * nf + g];
+              vr = f2bf((float)v.re);
+              vi = f2bf((float)v.im);
+            }
+            Xs[0][q][kk] = vr;
+            Xs[1][q][kk] = vi;
           }
-          Xs[0][q][kk] = vr;
-          Xs[1][q][kk] = vi;
         }
         __syncthreads();
         if (live) {

@@ -132,14 +132,26 @@ def test_smooth_3d_ndd2_neumann_f32_storage():
     assert rel(to_np(u)[0], ref) < 1e-5
 
 
-@pytest.mark.parametrize("N,p,l_dd,nrhs", [(9, 2, 4, 2), (5, 4, 2, 1), (32, 2, 2, 4)])
+_AC_CACHE = {}
+
+
+def _coarse_3d(N, p):
+    if (N, p) not in _AC_CACHE:
+        k = hetero_k3(N, p, seed=16)
+        eps = 0.02 * k * k
+        _AC_CACHE[(N, p)] = (k, eps, coarse_matrix_3d(coarse_cell_values(k, p),
+                                                      coarse_cell_values(eps, p)))
+    return _AC_CACHE[(N, p)]
+
+
+@pytest.mark.parametrize("N,p,l_dd,nrhs", [(9, 2, 4, 2), (5, 4, 2, 1), (32, 2, 2, 5),
+                                           (32, 2, 2, 8)])
 def test_coarse_solve_3d(N, p, l_dd, nrhs):
     """27-point coarse matrix (exact-wavenumber fit); N = 32 puts a 33 x 33
-    coarse plane's right-hand sides beyond LDS (global staging path)."""
+    coarse plane's right-hand sides beyond LDS (staged, chunked-GEMV sweeps
+    with 4 and 8 right-hand sides per pass, a partial last pass at 5)."""
     print(f"case coarse3d N={N} p={p} nrhs={nrhs}", flush=True)
-    k = hetero_k3(N, p, seed=16)
-    eps = 0.02 * k * k
-    Ac = coarse_matrix_3d(coarse_cell_values(k, p), coarse_cell_values(eps, p))
+    k, eps, Ac = _coarse_3d(N, p)
     s = make_solver(k, p, l_dd, eps=eps, max_rhs=nrhs)
     rc = syn.random_complex((nrhs, Ac.shape[0]), seed=17)
     uc = to_np(s.coarse_solve(to_dev(rc)))
