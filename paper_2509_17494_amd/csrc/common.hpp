@@ -50,6 +50,18 @@ __host__ __device__ __forceinline__ void rmac(cx<T> &acc, T s, cx<T> b) {
 template <typename To, typename Ti>
 __host__ __device__ __forceinline__ cx<To> ccast(cx<Ti> a) { return {(To)a.re, (To)a.im}; }
 
+// Vector load of data that is read exactly once per launch (non-temporal hint).
+__device__ __forceinline__ cx<double> ld_stream(const cx<double> *p) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2 v = __builtin_nontemporal_load((const d2 *)p);
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> ld_stream(const cx<float> *p) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 v = __builtin_nontemporal_load((const f2 *)p);
+  return {v.x, v.y};
+}
+
 __host__ __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ __forceinline__ long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }
 

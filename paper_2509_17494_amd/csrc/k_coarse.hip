@@ -183,8 +183,9 @@ __global__ __launch_bounds__(256) void k_cgemv(const c64 *__restrict__ G, int ld
       const int b = u * 64 + lane;
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
-        g[u][i] = (b < ck && a0 + i < nrows) ? G[(long long)(a0 + i) * ld + col0 + c0 + b]
-                                             : c64{0, 0};
+        g[u][i] = (b < ck && a0 + i < nrows)
+                      ? ld_stream(G + (long long)(a0 + i) * ld + col0 + c0 + b)
+                      : c64{0, 0};
     }
 #pragma unroll
     for (int u = 0; u < CK / 64; ++u) {

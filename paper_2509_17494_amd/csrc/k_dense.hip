@@ -4,8 +4,8 @@
 // A_s^(i) of a(u, v; Omega^(i), Gamma) with the shifted coefficient
 // k^2 (1 + i alpha_s) + i eps and the absorbing term -i k on the sides of
 // Omega^(i) that are internal or inherit an absorbing boundary; invert it by
-// blocked Gauss-Jordan elimination; store B_i = diag(1/L_j) R_{U_i} A^{-1}
-// transposed (column-major, ld = n_U rounded up to 64) in the working
+// blocked Gauss-Jordan elimination; store B_i = diag(1/L_j) R_{U_i} A^{-1} in
+// blocks of 64 rows (the apply kernel's streaming order) in the working
 // precision.
 //
 // Gauss-Jordan runs without pivoting.  A_s^(i) = H - i S with S = alpha_s k^2 M
@@ -314,7 +314,8 @@ __global__ __launch_bounds__(256) void k_assemble_sub3(const Sub *__restrict__ s
   }
 }
 
-// B_i^T[k][j] = (A^{-1})[u_j][k] / L_{u_j} in the storage precision.
+// B_i[j][k] = (A^{-1})[u_j][k] / L_{u_j} in the storage precision, in blocks of
+// 64 rows: entry (j, k) at ((j / 64) n_Omega + k) 64 + j % 64.
 template <typename TB>
 __global__ __launch_bounds__(256) void k_extract_b(const Sub *__restrict__ subs, int s0,
                                                    const c64 *__restrict__ A, int ld,
@@ -331,7 +332,8 @@ __global__ __launch_bounds__(256) void k_extract_b(const Sub *__restrict__ subs,
   const c64 *arow = Ab + (long long)uj * ld;
   for (int k = blockIdx.y; k < s.nOm; k += gridDim.y) {
     const c64 v = arow[k];
-    B[s.boff + (long long)k * s.ldb + j] = cx<TB>{(TB)(v.re * invL), (TB)(v.im * invL)};
+    B[s.boff + ((long long)(j / 64) * s.nOm + k) * 64 + (j % 64)] =
+        cx<TB>{(TB)(v.re * invL), (TB)(v.im * invL)};
   }
 }
 

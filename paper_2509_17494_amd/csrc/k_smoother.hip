@@ -8,11 +8,12 @@
 //   gather  X_i = R_{Omega_i} r            (structured box, no index maps)
 //   GEMV    Y_i = B_i X_i                  (k_dd_apply: streams B_i once)
 //   gather  v_j = sum_i (Y_i)_j            (k_dd_accumulate: fixed order)
-// B_i is stored transposed (column k of B_i contiguous, leading dimension
-// ldb = n_U rounded up to 64), so lane j of a wavefront owns output row j and
-// every load of a wavefront is 64 consecutive complex entries; the gathered
-// X chunk sits in LDS and is read as a broadcast.  No atomics: results are
-// bitwise reproducible.
+// B_i is stored in blocks of 64 rows (n_U padded to ldb, a multiple of 64):
+// block rb holds, for k = 0 .. n_Omega - 1, the 64 entries B_i[64 rb + l][k]
+// contiguously, so lane l of a wavefront owns output row 64 rb + l, every load
+// of a wavefront is 1 KiB (FP64) of consecutive entries, and one wavefront
+// streams one contiguous n_Omega x 64 region.  The gathered X chunk sits in LDS
+// and is read as a broadcast.  No atomics: results are bitwise reproducible.
 #include "ctx.hpp"
 
 namespace th {
@@ -46,10 +47,10 @@ __global__ __launch_bounds__(256) void k_dd_apply(const Sub *__restrict__ subs,
       }
       __syncthreads();
       if (live) {
-        const cx<TB> *bp = Bi + (long long)k0 * s.ldb + j;
-#pragma unroll 8
+        const cx<TB> *bp = Bi + ((long long)(j / 64) * s.nOm + k0) * 64 + (j % 64);
+#pragma unroll 16
         for (int kk = 0; kk < kc; ++kk) {
-          const cx<T> b = ccast<T>(bp[(long long)kk * s.ldb]);
+          const cx<T> b = ccast<T>(ld_stream(bp + (long long)kk * 64));
 #pragma unroll
           for (int q = 0; q < NR; ++q) cmac(acc[q], b, Xs[kk * NR + q]);
         }

@@ -103,8 +103,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_dd_mfma(const Sub *__restrict__ 
           for (int kq = 0; kq < kbe; ++kq) {
             const unsigned short *fr = B + mf_frag(s, rb, kb0 + kq, 0) + lane * 8;
             const unsigned short *fi = B + mf_frag(s, rb, kb0 + kq, 1) + lane * 8;
-            const u32x4 ur = *(const u32x4 *)fr;
-            const u32x4 ui = *(const u32x4 *)fi;
+            const u32x4 ur = __builtin_nontemporal_load((const u32x4 *)fr);
+            const u32x4 ui = __builtin_nontemporal_load((const u32x4 *)fi);
             const u32x4 uin = ui ^ u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
             const bf16x8 br = __builtin_bit_cast(bf16x8, ur);
             const bf16x8 bi = __builtin_bit_cast(bf16x8, ui);
