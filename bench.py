@@ -31,7 +31,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dd_apply_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2509_17494_amd", "csrc", "k_smoother.hip")
+# sources of the batched subdomain apply kernel (its file and the headers it uses)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2509_17494_amd", "csrc", f)
+               for f in ("k_smoother.hip", "common.hpp", "ctx.hpp")]
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def parse():
@@ -94,7 +103,7 @@ def traffic_entry(workload_name):
         return None
     try:
         d = json.load(open(TRAFFIC_FILE))
-        src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        src_hash = kernel_sources_sha256()
         e = d.get(workload_name)
         if not e or e.get("kernel_sha256") != src_hash:
             return None
