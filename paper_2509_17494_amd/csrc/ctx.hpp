@@ -10,6 +10,10 @@
 
 namespace th {
 
+// Block width of the batched Gauss-Jordan inversion; matrices handed to it are
+// padded to a multiple of this.
+constexpr int kGJBlock = 64;
+
 // One subdomain: U = non-overlapping cell box, Om = U plus one cell layer
 // clipped to the domain (Sec. 4.1, 4.4).  Boxes are half-open cell ranges.
 // In 2-D the z extents are a single node layer (u0z = o0z = 0, nuz = noz = 1),

@@ -234,9 +234,11 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-#pragma unroll 4
+  // rows are streamed once when one pass covers all right-hand sides
+  const bool once = gridDim.y == 1;
+#pragma unroll 8
   for (int b = lane; b < nb; b += 64) {
-    const c64 g = row[b];
+    const c64 g = once ? ld_stream(row + b) : row[b];
 #pragma unroll
     for (int q = 0; q < RC; ++q) cmac(acc[q], g, xs[q * nb + b]);
   }
@@ -271,8 +273,10 @@ __global__ __launch_bounds__(64 * CW) void k_cbwd(const c64 *__restrict__ G, int
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
+  const bool once = gridDim.y == 1;
+#pragma unroll 4
   for (int c = lane; c < L; c += 64) {
-    const c64 g = row[c];
+    const c64 g = once ? ld_stream(row + c) : row[c];
 #pragma unroll
     for (int q = 0; q < RC; ++q) cmac(acc[q], g, ws[q * L + c]);
   }
@@ -334,7 +338,7 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   cd.goff[0] = 0;
   for (int J = 0; J < nblk; ++J) {
     const int nb = (cd.line0[J + 1] - cd.line0[J]) * L;
-    cd.ld[J] = ceil_div(nb, 32) * 32;
+    cd.ld[J] = ceil_div(nb, kGJBlock) * kGJBlock;
     cd.goff[J + 1] = cd.goff[J] + (long long)cd.ld[J] * cd.ld[J];
   }
   const size_t st_bytes = (size_t)L * ny * 3 * C * sizeof(c64);
@@ -350,13 +354,13 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   if (hipMalloc(&cd.G, (size_t)cd.goff[nblk] * sizeof(c64)) != hipSuccess ||
       hipMalloc(&cd.st, st_bytes) != hipSuccess ||
       hipMalloc(&cd.tbuf, t_bytes) != hipSuccess ||
-      hipMalloc(&pws, 32 * 32 * sizeof(c64) + 64) != hipSuccess) {
+      hipMalloc(&pws, kGJBlock * kGJBlock * sizeof(c64) + 64) != hipSuccess) {
     if (pws) (void)hipFree(pws);
     set_error("cannot allocate the coarse factors");
     return TH_ENOMEM;
   }
   TH_HIP_CHECK_RET(hipMemcpyAsync(cd.st, st.data(), st_bytes, hipMemcpyHostToDevice, s));
-  int *flag = (int *)(pws + 32 * 32);
+  int *flag = (int *)(pws + kGJBlock * kGJBlock);
   TH_HIP_CHECK_RET(hipMemsetAsync(flag, 0, sizeof(int), s));
   int rc = 0;
   for (int J = 0; J < nblk && rc == 0; ++J) {

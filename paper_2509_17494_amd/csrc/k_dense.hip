@@ -12,11 +12,11 @@
 // + k M_Gamma (plus eps M) symmetric positive definite, so i A_s^(i) has a
 // positive definite Hermitian part; that property passes to every leading
 // block and every Schur complement, so all pivots are nonzero.  The blocked
-// in-place sweep over 32-wide block columns k is
+// in-place sweep over 64-wide block columns k is
 //   P = A_kk^{-1};  A_kj <- P A_kj (j != k);  A_ij <- A_ij - A_ik A_kj;
 //   A_ik <- -A_ik P (i != k);  A_kk <- P,
 // and after the last block A holds A^{-1}.  Matrices are padded with an
-// identity block to a multiple of 32, which leaves the inverse unchanged on
+// identity block to a multiple of 64, which leaves the inverse unchanged on
 // the leading block.
 #include <algorithm>
 #include <chrono>
@@ -28,12 +28,16 @@
 
 namespace th {
 
-constexpr int GJ_BS = 32;   // block width of the elimination
-constexpr int GJ_T = 64;    // tile edge of the panel / update kernels
+constexpr int GJ_BS = kGJBlock;  // block width of the elimination (64)
+constexpr int GJ_T = 64;         // tile edge of the update kernel
+constexpr int GJ_KH = 32;        // k-slice of the update staged in LDS at a time
+constexpr int GJ_PT = 32;        // tile width of the panel kernels
 
 // ---------------------------------------------------------------------------
 // Gauss-Jordan kernels.  Matrix b of the batch starts at A + b * stride and is
-// row-major with leading dimension ld; n is a multiple of GJ_BS.
+// row-major with leading dimension ld; n is a multiple of GJ_BS.  A rank-64
+// update per block column reads and writes the trailing matrix once per 64
+// columns of elimination.
 
 __global__ __launch_bounds__(256) void k_gj_diag(c64 *A, int ld, long long stride, int kb,
                                                  c64 *pbuf, int *flag) {
@@ -75,24 +79,25 @@ __global__ __launch_bounds__(256) void k_gj_diag(c64 *A, int ld, long long strid
   }
 }
 
-// A_kj <- P A_kj for the 64-column tile blockIdx.x (columns of block k skipped)
+// A_kj <- P A_kj for the GJ_PT-column tile blockIdx.x (columns of block k skipped)
 __global__ __launch_bounds__(256) void k_gj_rowpanel(c64 *A, int ld, long long stride, int n, int kb,
                                                      const c64 *pbuf) {
   __shared__ c64 Ps[GJ_BS][GJ_BS + 1];
-  __shared__ c64 Ts[GJ_BS][GJ_T + 1];
-  const int j0 = blockIdx.x * GJ_T;
+  __shared__ c64 Ts[GJ_BS][GJ_PT + 1];
+  const int j0 = blockIdx.x * GJ_PT;
+  if (j0 / GJ_BS == kb) return;  // the whole tile lies in block column k (uniform)
   c64 *Ab = A + blockIdx.y * stride + (long long)kb * GJ_BS * ld;
   const c64 *pb = pbuf + (long long)blockIdx.y * GJ_BS * GJ_BS;
   for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) Ps[t / GJ_BS][t % GJ_BS] = pb[t];
-  for (int t = threadIdx.x; t < GJ_BS * GJ_T; t += blockDim.x) {
-    int i = t / GJ_T, j = t % GJ_T;
+  for (int t = threadIdx.x; t < GJ_BS * GJ_PT; t += blockDim.x) {
+    int i = t / GJ_PT, j = t % GJ_PT;
     Ts[i][j] = (j0 + j < n) ? Ab[(long long)i * ld + j0 + j] : c64{0, 0};
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < GJ_BS * GJ_T; t += blockDim.x) {
-    int i = t / GJ_T, j = t % GJ_T;
+  for (int t = threadIdx.x; t < GJ_BS * GJ_PT; t += blockDim.x) {
+    int i = t / GJ_PT, j = t % GJ_PT;
     int col = j0 + j;
-    if (col >= n || (col / GJ_BS) == kb) continue;
+    if (col >= n) continue;
     c64 acc = {0, 0};
 #pragma unroll 8
     for (int q = 0; q < GJ_BS; ++q) cmac(acc, Ps[i][q], Ts[q][j]);
@@ -100,24 +105,25 @@ __global__ __launch_bounds__(256) void k_gj_rowpanel(c64 *A, int ld, long long s
   }
 }
 
-// A_ik <- -A_ik P for the 64-row tile blockIdx.x (rows of block k skipped)
+// A_ik <- -A_ik P for the GJ_PT-row tile blockIdx.x (rows of block k skipped)
 __global__ __launch_bounds__(256) void k_gj_colpanel(c64 *A, int ld, long long stride, int n, int kb,
                                                      const c64 *pbuf) {
   __shared__ c64 Ps[GJ_BS][GJ_BS + 1];
-  __shared__ c64 Ts[GJ_T][GJ_BS + 1];
-  const int i0 = blockIdx.x * GJ_T;
+  __shared__ c64 Ts[GJ_PT][GJ_BS + 1];
+  const int i0 = blockIdx.x * GJ_PT;
+  if (i0 / GJ_BS == kb) return;  // uniform
   c64 *Ab = A + blockIdx.y * stride + kb * GJ_BS;
   const c64 *pb = pbuf + (long long)blockIdx.y * GJ_BS * GJ_BS;
   for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) Ps[t / GJ_BS][t % GJ_BS] = pb[t];
-  for (int t = threadIdx.x; t < GJ_T * GJ_BS; t += blockDim.x) {
+  for (int t = threadIdx.x; t < GJ_PT * GJ_BS; t += blockDim.x) {
     int i = t / GJ_BS, j = t % GJ_BS;
     Ts[i][j] = (i0 + i < n) ? Ab[(long long)(i0 + i) * ld + j] : c64{0, 0};
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < GJ_T * GJ_BS; t += blockDim.x) {
+  for (int t = threadIdx.x; t < GJ_PT * GJ_BS; t += blockDim.x) {
     int i = t / GJ_BS, j = t % GJ_BS;
     int row = i0 + i;
-    if (row >= n || (row / GJ_BS) == kb) continue;
+    if (row >= n) continue;
     c64 acc = {0, 0};
 #pragma unroll 8
     for (int q = 0; q < GJ_BS; ++q) cmac(acc, Ts[i][q], Ps[q][j]);
@@ -126,48 +132,54 @@ __global__ __launch_bounds__(256) void k_gj_colpanel(c64 *A, int ld, long long s
 }
 
 // A_ij <- A_ij - A_ik A_kj on the 64x64 tile (blockIdx.x, blockIdx.y), entries
-// in block row k or block column k left untouched.
+// in block row k or block column k left untouched; the 64-wide k range is
+// staged through LDS in two slices.
 __global__ __launch_bounds__(256) void k_gj_update(c64 *A, int ld, long long stride, int n, int kb) {
-  __shared__ c64 As[GJ_T][GJ_BS + 1];
-  __shared__ c64 Bs[GJ_BS][GJ_T + 1];
+  __shared__ c64 As[GJ_T][GJ_KH + 1];
+  __shared__ c64 Bs[GJ_KH][GJ_T + 1];
   const int j0 = blockIdx.x * GJ_T, i0 = blockIdx.y * GJ_T;
+  // tiles wholly inside block row or block column k have nothing to update (uniform)
+  if (i0 / GJ_BS == kb || j0 / GJ_BS == kb) return;
   c64 *Ab = A + blockIdx.z * stride;
-  const int k0 = kb * GJ_BS;
-  for (int t = threadIdx.x; t < GJ_T * GJ_BS; t += blockDim.x) {
-    int i = t / GJ_BS, q = t % GJ_BS;
-    As[i][q] = (i0 + i < n) ? Ab[(long long)(i0 + i) * ld + k0 + q] : c64{0, 0};
-  }
-  for (int t = threadIdx.x; t < GJ_BS * GJ_T; t += blockDim.x) {
-    int q = t / GJ_T, j = t % GJ_T;
-    Bs[q][j] = (j0 + j < n) ? Ab[(long long)(k0 + q) * ld + j0 + j] : c64{0, 0};
-  }
-  __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   c64 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = {0, 0};
+  for (int h = 0; h < GJ_BS / GJ_KH; ++h) {
+    const int k0 = kb * GJ_BS + h * GJ_KH;
+    if (h) __syncthreads();
+    for (int t = threadIdx.x; t < GJ_T * GJ_KH; t += blockDim.x) {
+      int i = t / GJ_KH, q = t % GJ_KH;
+      As[i][q] = (i0 + i < n) ? Ab[(long long)(i0 + i) * ld + k0 + q] : c64{0, 0};
+    }
+    for (int t = threadIdx.x; t < GJ_KH * GJ_T; t += blockDim.x) {
+      int q = t / GJ_T, j = t % GJ_T;
+      Bs[q][j] = (j0 + j < n) ? Ab[(long long)(k0 + q) * ld + j0 + j] : c64{0, 0};
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int q = 0; q < GJ_BS; ++q) {
-    c64 av[4], bv[4];
+    for (int q = 0; q < GJ_KH; ++q) {
+      c64 av[4], bv[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = As[ty + 16 * a][q];
+      for (int a = 0; a < 4; ++a) av[a] = As[ty + 16 * a][q];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = Bs[q][tx + 16 * b];
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[q][tx + 16 * b];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) cmac(acc[a][b], av[a], bv[b]);
+        for (int b = 0; b < 4; ++b) cmac(acc[a][b], av[a], bv[b]);
+    }
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int row = i0 + ty + 16 * a;
-    if (row >= n || (row / GJ_BS) == kb) continue;
+    if (row >= n) continue;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int col = j0 + tx + 16 * b;
-      if (col >= n || (col / GJ_BS) == kb) continue;
+      if (col >= n) continue;
       c64 *p = Ab + (long long)row * ld + col;
       *p = *p - acc[a][b];
     }
@@ -176,22 +188,22 @@ __global__ __launch_bounds__(256) void k_gj_update(c64 *A, int ld, long long str
 
 int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStream_t s,
                       c64 *pbuf_flag_ws) {
-  // pbuf_flag_ws: batch * 32 * 32 complex for the inverted diagonal blocks,
-  // followed by one int flag (zeroed by the caller)
+  // pbuf_flag_ws: batch * GJ_BS * GJ_BS complex for the inverted diagonal
+  // blocks, followed by one int flag (zeroed by the caller)
   if (n % GJ_BS) {
-    set_error("gauss-jordan size must be a multiple of 32");
+    set_error("gauss-jordan size must be a multiple of the block width");
     return TH_EINVAL;
   }
   c64 *pbuf = pbuf_flag_ws;
   int *flag = (int *)(pbuf + (long long)batch * GJ_BS * GJ_BS);
   const int nbk = n / GJ_BS;
-  const int nt = ceil_div(n, GJ_T);
+  const int nt = ceil_div(n, GJ_T), np = ceil_div(n, GJ_PT);
   for (int kb = 0; kb < nbk; ++kb) {
     hipLaunchKernelGGL(k_gj_diag, dim3(batch), dim3(256), 0, s, A, ld, stride, kb, pbuf, flag);
-    hipLaunchKernelGGL(k_gj_rowpanel, dim3(nt, batch), dim3(256), 0, s, A, ld, stride, n, kb,
+    hipLaunchKernelGGL(k_gj_rowpanel, dim3(np, batch), dim3(256), 0, s, A, ld, stride, n, kb,
                        (const c64 *)pbuf);
     hipLaunchKernelGGL(k_gj_update, dim3(nt, nt, batch), dim3(256), 0, s, A, ld, stride, n, kb);
-    hipLaunchKernelGGL(k_gj_colpanel, dim3(nt, batch), dim3(256), 0, s, A, ld, stride, n, kb,
+    hipLaunchKernelGGL(k_gj_colpanel, dim3(np, batch), dim3(256), 0, s, A, ld, stride, n, kb,
                        (const c64 *)pbuf);
     TH_HIP_CHECK_RET(hipGetLastError());
   }
