@@ -69,10 +69,15 @@ def workload(name):
     return cfg, spec
 
 
-def dd_apply_bytes(info_sub, nrhs, mat_bytes, vec_bytes):
-    """Algorithmic bytes of one batched subdomain apply: every B_i entry once,
-    the gathered patch X_i and the output rows Y_i once per right-hand side."""
-    b = sum(nu * no for nu, no in info_sub) * mat_bytes
+def dd_apply_bytes(info_sub, nrhs, mat_bytes, vec_bytes, symmetric=False):
+    """Algorithmic bytes of one batched subdomain apply: every stored B_i entry
+    once (with the symmetric layout the U x U block counts n_U (n_U + 1) / 2
+    entries), the gathered patch X_i and the output rows Y_i once per
+    right-hand side."""
+    if symmetric:
+        b = sum(nu * (nu + 1) // 2 + nu * (no - nu) for nu, no in info_sub) * mat_bytes
+    else:
+        b = sum(nu * no for nu, no in info_sub) * mat_bytes
     v = sum(no + nu for nu, no in info_sub) * vec_bytes * nrhs
     return b + v
 
@@ -236,7 +241,8 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
     mat_bytes = {"f64": 16, "f32": 8, "bf16": 4}[spec["gemm"]]
     vec_bytes = 16 if precond == "c128" else 8
     subs = subdomain_sizes(N, p, spec["l_dd"], dim)
-    alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes)
+    sym = info["smoother_layout"] == 1
+    alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes, symmetric=sym)
     flops = 8.0 * sum(nu * no for nu, no in subs) * R
     dd_ms, dd_n = kt["dd_apply"]
     avg_ms = dd_ms / max(dd_n, 1)
@@ -246,6 +252,7 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         "ms_per_step": elapsed / steps * 1e3, "gmres_iters": iters[-1], "max_rel_res": worst,
         "setup_s": t_setup, "info": info,
         "kernel_ms_per_step": {k: round(v[0] / ksteps, 4) for k, v in kt.items()},
+        "layout": ["dense", "symmetric", "matrix-core"][info["smoother_layout"]],
         "dd": {"alg_bytes": alg, "flops": flops, "avg_ms": avg_ms, "launches": dd_n,
                "gbs": alg / (avg_ms * 1e-3) / 1e9, "tflops": flops / (avg_ms * 1e-3) / 1e12},
         "desc": f"{name}: {dim}-D Q{p}, {N}^{dim} cells ({info['n_fine']} DOF), {R} RHS, "
@@ -273,7 +280,8 @@ def main():
     traffic = traffic_entry(a.workload)
     roof = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_dd_apply" if prim["gemm"] != "bf16" else "k_dd_mfma",
+            "kernel": {"dense": "k_dd_apply", "symmetric": "k_dd_sym + k_dd_symred",
+                       "matrix-core": "k_dd_mfma"}[prim["layout"]],
             "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": round(d["avg_ms"], 4),
             "launches": d["launches"]}
     info = prim["info"]

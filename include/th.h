@@ -134,6 +134,9 @@ typedef struct {
   int coarse_lines;       /* grid lines (2-D) or planes (3-D) per coarse super-block */
   int n_fallback_cells;   /* TH_COARSE_MLP: coarse cells that fell back to the plain fit */
   double t_stencil_s;     /* time spent computing the per-cell coarse weights */
+  int smoother_layout;    /* storage of the subdomain operators: 0 dense rows (FP64/FP32),
+                             1 symmetric tiles (FP64/FP32; the U x U block of the symmetric
+                             inverse stored once), 2 matrix-core fragments (BF16) */
 } th_info;
 
 /* Create a context on HIP device `hip_device`, ordering work on `hip_stream`
@@ -147,7 +150,9 @@ th_status th_get_info(const th_ctx *ctx, th_info *info);
  * coefficients, the subdomains U^(i) and Omega^(i) = U^(i) + one cell layer,
  * and for every subdomain the dense operator B_i = diag(1/L_j) R_{U_i}
  * (A_s^(i))^{-1} (n_U x n_Omega), computed on the device in FP64 and stored
- * in desc->gemm precision.  Blocking.  Errors: TH_EINVAL (odd order, n < 1,
+ * in desc->gemm precision.  A_s^(i) is complex symmetric, so for FP64/FP32
+ * storage the U x U block of its inverse is kept once (upper 64 x 64 tiles)
+ * whenever that stores at most 80 % of the dense bytes (th_info.smoother_layout).  Blocking.  Errors: TH_EINVAL (odd order, n < 1,
  * k <= 0 or NaN, l_dd < 1, dim not 2 or 3), TH_EUNSUPPORTED (3-D order above
  * 4), TH_ENOMEM, TH_ENUMERIC (zero pivot). */
 th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *desc);

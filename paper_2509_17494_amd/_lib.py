@@ -50,7 +50,8 @@ class Info(C.Structure):
                 ("coarse_bytes", C.c_longlong), ("t_setup_fine_s", C.c_double),
                 ("t_setup_coarse_s", C.c_double), ("smoother_cfg", C.c_int),
                 ("smoother_grid", C.c_int), ("coarse_lines", C.c_int),
-                ("n_fallback_cells", C.c_int), ("t_stencil_s", C.c_double)]
+                ("n_fallback_cells", C.c_int), ("t_stencil_s", C.c_double),
+                ("smoother_layout", C.c_int)]
 
 
 _lib = None

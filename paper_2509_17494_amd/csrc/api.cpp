@@ -115,8 +115,9 @@ static void free_graphs(th_ctx *c) {
 }
 
 static void free_fine(th_ctx *c) {
-  void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,   c->d_subs, c->d_nblk, c->d_B,  c->w_r,
-                  c->w_v,   c->w_rr,   c->w_y,   c->w_rc,   c->w_uc,   c->w_t, c->w_rc32};
+  void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,  c->d_subs, c->d_nblk, c->d_B, c->w_r,
+                  c->w_v,   c->w_rr,   c->w_y,  c->w_rc,   c->w_uc,   c->w_t, c->w_rc32,
+                  c->d_eidx, c->w_p};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_kap = c->d_kaps = nullptr;
@@ -124,6 +125,8 @@ static void free_fine(th_ctx *c) {
   c->d_subs = nullptr;
   c->d_nblk = nullptr;
   c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = c->w_rc32 = nullptr;
+  c->d_eidx = nullptr;
+  c->w_p = nullptr;
   c->fine_ready = false;
 }
 
@@ -222,6 +225,7 @@ th_status th_get_info(const th_ctx *ctx, th_info *info) {
   info->coarse_lines = ctx->coarse.nblk > 0 ? ctx->coarse.line0[1] - ctx->coarse.line0[0] : 0;
   info->n_fallback_cells = ctx->n_fallback;
   info->t_stencil_s = ctx->t_stencil;
+  info->smoother_layout = ctx->layout;
   return TH_OK;
 }
 
@@ -335,15 +339,56 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
         const bool inner[6] = {s.o0x > 0, s.o1x < N, s.o0y > 0, s.o1y < N, s.o0z > 0, s.o1z < N};
         for (int sd = 0; sd < 2 * c->dim; ++sd)
           if (inner[sd] || d->bc[sd] == TH_BC_ROBIN) s.robin |= 1 << sd;
-        s.boff = boff;
+        s.nrb = (s.nU + kSymTile - 1) / kSymTile;
+        s.neb = (s.nOm - s.nU + kSymTile - 1) / kSymTile;
         s.yoff = yoff;
-        // element offsets: complex entries (F64/F32) or bf16 values (MFMA layout)
-        boff += (d->gemm == TH_GEMM_BF16) ? mfma_store_elems(s) : (long long)s.nOm * s.ldb;
         yoff += s.nU;
         max_ldb = std::max(max_ldb, s.ldb);
         max_nom = std::max(max_nom, s.nOm);
         c->subs.push_back(s);
       }
+  // storage layout: the symmetric tiles (U x U block of the symmetric inverse
+  // stored once) when they need at most 80 % of the dense bytes
+  auto sym_elems = [](const Sub &s) {
+    return ((long long)s.nrb * (s.nrb + 1) / 2 + (long long)s.nrb * s.neb) * kSymTile * kSymTile;
+  };
+  {
+    long long dense = 0, sym = 0;
+    for (const Sub &s : c->subs) {
+      dense += (long long)s.nOm * s.ldb;
+      sym += sym_elems(s);
+    }
+    c->layout = (d->gemm == TH_GEMM_BF16) ? 2 : (10 * sym <= 8 * dense ? 1 : 0);
+  }
+  std::vector<int> eidx;
+  long long poff = 0;
+  c->max_pairs = 0;
+  for (Sub &s : c->subs) {
+    s.boff = boff;
+    // element offsets: complex entries (F64/F32) or bf16 values (matrix-core layout)
+    boff += c->layout == 2 ? mfma_store_elems(s)
+                           : (c->layout == 1 ? sym_elems(s) : (long long)s.nOm * s.ldb);
+    s.eoff = (long long)eidx.size();
+    s.poff = poff;
+    if (c->layout == 1) {
+      // ring nodes Omega \ U in Omega-local order
+      const int ux0 = (s.u0x - s.o0x) * P, ux1 = (s.u1x - s.o0x) * P;
+      const int uy0 = (s.u0y - s.o0y) * P, uy1 = (s.u1y - s.o0y) * P;
+      const int uz0 = (s.u0z - s.o0z) * P, uz1 = (s.u1z - s.o0z) * P;
+      for (int k = 0; k < s.nOm; ++k) {
+        const int kx = k % s.nox, ky = (k / s.nox) % s.noy, kz = k / (s.nox * s.noy);
+        const bool inU = kx >= ux0 && kx <= ux1 && ky >= uy0 && ky <= uy1 && kz >= uz0 && kz <= uz1;
+        if (!inU) eidx.push_back(k);
+      }
+      if ((long long)eidx.size() - s.eoff != s.nOm - s.nU) {
+        free_fine(c);
+        return fail(ctx, TH_EINVAL, "internal error: ring node count");
+      }
+      poff += (long long)s.nrb * (s.nrb + 1) / 2 * kSymTile;
+      c->max_pairs = std::max(c->max_pairs, (s.nrb + 1) / 2);
+    }
+  }
+  c->p_rows = poff;
   c->max_ldb = max_ldb;
   c->max_nom = max_nom;
   c->max_rowblocks = (max_ldb + 255) / 256;
@@ -360,7 +405,9 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return hipMalloc(p, bytes) == hipSuccess;
   };
   const size_t R = (size_t)d->max_rhs;
-  bool ok = alloc((void **)&c->d_kap, ncell * sizeof(c64)) &&
+  bool ok = alloc((void **)&c->d_eidx, eidx.size() * sizeof(int)) &&
+            alloc(&c->w_p, R * c->p_rows * sizeof(c64)) &&
+            alloc((void **)&c->d_kap, ncell * sizeof(c64)) &&
             alloc((void **)&c->d_kaps, ncell * sizeof(c64)) &&
             alloc((void **)&c->d_k, ncell * sizeof(double)) &&
             alloc((void **)&c->d_subs, c->subs.size() * sizeof(Sub)) &&
@@ -380,6 +427,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
                      hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(c->d_nblk, nblk.data(), nblk.size() * sizeof(int), hipMemcpyHostToDevice,
                      st) ||
+      (!eidx.empty() && hipMemcpyAsync(c->d_eidx, eidx.data(), eidx.size() * sizeof(int),
+                                       hipMemcpyHostToDevice, st)) ||
       hipMemsetAsync(c->d_B, 0, c->b_bytes, st)) {
     free_fine(c);
     return fail(ctx, TH_EHIP, "upload failed in setup_fine");

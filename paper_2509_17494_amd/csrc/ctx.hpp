@@ -23,11 +23,23 @@ struct Sub {
   int o0x, o1x, o0y, o1y, o0z, o1z;  // Omega cell box
   int nux, nuy, nuz, nox, noy, noz;  // node counts of closed U / Omega per direction
   int nU, nOm;                // nodes of closed U / Omega
-  int ldb;                    // leading dimension (padded n_U) of stored B_i^T
+  int ldb;                    // n_U padded to a multiple of 64 (rows of the stored B_i)
   int robin;                  // bit s set: absorbing term on side s of Omega (x-,x+,y-,y+,z-,z+)
   long long boff;             // element offset of B_i in the operator store
   long long yoff;             // offset of this subdomain's rows in the Y scratch
+  // symmetric-tile layout (FP64/FP32 operators): 64-row blocks of U, 64-column
+  // blocks of the ring Omega \ U, ring node list and partial-sum rows
+  int nrb, neb;
+  long long eoff;             // offset of the ring node list (Omega-local indices)
+  long long poff;             // offset of the transposed-tile partials
 };
+
+constexpr int kSymTile = 64;
+
+// index of the upper tile (a, b), a <= b, among the nrb (nrb + 1) / 2 upper tiles
+__host__ __device__ __forceinline__ int sym_tile(int a, int b, int nrb) {
+  return a * nrb - a * (a - 1) / 2 + (b - a);
+}
 
 // global node index of local Omega node k of subdomain s
 __host__ __device__ __forceinline__ long long om_node(const Sub &s, int k, int P, int n1) {
@@ -46,6 +58,13 @@ __host__ __device__ __forceinline__ void u_node(const Sub &s, int j, int P, int 
   g[2] = s.u0z * P + jz;
   uj = (((s.u0z - s.o0z) * P + jz) * s.noy + (s.u0y - s.o0y) * P + jy) * s.nox +
        (s.u0x - s.o0x) * P + jx;
+}
+
+// global node index of local node j of closed U
+__host__ __device__ __forceinline__ long long u_global(const Sub &s, int j, int P, int n1) {
+  int g[3], uj;
+  u_node(s, j, P, g, uj);
+  return ((long long)g[2] * n1 + g[1]) * n1 + g[0];
 }
 
 // Geometry and coefficients of the fine operator, passed to kernels by value.
@@ -107,6 +126,10 @@ struct th_ctx {
   int *d_nblk = nullptr;       // per node index along an axis: first block, count (2 ints)
   void *d_B = nullptr;         // operator store (layout depends on gemm)
   long long b_entries = 0, b_bytes = 0, y_rows = 0;
+  int layout = 0;              // 0 dense 64-row blocks, 1 symmetric tiles, 2 matrix-core BF16
+  int *d_eidx = nullptr;       // ring node lists (symmetric layout)
+  long long p_rows = 0;        // partial-sum rows per right-hand side (symmetric layout)
+  int max_pairs = 0;           // largest number of 64-row block pairs of a subdomain
   int max_ldb = 0, max_nom = 0, max_rowblocks = 0;
 
   // workspaces (fine vectors of max_rhs, both precisions as needed)
@@ -118,6 +141,7 @@ struct th_ctx {
   void *w_uc = nullptr;        // coarse solution (FP64)
   void *w_t = nullptr;         // coarse sweep temporaries
   void *w_rc32 = nullptr;      // coarse rhs in working precision
+  void *w_p = nullptr;         // transposed-tile partial sums (symmetric layout)
   size_t ws_bytes = 0;
 
   th::CoarseData coarse;

@@ -349,6 +349,54 @@ __global__ __launch_bounds__(256) void k_extract_b(const Sub *__restrict__ subs,
   }
 }
 
+// Symmetric-tile layout (see the apply kernel): workgroup = one tile of one
+// subdomain; entries (l, c) row-major.  Upper tile (a, b): rows 64 a + l and
+// columns 64 b + c of the U x U block of A^{-1}; ring tile (a, e): rows
+// 64 a + l of U, ring columns 64 e + c.  No weights (applied after the sum).
+template <typename TB>
+__global__ __launch_bounds__(256) void k_extract_sym(const Sub *__restrict__ subs, int s0,
+                                                     const c64 *__restrict__ A, int ld,
+                                                     long long stride,
+                                                     const int *__restrict__ eidx,
+                                                     cx<TB> *__restrict__ B, int P) {
+  constexpr int ST = kSymTile;
+  const Sub s = subs[s0 + blockIdx.y];
+  const c64 *Ab = A + blockIdx.y * stride;
+  const int nrb = s.nrb, neb = s.neb;
+  const int nS = nrb * (nrb + 1) / 2, nE = s.nOm - s.nU;
+  const int t = blockIdx.x;
+  if (t >= nS + nrb * neb) return;  // uniform
+  int a, b = -1, e = -1;
+  if (t < nS) {
+    a = 0;
+    while (a + 1 < nrb && sym_tile(a + 1, a + 1, nrb) <= t) ++a;
+    b = a + (t - sym_tile(a, a, nrb));
+  } else {
+    a = (t - nS) / neb;
+    e = (t - nS) - a * neb;
+  }
+  cx<TB> *tile = B + s.boff + (long long)t * (ST * ST);
+  for (int q = threadIdx.x; q < ST * ST; q += blockDim.x) {
+    const int l = q / ST, cc = q % ST;
+    const int i = a * ST + l;
+    c64 v = {0, 0};
+    if (i < s.nU) {
+      int g[3], ui;
+      u_node(s, i, P, g, ui);
+      int col = -1;
+      if (b >= 0) {
+        const int j = b * ST + cc;
+        if (j < s.nU) u_node(s, j, P, g, col);
+      } else {
+        const int k = e * ST + cc;
+        if (k < nE) col = eidx[s.eoff + k];
+      }
+      if (col >= 0) v = Ab[(long long)ui * ld + col];
+    }
+    tile[q] = cx<TB>{(TB)v.re, (TB)v.im};
+  }
+}
+
 int setup_subdomain_operators(th_ctx *c) {
   hipStream_t s = c->stream;
   const int nsub = (int)c->subs.size();
@@ -410,9 +458,20 @@ int setup_subdomain_operators(th_ctx *c) {
     rc = gj_invert_batched(work, npad, npad, mat, nb, s, pws);
     if (rc) break;
     dim3 ge(ceil_div(c->max_ldb, 256), 64, nb);
+    int max_tiles = 0;
+    for (const Sub &sb : c->subs)
+      max_tiles = std::max(max_tiles, sb.nrb * (sb.nrb + 1) / 2 + sb.nrb * sb.neb);
     if (c->desc.gemm == TH_GEMM_BF16) {
       rc = launch_extract_b_mfma(c, s0, nb, work, npad, mat, s);
       if (rc) break;
+    } else if (c->layout == 1 && c->desc.gemm == TH_GEMM_F32) {
+      hipLaunchKernelGGL((k_extract_sym<float>), dim3(max_tiles, nb), dim3(256), 0, s, c->d_subs,
+                         s0, (const c64 *)work, npad, mat, (const int *)c->d_eidx,
+                         (cx<float> *)c->d_B, c->P);
+    } else if (c->layout == 1) {
+      hipLaunchKernelGGL((k_extract_sym<double>), dim3(max_tiles, nb), dim3(256), 0, s, c->d_subs,
+                         s0, (const c64 *)work, npad, mat, (const int *)c->d_eidx,
+                         (cx<double> *)c->d_B, c->P);
     } else if (c->desc.gemm == TH_GEMM_F32)
       hipLaunchKernelGGL((k_extract_b<float>), ge, dim3(256), 0, s, c->d_subs, s0,
                          (const c64 *)work, npad, mat, c->d_nblk, (cx<float> *)c->d_B, c->P);

@@ -64,6 +64,156 @@ __global__ __launch_bounds__(256) void k_dd_apply(const Sub *__restrict__ subs,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric-tile layout.  A_s^(i) is complex symmetric (a symmetric bilinear
+// form, no conjugation), hence so is its inverse, and the U x U block of
+// R_U (A_s^(i))^{-1} is stored once: upper 64 x 64 tiles (a, b), a <= b, then
+// the 64 x 64 tiles (a, e) of the U x ring block (ring = Omega \ U, in
+// Omega-local order), every tile row-major; no weights folded in.  A
+// workgroup owns the row blocks w and nrb - 1 - w of one subdomain (equal
+// work for all pairs) and reads each of their tiles once: a tile (a, b)
+// contributes S_ab x_b to the rows of block a (accumulated in registers) and,
+// for a < b, S_ab^T x_a to the rows of block b, written as a partial vector
+// that k_dd_symred adds in a fixed order.  Thread (tx, ty) owns rows ty + 16 i
+// and columns tx + 16 j of a tile, so every load of a wavefront covers 4 x 256
+// consecutive bytes (FP64).
+template <typename TB, typename T>
+__global__ __launch_bounds__(256) void k_dd_sym(const Sub *__restrict__ subs,
+                                                const cx<TB> *__restrict__ B,
+                                                const int *__restrict__ eidx,
+                                                const cx<T> *__restrict__ r, cx<T> *__restrict__ Y,
+                                                cx<T> *__restrict__ Pp, int P, int n1, long long nf,
+                                                long long yrows, long long prows, int nrhs) {
+  constexpr int ST = kSymTile;
+  __shared__ cx<T> red[16][ST + 1];
+  const Sub s = subs[blockIdx.y];
+  const int nrb = s.nrb, neb = s.neb, w = blockIdx.x;
+  if (w >= (nrb + 1) / 2) return;  // uniform
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int nS = nrb * (nrb + 1) / 2, nE = s.nOm - s.nU;
+  const cx<TB> *Bs = B + s.boff;
+  for (int q = 0; q < nrhs; ++q) {
+    const cx<T> *rq = r + (long long)q * nf;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int a = pass == 0 ? w : nrb - 1 - w;
+      if (pass == 1 && a == w) break;  // middle block of an odd count
+      cx<T> xa[4], acc[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = a * ST + ty + 16 * i;
+        xa[i] = j < s.nU ? rq[u_global(s, j, P, n1)] : cx<T>{0, 0};
+        acc[i] = {0, 0};
+      }
+      for (int b = a; b < nrb; ++b) {
+        const cx<TB> *tile = Bs + (long long)sym_tile(a, b, nrb) * (ST * ST);
+        cx<T> xb[4], pb[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int j = b * ST + tx + 16 * jj;
+          xb[jj] = j < s.nU ? rq[u_global(s, j, P, n1)] : cx<T>{0, 0};
+          pb[jj] = {0, 0};
+        }
+        cx<T> v[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            v[i][jj] = ccast<T>(ld_stream(tile + (ty + 16 * i) * ST + tx + 16 * jj));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            cmac(acc[i], v[i][jj], xb[jj]);
+            cmac(pb[jj], v[i][jj], xa[i]);
+          }
+        if (b > a) {  // uniform: transposed contribution to the rows of block b
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) red[ty][tx + 16 * jj] = pb[jj];
+          __syncthreads();
+          if (threadIdx.x < ST) {
+            cx<T> sum = {0, 0};
+            for (int t = 0; t < 16; ++t) sum = sum + red[t][threadIdx.x];
+            Pp[(long long)q * prows + s.poff + (long long)sym_tile(a, b, nrb) * ST + threadIdx.x] =
+                sum;
+          }
+          __syncthreads();
+        }
+      }
+      for (int e = 0; e < neb; ++e) {
+        const cx<TB> *tile = Bs + (long long)(nS + a * neb + e) * (ST * ST);
+        cx<T> xe[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int k = e * ST + tx + 16 * jj;
+          xe[jj] = k < nE ? rq[om_node(s, eidx[s.eoff + k], P, n1)] : cx<T>{0, 0};
+        }
+        cx<T> v[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            v[i][jj] = ccast<T>(ld_stream(tile + (ty + 16 * i) * ST + tx + 16 * jj));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) cmac(acc[i], v[i][jj], xe[jj]);
+      }
+      // sum the 16 column owners of each row (lanes 16 ty .. 16 ty + 15)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          acc[i].re += __shfl_xor(acc[i].re, o, 64);
+          acc[i].im += __shfl_xor(acc[i].im, o, 64);
+        }
+      if (tx == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = a * ST + ty + 16 * i;
+          if (j < s.nU) Y[(long long)q * yrows + s.yoff + j] = acc[i];
+        }
+      }
+    }
+  }
+}
+
+// Y_i[j] = (Y_i[j] + sum_{a < j / 64} partial(a, j / 64)[j % 64]) / L_j, the
+// partials added in ascending a.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dd_symred(const Sub *__restrict__ subs,
+                                                   const int *__restrict__ nblk,
+                                                   const cx<T> *__restrict__ Pp,
+                                                   cx<T> *__restrict__ Y, int P, long long yrows,
+                                                   long long prows) {
+  constexpr int ST = kSymTile;
+  const Sub s = subs[blockIdx.y];
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= s.nU) return;
+  const long long q = blockIdx.z;
+  const int b = j / ST, c = j % ST;
+  cx<T> *y = Y + q * yrows + s.yoff + j;
+  cx<T> acc = *y;
+  const cx<T> *pp = Pp + q * prows + s.poff + c;
+  for (int a = 0; a < b; ++a) acc = acc + pp[(long long)sym_tile(a, b, s.nrb) * ST];
+  int gn[3], uj;
+  u_node(s, j, P, gn, uj);
+  const T invL = (T)(1.0 / (double)(nblk[2 * gn[0] + 1] * nblk[2 * gn[1] + 1] * nblk[2 * gn[2] + 1]));
+  *y = cx<T>{acc.re * invL, acc.im * invL};
+}
+
+template <typename TB, typename T>
+static int dd_sym_t(const th_ctx *c, const void *r, void *y, int nrhs, hipStream_t s) {
+  const unsigned nsub = (unsigned)c->subs.size();
+  hipLaunchKernelGGL((k_dd_sym<TB, T>), dim3(c->max_pairs, nsub), dim3(256), 0, s, c->d_subs,
+                     (const cx<TB> *)c->d_B, (const int *)c->d_eidx, (const cx<T> *)r, (cx<T> *)y,
+                     (cx<T> *)c->w_p, c->P, c->n1, c->nf, c->y_rows, c->p_rows, nrhs);
+  hipLaunchKernelGGL((k_dd_symred<T>), dim3(ceil_div(c->max_ldb, 256), nsub, nrhs), dim3(256), 0,
+                     s, c->d_subs, (const int *)c->d_nblk, (const cx<T> *)c->w_p, (cx<T> *)y,
+                     c->P, c->y_rows, c->p_rows);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
 // v_j (assign) or u_j += sum over the closed U^(i) containing node j of (Y_i)_j,
 // subdomains in ascending order.
 template <typename T>
@@ -122,9 +272,15 @@ int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32,
     case TH_GEMM_BF16:
       return launch_dd_mfma(c, r, y, nrhs, f32, c->mfma_cfg, c->mfma_grid, s);
     case TH_GEMM_F64:
+      if (c->layout == 1)
+        return f32 ? dd_sym_t<double, float>(c, r, y, nrhs, s)
+                   : dd_sym_t<double, double>(c, r, y, nrhs, s);
       return f32 ? dd_apply_t<double, float>(c, r, y, nrhs, s)
                  : dd_apply_t<double, double>(c, r, y, nrhs, s);
     case TH_GEMM_F32:
+      if (c->layout == 1)
+        return f32 ? dd_sym_t<float, float>(c, r, y, nrhs, s)
+                   : dd_sym_t<float, double>(c, r, y, nrhs, s);
       return f32 ? dd_apply_t<float, float>(c, r, y, nrhs, s)
                  : dd_apply_t<float, double>(c, r, y, nrhs, s);
     default:

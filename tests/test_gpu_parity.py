@@ -48,6 +48,7 @@ CASES = [  # (N, p, l_dd): several tiles of the operator kernel and ragged tails
     (19, 4, 6),
     (7, 6, 3),
     (5, 8, 2),
+    (33, 4, 8),  # large enough for the symmetric-tile operator layout
 ]
 
 
@@ -211,6 +212,13 @@ def test_smooth_bf16_matrix_cores(N, p, l_dd, nrhs):
         assert err_emu < 2e-3
         # cost of the precision choice (BF16 unit roundoff 2^-8 on both operands)
         assert err < 5e-2
+
+
+@pytest.mark.parametrize("N,p,l_dd,layout", [(19, 4, 6, 0), (33, 4, 8, 1)])
+def test_operator_layout_choice(N, p, l_dd, layout):
+    """Dense rows below, symmetric tiles above the 80 % storage threshold."""
+    s = make_solver(hetero_k(N, p, seed=1), p, l_dd, max_rhs=1, coarse=None)
+    assert s.info()["smoother_layout"] == layout
 
 
 def test_smooth_f32_storage():
