@@ -117,7 +117,7 @@ static void free_graphs(th_ctx *c) {
 static void free_fine(th_ctx *c) {
   void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,  c->d_subs, c->d_nblk, c->d_B, c->w_r,
                   c->w_v,   c->w_rr,   c->w_y,  c->w_rc,   c->w_uc,   c->w_t, c->w_rc32,
-                  c->d_eidx, c->w_p};
+                  c->d_eidx, c->w_p, c->w_x};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_kap = c->d_kaps = nullptr;
@@ -126,7 +126,7 @@ static void free_fine(th_ctx *c) {
   c->d_nblk = nullptr;
   c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = c->w_rc32 = nullptr;
   c->d_eidx = nullptr;
-  c->w_p = nullptr;
+  c->w_p = c->w_x = nullptr;
   c->fine_ready = false;
 }
 
@@ -361,7 +361,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     c->layout = (d->gemm == TH_GEMM_BF16) ? 2 : (10 * sym <= 8 * dense ? 1 : 0);
   }
   std::vector<int> eidx;
-  long long poff = 0;
+  long long poff = 0, xoff = 0;
   c->max_pairs = 0;
   for (Sub &s : c->subs) {
     s.boff = boff;
@@ -370,6 +370,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
                            : (c->layout == 1 ? sym_elems(s) : (long long)s.nOm * s.ldb);
     s.eoff = (long long)eidx.size();
     s.poff = poff;
+    s.xoff = xoff;
     if (c->layout == 1) {
       // ring nodes Omega \ U in Omega-local order
       const int ux0 = (s.u0x - s.o0x) * P, ux1 = (s.u1x - s.o0x) * P;
@@ -385,10 +386,12 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
         return fail(ctx, TH_EINVAL, "internal error: ring node count");
       }
       poff += (long long)s.nrb * (s.nrb + 1) / 2 * kSymTile;
+      xoff += s.nOm;
       c->max_pairs = std::max(c->max_pairs, (s.nrb + 1) / 2);
     }
   }
   c->p_rows = poff;
+  c->x_rows = xoff;
   c->max_ldb = max_ldb;
   c->max_nom = max_nom;
   c->max_rowblocks = (max_ldb + 255) / 256;
@@ -407,6 +410,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   const size_t R = (size_t)d->max_rhs;
   bool ok = alloc((void **)&c->d_eidx, eidx.size() * sizeof(int)) &&
             alloc(&c->w_p, R * c->p_rows * sizeof(c64)) &&
+            alloc(&c->w_x, R * c->x_rows * sizeof(c64)) &&
             alloc((void **)&c->d_kap, ncell * sizeof(c64)) &&
             alloc((void **)&c->d_kaps, ncell * sizeof(c64)) &&
             alloc((void **)&c->d_k, ncell * sizeof(double)) &&

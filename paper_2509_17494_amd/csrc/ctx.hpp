@@ -32,6 +32,7 @@ struct Sub {
   int nrb, neb;
   long long eoff;             // offset of the ring node list (Omega-local indices)
   long long poff;             // offset of the transposed-tile partials
+  long long xoff;             // offset of the gathered patch (U nodes, then ring nodes)
 };
 
 constexpr int kSymTile = 64;
@@ -129,6 +130,7 @@ struct th_ctx {
   int layout = 0;              // 0 dense 64-row blocks, 1 symmetric tiles, 2 matrix-core BF16
   int *d_eidx = nullptr;       // ring node lists (symmetric layout)
   long long p_rows = 0;        // partial-sum rows per right-hand side (symmetric layout)
+  long long x_rows = 0;        // gathered patch rows per right-hand side (symmetric layout)
   int max_pairs = 0;           // largest number of 64-row block pairs of a subdomain
   int max_ldb = 0, max_nom = 0, max_rowblocks = 0;
 
@@ -142,6 +144,7 @@ struct th_ctx {
   void *w_t = nullptr;         // coarse sweep temporaries
   void *w_rc32 = nullptr;      // coarse rhs in working precision
   void *w_p = nullptr;         // transposed-tile partial sums (symmetric layout)
+  void *w_x = nullptr;         // gathered patches X_i (symmetric layout)
   size_t ws_bytes = 0;
 
   th::CoarseData coarse;

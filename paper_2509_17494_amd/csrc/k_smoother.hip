@@ -74,34 +74,51 @@ __global__ __launch_bounds__(256) void k_dd_apply(const Sub *__restrict__ subs,
 // work for all pairs) and reads each of their tiles once: a tile (a, b)
 // contributes S_ab x_b to the rows of block a (accumulated in registers) and,
 // for a < b, S_ab^T x_a to the rows of block b, written as a partial vector
-// that k_dd_symred adds in a fixed order.  Thread (tx, ty) owns rows ty + 16 i
-// and columns tx + 16 j of a tile, so every load of a wavefront covers 4 x 256
-// consecutive bytes (FP64).
+// that k_dd_symred adds in a fixed order.  Thread (tx, ty) owns rows 4 ty + i
+// and columns tx + 16 j of a tile, so a wavefront streams 16 consecutive rows
+// (16 KiB, FP64) of every tile.  The patch X_i is gathered once per launch into a
+// contiguous buffer (U nodes, then ring nodes) by k_dd_gather.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dd_gather(const Sub *__restrict__ subs,
+                                                   const int *__restrict__ eidx,
+                                                   const cx<T> *__restrict__ r,
+                                                   cx<T> *__restrict__ X, int P, int n1,
+                                                   long long nf, long long xrows) {
+  const Sub s = subs[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= s.nOm) return;
+  const long long q = blockIdx.z;
+  const long long g = i < s.nU ? u_global(s, i, P, n1) : om_node(s, eidx[s.eoff + i - s.nU], P, n1);
+  X[q * xrows + s.xoff + i] = r[q * nf + g];
+}
+
 template <typename TB, typename T>
 __global__ __launch_bounds__(256) void k_dd_sym(const Sub *__restrict__ subs,
                                                 const cx<TB> *__restrict__ B,
-                                                const int *__restrict__ eidx,
-                                                const cx<T> *__restrict__ r, cx<T> *__restrict__ Y,
-                                                cx<T> *__restrict__ Pp, int P, int n1, long long nf,
+                                                const cx<T> *__restrict__ X, cx<T> *__restrict__ Y,
+                                                cx<T> *__restrict__ Pp, long long xrows,
                                                 long long yrows, long long prows, int nrhs) {
   constexpr int ST = kSymTile;
-  __shared__ cx<T> red[16][ST + 1];
+  // double-buffered: the partial of a tile is reduced from one buffer while the
+  // next tile fills the other, one barrier per tile
+  __shared__ cx<T> red[2][16][ST + 1];
   const Sub s = subs[blockIdx.y];
   const int nrb = s.nrb, neb = s.neb, w = blockIdx.x;
   if (w >= (nrb + 1) / 2) return;  // uniform
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int nS = nrb * (nrb + 1) / 2, nE = s.nOm - s.nU;
   const cx<TB> *Bs = B + s.boff;
+  int buf = 0;
   for (int q = 0; q < nrhs; ++q) {
-    const cx<T> *rq = r + (long long)q * nf;
+    const cx<T> *xq = X + (long long)q * xrows + s.xoff;  // U nodes, then ring nodes
     for (int pass = 0; pass < 2; ++pass) {
       const int a = pass == 0 ? w : nrb - 1 - w;
       if (pass == 1 && a == w) break;  // middle block of an odd count
       cx<T> xa[4], acc[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int j = a * ST + ty + 16 * i;
-        xa[i] = j < s.nU ? rq[u_global(s, j, P, n1)] : cx<T>{0, 0};
+        const int j = a * ST + 4 * ty + i;
+        xa[i] = j < s.nU ? xq[j] : cx<T>{0, 0};
         acc[i] = {0, 0};
       }
       for (int b = a; b < nrb; ++b) {
@@ -110,7 +127,7 @@ __global__ __launch_bounds__(256) void k_dd_sym(const Sub *__restrict__ subs,
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int j = b * ST + tx + 16 * jj;
-          xb[jj] = j < s.nU ? rq[u_global(s, j, P, n1)] : cx<T>{0, 0};
+          xb[jj] = j < s.nU ? xq[j] : cx<T>{0, 0};
           pb[jj] = {0, 0};
         }
         cx<T> v[4][4];
@@ -118,7 +135,7 @@ __global__ __launch_bounds__(256) void k_dd_sym(const Sub *__restrict__ subs,
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj)
-            v[i][jj] = ccast<T>(ld_stream(tile + (ty + 16 * i) * ST + tx + 16 * jj));
+            v[i][jj] = ccast<T>(ld_stream(tile + (4 * ty + i) * ST + tx + 16 * jj));
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -128,15 +145,15 @@ __global__ __launch_bounds__(256) void k_dd_sym(const Sub *__restrict__ subs,
           }
         if (b > a) {  // uniform: transposed contribution to the rows of block b
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) red[ty][tx + 16 * jj] = pb[jj];
+          for (int jj = 0; jj < 4; ++jj) red[buf][ty][tx + 16 * jj] = pb[jj];
           __syncthreads();
           if (threadIdx.x < ST) {
             cx<T> sum = {0, 0};
-            for (int t = 0; t < 16; ++t) sum = sum + red[t][threadIdx.x];
+            for (int t = 0; t < 16; ++t) sum = sum + red[buf][t][threadIdx.x];
             Pp[(long long)q * prows + s.poff + (long long)sym_tile(a, b, nrb) * ST + threadIdx.x] =
                 sum;
           }
-          __syncthreads();
+          buf ^= 1;
         }
       }
       for (int e = 0; e < neb; ++e) {
@@ -145,14 +162,14 @@ __global__ __launch_bounds__(256) void k_dd_sym(const Sub *__restrict__ subs,
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int k = e * ST + tx + 16 * jj;
-          xe[jj] = k < nE ? rq[om_node(s, eidx[s.eoff + k], P, n1)] : cx<T>{0, 0};
+          xe[jj] = k < nE ? xq[s.nU + k] : cx<T>{0, 0};
         }
         cx<T> v[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj)
-            v[i][jj] = ccast<T>(ld_stream(tile + (ty + 16 * i) * ST + tx + 16 * jj));
+            v[i][jj] = ccast<T>(ld_stream(tile + (4 * ty + i) * ST + tx + 16 * jj));
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -169,7 +186,7 @@ __global__ __launch_bounds__(256) void k_dd_sym(const Sub *__restrict__ subs,
       if (tx == 0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int j = a * ST + ty + 16 * i;
+          const int j = a * ST + 4 * ty + i;
           if (j < s.nU) Y[(long long)q * yrows + s.yoff + j] = acc[i];
         }
       }
@@ -204,9 +221,12 @@ __global__ __launch_bounds__(256) void k_dd_symred(const Sub *__restrict__ subs,
 template <typename TB, typename T>
 static int dd_sym_t(const th_ctx *c, const void *r, void *y, int nrhs, hipStream_t s) {
   const unsigned nsub = (unsigned)c->subs.size();
+  hipLaunchKernelGGL((k_dd_gather<T>), dim3(ceil_div(c->max_nom, 256), nsub, nrhs), dim3(256), 0,
+                     s, c->d_subs, (const int *)c->d_eidx, (const cx<T> *)r, (cx<T> *)c->w_x, c->P,
+                     c->n1, c->nf, c->x_rows);
   hipLaunchKernelGGL((k_dd_sym<TB, T>), dim3(c->max_pairs, nsub), dim3(256), 0, s, c->d_subs,
-                     (const cx<TB> *)c->d_B, (const int *)c->d_eidx, (const cx<T> *)r, (cx<T> *)y,
-                     (cx<T> *)c->w_p, c->P, c->n1, c->nf, c->y_rows, c->p_rows, nrhs);
+                     (const cx<TB> *)c->d_B, (const cx<T> *)c->w_x, (cx<T> *)y, (cx<T> *)c->w_p,
+                     c->x_rows, c->y_rows, c->p_rows, nrhs);
   hipLaunchKernelGGL((k_dd_symred<T>), dim3(ceil_div(c->max_ldb, 256), nsub, nrhs), dim3(256), 0,
                      s, c->d_subs, (const int *)c->d_nblk, (const cx<T> *)c->w_p, (cx<T> *)y,
                      c->P, c->y_rows, c->p_rows);
