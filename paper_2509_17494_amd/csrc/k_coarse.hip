@@ -236,7 +236,8 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
   // rows are streamed once when one pass covers all right-hand sides
   const bool once = gridDim.y == 1;
-#pragma unroll 8
+  constexpr int UNR = RC == 1 ? 8 : 4;  // deeper unrolling only where registers allow
+#pragma unroll UNR
   for (int b = lane; b < nb; b += 64) {
     const c64 g = once ? ld_stream(row + b) : row[b];
 #pragma unroll
