@@ -152,9 +152,10 @@ th_status th_get_info(const th_ctx *ctx, th_info *info);
  * (A_s^(i))^{-1} (n_U x n_Omega), computed on the device in FP64 and stored
  * in desc->gemm precision.  A_s^(i) is complex symmetric, so for FP64/FP32
  * storage the U x U block of its inverse is kept once (upper 64 x 64 tiles)
- * whenever that stores at most 80 % of the dense bytes (th_info.smoother_layout).  Blocking.  Errors: TH_EINVAL (odd order, n < 1,
- * k <= 0 or NaN, l_dd < 1, dim not 2 or 3), TH_EUNSUPPORTED (3-D order above
- * 4), TH_ENOMEM, TH_ENUMERIC (zero pivot). */
+ * whenever that stores at most 80 % of the dense bytes (th_info.smoother_layout).
+ * Blocking.  Errors: TH_EINVAL (odd order, n < 1, k <= 0 or NaN, l_dd < 1, dim
+ * not 2 or 3), TH_EUNSUPPORTED (3-D order above 4), TH_ENOMEM, TH_ENUMERIC
+ * (zero pivot). */
 th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *desc);
 
 /* Build the coarse QSFEM quasi-FE matrix (Sec. 3.3, eq. element_wise_qsfem;

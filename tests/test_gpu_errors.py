@@ -1,0 +1,100 @@
+"""Error handling through the C ABI (status codes documented in the header)
+and the stationary two-grid iteration against the oracle.  Every failure
+here is a host-side check: no kernel is launched with invalid input."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle.twogrid import TwoGrid
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def solver(k, **kw):
+    from paper_2509_17494_amd import TwoGridSolver
+    return TwoGridSolver(k, **kw)
+
+
+def status_of(fn):
+    from paper_2509_17494_amd import THError
+    with pytest.raises(THError) as e:
+        fn()
+    return e.value.status
+
+
+def test_setup_rejects_invalid_problems():
+    from paper_2509_17494_amd import _lib as L
+    k = np.full((6, 6), 10.0)
+    assert status_of(lambda: solver(k, order=3)) == L.TH_EINVAL        # odd order
+    assert status_of(lambda: solver(k, order=10)) == L.TH_EINVAL       # above 8
+    bad = k.copy()
+    bad[2, 3] = -1.0
+    assert status_of(lambda: solver(bad, order=2)) == L.TH_EINVAL      # k <= 0
+    bad[2, 3] = np.nan
+    assert status_of(lambda: solver(bad, order=2)) == L.TH_EINVAL      # NaN
+    assert status_of(lambda: solver(k, order=2, l_dd=0)) == L.TH_EINVAL
+    assert status_of(lambda: solver(k, order=2, alpha_s=-0.1)) == L.TH_EINVAL
+    k3 = np.full((3, 3, 3), 5.0)
+    assert status_of(lambda: solver(k3, order=6)) == L.TH_EUNSUPPORTED  # 3-D order 6
+
+
+def test_coarse_schemes_rejected_where_unsupported():
+    from paper_2509_17494_amd import CoarseStencilMLP, _lib as L
+    k3 = np.full((4, 4, 4), 5.0)
+    s = solver(k3, order=2, l_dd=2, coarse=None)
+    net = CoarseStencilMLP()
+    assert status_of(lambda: s.setup_coarse("mlp", (net, 1e-3))) == L.TH_EUNSUPPORTED
+    k = np.full((8, 8), 8.0)
+    s2 = solver(k, order=2, l_dd=4, coarse=None)
+    # the plain fit needs fine k h < pi in every cell
+    hot = np.full((8, 8), 8.0 * 8 * 4.1 / 2)
+    s3 = solver(hot, order=2, l_dd=4, coarse=None)
+    assert status_of(lambda: s3.setup_coarse("plainfit")) == L.TH_EINVAL
+    # a step that needs the coarse level before it exists
+    f = torch.zeros((1, s2.n_fine), dtype=torch.complex128, device="cuda")
+    assert status_of(lambda: s2.twogrid(f.clone(), f)) == L.TH_ESTATE
+
+
+def test_vector_calls_reject_more_rhs_than_setup_allowed():
+    from paper_2509_17494_amd import _lib as L
+    k = np.full((8, 8), 8.0)
+    s = solver(k, order=2, l_dd=4, max_rhs=1)
+    u = torch.zeros((2, s.n_fine), dtype=torch.complex128, device="cuda")
+    with pytest.raises(ValueError):  # the binding checks first
+        s.residual(u, u.clone())
+    r = torch.empty_like(u)
+    p = lambda t: C.c_void_p(t.data_ptr())
+    st = s._lib.th_residual(s._h, p(u), p(u), p(r), 2, L.TH_C128)  # the C ABI checks too
+    torch.cuda.synchronize()
+    assert st == L.TH_EINVAL
+
+
+def test_gmres_reports_not_converged_with_last_iterate():
+    from paper_2509_17494_amd import _lib as L
+    cfg = syn.config("C1")
+    f = syn.gaussian_load(cfg["n"], cfg["p"], cfg["centres"], cfg["sigma"])
+    s = solver(cfg["k"], order=cfg["p"], l_dd=cfg["l_dd"], max_rhs=1)
+    u, st = s.solve(torch.from_numpy(f).to("cuda"), maxit=2)
+    assert st.status == L.TH_ENOTCONV and st.iters == 2
+    assert 1e-6 < st.rel_res < 1.0
+
+
+def test_stationary_iteration_matches_oracle_steps():
+    """u_{m+1} = TwoGridStep(u_m, f) from u_0 = 0 (Alg. 1 as a stationary
+    method): three steps against the oracle's three steps."""
+    N, p, l_dd = 12, 4, 4
+    k = syn.wavenumber_from_speed(syn.grf_speed(N, 2, 0.2, 1.5, 4.0, seed=3), p * N / 10.0)
+    tg = TwoGrid(p, k, alpha_s=0.5, l_dd=l_dd)
+    f = syn.gaussian_load(N, p, [[0.5, 0.5]], 2.0 / N)[0]
+    x = np.zeros_like(f)
+    for _ in range(3):
+        x = tg.twogrid_step(x, f)
+    s = solver(k, order=p, l_dd=l_dd, max_rhs=1)
+    u, st = s.solve(torch.from_numpy(f[None]).to("cuda"), method="stationary", maxit=3, rtol=1e-300)
+    got = u.cpu().numpy()[0]
+    assert st.iters == 3
+    assert np.linalg.norm(got - x) / np.linalg.norm(x) < 1e-11
