@@ -1,15 +1,17 @@
 """FP64 reference of the coarse-stencil surrogate network (a project
 addition; no passage of the paper defines it).
 
-Architecture: 3 inputs -> 64 -> 64 -> 2 outputs, SiLU activations, three
-affine layers.  Inputs are standardised (eta_c = h_c k, order p, damping
-ratio); the two outputs are the standardised y_m = log(max(-e_m, 0) + 1e-13)
-where e_m is the relative fine dispersion error (r_m / kh - 1) at the QSFEM
-directions t_1 = pi/16, t_2 = 3 pi/16.  Loss: mean squared error over
-samples and outputs.  Optimiser: Adam (Kingma & Ba 2015) with bias correction.
+Architecture: 3 inputs -> 64 -> 64 -> n_out outputs, SiLU activations,
+three affine layers.  Inputs are standardised (eta_c = h_c k, order p,
+damping ratio); the outputs are the standardised y_m = log(max(-e_m, 0) +
+1e-13) where e_m is the relative fine dispersion error (r_m / kh - 1): in 2-D
+(n_out = 2) at the QSFEM directions t_1 = pi/16, t_2 = 3 pi/16, in 3-D
+(n_out = 3) along the three directions of the 27-point fit.  Loss: mean
+squared error over samples and outputs.  Optimiser: Adam (Kingma & Ba 2015)
+with bias correction.
 
 Parameter layout (flat, the order the device code uses):
-  W1 (64 x 3, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2).
+  W1 (64 x 3, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (n_out x 64), b3 (n_out).
 """
 from __future__ import annotations
 
@@ -17,13 +19,29 @@ import numpy as np
 
 N_IN, WIDTH, N_OUT = 3, 64, 2
 E_FLOOR = 1e-13
-SHAPES = [(WIDTH, N_IN), (WIDTH,), (WIDTH, WIDTH), (WIDTH,), (N_OUT, WIDTH), (N_OUT,)]
-N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)
+
+
+def shapes(n_out: int = N_OUT):
+    return [(WIDTH, N_IN), (WIDTH,), (WIDTH, WIDTH), (WIDTH,), (n_out, WIDTH), (n_out,)]
+
+
+def n_params(n_out: int = N_OUT) -> int:
+    return sum(int(np.prod(s)) for s in shapes(n_out))
+
+
+N_PARAMS = n_params(N_OUT)
+
+
+def n_out_of(theta) -> int:
+    """Number of outputs of a flat parameter vector."""
+    n_out = (len(theta) - n_params(0)) // (WIDTH + 1)
+    assert n_params(n_out) == len(theta)
+    return n_out
 
 
 def unpack(theta: np.ndarray):
     out, o = [], 0
-    for s in SHAPES:
+    for s in shapes(n_out_of(theta)):
         n = int(np.prod(s))
         out.append(theta[o:o + n].reshape(s))
         o += n
@@ -40,7 +58,7 @@ def dsilu(a):
 
 
 def forward(theta, x):
-    """x: (n, 3) standardised inputs -> (n, 2) outputs and the cache."""
+    """x: (n, 3) standardised inputs -> (n, n_out) outputs and the cache."""
     W1, b1, W2, b2, W3, b3 = unpack(theta)
     a1 = x @ W1.T + b1
     h1 = silu(a1)
@@ -51,13 +69,13 @@ def forward(theta, x):
 
 
 def loss_and_grad(theta, x, t):
-    """Mean squared error over all n * 2 outputs and its gradient."""
+    """Mean squared error over all n * n_out outputs and its gradient."""
     W1, b1, W2, b2, W3, b3 = unpack(theta)
     y, (x, a1, h1, a2, h2) = forward(theta, x)
     n = x.shape[0]
     d = y - t
     loss = float(np.mean(d * d))
-    dy = 2.0 * d / (n * N_OUT)
+    dy = 2.0 * d / (n * y.shape[1])
     gW3 = dy.T @ h2
     gb3 = dy.sum(axis=0)
     dh2 = dy @ W3

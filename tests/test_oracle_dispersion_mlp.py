@@ -89,13 +89,15 @@ def test_plain_fit_matches_fine_dispersion_at_the_two_angles(p, eta):
 
 
 # ---------------------------------------------------------------- MLP --------
-def test_mlp_gradient_by_central_differences():
+@pytest.mark.parametrize("n_out", [2, 3])
+def test_mlp_gradient_by_central_differences(n_out):
     rng = np.random.default_rng(0)
-    theta = rng.standard_normal(mlp.N_PARAMS) * 0.3
+    theta = rng.standard_normal(mlp.n_params(n_out)) * 0.3
     x = rng.standard_normal((7, 3))
-    t = rng.standard_normal((7, 2))
+    t = rng.standard_normal((7, n_out))
     _, g = mlp.loss_and_grad(theta, x, t)
-    idx = rng.choice(mlp.N_PARAMS, 40, replace=False)
+    assert mlp.n_out_of(theta) == n_out
+    idx = rng.choice(mlp.n_params(n_out), 40, replace=False)
     for i in idx:
         e = np.zeros_like(theta)
         e[i] = 1e-6
