@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
     ap.add_argument("--precond", default=None, choices=["c128", "c64"])
+    ap.add_argument("--alpha-s", type=float, default=None,
+                    help="smoother shift alpha_s (default: the workload's, 0.5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--verbose", action="store_true")
@@ -183,7 +185,7 @@ def cpu_baseline(cfg_name):
 
 
 def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, verbose=False,
-                 gemm=None):
+                 gemm=None, alpha_s=None):
     """Set up one workload, then time `steps` solves to 1e-6 after `warmup`
     untimed ones.  With timing, HIP events record every kernel class over the
     timed region (graph replay is off then); without it a separate one-solve
@@ -197,6 +199,8 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
     kry = {k: spec[k] for k in ("restart", "maxit") if k in spec}
     if gemm:
         spec["gemm"] = gemm
+    if alpha_s is not None:
+        spec["alpha_s"] = alpha_s
     N, p, dim = cfg["n"], cfg["p"], cfg.get("dim", 2)
     f_host = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"], dim=dim)
     R = f_host.shape[0]
@@ -275,7 +279,7 @@ def main():
         sys.exit(2)
     mixed = a.workload in ("C3", "C4")
     prim = run_workload(a.workload, a.steps, a.warmup, precond=a.precond, graph=mixed,
-                        timing=not mixed, verbose=a.verbose)
+                        timing=not mixed, verbose=a.verbose, alpha_s=a.alpha_s)
     d = prim["dd"]
     traffic = traffic_entry(a.workload)
     roof = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

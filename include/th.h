@@ -66,7 +66,7 @@ typedef enum {
   TH_COARSE_PLAINFIT = 2, /* per-cell plain dispersion-matching fit (th_plain_fit, or
                              th_plain_fit3d in 3-D) */
   TH_COARSE_MLP = 3       /* per-cell surrogate network with fallback to the plain fit
-                             (2-D only) */
+                             (network family matching the dimension) */
 } th_coarse_scheme;
 
 typedef struct th_mlp th_mlp;
@@ -162,8 +162,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *desc);
  * 27-point in 3-D) on the coarse vertex grid and factorise it once in FP64 on
  * the device (block-tridiagonal elimination over grid lines, or planes in
  * 3-D, with explicit inverses of the diagonal Schur blocks).  Needs
- * th_setup_fine.  Blocking.  Errors: TH_EINVAL, TH_EUNSUPPORTED (surrogate
- * scheme in 3-D), TH_ENOMEM, TH_ENUMERIC. */
+ * th_setup_fine.  Blocking.  Errors: TH_EINVAL (also: surrogate network of the
+ * other dimension's family), TH_ENOMEM, TH_ENUMERIC. */
 th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *desc);
 
 /* r = f - A u (fine Galerkin matrix, eq. bilin_form).  Stream-ordered. */
@@ -239,10 +239,15 @@ th_status th_plain_fit(const double *samples, int n, double *e_out, double *q_ou
  *   samples: HOST n x 3; e_out: HOST n x 3 or NULL; q_out: HOST n x 4 or NULL. */
 th_status th_plain_fit3d(const double *samples, int n, double *e_out, double *q_out);
 
-/* Surrogate network 3 -> 64 -> 64 -> 2 (SiLU), inputs standardised samples,
- * outputs standardised log(max(-e_m, 0) + 1e-13); FP32 master weights with a
- * BF16 copy, FP32 accumulation.  Weight layout (n_params = 4546 floats):
- * W1 (64 x 3 row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2). */
+/* Surrogate network 3 -> 64 -> 64 -> n_out (SiLU), inputs standardised
+ * samples, outputs standardised log(max(-e_m, 0) + 1e-13) of the fine
+ * dispersion errors of a stencil family: n_out = 2 for the 9-point family
+ * (th_plain_fit's e_m, 2-D problems), 3 for the 27-point family
+ * (th_plain_fit3d's e_m, 3-D problems).  FP32 master weights with a BF16
+ * copy, FP32 accumulation.  Weight layout (n_params = 4355 + 65 n_out floats:
+ * 4546 or 4611): W1 (64 x 3 row-major), b1 (64), W2 (64 x 64), b2 (64),
+ * W3 (n_out x 64), b3 (n_out).  Below, arrays of "n_out" values follow the
+ * network's family. */
 typedef struct {
   int epochs;           /* passes over the samples */
   int batch;            /* samples per step (multiple of 64) */
@@ -256,20 +261,24 @@ typedef struct {
   double t_targets_s, t_train_s;  /* plain-fit targets on the host / training on the device */
 } th_mlp_train_stats;
 
-th_status th_mlp_create(th_mlp **out, int hip_device, void *hip_stream);
+th_status th_mlp_create(th_mlp **out, int hip_device, void *hip_stream);  /* 2-D family */
+/* dim 2: the 9-point family, dim 3: the 27-point family; TH_EINVAL otherwise */
+th_status th_mlp_create_family(th_mlp **out, int hip_device, void *hip_stream, int dim);
+/* the network's dimension and parameter count */
+th_status th_mlp_info(const th_mlp *m, int *dim, int *n_params);
 void th_mlp_destroy(th_mlp *m);
 const char *th_mlp_last_error(const th_mlp *m);
-th_status th_mlp_num_params(int *n_params);
+th_status th_mlp_num_params(int *n_params);  /* of the 2-D family */
 /* theta: HOST FP32 weights in the layout above (the BF16 copy is refreshed) */
 th_status th_mlp_set_weights(th_mlp *m, const float *theta, int n_params);
 th_status th_mlp_get_weights(const th_mlp *m, float *theta, int n_params);
 /* standardisation: x_std = (x - in_mean) / in_std, y_std = (y - out_mean) / out_std */
-th_status th_mlp_set_scaling(th_mlp *m, const double in_mean[3], const double in_std[3],
-                             const double out_mean[2], const double out_std[2]);
-th_status th_mlp_get_scaling(const th_mlp *m, double in_mean[3], double in_std[3],
-                             double out_mean[2], double out_std[2]);
+th_status th_mlp_set_scaling(th_mlp *m, const double *in_mean, const double *in_std,
+                             const double *out_mean, const double *out_std);
+th_status th_mlp_get_scaling(const th_mlp *m, double *in_mean, double *in_std, double *out_mean,
+                             double *out_std);
 /* Loss (mean squared error) and gradient for HOST standardised data
- * x_std (n x 3) and y_std (n x 2), computed by the device kernels; bf16 selects
+ * x_std (n x 3) and y_std (n x n_out), computed by the device kernels; bf16 selects
  * the BF16 weight copy.  grad: HOST n_params floats. */
 th_status th_mlp_loss_grad(th_mlp *m, const float *x_std, const float *y_std, int n, int bf16,
                            double *loss, float *grad);
@@ -277,7 +286,7 @@ th_status th_mlp_loss_grad(th_mlp *m, const float *x_std, const float *y_std, in
  * from the samples, Adam steps on the device from the current weights. */
 th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_train_opts *opts,
                        th_mlp_train_stats *stats);
-/* Device inference for n HOST samples: e_out (HOST n x 2) = predicted e_m. */
+/* Device inference for n HOST samples: e_out (HOST n x n_out) = predicted e_m. */
 th_status th_mlp_predict(th_mlp *m, const double *samples, int n, int bf16, double *e_out);
 
 #ifdef __cplusplus

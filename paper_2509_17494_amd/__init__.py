@@ -338,25 +338,28 @@ class TrainStats:
 
 class CoarseStencilMLP:
     """Surrogate network for the per-cell dispersion errors of the fine scheme
-    (3 -> 64 -> 64 -> 2, SiLU), trained and evaluated by the library's HIP
-    kernels (FP32 master weights, BF16 copy, FP32 accumulation)."""
+    (3 -> 64 -> 64 -> n_out, SiLU; n_out = 2 for the 9-point family of 2-D
+    problems, 3 for the 27-point family of 3-D problems), trained and
+    evaluated by the library's HIP kernels (FP32 master weights, BF16 copy,
+    FP32 accumulation)."""
 
-    def __init__(self, weights=None, device: int | None = None):
+    def __init__(self, weights=None, device: int | None = None, dim: int = 2):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        n = C.c_int()
-        self._lib.th_mlp_num_params(C.byref(n))
-        self.n_params = n.value
         with torch.cuda.device(self.device):
             self._stream = torch.cuda.current_stream(self.device)
             h = C.c_void_p()
-            st = self._lib.th_mlp_create(C.byref(h), self.device.index,
-                                         C.c_void_p(self._stream.cuda_stream))
+            st = self._lib.th_mlp_create_family(C.byref(h), self.device.index,
+                                                C.c_void_p(self._stream.cuda_stream), int(dim))
             if st != 0:
-                raise THError(st, "th_mlp_create failed")
+                raise THError(st, "th_mlp_create_family failed")
             self._h = h
+        d, n = C.c_int(), C.c_int()
+        self._check(self._lib.th_mlp_info(self._h, C.byref(d), C.byref(n)))
+        self.dim, self.n_params = d.value, n.value
+        self.n_out = 3 if self.dim == 3 else 2
         if weights is not None:
             self.set_weights(weights)
 
@@ -392,7 +395,7 @@ class CoarseStencilMLP:
         self._keep = a
 
     def scaling(self):
-        a = [np.zeros(3), np.zeros(3), np.zeros(2), np.zeros(2)]
+        a = [np.zeros(3), np.zeros(3), np.zeros(self.n_out), np.zeros(self.n_out)]
         self._check(self._lib.th_mlp_get_scaling(self._h, *[v.ctypes.data for v in a]))
         return a
 
@@ -415,7 +418,7 @@ class CoarseStencilMLP:
 
     def predict(self, samples, bf16=True):
         x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64))
-        e = np.zeros((x.shape[0], 2))
+        e = np.zeros((x.shape[0], self.n_out))
         self._check(self._lib.th_mlp_predict(self._h, x.ctypes.data, x.shape[0],
                                              1 if bf16 else 0, e.ctypes.data))
         return e

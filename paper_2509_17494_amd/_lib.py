@@ -117,6 +117,8 @@ def load_mlp(lib):
         "th_plain_fit3d": ([vp, i, vp, vp], i),
         "th_mlp_num_params": ([C.POINTER(i)], i),
         "th_mlp_create": ([C.POINTER(vp), i, vp], i),
+        "th_mlp_create_family": ([C.POINTER(vp), i, vp, i], i),
+        "th_mlp_info": ([vp, C.POINTER(i), C.POINTER(i)], i),
         "th_mlp_destroy": ([vp], None),
         "th_mlp_last_error": ([vp], C.c_char_p),
         "th_mlp_set_weights": ([vp, vp, i], i),

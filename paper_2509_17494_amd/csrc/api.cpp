@@ -474,7 +474,7 @@ static th_status coarse_stencil_2d(th_ctx *c, const th_coarse_desc *d, std::vect
         if (!(smp[3 * ci] * c->P / 2.0 < M_PI))
           return fail(c, TH_EINVAL, "dispersion fit needs fine k h < pi in every cell");
       }
-    int rc = coarse_weights(d->scheme, d->mlp, d->fallback_tau, smp.data(), Nc * Nc, qw.data(),
+    int rc = coarse_weights(2, d->scheme, d->mlp, d->fallback_tau, smp.data(), Nc * Nc, qw.data(),
                             &c->n_fallback);
     if (rc) return finish(c, rc);
   } else {
@@ -535,12 +535,10 @@ static th_status coarse_stencil_3d(th_ctx *c, const th_coarse_desc *d, std::vect
   auto fine_of = [&](long long cz, long long cy, long long cxx) {
     return ((cz / R) * N + cy / R) * N + cxx / R;
   };
-  if (d->scheme == TH_COARSE_MLP)
-    return fail(c, TH_EUNSUPPORTED, "the surrogate network covers the 2-D stencil family only");
   std::vector<double> qw((size_t)ncc * 4);
   const auto ts0 = std::chrono::steady_clock::now();
   c->n_fallback = 0;
-  if (d->scheme == TH_COARSE_PLAINFIT) {
+  if (d->scheme == TH_COARSE_PLAINFIT || d->scheme == TH_COARSE_MLP) {
     std::vector<double> smp((size_t)ncc * 3);
     for (long long ci = 0; ci < ncc; ++ci) {
       const long long fi = fine_of(ci / ((long long)Nc * Nc), (ci / Nc) % Nc, ci % Nc);
@@ -551,7 +549,9 @@ static th_status coarse_stencil_3d(th_ctx *c, const th_coarse_desc *d, std::vect
       if (!(smp[3 * ci] * c->P / 2.0 < M_PI))
         return fail(c, TH_EINVAL, "dispersion fit needs fine k h < pi in every cell");
     }
-    plain_fit27_batch(smp.data(), (int)ncc, nullptr, qw.data());
+    int rc = coarse_weights(3, d->scheme, d->mlp, d->fallback_tau, smp.data(), (int)ncc,
+                            qw.data(), &c->n_fallback);
+    if (rc) return finish(c, rc);
   } else {
     for (long long ci = 0; ci < ncc; ++ci) {
       if (d->scheme == TH_COARSE_QSFEM) {

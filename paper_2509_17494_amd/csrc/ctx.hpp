@@ -235,7 +235,7 @@ void fit27_from_radii(double eta, const double z[3], double qw[4]);
 void plain_fit27_batch(const double *x, int n, double *e_out, double *q_out);
 
 // mlp_api.cpp
-int coarse_weights(int scheme, const th_mlp *m, double tau, const double *samples, int n,
+int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const double *samples, int n,
                    double *q_out, int *n_fallback);
 
 // k_coarse.hip

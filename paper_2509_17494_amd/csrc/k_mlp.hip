@@ -1,6 +1,7 @@
-// Coarse-stencil surrogate network on the device: 3 -> 64 -> 64 -> 2 MLP with
-// SiLU activations (a project addition that replaces the per-cell
-// dispersion root finding of the plain fit by inference).
+// Coarse-stencil surrogate network on the device: 3 -> 64 -> 64 -> NOUT MLP
+// with SiLU activations (a project addition that replaces the per-cell
+// dispersion root finding of the plain fit by inference); NOUT = 2 for the
+// 9-point family, 3 for the 27-point family.
 //
 // Training step (k_mlp_step): a workgroup takes 64 samples, keeps the weights
 // (FP32, or the BF16 copy widened to FP32) and every activation in LDS, runs
@@ -13,12 +14,14 @@
 
 namespace th {
 
-constexpr int MLP_IN = 3, MLP_W = 64, MLP_OUT = 2, MLP_S = 64;
+constexpr int MLP_IN = 3, MLP_W = 64, MLP_S = 64;
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + MLP_W * MLP_IN, OFF_W2 = OFF_B1 + MLP_W,
-              OFF_B2 = OFF_W2 + MLP_W * MLP_W, OFF_W3 = OFF_B2 + MLP_W,
-              OFF_B3 = OFF_W3 + MLP_OUT * MLP_W, MLP_P = OFF_B3 + MLP_OUT;
+              OFF_B2 = OFF_W2 + MLP_W * MLP_W, OFF_W3 = OFF_B2 + MLP_W;
+template <int NOUT> struct MlpShape {
+  static constexpr int B3 = OFF_W3 + NOUT * MLP_W, P = B3 + NOUT;
+};
 
-int mlp_num_params() { return MLP_P; }
+int mlp_num_params(int n_out) { return OFF_W3 + n_out * (MLP_W + 1); }
 
 __device__ __forceinline__ float bf2f(unsigned short b) {
   return __uint_as_float(((unsigned int)b) << 16);
@@ -30,6 +33,7 @@ __device__ __forceinline__ unsigned short f2bf_rne(float x) {
 }
 __device__ __forceinline__ float sigm(float a) { return 1.0f / (1.0f + expf(-a)); }
 
+template <int MLP_OUT>
 __global__ __launch_bounds__(256) void k_mlp_step(const float *__restrict__ master,
                                                   const unsigned short *__restrict__ wbf, int use_bf16,
                                                   const float *__restrict__ x,
@@ -37,6 +41,7 @@ __global__ __launch_bounds__(256) void k_mlp_step(const float *__restrict__ mast
                                                   int count, float inv_norm,
                                                   float *__restrict__ gpart,
                                                   float *__restrict__ lpart) {
+  constexpr int MLP_P = MlpShape<MLP_OUT>::P, OFF_B3 = MlpShape<MLP_OUT>::B3;
   __shared__ float W[MLP_P];
   __shared__ float X[MLP_S][MLP_IN];
   __shared__ float A1[MLP_S][MLP_W], H1[MLP_S][MLP_W], A2[MLP_S][MLP_W], H2[MLP_S][MLP_W];
@@ -152,6 +157,7 @@ __global__ __launch_bounds__(256) void k_mlp_step(const float *__restrict__ mast
 
 // Fixed-order reduction of the partials; Adam on the FP32 master weights
 // (step >= 1), or only the reduced gradient (step == 0).
+template <int MLP_OUT>
 __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ master,
                                                   unsigned short *__restrict__ wbf,
                                                   float *__restrict__ m1, float *__restrict__ m2,
@@ -159,6 +165,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ master,
                                                   const float *__restrict__ lpart, int nblk,
                                                   int step, float lr, float *__restrict__ grad_out,
                                                   float *__restrict__ loss_out) {
+  constexpr int MLP_P = MlpShape<MLP_OUT>::P;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     float l = 0.0f;
@@ -182,10 +189,12 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ master,
   wbf[i] = f2bf_rne(w);
 }
 
+template <int MLP_OUT>
 __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ master,
                                                    const unsigned short *__restrict__ wbf,
                                                    int use_bf16, const float *__restrict__ x,
                                                    float *__restrict__ y, int n) {
+  constexpr int MLP_P = MlpShape<MLP_OUT>::P, OFF_B3 = MlpShape<MLP_OUT>::B3;
   __shared__ float W[MLP_P];
   for (int i = threadIdx.x; i < MLP_P; i += blockDim.x) W[i] = use_bf16 ? bf2f(wbf[i]) : master[i];
   __syncthreads();
@@ -212,29 +221,42 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ mas
 }
 
 // --------------------------------------------------------------------------
-int mlp_step_launch(const float *master, const unsigned short *wbf, bool bf16, const float *x,
-                    const float *t, int n, int off, int count, float inv_norm, float *gpart,
-                    float *lpart, hipStream_t s) {
+int mlp_step_launch(int n_out, const float *master, const unsigned short *wbf, bool bf16,
+                    const float *x, const float *t, int n, int off, int count, float inv_norm,
+                    float *gpart, float *lpart, hipStream_t s) {
   const int nblk = ceil_div(count, MLP_S);
-  hipLaunchKernelGGL(k_mlp_step, dim3(nblk), dim3(256), 0, s, master, wbf, bf16 ? 1 : 0, x, t, n,
-                     off, count, inv_norm, gpart, lpart);
+  if (n_out == 3)
+    hipLaunchKernelGGL(k_mlp_step<3>, dim3(nblk), dim3(256), 0, s, master, wbf, bf16 ? 1 : 0, x,
+                       t, n, off, count, inv_norm, gpart, lpart);
+  else
+    hipLaunchKernelGGL(k_mlp_step<2>, dim3(nblk), dim3(256), 0, s, master, wbf, bf16 ? 1 : 0, x,
+                       t, n, off, count, inv_norm, gpart, lpart);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
 
-int mlp_adam_launch(float *master, unsigned short *wbf, float *m1, float *m2, const float *gpart,
-                    const float *lpart, int nblk, int step, float lr, float *grad_out,
-                    float *loss_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_adam, dim3(ceil_div(MLP_P, 256)), dim3(256), 0, s, master, wbf, m1, m2,
-                     gpart, lpart, nblk, step, lr, grad_out, loss_out);
+int mlp_adam_launch(int n_out, float *master, unsigned short *wbf, float *m1, float *m2,
+                    const float *gpart, const float *lpart, int nblk, int step, float lr,
+                    float *grad_out, float *loss_out, hipStream_t s) {
+  const unsigned g = (unsigned)ceil_div(mlp_num_params(n_out), 256);
+  if (n_out == 3)
+    hipLaunchKernelGGL(k_mlp_adam<3>, dim3(g), dim3(256), 0, s, master, wbf, m1, m2, gpart, lpart,
+                       nblk, step, lr, grad_out, loss_out);
+  else
+    hipLaunchKernelGGL(k_mlp_adam<2>, dim3(g), dim3(256), 0, s, master, wbf, m1, m2, gpart, lpart,
+                       nblk, step, lr, grad_out, loss_out);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
 
-int mlp_infer_launch(const float *master, const unsigned short *wbf, bool bf16, const float *x,
-                     float *y, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_infer, dim3(ceil_div(n, 256)), dim3(256), 0, s, master, wbf,
-                     bf16 ? 1 : 0, x, y, n);
+int mlp_infer_launch(int n_out, const float *master, const unsigned short *wbf, bool bf16,
+                     const float *x, float *y, int n, hipStream_t s) {
+  if (n_out == 3)
+    hipLaunchKernelGGL(k_mlp_infer<3>, dim3(ceil_div(n, 256)), dim3(256), 0, s, master, wbf,
+                       bf16 ? 1 : 0, x, y, n);
+  else
+    hipLaunchKernelGGL(k_mlp_infer<2>, dim3(ceil_div(n, 256)), dim3(256), 0, s, master, wbf,
+                       bf16 ? 1 : 0, x, y, n);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
@@ -244,8 +266,9 @@ __global__ void k_f2bf(const float *__restrict__ a, unsigned short *__restrict__
   if (i < n) b[i] = f2bf_rne(a[i]);
 }
 
-int mlp_refresh_bf16(const float *master, unsigned short *wbf, hipStream_t s) {
-  hipLaunchKernelGGL(k_f2bf, dim3(ceil_div(MLP_P, 256)), dim3(256), 0, s, master, wbf, MLP_P);
+int mlp_refresh_bf16(int n_out, const float *master, unsigned short *wbf, hipStream_t s) {
+  const int P = mlp_num_params(n_out);
+  hipLaunchKernelGGL(k_f2bf, dim3(ceil_div(P, 256)), dim3(256), 0, s, master, wbf, P);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }

@@ -15,16 +15,24 @@ namespace th {
 void plain_fit_batch(const double *x, int n, double *e_out, double *q_out);
 void fit_from_errors(double eta, const double e[2], double qw[3]);
 double effective_eta(double eta_c, double shift);
-int mlp_num_params();
-int mlp_step_launch(const float *master, const unsigned short *wbf, bool bf16, const float *x,
-                    const float *t, int n, int off, int count, float inv_norm, float *gpart,
-                    float *lpart, hipStream_t s);
-int mlp_adam_launch(float *master, unsigned short *wbf, float *m1, float *m2, const float *gpart,
-                    const float *lpart, int nblk, int step, float lr, float *grad_out,
-                    float *loss_out, hipStream_t s);
-int mlp_infer_launch(const float *master, const unsigned short *wbf, bool bf16, const float *x,
-                     float *y, int n, hipStream_t s);
-int mlp_refresh_bf16(const float *master, unsigned short *wbf, hipStream_t s);
+int mlp_num_params(int n_out);
+int mlp_step_launch(int n_out, const float *master, const unsigned short *wbf, bool bf16,
+                    const float *x, const float *t, int n, int off, int count, float inv_norm,
+                    float *gpart, float *lpart, hipStream_t s);
+int mlp_adam_launch(int n_out, float *master, unsigned short *wbf, float *m1, float *m2,
+                    const float *gpart, const float *lpart, int nblk, int step, float lr,
+                    float *grad_out, float *loss_out, hipStream_t s);
+int mlp_infer_launch(int n_out, const float *master, const unsigned short *wbf, bool bf16,
+                     const float *x, float *y, int n, hipStream_t s);
+int mlp_refresh_bf16(int n_out, const float *master, unsigned short *wbf, hipStream_t s);
+
+// fine dispersion errors of a stencil family: 2 per sample (9-point) or 3 (27-point)
+static void family_errors(int n_out, const double *x, int n, double *e_out) {
+  if (n_out == 3)
+    plain_fit27_batch(x, n, e_out, nullptr);
+  else
+    plain_fit_batch(x, n, e_out, nullptr);
+}
 }  // namespace th
 
 using namespace th;
@@ -38,7 +46,8 @@ struct th_mlp {
   float *d_master = nullptr, *d_m1 = nullptr, *d_m2 = nullptr;
   unsigned short *d_bf = nullptr;
   double in_mean[3] = {0, 0, 0}, in_std[3] = {1, 1, 1};
-  double out_mean[2] = {0, 0}, out_std[2] = {1, 1};
+  double out_mean[3] = {0, 0, 0}, out_std[3] = {1, 1, 1};
+  int n_out = 2;               // 2: 9-point family (2-D), 3: 27-point family (3-D)
   bool has_weights = false;
 };
 
@@ -101,19 +110,32 @@ th_status th_plain_fit3d(const double *samples, int n, double *e_out, double *q_
 
 th_status th_mlp_num_params(int *n_params) {
   if (!n_params) return TH_EINVAL;
-  *n_params = mlp_num_params();
+  *n_params = mlp_num_params(2);
+  return TH_OK;
+}
+
+th_status th_mlp_info(const th_mlp *m, int *dim, int *n_params) {
+  if (!m || !dim || !n_params) return TH_EINVAL;
+  *dim = m->n_out == 3 ? 3 : 2;
+  *n_params = mlp_num_params(m->n_out);
   return TH_OK;
 }
 
 th_status th_mlp_create(th_mlp **out, int hip_device, void *hip_stream) {
+  return th_mlp_create_family(out, hip_device, hip_stream, 2);
+}
+
+th_status th_mlp_create_family(th_mlp **out, int hip_device, void *hip_stream, int dim) {
   if (!out) return TH_EINVAL;
   *out = nullptr;
+  if (dim != 2 && dim != 3) return TH_EINVAL;
   if (hipSetDevice(hip_device) != hipSuccess) return TH_EHIP;
   th_mlp *m = new (std::nothrow) th_mlp();
   if (!m) return TH_ENOMEM;
   m->device = hip_device;
   m->stream = (hipStream_t)hip_stream;
-  const int P = mlp_num_params();
+  m->n_out = dim == 3 ? 3 : 2;
+  const int P = mlp_num_params(m->n_out);
   if (hipMalloc(&m->d_master, P * sizeof(float)) != hipSuccess ||
       hipMalloc(&m->d_m1, P * sizeof(float)) != hipSuccess ||
       hipMalloc(&m->d_m2, P * sizeof(float)) != hipSuccess ||
@@ -139,7 +161,7 @@ const char *th_mlp_last_error(const th_mlp *m) { return m ? m->err.c_str() : "nu
 
 th_status th_mlp_set_weights(th_mlp *m, const float *theta, int n_params) {
   if (!m) return TH_EINVAL;
-  const int P = mlp_num_params();
+  const int P = mlp_num_params(m->n_out);
   if (!theta || n_params != P) return mfail(m, TH_EINVAL, "weights must hold n_params floats");
   for (int i = 0; i < P; ++i)
     if (!std::isfinite(theta[i])) return mfail(m, TH_EINVAL, "non-finite weight");
@@ -148,7 +170,7 @@ th_status th_mlp_set_weights(th_mlp *m, const float *theta, int n_params) {
       hipMemsetAsync(m->d_m1, 0, P * sizeof(float), m->stream) ||
       hipMemsetAsync(m->d_m2, 0, P * sizeof(float), m->stream))
     return mfail(m, TH_EHIP, "upload failed");
-  int rc = mlp_refresh_bf16(m->d_master, m->d_bf, m->stream);
+  int rc = mlp_refresh_bf16(m->n_out, m->d_master, m->d_bf, m->stream);
   if (rc) return mfail(m, (th_status)rc, get_error());
   if (hipStreamSynchronize(m->stream) != hipSuccess) return mfail(m, TH_EHIP, "synchronisation failed");
   m->has_weights = true;
@@ -156,7 +178,7 @@ th_status th_mlp_set_weights(th_mlp *m, const float *theta, int n_params) {
 }
 
 th_status th_mlp_get_weights(const th_mlp *m, float *theta, int n_params) {
-  if (!m || !theta || n_params != mlp_num_params()) return TH_EINVAL;
+  if (!m || !theta || n_params != mlp_num_params(m->n_out)) return TH_EINVAL;
   if (hipSetDevice(m->device) != hipSuccess) return TH_EHIP;
   if (hipMemcpyAsync(theta, m->d_master, n_params * sizeof(float), hipMemcpyDeviceToHost,
                      m->stream) != hipSuccess ||
@@ -165,27 +187,27 @@ th_status th_mlp_get_weights(const th_mlp *m, float *theta, int n_params) {
   return TH_OK;
 }
 
-th_status th_mlp_set_scaling(th_mlp *m, const double in_mean[3], const double in_std[3],
-                             const double out_mean[2], const double out_std[2]) {
+th_status th_mlp_set_scaling(th_mlp *m, const double *in_mean, const double *in_std,
+                             const double *out_mean, const double *out_std) {
   if (!m || !in_mean || !in_std || !out_mean || !out_std) return TH_EINVAL;
   for (int i = 0; i < 3; ++i)
     if (!(in_std[i] > 0.0)) return mfail(m, TH_EINVAL, "scales must be positive");
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < m->n_out; ++i)
     if (!(out_std[i] > 0.0)) return mfail(m, TH_EINVAL, "scales must be positive");
   std::memcpy(m->in_mean, in_mean, sizeof(m->in_mean));
   std::memcpy(m->in_std, in_std, sizeof(m->in_std));
-  std::memcpy(m->out_mean, out_mean, sizeof(m->out_mean));
-  std::memcpy(m->out_std, out_std, sizeof(m->out_std));
+  std::memcpy(m->out_mean, out_mean, m->n_out * sizeof(double));
+  std::memcpy(m->out_std, out_std, m->n_out * sizeof(double));
   return TH_OK;
 }
 
-th_status th_mlp_get_scaling(const th_mlp *m, double in_mean[3], double in_std[3],
-                             double out_mean[2], double out_std[2]) {
+th_status th_mlp_get_scaling(const th_mlp *m, double *in_mean, double *in_std, double *out_mean,
+                             double *out_std) {
   if (!m || !in_mean || !in_std || !out_mean || !out_std) return TH_EINVAL;
   std::memcpy(in_mean, m->in_mean, sizeof(m->in_mean));
   std::memcpy(in_std, m->in_std, sizeof(m->in_std));
-  std::memcpy(out_mean, m->out_mean, sizeof(m->out_mean));
-  std::memcpy(out_std, m->out_std, sizeof(m->out_std));
+  std::memcpy(out_mean, m->out_mean, m->n_out * sizeof(double));
+  std::memcpy(out_std, m->out_std, m->n_out * sizeof(double));
   return TH_OK;
 }
 
@@ -195,27 +217,30 @@ th_status th_mlp_loss_grad(th_mlp *m, const float *x_std, const float *y_std, in
   if (!x_std || !y_std || n < 1 || !loss || !grad) return mfail(m, TH_EINVAL, "bad arguments");
   if (!m->has_weights) return mfail(m, TH_ESTATE, "weights not set");
   if (hipSetDevice(m->device) != hipSuccess) return mfail(m, TH_EHIP, "hipSetDevice failed");
-  const int P = mlp_num_params();
+  const int P = mlp_num_params(m->n_out);
   const int nblk = (n + 63) / 64;
+  const int no = m->n_out;
   DevBuf b;
-  float *dx = b.alloc<float>((size_t)n * 3), *dy = b.alloc<float>((size_t)n * 2);
+  float *dx = b.alloc<float>((size_t)n * 3), *dy = b.alloc<float>((size_t)n * no);
   float *gp = b.alloc<float>((size_t)nblk * P), *lp = b.alloc<float>(nblk);
   float *gd = b.alloc<float>(P), *ld = b.alloc<float>(1);
   if (!dx || !dy || !gp || !lp || !gd || !ld) return mfail(m, TH_ENOMEM, "device allocation failed");
   hipStream_t s = m->stream;
   if (hipMemcpyAsync(dx, x_std, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, s) ||
-      hipMemcpyAsync(dy, y_std, (size_t)n * 2 * sizeof(float), hipMemcpyHostToDevice, s))
+      hipMemcpyAsync(dy, y_std, (size_t)n * no * sizeof(float), hipMemcpyHostToDevice, s))
     return mfail(m, TH_EHIP, "upload failed");
-  int rc = mlp_step_launch(m->d_master, m->d_bf, bf16 != 0, dx, dy, n, 0, n, 1.0f / (2.0f * n), gp,
-                           lp, s);
-  if (!rc) rc = mlp_adam_launch(m->d_master, m->d_bf, m->d_m1, m->d_m2, gp, lp, nblk, 0, 0.0f, gd, ld, s);
+  int rc = mlp_step_launch(no, m->d_master, m->d_bf, bf16 != 0, dx, dy, n, 0, n,
+                           1.0f / ((float)no * n), gp, lp, s);
+  if (!rc)
+    rc = mlp_adam_launch(no, m->d_master, m->d_bf, m->d_m1, m->d_m2, gp, lp, nblk, 0, 0.0f, gd, ld,
+                         s);
   if (rc) return mfail(m, (th_status)rc, get_error());
   float lh = 0.0f;
   if (hipMemcpyAsync(grad, gd, P * sizeof(float), hipMemcpyDeviceToHost, s) ||
       hipMemcpyAsync(&lh, ld, sizeof(float), hipMemcpyDeviceToHost, s) ||
       hipStreamSynchronize(s))
     return mfail(m, TH_EHIP, "download failed");
-  *loss = lh / (2.0 * n);
+  *loss = lh / ((double)no * n);
   return TH_OK;
 }
 
@@ -229,9 +254,10 @@ th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_tra
   if (!m->has_weights) return mfail(m, TH_ESTATE, "initial weights not set");
   if (hipSetDevice(m->device) != hipSuccess) return mfail(m, TH_EHIP, "hipSetDevice failed");
   auto t0 = std::chrono::steady_clock::now();
-  std::vector<double> e((size_t)n * 2);
-  plain_fit_batch(samples, n, e.data(), nullptr);
-  std::vector<double> y((size_t)n * 2);
+  const int no = m->n_out;
+  std::vector<double> e((size_t)n * no);
+  family_errors(no, samples, n, e.data());
+  std::vector<double> y((size_t)n * no);
   for (size_t i = 0; i < y.size(); ++i) y[i] = std::log(std::max(-e[i], 0.0) + kEFloor);
   auto t1 = std::chrono::steady_clock::now();
   // standardisation from the samples
@@ -244,26 +270,27 @@ th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_tra
     m->in_mean[c] = mu;
     m->in_std[c] = sd > 1e-12 ? sd : 1.0;
   }
-  for (int c = 0; c < 2; ++c) {
+  for (int c = 0; c < no; ++c) {
     double s = 0, s2 = 0;
-    for (int i = 0; i < n; ++i) s += y[2 * i + c];
+    for (int i = 0; i < n; ++i) s += y[(size_t)no * i + c];
     const double mu = s / n;
-    for (int i = 0; i < n; ++i) s2 += (y[2 * i + c] - mu) * (y[2 * i + c] - mu);
+    for (int i = 0; i < n; ++i) s2 += (y[(size_t)no * i + c] - mu) * (y[(size_t)no * i + c] - mu);
     const double sd = std::sqrt(s2 / n);
     m->out_mean[c] = mu;
     m->out_std[c] = sd > 1e-12 ? sd : 1.0;
   }
-  std::vector<float> xs((size_t)n * 3), ys((size_t)n * 2);
+  std::vector<float> xs((size_t)n * 3), ys((size_t)n * no);
   for (int i = 0; i < n; ++i) {
     for (int c = 0; c < 3; ++c)
       xs[3 * i + c] = (float)((samples[3 * i + c] - m->in_mean[c]) / m->in_std[c]);
-    for (int c = 0; c < 2; ++c) ys[2 * i + c] = (float)((y[2 * i + c] - m->out_mean[c]) / m->out_std[c]);
+    for (int c = 0; c < no; ++c)
+      ys[(size_t)no * i + c] = (float)((y[(size_t)no * i + c] - m->out_mean[c]) / m->out_std[c]);
   }
-  const int P = mlp_num_params();
+  const int P = mlp_num_params(m->n_out);
   const int B = std::min(o->batch, (n + 63) / 64 * 64);
   const int nblk = B / 64;
   DevBuf b;
-  float *dx = b.alloc<float>((size_t)n * 3), *dy = b.alloc<float>((size_t)n * 2);
+  float *dx = b.alloc<float>((size_t)n * 3), *dy = b.alloc<float>((size_t)n * no);
   float *gp = b.alloc<float>((size_t)nblk * P), *lp = b.alloc<float>(nblk), *ld = b.alloc<float>(1);
   if (!dx || !dy || !gp || !lp || !ld) return mfail(m, TH_ENOMEM, "device allocation failed");
   hipStream_t s = m->stream;
@@ -274,14 +301,14 @@ th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_tra
   const int steps_per_epoch = std::max(1, n / B);
   int step = 0;
   float lfirst = 0.0f, llast = 0.0f;
-  const float inv_norm = 1.0f / (2.0f * B);
+  const float inv_norm = 1.0f / ((float)no * B);
   for (int ep = 0; ep < o->epochs; ++ep)
     for (int bi = 0; bi < steps_per_epoch; ++bi) {
       const int off = (int)(((long long)bi * B + (long long)ep * 7919) % n);
-      int rc = mlp_step_launch(m->d_master, m->d_bf, o->bf16 != 0, dx, dy, n, off, B, inv_norm, gp,
-                               lp, s);
+      int rc = mlp_step_launch(no, m->d_master, m->d_bf, o->bf16 != 0, dx, dy, n, off, B, inv_norm,
+                               gp, lp, s);
       if (!rc)
-        rc = mlp_adam_launch(m->d_master, m->d_bf, m->d_m1, m->d_m2, gp, lp, nblk, ++step,
+        rc = mlp_adam_launch(no, m->d_master, m->d_bf, m->d_m1, m->d_m2, gp, lp, nblk, ++step,
                              (float)o->lr, nullptr, ld, s);
       if (rc) return mfail(m, (th_status)rc, get_error());
       if (step == 1) {
@@ -294,8 +321,8 @@ th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_tra
     return mfail(m, TH_EHIP, "download failed");
   auto t2 = std::chrono::steady_clock::now();
   if (stats) {
-    stats->loss_first = lfirst / (2.0 * B);
-    stats->loss_last = llast / (2.0 * B);
+    stats->loss_first = lfirst / ((double)no * B);
+    stats->loss_last = llast / ((double)no * B);
     stats->steps = step;
     stats->t_targets_s = std::chrono::duration<double>(t1 - t0).count();
     stats->t_train_s = std::chrono::duration<double>(t2 - t1).count();
@@ -307,44 +334,62 @@ th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_tra
 
 namespace th {
 
-// Device inference: e_out (n x 2) from raw samples.
+// Device inference: e_out (n x n_out) from raw samples.
 int mlp_predict_impl(const th_mlp *m, const double *samples, int n, bool bf16, double *e_out) {
-  std::vector<float> xs((size_t)n * 3), ys((size_t)n * 2);
+  const int no = m->n_out;
+  std::vector<float> xs((size_t)n * 3), ys((size_t)n * no);
   for (int i = 0; i < n; ++i)
     for (int c = 0; c < 3; ++c)
       xs[3 * i + c] = (float)((samples[3 * i + c] - m->in_mean[c]) / m->in_std[c]);
   DevBuf b;
-  float *dx = b.alloc<float>((size_t)n * 3), *dy = b.alloc<float>((size_t)n * 2);
+  float *dx = b.alloc<float>((size_t)n * 3), *dy = b.alloc<float>((size_t)n * no);
   if (!dx || !dy) {
     set_error("device allocation failed");
     return TH_ENOMEM;
   }
   hipStream_t s = m->stream;
   TH_HIP_CHECK_RET(hipMemcpyAsync(dx, xs.data(), xs.size() * sizeof(float), hipMemcpyHostToDevice, s));
-  int rc = mlp_infer_launch(m->d_master, m->d_bf, bf16, dx, dy, n, s);
+  int rc = mlp_infer_launch(no, m->d_master, m->d_bf, bf16, dx, dy, n, s);
   if (rc) return rc;
   TH_HIP_CHECK_RET(hipMemcpyAsync(ys.data(), dy, ys.size() * sizeof(float), hipMemcpyDeviceToHost, s));
   TH_HIP_CHECK_RET(hipStreamSynchronize(s));
   for (int i = 0; i < n; ++i)
-    for (int c = 0; c < 2; ++c) {
-      const double yr = ys[2 * i + c] * m->out_std[c] + m->out_mean[c];
-      e_out[2 * i + c] = -(std::exp(yr) - kEFloor);
+    for (int c = 0; c < no; ++c) {
+      const double yr = ys[(size_t)no * i + c] * m->out_std[c] + m->out_mean[c];
+      e_out[(size_t)no * i + c] = -(std::exp(yr) - kEFloor);
     }
   return 0;
 }
 
-// Per-cell weights for the coarse schemes PLAINFIT / MLP.  samples: n x 3
-// (eta_c, p, shift).  For MLP, the network's e_m are compared with the fine
-// dispersion errors interpolated from a table of exact values (256 nodes in
-// eta, cubic Lagrange); cells beyond tau get the exact plain fit.
-int coarse_weights(int scheme, const th_mlp *m, double tau, const double *samples, int n,
+// Per-cell weights for the coarse schemes PLAINFIT / MLP of a dim-dimensional
+// problem.  samples: n x 3 (eta_c, p, shift); q_out: n x 3 (2-D) or n x 4
+// (3-D).  For MLP, the network's e_m are compared with the fine dispersion
+// errors interpolated from a table of exact values (256 nodes in eta, cubic
+// Lagrange in log space); cells beyond tau get the exact plain fit.
+int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const double *samples, int n,
                    double *q_out, int *n_fallback) {
   *n_fallback = 0;
+  const int no = dim == 3 ? 3 : 2, nq = dim == 3 ? 4 : 3;
+  auto weights_from = [&](int i, double eta, const double *e) {
+    if (dim == 3) {
+      const double z[3] = {eta * (1.0 + e[0]), eta * (1.0 + e[1]), eta * (1.0 + e[2])};
+      fit27_from_radii(eta, z, q_out + (size_t)nq * i);
+    } else {
+      fit_from_errors(eta, e, q_out + (size_t)nq * i);
+    }
+  };
   if (scheme == TH_COARSE_PLAINFIT) {
-    plain_fit_batch(samples, n, nullptr, q_out);
+    if (dim == 3)
+      plain_fit27_batch(samples, n, nullptr, q_out);
+    else
+      plain_fit_batch(samples, n, nullptr, q_out);
     return 0;
   }
-  std::vector<double> e((size_t)n * 2);
+  if (!m || m->n_out != no) {
+    set_error("the surrogate network's stencil family does not match the problem dimension");
+    return TH_EINVAL;
+  }
+  std::vector<double> e((size_t)n * no);
   int rc = mlp_predict_impl(m, samples, n, true, e.data());
   if (rc) return rc;
   // table of exact fine errors over the range of effective eta (per order)
@@ -363,43 +408,41 @@ int coarse_weights(int scheme, const th_mlp *m, double tau, const double *sample
   const int NT = 256;
   const double a = lo * 0.98, bnd = std::min(hi * 1.02, 0.999 * 2.0 * M_PI / p);
   const double dx = (bnd - a) / (NT - 1);
-  std::vector<double> tab_in((size_t)NT * 3), tab_e((size_t)NT * 2);
+  std::vector<double> tab_in((size_t)NT * 3), tab_e((size_t)NT * no);
   for (int i = 0; i < NT; ++i) {
     tab_in[3 * i] = a + dx * i;
     tab_in[3 * i + 1] = p;
     tab_in[3 * i + 2] = 0.0;
   }
-  plain_fit_batch(tab_in.data(), NT, tab_e.data(), nullptr);
+  family_errors(no, tab_in.data(), NT, tab_e.data());
   std::vector<int> bad;
   for (int i = 0; i < n; ++i) {
     const double xq = (eta_eff[i] - a) / dx;
     int j0 = std::max(0, std::min(NT - 4, (int)std::floor(xq) - 1));
     double mismatch = 0.0;
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < no; ++c) {
       double v = 0.0;  // cubic Lagrange in log space
       for (int j = j0; j < j0 + 4; ++j) {
         double w = 1.0;
         for (int l = j0; l < j0 + 4; ++l)
           if (l != j) w *= (xq - l) / (double)(j - l);
-        v += w * std::log(std::max(-tab_e[2 * j + c], 0.0) + kEFloor);
+        v += w * std::log(std::max(-tab_e[(size_t)no * j + c], 0.0) + kEFloor);
       }
       const double e_tab = -(std::exp(v) - kEFloor);
-      mismatch = std::max(mismatch, std::fabs(e[2 * i + c] - e_tab));
+      mismatch = std::max(mismatch, std::fabs(e[(size_t)no * i + c] - e_tab));
     }
     if (!(mismatch <= tau)) bad.push_back(i);
   }
   // exact plain fit for the flagged cells
   if (!bad.empty()) {
-    std::vector<double> sb(bad.size() * 3), eb(bad.size() * 2);
+    std::vector<double> sb(bad.size() * 3), eb(bad.size() * no);
     for (size_t k = 0; k < bad.size(); ++k)
       for (int c = 0; c < 3; ++c) sb[3 * k + c] = samples[3 * bad[k] + c];
-    plain_fit_batch(sb.data(), (int)bad.size(), eb.data(), nullptr);
-    for (size_t k = 0; k < bad.size(); ++k) {
-      e[2 * bad[k]] = eb[2 * k];
-      e[2 * bad[k] + 1] = eb[2 * k + 1];
-    }
+    family_errors(no, sb.data(), (int)bad.size(), eb.data());
+    for (size_t k = 0; k < bad.size(); ++k)
+      for (int c = 0; c < no; ++c) e[(size_t)no * bad[k] + c] = eb[(size_t)no * k + c];
   }
-  for (int i = 0; i < n; ++i) fit_from_errors(eta_eff[i], &e[2 * i], q_out + 3 * i);
+  for (int i = 0; i < n; ++i) weights_from(i, eta_eff[i], &e[(size_t)no * i]);
   *n_fallback = (int)bad.size();
   return 0;
 }

@@ -46,8 +46,11 @@ def test_coarse_schemes_rejected_where_unsupported():
     from paper_2509_17494_amd import CoarseStencilMLP, _lib as L
     k3 = np.full((4, 4, 4), 5.0)
     s = solver(k3, order=2, l_dd=2, coarse=None)
-    net = CoarseStencilMLP()
-    assert status_of(lambda: s.setup_coarse("mlp", (net, 1e-3))) == L.TH_EUNSUPPORTED
+    net = CoarseStencilMLP()  # the 9-point (2-D) family on a 3-D problem
+    assert status_of(lambda: s.setup_coarse("mlp", (net, 1e-3))) == L.TH_EINVAL
+    net3 = CoarseStencilMLP(dim=3)
+    s2d = solver(np.full((6, 6), 8.0), order=2, l_dd=3, coarse=None)
+    assert status_of(lambda: s2d.setup_coarse("mlp", (net3, 1e-3))) == L.TH_EINVAL
     k = np.full((8, 8), 8.0)
     s2 = solver(k, order=2, l_dd=4, coarse=None)
     # the plain fit needs fine k h < pi in every cell
