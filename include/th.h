@@ -50,7 +50,13 @@ typedef enum {
   TH_EUNSUPPORTED = -7   /* valid request this build does not implement */
 } th_status;
 
-typedef enum { TH_BC_ROBIN = 0, TH_BC_NEUMANN = 1 } th_bc;
+/* Boundary conditions per side (eq. Helmholtz_eq): absorbing du/dn - i k u = 0,
+ * Neumann du/dn = 0, homogeneous Dirichlet u = 0.  The nodes of a closed
+ * Dirichlet side are eliminated on the fine grid, on the coarse vertex grid,
+ * in every subdomain matrix and from I_P; vectors keep full length and the
+ * operators carry unit rows and columns there (th_residual returns f - u on
+ * those nodes).  With f = 0 on them, every iterate of th_solve is 0 there. */
+typedef enum { TH_BC_ROBIN = 0, TH_BC_NEUMANN = 1, TH_BC_DIRICHLET = 2 } th_bc;
 typedef enum { TH_C128 = 0, TH_C64 = 1 } th_dtype;
 
 /* Storage / arithmetic of the dense subdomain operators B_i.
@@ -62,7 +68,9 @@ typedef enum {
   TH_COARSE_QSFEM = 0,    /* per-cell QSFEM weights q(h_c k(c)), Sec. 3.3; in 3-D the
                              27-point stencil exact at k (see th_plain_fit3d) */
   TH_COARSE_WEIGHTS = 1,  /* caller-supplied per-coarse-cell (q0, q_edge, q_diag), or
-                             (q0, q_face, q_edge, q_corner) in 3-D */
+                             (q0, q_face, q_edge, q_corner) in 3-D; weights are on the
+                             2-D element scale (symbol -eta^2 at 0), a 3-D cell
+                             contributes h_c q */
   TH_COARSE_PLAINFIT = 2, /* per-cell plain dispersion-matching fit (th_plain_fit, or
                              th_plain_fit3d in 3-D) */
   TH_COARSE_MLP = 3       /* per-cell surrogate network with fallback to the plain fit

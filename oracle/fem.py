@@ -151,10 +151,11 @@ def global_box(N: int, dim: int):
 
 
 def helmholtz_matrix(p: int, k: np.ndarray, eps: np.ndarray | None = None,
-                     robin=None, alpha: float = 0.0) -> sp.csr_matrix:
+                     robin=None, alpha: float = 0.0, dirichlet=None) -> sp.csr_matrix:
     """Global matrix A (alpha = 0) or the complex-shifted A_s (alpha = alpha_s,
     Sec. 4.1: volume coefficient k^2 + i alpha k^2 + i eps; the boundary term
-    keeps -i k)."""
+    keeps -i k).  `dirichlet`: 2*dim booleans, sides whose nodes are
+    eliminated (unit rows and columns)."""
     dim = k.ndim
     N = k.shape[0]
     if eps is None:
@@ -162,7 +163,10 @@ def helmholtz_matrix(p: int, k: np.ndarray, eps: np.ndarray | None = None,
     if robin is None:
         robin = (True,) * (2 * dim)
     kappa = k * k * (1.0 + 1j * alpha) + 1j * eps
-    return assemble_box(p, N, dim, global_box(N, dim), kappa, k, robin)
+    A = assemble_box(p, N, dim, global_box(N, dim), kappa, k, robin)
+    if dirichlet is not None and any(dirichlet):
+        A = eliminate(A, side_mask(N * p + 1, dim, dirichlet))
+    return A
 
 
 def node_coords_1d(N: int, p: int) -> np.ndarray:
@@ -172,3 +176,28 @@ def node_coords_1d(N: int, p: int) -> np.ndarray:
     for c in range(N):
         out[c * p: c * p + p + 1] = (c + x) * h
     return out
+
+
+# Homogeneous Dirichlet sides (eq. Helmholtz_eq, the part Gamma_0 of the
+# boundary).  Reading: the nodes of a closed Dirichlet side are not unknowns;
+# vectors keep full length and the matrix takes unit rows and columns there,
+# so with a zero right-hand side on those nodes the solution is the one of the
+# system with the nodes removed.
+def side_mask(n1: int, dim: int, sides) -> np.ndarray:
+    """Boolean mask over the n1^dim grid (x fastest): nodes lying on a side
+    flagged in `sides` (2*dim booleans, x-, x+, y-, y+, z-, z+)."""
+    grid = np.indices((n1,) * dim)[::-1]  # grid[axis], axis 0 = x
+    m = np.zeros((n1,) * dim, dtype=bool)
+    for a in range(dim):
+        if sides[2 * a]:
+            m |= grid[a] == 0
+        if sides[2 * a + 1]:
+            m |= grid[a] == n1 - 1
+    return m.ravel()
+
+
+def eliminate(A: sp.spmatrix, mask: np.ndarray) -> sp.csr_matrix:
+    """D A D + (I - D) with D the diagonal of the free (unmasked) nodes:
+    masked rows and columns are replaced by those of the identity."""
+    free = sp.diags((~mask).astype(float))
+    return (free @ A @ free + sp.diags(mask.astype(float))).tocsr()

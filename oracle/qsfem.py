@@ -23,6 +23,8 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
+from .fem import eliminate, side_mask
+
 
 def cs(eta):
     eta = np.asarray(eta, dtype=np.float64)
@@ -77,7 +79,7 @@ def cell_q_matrix(q0, qe, qd, dim: int = 2):
 
 
 def coarse_matrix(kc: np.ndarray, epsc: np.ndarray | None = None, robin=None,
-                  q: np.ndarray | None = None) -> sp.csr_matrix:
+                  q: np.ndarray | None = None, dirichlet=None) -> sp.csr_matrix:
     """Quasi-FE QSFEM matrix on the coarse vertex grid (2-D).
 
     kc: per coarse cell k, shape (Nc, Nc) indexed [y][x]; coarse spacing
@@ -86,6 +88,8 @@ def coarse_matrix(kc: np.ndarray, epsc: np.ndarray | None = None, robin=None,
         eta = hc k(c).
     (A_q)_{ab} = sum_{c in C(a,b)} q_{b-a}(hc k(c)) - int i eps phi_a phi_b
                  - int_{Gamma_abs} i k phi_a phi_b ds.
+    Vertices on the Dirichlet sides (4 booleans, x-, x+, y-, y+) are
+    eliminated (unit rows and columns), as on the fine level.
     """
     Nc = kc.shape[0]
     hc = 1.0 / Nc
@@ -120,6 +124,8 @@ def coarse_matrix(kc: np.ndarray, epsc: np.ndarray | None = None, robin=None,
     A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n)).tocsr()
     A.sum_duplicates()
+    if dirichlet is not None and any(dirichlet):
+        A = eliminate(A, side_mask(n1, 2, dirichlet))
     return A
 
 

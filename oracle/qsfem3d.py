@@ -29,7 +29,7 @@ import numpy as np
 import scipy.sparse as sp
 from scipy.optimize import brentq
 
-from .fem import ref_matrices
+from .fem import eliminate, ref_matrices, side_mask
 
 DIRS = np.array([[1.0, 0.2, 0.1], [1.0, 0.6, 0.3], [1.0, 0.9, 0.7]])
 DIRS = DIRS / np.linalg.norm(DIRS, axis=1)[:, None]
@@ -60,8 +60,15 @@ def q_weights(eta: float, radii=None):
     return N * P[0] / 8.0, N * P[1] / 4.0, N * P[2] / 2.0, N * P[3]
 
 
-def coarse_matrix_3d(kc: np.ndarray, epsc=None, robin=None, q=None) -> sp.csr_matrix:
-    """Quasi-FE 27-point matrix on the coarse vertex grid (kc indexed [z][y][x])."""
+def coarse_matrix_3d(kc: np.ndarray, epsc=None, robin=None, q=None,
+                     dirichlet=None) -> sp.csr_matrix:
+    """Quasi-FE 27-point matrix on the coarse vertex grid (kc indexed [z][y][x]);
+    vertices on the Dirichlet sides (6 booleans) are eliminated.
+
+    The weights q are normalised so that the stencil symbol at 0 is -eta^2,
+    the scale of a 2-D element matrix.  In 3-D the stiffness of a cell scales
+    as h_c (h^{d-2}), so a cell contributes h_c q next to the h_c^3 mass of
+    the -i eps term and the h_c^2 face mass of the absorbing term."""
     Nc = kc.shape[0]
     hc = 1.0 / Nc
     if epsc is None:
@@ -82,7 +89,7 @@ def coarse_matrix_3d(kc: np.ndarray, epsc=None, robin=None, q=None) -> sp.csr_ma
                 E = np.zeros((8, 8), dtype=complex)
                 for a, va in enumerate(verts):
                     for b, vb in enumerate(verts):
-                        E[a, b] = qq[sum(int(va[i] != vb[i]) for i in range(3))]
+                        E[a, b] = hc * qq[sum(int(va[i] != vb[i]) for i in range(3))]
                 E += -1j * epsc[cz, cy, cx] * Mq
                 sides = [(cx == 0, 2, 0), (cx == Nc - 1, 2, 1), (cy == 0, 1, 0),
                          (cy == Nc - 1, 1, 1), (cz == 0, 0, 0), (cz == Nc - 1, 0, 1)]
@@ -97,6 +104,8 @@ def coarse_matrix_3d(kc: np.ndarray, epsc=None, robin=None, q=None) -> sp.csr_ma
     A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n)).tocsr()
     A.sum_duplicates()
+    if dirichlet is not None and any(dirichlet):
+        A = eliminate(A, side_mask(n1, 3, dirichlet))
     return A
 
 

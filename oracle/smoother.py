@@ -10,7 +10,8 @@ Follows Sec. 4.1 and Sec. 4.4 of the paper:
     k^2 + i alpha_s k^2 + i eps, absorbing conditions on the internal
     boundary of Omega^(i) and the inherited conditions on the part of the
     boundary shared with Omega.  Reading: the absorbing term keeps -i k,
-    with k of the adjacent cell.
+    with k of the adjacent cell; nodes on a Dirichlet side of Omega are
+    eliminated from A_s^(i) as from A (unit rows and columns).
   * Averaged update, eq. RAS_like_update: every dof takes the mean of the
     local solutions of the closed U^(i) that contain it (L_j of them).
   * DDStep solves A_s^(i) w_i = -(R_i A_s - A_s^(i) R_i) v + R_i r, i.e.
@@ -27,7 +28,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fem import assemble_box, helmholtz_matrix
+from .fem import assemble_box, eliminate, helmholtz_matrix, side_mask
 
 
 def block_sizes(N: int, l_dd: int):
@@ -87,7 +88,8 @@ def multiplicity(subs, n_nodes: int) -> np.ndarray:
 class CSDDSmoother:
     """Alg. 2 with exact (sparse LU) subdomain solves."""
 
-    def __init__(self, p, k, eps, alpha_s, l_dd, robin=None, n_dd=1, A=None, A_s=None):
+    def __init__(self, p, k, eps, alpha_s, l_dd, robin=None, n_dd=1, A=None, A_s=None,
+                 dirichlet=None):
         self.dim = k.ndim
         self.N = k.shape[0]
         self.p = p
@@ -99,20 +101,26 @@ class CSDDSmoother:
         self.n_dd = n_dd
         kappa_s = k * k * (1.0 + 1j * alpha_s) + 1j * eps
         self.subs = decompose(N, p, dim, l_dd)
+        dmask = None
+        if dirichlet is not None and any(dirichlet):
+            dmask = side_mask(N * p + 1, dim, dirichlet)
         for s in self.subs:
             sides = []
             for a in range(dim):
                 for side in (0, 1):
                     on_boundary = (s.Om[a][0] == 0) if side == 0 else (s.Om[a][1] == N)
                     sides.append(robin[2 * a + side] if on_boundary else True)
-            s.A_loc = assemble_box(p, N, dim, s.Om, kappa_s, k, tuple(sides)).tocsc()
+            s.A_loc = assemble_box(p, N, dim, s.Om, kappa_s, k, tuple(sides))
+            if dmask is not None:
+                s.A_loc = eliminate(s.A_loc, dmask[s.om_nodes])
+            s.A_loc = s.A_loc.tocsc()
             s.lu = spla.splu(s.A_loc)
         self.n_nodes = (N * p + 1) ** dim
         self.L = multiplicity(self.subs, self.n_nodes)
         if A is None:
-            A = helmholtz_matrix(p, k, eps, robin, 0.0)
+            A = helmholtz_matrix(p, k, eps, robin, 0.0, dirichlet)
         if A_s is None:
-            A_s = helmholtz_matrix(p, k, eps, robin, alpha_s)
+            A_s = helmholtz_matrix(p, k, eps, robin, alpha_s, dirichlet)
         self.A = A
         self.A_s = A_s
 

@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .fem import gll, lagrange
+from .fem import gll, lagrange, side_mask
 
 
 def prolong_1d(N: int, p: int) -> sp.csr_matrix:
@@ -41,15 +41,24 @@ def prolong_1d(N: int, p: int) -> sp.csr_matrix:
     return sp.csr_matrix(P)
 
 
-def prolongation(N: int, p: int, dim: int = 2) -> sp.csr_matrix:
-    """Global I_P (fine nodes x coarse vertices), x fastest on both grids."""
+def prolongation(N: int, p: int, dim: int = 2, dirichlet=None) -> sp.csr_matrix:
+    """Global I_P (fine nodes x coarse vertices), x fastest on both grids.
+
+    With Dirichlet sides (2*dim booleans) the eliminated nodes leave both
+    spaces.  Reading: the rows of fine nodes and the columns of coarse
+    vertices on those sides are dropped (set to zero), so I_P maps the free
+    coarse vertices to the free fine nodes."""
     P1 = prolong_1d(N, p)
     out = P1
     for _ in range(dim - 1):
         out = sp.kron(P1, out, format="csr")
+    if dirichlet is not None and any(dirichlet):
+        free_f = sp.diags((~side_mask(N * p + 1, dim, dirichlet)).astype(float))
+        free_c = sp.diags((~side_mask(N * (p // 2) + 1, dim, dirichlet)).astype(float))
+        out = free_f @ out @ free_c
     return out.tocsr()
 
 
-def restriction(N: int, p: int, dim: int = 2) -> sp.csr_matrix:
+def restriction(N: int, p: int, dim: int = 2, dirichlet=None) -> sp.csr_matrix:
     """I_P^* = I_P^T."""
-    return prolongation(N, p, dim).T.tocsr()
+    return prolongation(N, p, dim, dirichlet).T.tocsr()

@@ -12,6 +12,10 @@ Readings (the outer Krylov method is not specified in the paper):
     (identical to GMRES for a fixed preconditioner, and to FGMRES);
   * stop when the recurrence residual |g_{j+1}| / ||f|| <= rtol.
 The coarse solve is a sparse LU of the quasi-FE QSFEM matrix.
+
+Dirichlet sides (eq. Helmholtz_eq): their nodes are eliminated on both levels
+and from I_P; a right-hand side that vanishes there gives iterates that vanish
+there, the iteration on the remaining unknowns.
 """
 from __future__ import annotations
 
@@ -27,7 +31,7 @@ from .transfer import prolongation
 
 class TwoGrid:
     def __init__(self, p, k, eps=None, alpha_s=0.5, l_dd=8, robin=None, n_dd=1,
-                 n_s=1, omega_c=1.0, coarse_q=None):
+                 n_s=1, omega_c=1.0, coarse_q=None, dirichlet=None):
         self.dim = k.ndim
         self.N = k.shape[0]
         self.p = p
@@ -35,17 +39,20 @@ class TwoGrid:
             eps = np.zeros_like(k)
         if robin is None:
             robin = (True,) * (2 * self.dim)
-        self.A = helmholtz_matrix(p, k, eps, robin, 0.0)
-        self.A_s = helmholtz_matrix(p, k, eps, robin, alpha_s)
+        if dirichlet is not None:
+            assert not any(r and d for r, d in zip(robin, dirichlet)), \
+                "a side is either absorbing or Dirichlet"
+        self.A = helmholtz_matrix(p, k, eps, robin, 0.0, dirichlet)
+        self.A_s = helmholtz_matrix(p, k, eps, robin, alpha_s, dirichlet)
         self.smoother = CSDDSmoother(p, k, eps, alpha_s, l_dd, robin, n_dd,
-                                     A=self.A, A_s=self.A_s)
-        self.I_P = prolongation(self.N, p, self.dim)
+                                     A=self.A, A_s=self.A_s, dirichlet=dirichlet)
+        self.I_P = prolongation(self.N, p, self.dim, dirichlet)
         kc = coarse_cell_values(k, p)
         epsc = coarse_cell_values(eps, p)
         if self.dim == 3:
-            self.A_c = coarse_matrix_3d(kc, epsc, robin, q=coarse_q)
+            self.A_c = coarse_matrix_3d(kc, epsc, robin, q=coarse_q, dirichlet=dirichlet)
         else:
-            self.A_c = coarse_matrix(kc, epsc, robin, q=coarse_q)
+            self.A_c = coarse_matrix(kc, epsc, robin, q=coarse_q, dirichlet=dirichlet)
         self.coarse_lu = spla.splu(self.A_c.tocsc())
         self.n_s = n_s
         self.omega_c = omega_c

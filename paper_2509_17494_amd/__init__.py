@@ -44,7 +44,7 @@ def load_library():
     return L.load()
 
 
-_BC = {"robin": L.TH_BC_ROBIN, "neumann": L.TH_BC_NEUMANN}
+_BC = {"robin": L.TH_BC_ROBIN, "neumann": L.TH_BC_NEUMANN, "dirichlet": L.TH_BC_DIRICHLET}
 _GEMM = {"f64": L.TH_GEMM_F64, "f32": L.TH_GEMM_F32, "bf16": L.TH_GEMM_BF16}
 
 

@@ -13,7 +13,7 @@ TH_OK, TH_EINVAL, TH_ESTATE, TH_ENOMEM, TH_EHIP, TH_ENOTCONV, TH_ENUMERIC, TH_EU
     0, -1, -2, -3, -4, -5, -6, -7)
 STATUS_NAMES = {0: "TH_OK", -1: "TH_EINVAL", -2: "TH_ESTATE", -3: "TH_ENOMEM", -4: "TH_EHIP",
                 -5: "TH_ENOTCONV", -6: "TH_ENUMERIC", -7: "TH_EUNSUPPORTED"}
-TH_BC_ROBIN, TH_BC_NEUMANN = 0, 1
+TH_BC_ROBIN, TH_BC_NEUMANN, TH_BC_DIRICHLET = 0, 1, 2
 TH_C128, TH_C64 = 0, 1
 TH_GEMM_F64, TH_GEMM_F32, TH_GEMM_BF16 = 0, 1, 2
 TH_COARSE_QSFEM, TH_COARSE_WEIGHTS, TH_COARSE_PLAINFIT, TH_COARSE_MLP = 0, 1, 2, 3

@@ -104,6 +104,7 @@ static FineOp make_op(const th_ctx *c, bool shifted) {
   op.robin = 0;
   for (int sd = 0; sd < 2 * c->dim; ++sd)
     if (c->desc.bc[sd] == TH_BC_ROBIN) op.robin |= 1 << sd;
+  op.dir = c->dir;
   op.kap = shifted ? c->d_kaps : c->d_kap;
   op.kr = c->d_k;
   return op;
@@ -247,8 +248,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   if (d->gemm != TH_GEMM_F64 && d->gemm != TH_GEMM_F32 && d->gemm != TH_GEMM_BF16)
     return fail(ctx, TH_EINVAL, "unknown subdomain operator storage");
   for (int sd = 0; sd < 2 * d->dim; ++sd)
-    if (d->bc[sd] != TH_BC_ROBIN && d->bc[sd] != TH_BC_NEUMANN)
-      return fail(ctx, TH_EINVAL, "boundary condition must be Robin or Neumann");
+    if (d->bc[sd] != TH_BC_ROBIN && d->bc[sd] != TH_BC_NEUMANN && d->bc[sd] != TH_BC_DIRICHLET)
+      return fail(ctx, TH_EINVAL, "boundary condition must be Robin, Neumann or Dirichlet");
   const long long ncell = (long long)d->n * d->n * (d->dim == 3 ? d->n : 1);
   for (long long i = 0; i < ncell; ++i) {
     if (!(d->k[i] > 0.0) || !std::isfinite(d->k[i]))
@@ -274,6 +275,9 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   c->nf = (long long)c->n1 * c->n1 * (c->dim == 3 ? c->n1 : 1);
   c->nc = (long long)c->nc1 * c->nc1 * (c->dim == 3 ? c->nc1 : 1);
   c->h = 1.0 / c->N;
+  c->dir = 0;
+  for (int sd = 0; sd < 2 * c->dim; ++sd)
+    if (d->bc[sd] == TH_BC_DIRICHLET) c->dir |= 1 << sd;
   make_ref1d(c->P, c->ref);
   c->h_k.assign(d->k, d->k + ncell);
   c->h_eps.assign(ncell, 0.0);
@@ -337,8 +341,11 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
         s.ldb = (s.nU + 63) / 64 * 64;
         s.robin = 0;
         const bool inner[6] = {s.o0x > 0, s.o1x < N, s.o0y > 0, s.o1y < N, s.o0z > 0, s.o1z < N};
-        for (int sd = 0; sd < 2 * c->dim; ++sd)
+        s.dir = 0;
+        for (int sd = 0; sd < 2 * c->dim; ++sd) {
           if (inner[sd] || d->bc[sd] == TH_BC_ROBIN) s.robin |= 1 << sd;
+          if (!inner[sd] && d->bc[sd] == TH_BC_DIRICHLET) s.dir |= 1 << sd;
+        }
         s.nrb = (s.nU + kSymTile - 1) / kSymTile;
         s.neb = (s.nOm - s.nU + kSymTile - 1) / kSymTile;
         s.yoff = yoff;
@@ -527,7 +534,9 @@ static th_status coarse_stencil_2d(th_ctx *c, const th_coarse_desc *d, std::vect
 
 // Per-cell weights (q0, q_face, q_edge, q_corner) and the 27-point quasi-FE
 // stencil on the 3-D coarse grid: the -i eps Q1 mass and the absorbing Q1
-// face mass are added per coarse cell as in 2-D.
+// face mass are added per coarse cell as in 2-D.  The weights are normalised
+// to the 2-D element scale (symbol -eta^2 at 0); a 3-D cell stiffness scales
+// as h_c, so a cell contributes h_c q.
 static th_status coarse_stencil_3d(th_ctx *c, const th_coarse_desc *d, std::vector<c64> &st) {
   const int Nc = c->N * c->R, nc1 = c->nc1, R = c->R, N = c->N;
   const double hc = 1.0 / Nc;
@@ -585,7 +594,7 @@ static th_status coarse_stencil_3d(th_ctx *c, const th_coarse_desc *d, std::vect
             const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
             const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
             const int diff = (ax != bx) + (ay != by) + (az != bz);
-            c64 v = {qw[4 * ci + diff], -ee * hc3 * m1[az][bz] * m1[ay][by] * m1[ax][bx]};
+            c64 v = {hc * qw[4 * ci + diff], -ee * hc3 * m1[az][bz] * m1[ay][by] * m1[ax][bx]};
             const double fx = kk * hc2 * m1[ay][by] * m1[az][bz];
             const double fy = kk * hc2 * m1[ax][bx] * m1[az][bz];
             const double fz = kk * hc2 * m1[ax][bx] * m1[ay][by];
@@ -601,6 +610,33 @@ static th_status coarse_stencil_3d(th_ctx *c, const th_coarse_desc *d, std::vect
           }
       }
   return TH_OK;
+}
+
+// Dirichlet sides: the coarse vertices on them are eliminated like the fine
+// nodes (unit rows and columns of the stencil matrix).
+static void eliminate_dirichlet(const th_ctx *c, std::vector<c64> &st) {
+  if (!c->dir) return;
+  const int n = c->nc1, dim = c->dim, S = dim == 3 ? 27 : 9, nz = dim == 3 ? n : 1;
+  auto on = [&](int x, int y, int z) {
+    return on_dir(c->dir, 0, x, n - 1) || on_dir(c->dir, 1, y, n - 1) ||
+           (dim == 3 && on_dir(c->dir, 2, z, n - 1));
+  };
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        c64 *row = &st[(size_t)S * (((long long)z * n + y) * n + x)];
+        if (on(x, y, z)) {
+          for (int t = 0; t < S; ++t) row[t] = c64{0, 0};
+          row[S / 2] = c64{1.0, 0.0};
+          continue;
+        }
+        for (int t = 0; t < S; ++t) {
+          const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = dim == 3 ? t / 9 - 1 : 0;
+          const int xx = x + dx, yy = y + dy, zz = z + dz;
+          if (xx < 0 || xx >= n || yy < 0 || yy >= n || zz < 0 || zz >= nz) continue;
+          if (on(xx, yy, zz)) row[t] = c64{0, 0};
+        }
+      }
 }
 
 th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
@@ -623,6 +659,7 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
   {
     const th_status sc = c->dim == 3 ? coarse_stencil_3d(c, d, st) : coarse_stencil_2d(c, d, st);
     if (sc) return sc;
+    eliminate_dirichlet(c, st);
   }
   int rc = setup_coarse_factors(c, st);
   if (rc) {
@@ -727,12 +764,13 @@ static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, b
   void *ucv = f32 ? c->w_rc32 : c->w_uc;
   {
     KTimer kt(c, TH_KT_RESTRICT);
-    rc = launch_restrict(c->dim, c->N, c->P, c->ref, c->w_r, rcv, nrhs, f32, s);
+    rc = launch_restrict(c->dim, c->N, c->P, c->dir, c->ref, c->w_r, rcv, nrhs, f32, s);
   }
   if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32);
   if (!rc) {
     KTimer kt(c, TH_KT_PROLONG);
-    rc = launch_prolong(c->dim, c->N, c->P, c->ref, ucv, u, c->desc.omega_c, nrhs, f32, s);
+    rc = launch_prolong(c->dim, c->N, c->P, c->dir, c->ref, ucv, u, c->desc.omega_c, nrhs, f32,
+                        s);
   }
   for (int i = 0; i < c->desc.n_s && rc == 0; ++i) rc = smooth_impl(c, u, f, nrhs, f32, false);
   return rc;
@@ -773,17 +811,16 @@ th_status th_smooth(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt) 
 th_status th_restrict(th_ctx *ctx, const void *r, void *rc, int nrhs, th_dtype dt) {
   th_status st = check_vec_call(ctx, r, rc, nrhs, dt, false);
   if (st) return st;
-  return finish(ctx, launch_restrict(ctx->dim, ctx->N, ctx->P, ctx->ref, r, rc, nrhs, is_f32(dt),
-                                     ctx->stream));
+  return finish(ctx, launch_restrict(ctx->dim, ctx->N, ctx->P, ctx->dir, ctx->ref, r, rc, nrhs,
+                                     is_f32(dt), ctx->stream));
 }
 
 th_status th_prolong(th_ctx *ctx, const void *uc, void *u, double omega_c, int nrhs, th_dtype dt) {
   th_status st = check_vec_call(ctx, uc, u, nrhs, dt, false);
   if (st) return st;
   if (!std::isfinite(omega_c)) return fail(ctx, TH_EINVAL, "omega_c must be finite");
-  return finish(ctx, launch_prolong(ctx->dim, ctx->N, ctx->P, ctx->ref, uc, u, omega_c, nrhs,
-                                    is_f32(dt),
-                                    ctx->stream));
+  return finish(ctx, launch_prolong(ctx->dim, ctx->N, ctx->P, ctx->dir, ctx->ref, uc, u, omega_c,
+                                    nrhs, is_f32(dt), ctx->stream));
 }
 
 th_status th_coarse_solve(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt) {

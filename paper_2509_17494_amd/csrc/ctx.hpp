@@ -25,6 +25,7 @@ struct Sub {
   int nU, nOm;                // nodes of closed U / Omega
   int ldb;                    // n_U padded to a multiple of 64 (rows of the stored B_i)
   int robin;                  // bit s set: absorbing term on side s of Omega (x-,x+,y-,y+,z-,z+)
+  int dir;                    // bit s set: side s of Omega lies on a Dirichlet side of the domain
   long long boff;             // element offset of B_i in the operator store
   long long yoff;             // offset of this subdomain's rows in the Y scratch
   // symmetric-tile layout (FP64/FP32 operators): 64-row blocks of U, 64-column
@@ -36,6 +37,12 @@ struct Sub {
 };
 
 constexpr int kSymTile = 64;
+
+// Node (or vertex) index i along `axis` of a grid whose last index is `last`
+// lies on a Dirichlet side (bit 2 axis: low side, bit 2 axis + 1: high side).
+__host__ __device__ __forceinline__ bool on_dir(int dir, int axis, int i, int last) {
+  return (i == 0 && ((dir >> (2 * axis)) & 1)) || (i == last && ((dir >> (2 * axis)) & 2));
+}
 
 // index of the upper tile (a, b), a <= b, among the nrb (nrb + 1) / 2 upper tiles
 __host__ __device__ __forceinline__ int sym_tile(int a, int b, int nrb) {
@@ -75,6 +82,7 @@ struct FineOp {
   long long nf;               // nodes
   double h;
   int robin;                  // bit s: Robin on global side s (x-,x+,y-,y+,z-,z+)
+  int dir;                    // bit s: Dirichlet on global side s (nodes eliminated)
   const c64 *kap;             // per cell volume coefficient (k^2 + i eps) or shifted
   const double *kr;           // per cell k for the absorbing term
 };
@@ -120,6 +128,7 @@ struct th_ctx {
   std::vector<double> h_k, h_eps;
 
   // subdomains
+  int dir = 0;                 // bit s: Dirichlet on global side s
   int M = 0;                   // blocks per direction
   std::vector<int> blk_start;  // M+1 cell starts
   std::vector<th::Sub> subs;
@@ -201,14 +210,16 @@ const std::string &get_error();
 void make_ref1d(int p, Ref1D &ref);
 void gll_points(int p, std::vector<double> &x, std::vector<double> &w);
 
-// k_operator.hip: out = f + sgn * (A u)   (f may be null)
+// k_operator.hip: out = f + sgn * (A u)   (f may be null); A carries unit rows
+// and columns on the Dirichlet nodes (op.dir): u is read as zero there and
+// out = f + sgn u.
 int launch_apply(const FineOp &op, const Ref1D &ref, const void *u, const void *f, void *out,
                  int nrhs, bool f32, double sgn, hipStream_t s);
 
 // k_transfer.hip
-int launch_restrict(int dim, int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs,
+int launch_restrict(int dim, int N, int P, int dir, const Ref1D &ref, const void *r, void *rc, int nrhs,
                     bool f32, hipStream_t s);
-int launch_prolong(int dim, int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
+int launch_prolong(int dim, int N, int P, int dir, const Ref1D &ref, const void *uc, void *u, double omega,
                    int nrhs, bool f32, hipStream_t s);
 
 // k_smoother.hip

@@ -212,7 +212,9 @@ int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStr
 
 // ---------------------------------------------------------------------------
 // Dense subdomain assembly: one thread per row (local Omega node); every
-// thread writes only its own row, summing its cells in a fixed order.
+// thread writes only its own row, summing its cells in a fixed order.  Nodes
+// on a Dirichlet side of the domain get a unit row and column (the buffer is
+// zero on entry).
 
 template <int P>
 __global__ __launch_bounds__(256) void k_assemble_sub(const Sub *__restrict__ subs, int s0,
@@ -232,6 +234,10 @@ __global__ __launch_bounds__(256) void k_assemble_sub(const Sub *__restrict__ su
   }
   const int ncx = s.o1x - s.o0x, ncy = s.o1y - s.o0y;
   const int ax = a % s.nox, ay = a / s.nox;
+  if (on_dir(s.dir, 0, ax, ncx * P) || on_dir(s.dir, 1, ay, ncy * P)) {
+    row[a] = c64{1.0, 0.0};
+    return;
+  }
   const int chx = min(ax / P, ncx - 1), chy = min(ay / P, ncy - 1);
   const int nxc = (ax % P == 0 && ax > 0 && ax < ncx * P) ? 2 : 1;
   const int nyc = (ay % P == 0 && ay > 0 && ay < ncy * P) ? 2 : 1;
@@ -249,7 +255,9 @@ __global__ __launch_bounds__(256) void k_assemble_sub(const Sub *__restrict__ su
       const bool ryh = (s.robin & 8) && lcy == ncy - 1 && ly == P;
       for (int by = 0; by < NP; ++by) {
         const double Ky = ref.K[ly * NP + by], My = ref.M[ly * NP + by];
+        if (on_dir(s.dir, 1, lcy * P + by, ncy * P)) continue;
         for (int bx = 0; bx < NP; ++bx) {
+          if (on_dir(s.dir, 0, lcx * P + bx, ncx * P)) continue;
           const double Kx = ref.K[lx * NP + bx], Mx = ref.M[lx * NP + bx];
           const double mm = h2 * My * Mx;
           c64 v = {Ky * Mx + My * Kx - kap.re * mm, -kap.im * mm};
@@ -283,6 +291,11 @@ __global__ __launch_bounds__(256) void k_assemble_sub3(const Sub *__restrict__ s
   }
   const int nc[3] = {s.o1x - s.o0x, s.o1y - s.o0y, s.o1z - s.o0z};
   const int al[3] = {a % s.nox, (a / s.nox) % s.noy, a / (s.nox * s.noy)};
+  if (on_dir(s.dir, 0, al[0], nc[0] * P) || on_dir(s.dir, 1, al[1], nc[1] * P) ||
+      on_dir(s.dir, 2, al[2], nc[2] * P)) {
+    row[a] = c64{1.0, 0.0};
+    return;
+  }
   int ch[3], nq[3];
   for (int d = 0; d < 3; ++d) {
     ch[d] = min(al[d] / P, nc[d] - 1);
@@ -306,9 +319,12 @@ __global__ __launch_bounds__(256) void k_assemble_sub3(const Sub *__restrict__ s
         const bool rzh = (s.robin & 32) && lcz == nc[2] - 1 && lz == P;
         for (int bz = 0; bz < NP; ++bz) {
           const double Kz = ref.K[lz * NP + bz], Mz = ref.M[lz * NP + bz];
+          if (on_dir(s.dir, 2, lcz * P + bz, nc[2] * P)) continue;
           for (int by = 0; by < NP; ++by) {
             const double Ky = ref.K[ly * NP + by], My = ref.M[ly * NP + by];
+            if (on_dir(s.dir, 1, lcy * P + by, nc[1] * P)) continue;
             for (int bx = 0; bx < NP; ++bx) {
+              if (on_dir(s.dir, 0, lcx * P + bx, nc[0] * P)) continue;
               const double Kx = ref.K[lx * NP + bx], Mx = ref.M[lx * NP + bx];
               const double mmm = h3 * Mz * My * Mx;
               c64 v = {h * (Kz * My * Mx + Mz * Ky * Mx + Mz * My * Kx) - kap.re * mmm,

@@ -14,6 +14,9 @@
 //           result is deterministic (no atomics).
 // A workgroup owns the nodes of a TC x TC cell tile (low edges included) and
 // reads one extra cell layer on the low sides.
+//
+// Dirichlet sides (op.dir): their nodes are eliminated with unit rows and
+// columns, so u is read as zero there and the row of such a node is u itself.
 #include "ctx.hpp"
 
 namespace th {
@@ -61,6 +64,12 @@ __global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<
     cx<T> uv[NP];
 #pragma unroll
     for (int b = 0; b < NP; ++b) uv[b] = urow[b];
+    if (op.dir) {
+      const bool rowd = on_dir(op.dir, 1, jy, N * P);
+#pragma unroll
+      for (int b = 0; b < NP; ++b)
+        if (rowd || on_dir(op.dir, 0, c * P + b, N * P)) uv[b] = cx<T>{0, 0};
+    }
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
       cx<T> w = {0, 0}, z = {0, 0};
@@ -121,7 +130,8 @@ __global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<
           const T kk = (T)op.kr[(long long)cyq * N + cxq];
           cx<T> m = {0, 0};
           for (int by = 0; by < NP; ++by)
-            rmac(m, sM[ay * NP + by], u[(long long)(cyq * P + by) * n1 + ix]);
+            if (!on_dir(op.dir, 1, cyq * P + by, NPn))
+              rmac(m, sM[ay * NP + by], u[(long long)(cyq * P + by) * n1 + ix]);
           rmac(s, kk, m);
         }
       }
@@ -132,7 +142,8 @@ __global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<
           const T kk = (T)op.kr[(long long)cyq * N + cxq];
           cx<T> m = {0, 0};
           for (int bx = 0; bx < NP; ++bx)
-            rmac(m, sM[ax * NP + bx], u[(long long)iy * n1 + cxq * P + bx]);
+            if (!on_dir(op.dir, 0, cxq * P + bx, NPn))
+              rmac(m, sM[ax * NP + bx], u[(long long)iy * n1 + cxq * P + bx]);
           rmac(s, kk, m);
         }
       }
@@ -141,6 +152,7 @@ __global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<
       acc.im -= h * s.re;
     }
     const long long g = (long long)iy * n1 + ix;
+    if (op.dir && (on_dir(op.dir, 0, ix, NPn) || on_dir(op.dir, 1, iy, NPn))) acc = u[g];
     cx<T> o = f ? f[g] : cx<T>{0, 0};
     o.re = fma(sgn, acc.re, o.re);
     o.im = fma(sgn, acc.im, o.im);
@@ -199,8 +211,11 @@ __global__ __launch_bounds__(256) void k_apply3d(FineOp op, Ref1D ref, const cx<
   for (int i = threadIdx.x; i < nnx * nny * nnz; i += blockDim.x) {
     const int jx = i % nnx, t = i / nnx;
     const int jy = t % nny, jz = t / nny;
-    Us[(jz * NN + jy) * NN + jx] =
-        u[((long long)(czs * P + jz) * n1 + cys * P + jy) * n1 + cxs * P + jx];
+    cx<T> v = u[((long long)(czs * P + jz) * n1 + cys * P + jy) * n1 + cxs * P + jx];
+    if (op.dir && (on_dir(op.dir, 0, cxs * P + jx, N * P) || on_dir(op.dir, 1, cys * P + jy, N * P) ||
+                   on_dir(op.dir, 2, czs * P + jz, N * P)))
+      v = cx<T>{0, 0};
+    Us[(jz * NN + jy) * NN + jx] = v;
   }
   __syncthreads();
 
@@ -326,6 +341,9 @@ __global__ __launch_bounds__(256) void k_apply3d(FineOp op, Ref1D ref, const cx<
       acc.im -= h2 * s.re;
     }
     const long long g = ((long long)iz * n1 + iy) * n1 + ix;
+    if (op.dir && (on_dir(op.dir, 0, ix, NPn) || on_dir(op.dir, 1, iy, NPn) ||
+                   on_dir(op.dir, 2, iz, NPn)))
+      acc = u[g];
     cx<T> o = f ? f[g] : cx<T>{0, 0};
     o.re = fma(sgn, acc.re, o.re);
     o.im = fma(sgn, acc.im, o.im);

@@ -11,6 +11,11 @@
 // fine node over the (r+1)^d coarse points of its cell, restriction per
 // coarse point over the fine nodes of the cells around it, every fine node
 // counted once.
+//
+// Dirichlet sides (dir, bit per side): their fine nodes and coarse vertices are
+// not unknowns; the rows of I_P for those fine nodes and its columns for those
+// vertices are zero.  The weights are masked per axis (a point lies on a
+// Dirichlet side when one of its coordinates does).
 #include "ctx.hpp"
 
 namespace th {
@@ -26,7 +31,8 @@ __device__ __forceinline__ double p1w(const double *L, int N, int i, int J) {
 // The grids are n1^DIM (fine) and nc1^DIM (coarse), x fastest; in 2-D the z
 // loops collapse to one iteration with unit weight.
 template <int DIM, int P, typename T>
-__global__ __launch_bounds__(256) void k_prolong(int N, Ref1D ref, const cx<T> *__restrict__ uc,
+__global__ __launch_bounds__(256) void k_prolong(int N, int dir, Ref1D ref,
+                                                 const cx<T> *__restrict__ uc,
                                                  cx<T> *__restrict__ u, T omega, long long nf,
                                                  long long ncn) {
   constexpr int R = P / 2;
@@ -43,22 +49,25 @@ __global__ __launch_bounds__(256) void k_prolong(int N, Ref1D ref, const cx<T> *
     const int cxq = min(ix / P, N - 1), cyq = min(iy / P, N - 1);
     const int czq = DIM == 3 ? min(iz / P, N - 1) : 0;
     const int ax = ix - cxq * P, ay = iy - cyq * P, az = iz - czq * P;
+    if (dir && (on_dir(dir, 0, ix, n1 - 1) || on_dir(dir, 1, iy, n1 - 1) ||
+                (DIM == 3 && on_dir(dir, 2, iz, n1 - 1))))
+      continue;  // a zero row of I_P: u keeps its value
     cx<T> acc = {0, 0};
 #pragma unroll
     for (int bz = 0; bz <= RZ; ++bz) {
       const T wz = DIM == 3 ? (T)ref.L[az * (R + 1) + bz] : (T)1;
-      if (wz == (T)0) continue;
+      if (wz == (T)0 || (DIM == 3 && on_dir(dir, 2, czq * R + bz, nc1 - 1))) continue;
       cx<T> pl = {0, 0};
 #pragma unroll
       for (int by = 0; by <= R; ++by) {
         const T wy = (T)ref.L[ay * (R + 1) + by];
-        if (wy == (T)0) continue;
+        if (wy == (T)0 || on_dir(dir, 1, cyq * R + by, nc1 - 1)) continue;
         cx<T> row = {0, 0};
         const cx<T> *ucr = uc + ((long long)(czq * R + bz) * nc1 + cyq * R + by) * nc1 + cxq * R;
 #pragma unroll
         for (int bx = 0; bx <= R; ++bx) {
           const T wx = (T)ref.L[ax * (R + 1) + bx];
-          if (wx == (T)0) continue;
+          if (wx == (T)0 || on_dir(dir, 0, cxq * R + bx, nc1 - 1)) continue;
           rmac(row, wx, ucr[bx]);
         }
         rmac(pl, wy, row);
@@ -74,7 +83,8 @@ __global__ __launch_bounds__(256) void k_prolong(int N, Ref1D ref, const cx<T> *
 }
 
 template <int DIM, int P, typename T>
-__global__ __launch_bounds__(256) void k_restrict(int N, Ref1D ref, const cx<T> *__restrict__ r,
+__global__ __launch_bounds__(256) void k_restrict(int N, int dir, Ref1D ref,
+                                                  const cx<T> *__restrict__ r,
                                                   cx<T> *__restrict__ rc, long long nf,
                                                   long long ncn) {
   constexpr int R = P / 2;
@@ -87,6 +97,11 @@ __global__ __launch_bounds__(256) void k_restrict(int N, Ref1D ref, const cx<T> 
     const int Jx = (int)(G % nc1);
     const long long t = G / nc1;
     const int Jy = (int)(t % nc1), Jz = (int)(t / nc1);
+    if (on_dir(dir, 0, Jx, nc1 - 1) || on_dir(dir, 1, Jy, nc1 - 1) ||
+        (DIM == 3 && on_dir(dir, 2, Jz, nc1 - 1))) {
+      rc[G] = cx<T>{0, 0};
+      continue;
+    }
     // cells whose coarse points include J: c R <= J <= c R + R; fine node range of those cells
     const int ixs = max((Jx % R == 0) ? Jx / R - 1 : Jx / R, 0) * P;
     const int ixe = (min(Jx / R, N - 1) + 1) * P;
@@ -97,16 +112,16 @@ __global__ __launch_bounds__(256) void k_restrict(int N, Ref1D ref, const cx<T> 
     cx<T> acc = {0, 0};
     for (int iz = izs; iz <= ize; ++iz) {
       const T wz = DIM == 3 ? (T)p1w<P>(ref.L, N, iz, Jz) : (T)1;
-      if (wz == (T)0) continue;
+      if (wz == (T)0 || (DIM == 3 && on_dir(dir, 2, iz, n1 - 1))) continue;
       cx<T> pl = {0, 0};
       for (int iy = iys; iy <= iye; ++iy) {
         const T wy = (T)p1w<P>(ref.L, N, iy, Jy);
-        if (wy == (T)0) continue;
+        if (wy == (T)0 || on_dir(dir, 1, iy, n1 - 1)) continue;
         cx<T> row = {0, 0};
         const cx<T> *rr = r + ((long long)iz * n1 + iy) * n1;
         for (int ix = ixs; ix <= ixe; ++ix) {
           const T wx = (T)p1w<P>(ref.L, N, ix, Jx);
-          if (wx == (T)0) continue;
+          if (wx == (T)0 || on_dir(dir, 0, ix, n1 - 1)) continue;
           rmac(row, wx, rr[ix]);
         }
         rmac(pl, wy, row);
@@ -125,21 +140,22 @@ static long long ipow(long long b, int e) {
 }
 
 template <int DIM, int P, typename T>
-static int prolong_t(int N, const Ref1D &ref, const void *uc, void *u, double omega, int nrhs,
-                     hipStream_t s) {
+static int prolong_t(int N, int dir, const Ref1D &ref, const void *uc, void *u, double omega,
+                     int nrhs, hipStream_t s) {
   const long long nf = ipow(N * P + 1, DIM), ncn = ipow(N * (P / 2) + 1, DIM);
   int blocks = (int)std::min<long long>(ceil_div_ll(nf, 256), 65535);
-  hipLaunchKernelGGL((k_prolong<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
+  hipLaunchKernelGGL((k_prolong<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, dir, ref,
                      (const cx<T> *)uc, (cx<T> *)u, (T)omega, nf, ncn);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
 
 template <int DIM, int P, typename T>
-static int restrict_t(int N, const Ref1D &ref, const void *r, void *rc, int nrhs, hipStream_t s) {
+static int restrict_t(int N, int dir, const Ref1D &ref, const void *r, void *rc, int nrhs,
+                      hipStream_t s) {
   const long long nf = ipow(N * P + 1, DIM), ncn = ipow(N * (P / 2) + 1, DIM);
   int blocks = (int)std::min<long long>(ceil_div_ll(ncn, 256), 65535);
-  hipLaunchKernelGGL((k_restrict<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, ref,
+  hipLaunchKernelGGL((k_restrict<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, dir, ref,
                      (const cx<T> *)r, (cx<T> *)rc, nf, ncn);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
@@ -153,17 +169,18 @@ static int restrict_t(int N, const Ref1D &ref, const void *r, void *rc, int nrhs
     case 8: return F32_ ? CALL_F(8) : CALL_D(8);  \
   }
 
-int launch_prolong(int dim, int N, int P, const Ref1D &ref, const void *uc, void *u, double omega,
+int launch_prolong(int dim, int N, int P, int dir, const Ref1D &ref, const void *uc, void *u,
+                   double omega,
                    int nrhs, bool f32, hipStream_t s) {
   if (dim == 3) {
-#define CF(p) prolong_t<3, p, float>(N, ref, uc, u, omega, nrhs, s)
-#define CD(p) prolong_t<3, p, double>(N, ref, uc, u, omega, nrhs, s)
+#define CF(p) prolong_t<3, p, float>(N, dir, ref, uc, u, omega, nrhs, s)
+#define CD(p) prolong_t<3, p, double>(N, dir, ref, uc, u, omega, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
   } else {
-#define CF(p) prolong_t<2, p, float>(N, ref, uc, u, omega, nrhs, s)
-#define CD(p) prolong_t<2, p, double>(N, ref, uc, u, omega, nrhs, s)
+#define CF(p) prolong_t<2, p, float>(N, dir, ref, uc, u, omega, nrhs, s)
+#define CD(p) prolong_t<2, p, double>(N, dir, ref, uc, u, omega, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
@@ -172,17 +189,18 @@ int launch_prolong(int dim, int N, int P, const Ref1D &ref, const void *uc, void
   return TH_EUNSUPPORTED;
 }
 
-int launch_restrict(int dim, int N, int P, const Ref1D &ref, const void *r, void *rc, int nrhs,
+int launch_restrict(int dim, int N, int P, int dir, const Ref1D &ref, const void *r, void *rc,
+                    int nrhs,
                     bool f32, hipStream_t s) {
   if (dim == 3) {
-#define CF(p) restrict_t<3, p, float>(N, ref, r, rc, nrhs, s)
-#define CD(p) restrict_t<3, p, double>(N, ref, r, rc, nrhs, s)
+#define CF(p) restrict_t<3, p, float>(N, dir, ref, r, rc, nrhs, s)
+#define CD(p) restrict_t<3, p, double>(N, dir, ref, r, rc, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
   } else {
-#define CF(p) restrict_t<2, p, float>(N, ref, r, rc, nrhs, s)
-#define CD(p) restrict_t<2, p, double>(N, ref, r, rc, nrhs, s)
+#define CF(p) restrict_t<2, p, float>(N, dir, ref, r, rc, nrhs, s)
+#define CD(p) restrict_t<2, p, double>(N, dir, ref, r, rc, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD

@@ -21,6 +21,11 @@ Input recipe (project definitions; the paper's own experiments use constant k):
     grid, then mapped affinely so that min = c_min and max = c_max exactly;
   * angular frequency omega = 2*pi*W*c_min so that the slowest speed has W
     wavelengths across the unit domain; k = omega / c per cell;
+  * absorbing layer (the recipe of the paper's convergence tests, Sec. 7):
+    over about 40 DOFs (40 / p cells) next to a flagged side the damping eps
+    rises with a sin^2 profile from 0 to 2 k^2 / pi (D = 2 damping per
+    wavelength, Sec. 5.2); here the layer takes the outer cells of the unit
+    domain instead of cells added outside it;
   * Gaussian source g(x) = exp(-|x-x0|^2 / (2 sigma^2)), load vector by GLL
     quadrature on every cell: f_j = h^d * sum over cells containing node j of
     the tensor GLL weight of j in that cell times g(x_j).
@@ -38,6 +43,7 @@ __all__ = [
     "wavenumber_from_speed",
     "gaussian_centres_grid",
     "gaussian_load",
+    "absorbing_layer_eps",
     "random_complex",
     "config",
 ]
@@ -98,6 +104,29 @@ def wavenumber_from_speed(speed: np.ndarray, wavelengths: float,
     c0 = float(speed.min()) if cmin is None else float(cmin)
     omega = 2.0 * math.pi * wavelengths * c0
     return omega / speed
+
+
+def absorbing_layer_eps(k: np.ndarray, p: int, sides, dofs: float = 40.0) -> np.ndarray:
+    """Per-cell eps of absorbing layers along the sides flagged in `sides`
+    (2*dim booleans, x-, x+, y-, y+, z-, z+) for the per-cell wavenumber k
+    (indexed [z][y][x]).  Layer width L = dofs / p cells; a cell whose centre
+    lies at distance d < L from a flagged side gets
+    (2 k^2 / pi) sin^2(pi (L - d) / (2 L)); where layers meet, the larger."""
+    k = np.asarray(k, dtype=np.float64)
+    dim, N = k.ndim, k.shape[0]
+    L = dofs / p
+    centre = np.arange(N) + 0.5
+    ramp = np.zeros((N,) * dim)
+    for a in range(dim):
+        shape = [1] * dim
+        shape[dim - 1 - a] = N  # axis a = x is the last array axis
+        for hi in (0, 1):
+            if not sides[2 * a + hi]:
+                continue
+            d = (N - centre) if hi else centre
+            s = np.clip((L - d) / L, 0.0, 1.0).reshape(shape)
+            ramp = np.maximum(ramp, np.sin(0.5 * math.pi * s) ** 2)
+    return np.ascontiguousarray(2.0 * k * k / math.pi * ramp)
 
 
 def gaussian_centres_grid(m: int, dim: int = 2) -> np.ndarray:

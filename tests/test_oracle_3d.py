@@ -85,6 +85,8 @@ def test_27pt_dispersion_is_far_below_that_of_trilinear_fe():
 
 
 def test_27pt_quasi_fe_interior_stencil_and_absorbing_row_sums():
+    """Interior row h_c N P (the 3-D cell stiffness scales as h_c); absorbing
+    row sums of the face mass."""
     Nc, eta = 4, 0.9
     kc = np.full((Nc, Nc, Nc), eta * Nc)
     A = qsfem3d.coarse_matrix_3d(kc)
@@ -97,7 +99,7 @@ def test_27pt_quasi_fe_interior_stencil_and_absorbing_row_sums():
         for dy in (-1, 0, 1):
             for dx in (-1, 0, 1):
                 cls = abs(dx) + abs(dy) + abs(dz)
-                assert abs(row[c + (dz * n1 + dy) * n1 + dx] - Nn * P[cls]) < 1e-13
+                assert abs(row[c + (dz * n1 + dy) * n1 + dx] - Nn * P[cls] / Nc) < 1e-13
     assert row.nonzero()[0].size == 27
     assert abs(A - A.T).max() < 1e-14
     # absorbing term -i k int_face u v: row sums of the face Q1 mass are
