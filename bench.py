@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--study", default=None, choices=["table1"],
+                    help="instead of the benchmark, print the iteration counts of a parameter "
+                         "study (table1: the two-grid parameters of Table 1)")
     return ap.parse_args()
 
 
@@ -269,6 +272,56 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
     return res
 
 
+def study_table1(wavelengths=16.0, rtol=1e-6):
+    """GMRES iteration counts of the two-grid method for the parameter grid of
+    Table 1: constant k on the unit square, absorbing boundary on all sides,
+    a Gaussian source (sigma = 2h) off the centre, QSFEM coarse level.  The
+    paper states neither domain size nor tolerance: about 16 wavelengths
+    across the domain and a 1e-6 relative residual are used.  Prints one JSON
+    line per part."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import synthetic as syn
+    from paper_2509_17494_amd import TwoGridSolver
+
+    def iters(p, ppw, **kw):
+        N = max(2, round(ppw * wavelengths / p))
+        k = np.full((N, N), 2.0 * math.pi * p * N / ppw)  # ppw DOFs per wavelength
+        f = syn.gaussian_load(N, p, [[0.41, 0.57]], 2.0 / N)
+        s = TwoGridSolver(k, order=p, max_rhs=1, **kw)
+        _, st = s.solve(torch.from_numpy(f).to("cuda"), rtol=rtol, maxit=400)
+        s.close()
+        return st.iters if st.status == 0 else None
+
+    part_a = {}
+    for p, ppw in ((4, 10), (6, 8)):
+        for l_dd in (4, 6):
+            for n_dd in (1, 2):
+                row = [iters(p, ppw, alpha_s=a, l_dd=l_dd, n_dd=n_dd)
+                       for a in (0.1, 0.15, 0.2, 0.3, 0.4)]
+                part_a[f"p={p} ppw={ppw} subdomsize={l_dd} n_dd={n_dd}"] = row
+                print(f"table1a p={p} l_dd={l_dd} n_dd={n_dd}: {row}", file=sys.stderr,
+                      flush=True)
+    print(json.dumps({"study": "table1a", "columns": "alpha_s = 0.1, 0.15, 0.2, 0.3, 0.4",
+                      "wavelengths": wavelengths, "rtol": rtol, "iters": part_a}), flush=True)
+    part_b = {}
+    for n_s in (1, 2):
+        for om in (1.0, 0.8, 0.6):
+            row = {}
+            for p, ppws in ((4, (8, 10, 14)), (6, (6, 8, 10, 14))):
+                for ppw in ppws:
+                    row[f"p={p} ppw={ppw}"] = iters(p, ppw, alpha_s=0.2, l_dd=4, n_s=n_s,
+                                                    omega_c=om)
+            part_b[f"n_s={n_s} omega_c={om}"] = row
+            print(f"table1b n_s={n_s} omega_c={om}: {list(row.values())}", file=sys.stderr,
+                  flush=True)
+    print(json.dumps({"study": "table1b", "alpha_s": 0.2, "subdomsize": 4,
+                      "wavelengths": wavelengths, "rtol": rtol, "iters": part_b}), flush=True)
+
+
 def main():
     a = parse()
     if a.verbose:
@@ -277,6 +330,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if a.study == "table1":
+        study_table1()
+        return
     mixed = a.workload in ("C3", "C4")
     prim = run_workload(a.workload, a.steps, a.warmup, precond=a.precond, graph=mixed,
                         timing=not mixed, verbose=a.verbose, alpha_s=a.alpha_s)

@@ -1,0 +1,50 @@
+"""Trends of the parameter study of Table 1 on the GPU path (constant k on the
+unit square, absorbing sides, QSFEM coarse level, 16 wavelengths across the
+domain, GMRES to 1e-6).  The paper gives neither the domain size nor the
+tolerance, so the counts are not compared one by one; what is checked are its
+stated conclusions:
+  * (a) the iteration count depends only weakly on alpha_s, and a second DD
+    iteration per smoother step never costs iterations;
+  * (b) at p = 6 and 6 DOFs per wavelength, n_s = 2 with omega_c = 0.8 needs
+    clearly fewer iterations than n_s = 1 with omega_c = 1.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+WAVELENGTHS = 16.0
+
+
+def iters(p, ppw, **kw):
+    from paper_2509_17494_amd import TwoGridSolver
+    N = round(ppw * WAVELENGTHS / p)
+    k = np.full((N, N), 2.0 * math.pi * p * N / ppw)
+    f = syn.gaussian_load(N, p, [[0.41, 0.57]], 2.0 / N)
+    s = TwoGridSolver(k, order=p, max_rhs=1, **kw)
+    _, st = s.solve(torch.from_numpy(f).to("cuda"), rtol=1e-6, maxit=400)
+    s.close()
+    assert st.status == 0
+    return st.iters
+
+
+def test_weak_dependence_on_alpha_s_and_n_dd():
+    alphas = (0.1, 0.15, 0.2, 0.3, 0.4)
+    one = [iters(4, 10, alpha_s=a, l_dd=4, n_dd=1) for a in alphas]
+    two = [iters(4, 10, alpha_s=a, l_dd=4, n_dd=2) for a in alphas]
+    print(f"p=4 ppw=10 subdomsize 4: n_dd=1 {one}, n_dd=2 {two}", flush=True)
+    assert max(one) - min(one) <= 3 and max(two) - min(two) <= 3
+    assert all(b <= a for a, b in zip(one, two))
+
+
+def test_two_smoothing_steps_and_damped_correction_help_at_6_ppw():
+    base = iters(6, 6, alpha_s=0.2, l_dd=4, n_s=1, omega_c=1.0)
+    tuned = iters(6, 6, alpha_s=0.2, l_dd=4, n_s=2, omega_c=0.8)
+    print(f"p=6 ppw=6: n_s=1 omega_c=1 {base}, n_s=2 omega_c=0.8 {tuned}", flush=True)
+    assert tuned <= base - 3
