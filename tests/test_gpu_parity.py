@@ -221,11 +221,13 @@ def test_operator_layout_choice(N, p, l_dd, layout):
     assert s.info()["smoother_layout"] == layout
 
 
-def test_smooth_f32_storage():
-    N, p, l_dd = 21, 4, 8
+@pytest.mark.parametrize("N,p,l_dd,layout", [(19, 4, 6, 0), (21, 4, 8, 1)])
+def test_smooth_f32_storage(N, p, l_dd, layout):
+    """FP32-stored operators in both layouts (dense rows, symmetric tiles)."""
     k = hetero_k(N, p, seed=24)
     sm = CSDDSmoother(p, k, None, 0.5, l_dd)
     s = make_solver(k, p, l_dd, max_rhs=2, coarse=None, gemm="f32")
+    assert s.info()["smoother_layout"] == layout
     u0 = syn.random_complex((2, sm.n_nodes), seed=25)
     f = syn.random_complex((2, sm.n_nodes), seed=26)
     ref = np.stack([sm.apply(u0[i], f[i]) for i in range(2)])
