@@ -133,7 +133,7 @@ static void free_fine(th_ctx *c) {
 
 static void free_coarse(th_ctx *c) {
   free_graphs(c);  // graphs reference the coarse factors and workspaces
-  void *ptrs[] = {c->coarse.G, c->coarse.st, c->coarse.tbuf};
+  void *ptrs[] = {c->coarse.G, c->coarse.st, c->coarse.tbuf, c->coarse.pbuf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->coarse = CoarseData{};

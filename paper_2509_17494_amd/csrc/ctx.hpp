@@ -104,6 +104,7 @@ struct CoarseData {
   c64 *G = nullptr;           // inverses of the Schur blocks S_J (symmetric), row-major
   c64 *st = nullptr;          // per vertex 3 x C couplings [slab offset + 1][in-slab code]
   c64 *tbuf = nullptr;        // staging of slab right-hand sides for large slabs
+  c64 *pbuf = nullptr;        // column-chunk partial sums of the large-slab GEMV
   long long bytes = 0;
 };
 

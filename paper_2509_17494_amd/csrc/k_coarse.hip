@@ -16,11 +16,12 @@
 // sparse LU).  The solve is
 //   forward   y_J = G_J (r_J - L_J y_{J-1})
 //   backward  x_J = y_J - G_J[:, last slab] (U_J x_{J+1}[first slab]),
-// two launches per super-block, each a bandwidth-bound GEMV with one
-// wavefront per output row (coalesced row reads of G_J, the right-hand side
-// staged in LDS, or in global memory when a 3-D slab is too large for it;
-// fixed-order wavefront reductions).  K trades the bytes of G
-// (proportional to K) against the number of sequential launches (~2 ny / K).
+// each a bandwidth-bound GEMV: for slabs whose right-hand sides fit in LDS one
+// launch per step with one wavefront per output row (coalesced row reads of
+// G_J, fixed-order wavefront reductions); for larger (3-D) slabs a GEMV that
+// reads G_J through its symmetry with one thread per output row, over column
+// chunks summed in a fixed order.  K trades the bytes of G (proportional to K)
+// against the number of sequential launches (~2 ny / K).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -30,6 +31,7 @@
 namespace th {
 
 constexpr int CW = 8;  // wavefronts (rows) per workgroup in the sweeps
+constexpr int kCoarseChunk = 256;  // columns per partial sum of the large-slab GEMV
 
 // In-slab neighbourhood: C = 3 codes dx + 1 along a line (2-D), C = 9 codes
 // (dy + 1) 3 + dx + 1 in a plane (3-D).  The code from b back to a is C - 1 - code.
@@ -133,7 +135,8 @@ __device__ __forceinline__ c64 bwd_rhs(int c, int r, int nx, int L, int C, int l
 }
 
 // Staging in global memory for slabs whose right-hand sides do not fit in
-// LDS: xg[r n + i] for r < nrhs, n = nb (forward) or L (backward).
+// LDS, interleaved by column: xg[i nrhs + r] for r < nrhs, i < n, n = nb
+// (forward) or L (backward).
 __global__ __launch_bounds__(256) void k_cstage(int fwd, int n, int nx, int L, int C, int slab,
                                                 const c64 *__restrict__ st,
                                                 const c64 *__restrict__ rc,
@@ -141,73 +144,70 @@ __global__ __launch_bounds__(256) void k_cstage(int fwd, int n, int nx, int L, i
                                                 int nrhs, long long ncn, int has_prev) {
   const long long tot = (long long)n * nrhs;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < tot; i += (long long)gridDim.x * 256) {
-    const int r = (int)(i / n), a = (int)(i - (long long)r * n);
+    const int a = (int)(i / nrhs), r = (int)(i - (long long)a * nrhs);
     xg[i] = fwd ? fwd_rhs(a, r, nx, L, C, slab, st, rc, uc, ncn, has_prev)
                 : bwd_rhs(a, r, nx, L, C, slab, st, uc, ncn);
   }
 }
 
-// Sweep GEMV for large slabs: y_a = sum_b G[a][col0 + b] x[b] for the rows a
-// of one super-block and RC right-hand sides, x staged from xg (above) through
-// LDS in chunks of columns; every wavefront owns RPW rows, so each staged
-// value is reused RPW times from registers and G streams once per RC
-// right-hand sides.  sub = 0: uc[a] = y_a (forward), sub = 1: uc[a] -= y_a
-// (backward).
-template <int RC, int RPW>
-__global__ __launch_bounds__(256) void k_cgemv(const c64 *__restrict__ G, int ld, int nrows,
-                                               int col0, int ncols, const c64 *__restrict__ xg,
-                                               c64 *__restrict__ uc, long long row0, long long ncn,
-                                               int nrhs, int sub) {
-  constexpr int CK = 256;
-  __shared__ c64 Ts[RC][CK];
-  const int r0 = blockIdx.y * RC;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int a0 = (blockIdx.x * 4 + wave) * RPW;
-  c64 acc[RPW][RC];
+// Sweep GEMV for large slabs, y_a = sum_b G[a][col0 + b] x_b for the rows a of
+// one super-block and RC right-hand sides.  S_J is complex symmetric (A_c is,
+// and the Schur complement keeps it), so G_J = S_J^{-1} is too and the product
+// is formed as sum_b G[col0 + b][a] x_b: every thread owns one output row a,
+// every load instruction of a wavefront reads 64 consecutive entries of one
+// row of G (1 KiB), and x_b is the same for the whole wavefront (broadcast
+// LDS reads of the chunk's right-hand sides, staged once per workgroup).  No
+// cross-lane sums.  The columns are split in chunks of kCoarseChunk; chunk k
+// writes its partial sums to part[(k nrhs + q) nrows + a], and k_cpartsum adds
+// them in chunk order.
+template <int RC>
+__global__ __launch_bounds__(256) void k_cgemv_t(const c64 *__restrict__ G, int ld, int nrows,
+                                                 int col0, int ncols,
+                                                 const c64 *__restrict__ xg,
+                                                 c64 *__restrict__ part, int nrhs) {
+  constexpr int U = 8;  // rows of G in flight per thread
+  __shared__ c64 xs[kCoarseChunk][RC];
+  const int ch = blockIdx.y, r0 = blockIdx.z * RC;
+  const int b0 = ch * kCoarseChunk, nbk = min(kCoarseChunk, ncols - b0);
+  const int nq = min(RC, nrhs - r0);
+  for (int t = threadIdx.x; t < kCoarseChunk * RC; t += 256) {
+    const int b = t / RC, q = t - b * RC;
+    xs[b][q] = (b < nbk && q < nq) ? xg[(long long)(b0 + b) * nrhs + r0 + q] : c64{0, 0};
+  }
+  __syncthreads();
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= nrows) return;
+  c64 acc[RC];
 #pragma unroll
-  for (int i = 0; i < RPW; ++i)
+  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
+  const c64 *gp = G + (long long)(col0 + b0) * ld + a;
+  for (int b = 0; b < nbk; b += U) {  // b + u < kCoarseChunk: xs beyond nbk holds zeros
+    c64 g[U];
 #pragma unroll
-    for (int q = 0; q < RC; ++q) acc[i][q] = {0, 0};
-  for (int c0 = 0; c0 < ncols; c0 += CK) {
-    const int ck = min(CK, ncols - c0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < RC * CK; t += 256) {
-      const int q = t / CK, b = t - q * CK;
-      Ts[q][b] = (b < ck && r0 + q < nrhs) ? xg[(long long)(r0 + q) * ncols + c0 + b] : c64{0, 0};
-    }
-    __syncthreads();
-    // fixed trip count: all CK / 64 x RPW loads of G are issued before use
-    c64 g[CK / 64][RPW];
+    for (int u = 0; u < U; ++u)
+      g[u] = b + u < nbk ? ld_stream(gp + (long long)(b + u) * ld) : c64{0, 0};
 #pragma unroll
-    for (int u = 0; u < CK / 64; ++u) {
-      const int b = u * 64 + lane;
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int i = 0; i < RPW; ++i)
-        g[u][i] = (b < ck && a0 + i < nrows)
-                      ? ld_stream(G + (long long)(a0 + i) * ld + col0 + c0 + b)
-                      : c64{0, 0};
-    }
-#pragma unroll
-    for (int u = 0; u < CK / 64; ++u) {
-      const int b = u * 64 + lane;
-#pragma unroll
-      for (int q = 0; q < RC; ++q) {
-        const c64 x = Ts[q][b];  // zero beyond ck
-#pragma unroll
-        for (int i = 0; i < RPW; ++i) cmac(acc[i][q], g[u][i], x);
-      }
-    }
+      for (int q = 0; q < RC; ++q) cmac(acc[q], g[u], xs[b + u][q]);
   }
 #pragma unroll
-  for (int i = 0; i < RPW; ++i)
-#pragma unroll
-    for (int q = 0; q < RC; ++q) {
-      const c64 sm = wave_sum(acc[i][q]);
-      if (lane == 0 && a0 + i < nrows && r0 + q < nrhs) {
-        c64 *p = uc + (r0 + q) * ncn + row0 + a0 + i;
-        *p = sub ? *p - sm : sm;
-      }
-    }
+  for (int q = 0; q < RC; ++q)
+    if (q < nq) part[((long long)ch * nrhs + r0 + q) * nrows + a] = acc[q];
+}
+
+// uc[row0 + a] = sum_k part[k][q][a] (sub = 0) or uc[row0 + a] -= that sum
+// (sub = 1), the chunks added in ascending order.
+__global__ __launch_bounds__(256) void k_cpartsum(const c64 *__restrict__ part, int nch, int nrows,
+                                                  int nrhs, c64 *__restrict__ uc, long long row0,
+                                                  long long ncn, int sub) {
+  const long long t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= (long long)nrows * nrhs) return;
+  const int q = (int)(t / nrows), a = (int)(t - (long long)q * nrows);
+  c64 sm = {0, 0};
+  for (int k = 0; k < nch; ++k) sm = sm + part[((long long)k * nrhs + q) * nrows + a];
+  c64 *p = uc + q * ncn + row0 + a;
+  *p = sub ? *p - sm : sm;
 }
 
 // forward step of super-block J: y_J = G_J (r_J - L_J y_{J-1})
@@ -350,11 +350,13 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   int max_nb = 0;
   for (int J = 0; J < nblk; ++J) max_nb = std::max(max_nb, (cd.line0[J + 1] - cd.line0[J]) * L);
   const size_t t_bytes = (size_t)max_nb * R * sizeof(c64);
+  const size_t p_bytes = (size_t)ceil_div(max_nb, kCoarseChunk) * t_bytes;
   cd.bytes = cd.goff[nblk] * (long long)sizeof(c64) + (long long)st_bytes;
   c64 *pws = nullptr;
   if (hipMalloc(&cd.G, (size_t)cd.goff[nblk] * sizeof(c64)) != hipSuccess ||
       hipMalloc(&cd.st, st_bytes) != hipSuccess ||
       hipMalloc(&cd.tbuf, t_bytes) != hipSuccess ||
+      hipMalloc(&cd.pbuf, p_bytes) != hipSuccess ||
       hipMalloc(&pws, kGJBlock * kGJBlock * sizeof(c64) + 64) != hipSuccess) {
     if (pws) (void)hipFree(pws);
     set_error("cannot allocate the coarse factors");
@@ -388,24 +390,32 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   return 0;
 }
 
-// Large slabs: one staging launch and one chunked GEMV per step, G streamed
-// once per RCG right-hand sides.
-template <int RCG>
+// Large slabs: per step one staging launch, one GEMV over column chunks and one
+// fixed-order sum of the chunk partials; G streamed once per RC right-hand sides.
+template <int RC>
+static void gemv_large(const CoarseData &cd, const c64 *G, int ld, int nb, int col0, int ncols,
+                       c64 *uc, long long row0, long long ncn, int nrhs, int sub,
+                       hipStream_t s) {
+  const int nch = ceil_div(ncols, kCoarseChunk);
+  hipLaunchKernelGGL((k_cgemv_t<RC>), dim3(ceil_div(nb, 256), nch, ceil_div(nrhs, RC)), dim3(256),
+                     0, s, G, ld, nb, col0, ncols, (const c64 *)cd.tbuf, cd.pbuf, nrhs);
+  hipLaunchKernelGGL(k_cpartsum, dim3((unsigned)ceil_div_ll((long long)nb * nrhs, 256)), dim3(256),
+                     0, s, (const c64 *)cd.pbuf, nch, nb, nrhs, uc, row0, ncn, sub);
+}
+
+template <int RC>
 static int sweep_large_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
   const CoarseData &cd = c->coarse;
   const int nx = cd.nx, L = cd.L, C = cd.C;
   const long long ncn = (long long)L * cd.ny;
-  constexpr int RPW = RCG >= 8 ? 2 : 4;
-  const unsigned ychunks = (unsigned)ceil_div(nrhs, RCG);
   for (int J = 0; J < cd.nblk; ++J) {
     const int nb = (cd.line0[J + 1] - cd.line0[J]) * L;
     const unsigned sb = (unsigned)std::min<long long>(ceil_div_ll((long long)nb * nrhs, 256), 2048);
     hipLaunchKernelGGL(k_cstage, dim3(sb), dim3(256), 0, s, 1, nb, nx, L, C, cd.line0[J],
                        (const c64 *)cd.st, rcv, (const c64 *)uc, cd.tbuf, nrhs, ncn,
                        J > 0 ? 1 : 0);
-    hipLaunchKernelGGL((k_cgemv<RCG, RPW>), dim3(ceil_div(nb, 4 * RPW), ychunks), dim3(256), 0,
-                       s, (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, 0, nb,
-                       (const c64 *)cd.tbuf, uc, (long long)cd.line0[J] * L, ncn, nrhs, 0);
+    gemv_large<RC>(cd, cd.G + cd.goff[J], cd.ld[J], nb, 0, nb, uc, (long long)cd.line0[J] * L,
+                   ncn, nrhs, 0, s);
   }
   for (int J = cd.nblk - 2; J >= 0; --J) {
     const int kJ = cd.line0[J + 1] - cd.line0[J];
@@ -414,9 +424,8 @@ static int sweep_large_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream
     hipLaunchKernelGGL(k_cstage, dim3(sb), dim3(256), 0, s, 0, L, nx, L, C, cd.line0[J] + kJ,
                        (const c64 *)cd.st, (const c64 *)nullptr, (const c64 *)uc, cd.tbuf, nrhs,
                        ncn, 0);
-    hipLaunchKernelGGL((k_cgemv<RCG, RPW>), dim3(ceil_div(nb, 4 * RPW), ychunks), dim3(256), 0,
-                       s, (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, (kJ - 1) * L, L,
-                       (const c64 *)cd.tbuf, uc, (long long)cd.line0[J] * L, ncn, nrhs, 1);
+    gemv_large<RC>(cd, cd.G + cd.goff[J], cd.ld[J], nb, (kJ - 1) * L, L, uc,
+                   (long long)cd.line0[J] * L, ncn, nrhs, 1, s);
   }
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
