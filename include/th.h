@@ -84,6 +84,19 @@ typedef enum {
   TH_KRYLOV_STATIONARY = 1  /* u <- TwoGridStep(u, f) repeated */
 } th_krylov;
 
+/* Layout of the FP64/FP32 subdomain solves (th_fine_desc.layout).
+ *   DENSE:     B_i = diag(1/L_j) R_U (A_s^(i))^{-1}, n_U x n_Omega, 64-row blocks.
+ *   SYMMETRIC: the same with the U x U block of the symmetric inverse stored once
+ *              (upper 64 x 64 tiles).
+ *   SLAB:      block factorisation of A_s^(i) over slabs of P node layers along
+ *              the slowest axis (the inverses of its Schur blocks and the slab
+ *              couplings), applied by forward and backward sweeps: far fewer
+ *              bytes for large subdomains, two launches per slab.
+ *   AUTO picks by modelled time (bytes over bandwidth plus launches). */
+typedef enum {
+  TH_LAYOUT_AUTO = 0, TH_LAYOUT_DENSE = 1, TH_LAYOUT_SYMMETRIC = 2, TH_LAYOUT_SLAB = 3
+} th_layout;
+
 /* Fine-level problem and smoother parameters (Sec. 2, 3.1, 4.1, 4.4). */
 typedef struct {
   int dim;              /* 2 or 3 (3-D: orders 2 and 4) */
@@ -99,6 +112,8 @@ typedef struct {
   double omega_c;       /* coarse-grid correction relaxation */
   th_gemm gemm;         /* storage of the subdomain operators */
   int max_rhs;          /* largest nrhs of any later call (sizes the workspaces) */
+  th_layout layout;     /* FP64/FP32 storage layout of the subdomain solves (0 = automatic);
+                           BF16 storage has the matrix-core layout only */
 } th_fine_desc;
 
 typedef struct {
@@ -144,7 +159,8 @@ typedef struct {
   double t_stencil_s;     /* time spent computing the per-cell coarse weights */
   int smoother_layout;    /* storage of the subdomain operators: 0 dense rows (FP64/FP32),
                              1 symmetric tiles (FP64/FP32; the U x U block of the symmetric
-                             inverse stored once), 2 matrix-core fragments (BF16) */
+                             inverse stored once), 2 matrix-core fragments (BF16),
+                             3 slab factors (FP64/FP32) */
 } th_info;
 
 /* Create a context on HIP device `hip_device`, ordering work on `hip_stream`
@@ -156,14 +172,14 @@ th_status th_get_info(const th_ctx *ctx, th_info *info);
 
 /* Build the fine operator data and the smoother (Sec. 4.1, Alg. 2): per-cell
  * coefficients, the subdomains U^(i) and Omega^(i) = U^(i) + one cell layer,
- * and for every subdomain the dense operator B_i = diag(1/L_j) R_{U_i}
- * (A_s^(i))^{-1} (n_U x n_Omega), computed on the device in FP64 and stored
- * in desc->gemm precision.  A_s^(i) is complex symmetric, so for FP64/FP32
- * storage the U x U block of its inverse is kept once (upper 64 x 64 tiles)
- * whenever that stores at most 80 % of the dense bytes (th_info.smoother_layout).
+ * and for every subdomain the data of its solve, computed on the device in
+ * FP64 and stored in desc->gemm precision: the dense operator B_i =
+ * diag(1/L_j) R_{U_i} (A_s^(i))^{-1} (n_U x n_Omega; for FP64/FP32 possibly
+ * with the U x U block of the symmetric inverse kept once), or the slab
+ * factors of A_s^(i) (th_layout; th_info.smoother_layout reports the choice).
  * Blocking.  Errors: TH_EINVAL (odd order, n < 1, k <= 0 or NaN, l_dd < 1, dim
- * not 2 or 3), TH_EUNSUPPORTED (3-D order above 4), TH_ENOMEM, TH_ENUMERIC
- * (zero pivot). */
+ * not 2 or 3, a layout other than AUTO with BF16 storage), TH_EUNSUPPORTED (3-D
+ * order above 4), TH_ENOMEM, TH_ENUMERIC (zero pivot). */
 th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *desc);
 
 /* Build the coarse QSFEM quasi-FE matrix (Sec. 3.3, eq. element_wise_qsfem;

@@ -46,6 +46,9 @@ def load_library():
 
 _BC = {"robin": L.TH_BC_ROBIN, "neumann": L.TH_BC_NEUMANN, "dirichlet": L.TH_BC_DIRICHLET}
 _GEMM = {"f64": L.TH_GEMM_F64, "f32": L.TH_GEMM_F32, "bf16": L.TH_GEMM_BF16}
+_LAYOUT = {None: L.TH_LAYOUT_AUTO, "auto": L.TH_LAYOUT_AUTO, "dense": L.TH_LAYOUT_DENSE,
+           "symmetric": L.TH_LAYOUT_SYMMETRIC, "slab": L.TH_LAYOUT_SLAB}
+LAYOUT_NAMES = {0: "dense", 1: "symmetric", 2: "matrix-core", 3: "slab"}
 
 
 def _dt(t: torch.Tensor) -> int:
@@ -60,7 +63,9 @@ class TwoGridSolver:
     """One fine problem (unit square or cube, N^d cells, order p) on one GPU.
 
     k, eps: per-cell arrays of shape (N, N) indexed [y][x], or (N, N, N)
-    indexed [z][y][x] (host, float64); bc lists the sides x-, x+, y-, y+(, z-, z+).
+    indexed [z][y][x] (host, float64); bc lists the sides x-, x+, y-, y+(, z-, z+),
+    each "robin" (absorbing), "neumann" or "dirichlet".  layout: storage of the
+    FP64/FP32 subdomain solves ("dense", "symmetric", "slab"; None = automatic).
     Vectors are torch tensors on the solver's device of shape (nrhs, ndof)
     (or (ndof,) for one right-hand side), complex128 or complex64, contiguous.
     """
@@ -68,7 +73,7 @@ class TwoGridSolver:
     def __init__(self, k, eps=None, order: int = 2, alpha_s: float = 0.5, l_dd: int = 8,
                  n_dd: int = 1, n_s: int = 1, omega_c: float = 1.0, bc=None,
                  gemm: str = "f64", max_rhs: int = 1, device: int | None = None,
-                 coarse: str | None = "qsfem", coarse_q=None):
+                 coarse: str | None = "qsfem", coarse_q=None, layout: str | None = None):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
@@ -110,6 +115,7 @@ class TwoGridSolver:
             d.alpha_s, d.l_dd, d.n_dd, d.n_s, d.omega_c = alpha_s, l_dd, n_dd, n_s, omega_c
             d.gemm = _GEMM[gemm]
             d.max_rhs = self.max_rhs
+            d.layout = _LAYOUT[layout]
             self._check(self._lib.th_setup_fine(self._h, C.byref(d)))
             if coarse is not None:
                 self.setup_coarse(coarse, coarse_q)

@@ -14,6 +14,7 @@ TH_OK, TH_EINVAL, TH_ESTATE, TH_ENOMEM, TH_EHIP, TH_ENOTCONV, TH_ENUMERIC, TH_EU
 STATUS_NAMES = {0: "TH_OK", -1: "TH_EINVAL", -2: "TH_ESTATE", -3: "TH_ENOMEM", -4: "TH_EHIP",
                 -5: "TH_ENOTCONV", -6: "TH_ENUMERIC", -7: "TH_EUNSUPPORTED"}
 TH_BC_ROBIN, TH_BC_NEUMANN, TH_BC_DIRICHLET = 0, 1, 2
+TH_LAYOUT_AUTO, TH_LAYOUT_DENSE, TH_LAYOUT_SYMMETRIC, TH_LAYOUT_SLAB = 0, 1, 2, 3
 TH_C128, TH_C64 = 0, 1
 TH_GEMM_F64, TH_GEMM_F32, TH_GEMM_BF16 = 0, 1, 2
 TH_COARSE_QSFEM, TH_COARSE_WEIGHTS, TH_COARSE_PLAINFIT, TH_COARSE_MLP = 0, 1, 2, 3
@@ -26,7 +27,7 @@ class FineDesc(C.Structure):
                 ("k", C.POINTER(C.c_double)), ("eps", C.POINTER(C.c_double)),
                 ("bc", C.c_int * 6), ("alpha_s", C.c_double), ("l_dd", C.c_int),
                 ("n_dd", C.c_int), ("n_s", C.c_int), ("omega_c", C.c_double),
-                ("gemm", C.c_int), ("max_rhs", C.c_int)]
+                ("gemm", C.c_int), ("max_rhs", C.c_int), ("layout", C.c_int)]
 
 
 class CoarseDesc(C.Structure):

@@ -118,7 +118,7 @@ static void free_graphs(th_ctx *c) {
 static void free_fine(th_ctx *c) {
   void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,  c->d_subs, c->d_nblk, c->d_B, c->w_r,
                   c->w_v,   c->w_rr,   c->w_y,  c->w_rc,   c->w_uc,   c->w_t, c->w_rc32,
-                  c->d_eidx, c->w_p, c->w_x};
+                  c->d_eidx, c->w_p, c->w_x, c->w_z};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_kap = c->d_kaps = nullptr;
@@ -127,7 +127,8 @@ static void free_fine(th_ctx *c) {
   c->d_nblk = nullptr;
   c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = c->w_rc32 = nullptr;
   c->d_eidx = nullptr;
-  c->w_p = c->w_x = nullptr;
+  c->w_p = c->w_x = c->w_z = nullptr;
+  c->max_nsl = c->max_slab_rows = 0;
   c->fine_ready = false;
 }
 
@@ -247,6 +248,10 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return fail(ctx, TH_EINVAL, "alpha_s must be finite and >= 0, omega_c finite");
   if (d->gemm != TH_GEMM_F64 && d->gemm != TH_GEMM_F32 && d->gemm != TH_GEMM_BF16)
     return fail(ctx, TH_EINVAL, "unknown subdomain operator storage");
+  if (d->layout < TH_LAYOUT_AUTO || d->layout > TH_LAYOUT_SLAB)
+    return fail(ctx, TH_EINVAL, "unknown subdomain solve layout");
+  if (d->gemm == TH_GEMM_BF16 && d->layout != TH_LAYOUT_AUTO)
+    return fail(ctx, TH_EINVAL, "BF16 storage has the matrix-core layout only");
   for (int sd = 0; sd < 2 * d->dim; ++sd)
     if (d->bc[sd] != TH_BC_ROBIN && d->bc[sd] != TH_BC_NEUMANN && d->bc[sd] != TH_BC_DIRICHLET)
       return fail(ctx, TH_EINVAL, "boundary condition must be Robin, Neumann or Dirichlet");
@@ -348,24 +353,57 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
         }
         s.nrb = (s.nU + kSymTile - 1) / kSymTile;
         s.neb = (s.nOm - s.nU + kSymTile - 1) / kSymTile;
+        s.nsl = c->dim == 3 ? s.o1z - s.o0z : s.o1y - s.o0y;
+        s.lsz = c->dim == 3 ? s.nox * s.noy : s.nox;
         s.yoff = yoff;
         yoff += s.nU;
         max_ldb = std::max(max_ldb, s.ldb);
         max_nom = std::max(max_nom, s.nOm);
         c->subs.push_back(s);
       }
-  // storage layout: the symmetric tiles (U x U block of the symmetric inverse
-  // stored once) when they need at most 80 % of the dense bytes
+  // storage layout.  Explicit inverse rows: the symmetric tiles (U x U block
+  // of the symmetric inverse stored once) when they need at most 80 % of the
+  // dense bytes.  Slab factors instead when their modelled apply time (twice
+  // their bytes, plus two launches per slab) is lower.
   auto sym_elems = [](const Sub &s) {
     return ((long long)s.nrb * (s.nrb + 1) / 2 + (long long)s.nrb * s.neb) * kSymTile * kSymTile;
   };
+  const int cband = (c->dim == 3 ? (2 * P + 1) * (2 * P + 1) : 2 * P + 1) * P;
+  auto slab_elems = [&](const Sub &s) {
+    const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
+    return (long long)(s.nsl - 1) * m * m + ml * ml + (long long)(s.nsl - 1) * s.lsz * cband;
+  };
   {
-    long long dense = 0, sym = 0;
+    long long dense = 0, sym = 0, slab = 0;
+    int nsl = 0;
     for (const Sub &s : c->subs) {
       dense += (long long)s.nOm * s.ldb;
       sym += sym_elems(s);
+      slab += slab_elems(s);
+      nsl = std::max(nsl, s.nsl);
     }
-    c->layout = (d->gemm == TH_GEMM_BF16) ? 2 : (10 * sym <= 8 * dense ? 1 : 0);
+    // modelled streaming rates (bytes/s) of the three apply paths, 8 us per launch
+    const double es = d->gemm == TH_GEMM_F32 ? 8.0 : 16.0;
+    const int rows = 10 * sym <= 8 * dense ? 1 : 0;
+    const double t_rows = rows == 1 ? es * sym / 5.5e12 : es * dense / 6.5e12;
+    const double t_slab = 2.0 * es * slab / 4.0e12 + 2.0 * nsl * 8e-6;
+    // the sweeps keep a slab's right-hand sides in 48 KiB of LDS (complex128)
+    int max_lsz = 0;
+    for (const Sub &s : c->subs) max_lsz = std::max(max_lsz, s.lsz);
+    const bool slab_fits = (long long)(P + 1) * max_lsz * 16 <= 48 * 1024;
+    if (d->gemm == TH_GEMM_BF16)
+      c->layout = 2;
+    else if (d->layout == TH_LAYOUT_DENSE)
+      c->layout = 0;
+    else if (d->layout == TH_LAYOUT_SYMMETRIC)
+      c->layout = 1;
+    else if (d->layout == TH_LAYOUT_SLAB && !slab_fits) {
+      free_fine(c);
+      return fail(ctx, TH_EUNSUPPORTED, "subdomain slabs too large for the slab layout");
+    } else if (d->layout == TH_LAYOUT_SLAB)
+      c->layout = 3;
+    else
+      c->layout = slab_fits && t_slab < t_rows ? 3 : rows;
   }
   std::vector<int> eidx;
   long long poff = 0, xoff = 0;
@@ -373,8 +411,16 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   for (Sub &s : c->subs) {
     s.boff = boff;
     // element offsets: complex entries (F64/F32) or bf16 values (matrix-core layout)
-    boff += c->layout == 2 ? mfma_store_elems(s)
-                           : (c->layout == 1 ? sym_elems(s) : (long long)s.nOm * s.ldb);
+    if (c->layout == 3) {
+      const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
+      s.coff = boff + (long long)(s.nsl - 1) * m * m + ml * ml;
+      boff += slab_elems(s);
+      c->max_nsl = std::max(c->max_nsl, s.nsl);
+      c->max_slab_rows = std::max(c->max_slab_rows, (int)ml);
+    } else {
+      boff += c->layout == 2 ? mfma_store_elems(s)
+                             : (c->layout == 1 ? sym_elems(s) : (long long)s.nOm * s.ldb);
+    }
     s.eoff = (long long)eidx.size();
     s.poff = poff;
     s.xoff = xoff;
@@ -395,6 +441,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
       poff += (long long)s.nrb * (s.nrb + 1) / 2 * kSymTile;
       xoff += s.nOm;
       c->max_pairs = std::max(c->max_pairs, (s.nrb + 1) / 2);
+    } else if (c->layout == 3) {
+      xoff += s.nOm;
     }
   }
   c->p_rows = poff;
@@ -427,6 +475,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
             alloc(&c->w_y, R * c->y_rows * sizeof(c64));
   if (ok && d->n_dd > 1)
     ok = alloc(&c->w_v, R * c->nf * sizeof(c64)) && alloc(&c->w_rr, R * c->nf * sizeof(c64));
+  if (ok && c->layout == 3) ok = alloc(&c->w_z, R * c->x_rows * sizeof(c64));
   if (!ok) {
     free_fine(c);
     return fail(ctx, TH_ENOMEM, "device allocation failed in setup_fine");

@@ -33,7 +33,12 @@ struct Sub {
   int nrb, neb;
   long long eoff;             // offset of the ring node list (Omega-local indices)
   long long poff;             // offset of the transposed-tile partials
-  long long xoff;             // offset of the gathered patch (U nodes, then ring nodes)
+  long long xoff;             // offset of the gathered patch (U nodes, then ring nodes; the
+                              // slab layout: Omega-local order)
+  // slab-factor layout: slabs of P node layers along the slowest axis (y in
+  // 2-D, z in 3-D), nodes per layer, and the offset of the coupling bands
+  int nsl, lsz;
+  long long coff;
 };
 
 constexpr int kSymTile = 64;
@@ -130,6 +135,9 @@ struct th_ctx {
 
   // subdomains
   int dir = 0;                 // bit s: Dirichlet on global side s
+  int max_nsl = 0;             // slab layout: most slabs of a subdomain
+  int max_slab_rows = 0;       // slab layout: largest slab
+  void *w_z = nullptr;         // slab layout: per-subdomain solutions [R][x_rows]
   int M = 0;                   // blocks per direction
   std::vector<int> blk_start;  // M+1 cell starts
   std::vector<th::Sub> subs;
@@ -137,7 +145,8 @@ struct th_ctx {
   int *d_nblk = nullptr;       // per node index along an axis: first block, count (2 ints)
   void *d_B = nullptr;         // operator store (layout depends on gemm)
   long long b_entries = 0, b_bytes = 0, y_rows = 0;
-  int layout = 0;              // 0 dense 64-row blocks, 1 symmetric tiles, 2 matrix-core BF16
+  int layout = 0;              // 0 dense 64-row blocks, 1 symmetric tiles, 2 matrix-core BF16,
+                               // 3 slab factors
   int *d_eidx = nullptr;       // ring node lists (symmetric layout)
   long long p_rows = 0;        // partial-sum rows per right-hand side (symmetric layout)
   long long x_rows = 0;        // gathered patch rows per right-hand side (symmetric layout)
@@ -225,6 +234,11 @@ int launch_prolong(int dim, int N, int P, int dir, const Ref1D &ref, const void 
 
 // k_smoother.hip
 int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);
+// k_slab.hip: the slab-factor layout (apply, and its setup from the assembled
+// subdomain matrices of one batch)
+int launch_dd_slab(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);
+int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat, c64 *W0,
+                       c64 *W1, c64 *T1, int ldw, int ldt, c64 *pws, hipStream_t s);
 int launch_dd_accumulate(const th_ctx *c, const void *y, void *u, int nrhs, bool f32, bool assign,
                          hipStream_t s);
 

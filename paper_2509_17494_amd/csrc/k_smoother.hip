@@ -288,6 +288,7 @@ static int dd_apply_t(const th_ctx *c, const void *r, void *y, int nrhs, hipStre
 }
 
 int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s) {
+  if (c->layout == 3) return launch_dd_slab(c, r, y, nrhs, f32, s);
   switch (c->desc.gemm) {
     case TH_GEMM_BF16:
       return launch_dd_mfma(c, r, y, nrhs, f32, c->mfma_cfg, c->mfma_grid, s);
