@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dd_apply_traffic.json")
 # sources of the batched subdomain apply kernel (its file and the headers it uses)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2509_17494_amd", "csrc", f)
-               for f in ("k_smoother.hip", "common.hpp", "ctx.hpp")]
+               for f in ("k_smoother.hip", "k_slab.hip", "common.hpp", "ctx.hpp")]
 
 
 def kernel_sources_sha256():
@@ -104,6 +104,34 @@ def subdomain_sizes(N, p, l_dd, dim=2):
     for idx in itertools.product(range(M), repeat=dim):
         out.append((math.prod(nu1[b] for b in idx), math.prod(no1[b] for b in idx)))
     return out
+
+
+def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes):
+    """Algorithmic bytes and flops of one application in the slab-factor
+    layout: every stored G_t and coupling band read by the forward sweep, every
+    E_t (rows of slab t x first layer of slab t + 1) by the backward sweep, and
+    the patch X_i and the output rows Y_i once per right-hand side."""
+    import itertools
+    import math
+    M = math.ceil(N / l_dd)
+    base, rem = divmod(N, M)
+    sizes = [base + 1] * rem + [base] * (M - rem)
+    starts = [0]
+    for x in sizes:
+        starts.append(starts[-1] + x)
+    ocells = [min(starts[b + 1] + 1, N) - max(starts[b] - 1, 0) for b in range(M)]
+    cb = ((2 * p + 1) ** (dim - 1)) * p
+    g_entries, band_entries, vec = 0, 0, 0
+    for idx in itertools.product(range(M), repeat=dim):
+        no = [ocells[b] * p + 1 for b in idx]      # x first
+        nu = [sizes[b] * p + 1 for b in idx]
+        nsl, lsz = ocells[idx[-1]], math.prod(no[:-1])
+        m, ml = p * lsz, (p + 1) * lsz
+        g_entries += (nsl - 1) * m * m + ml * ml + (nsl - 1) * m * lsz  # G_t, then E_t
+        band_entries += (nsl - 1) * lsz * cb
+        vec += math.prod(no) + math.prod(nu)
+    byts = (g_entries + band_entries) * mat_bytes + vec * vec_bytes * nrhs
+    return byts, 8.0 * (g_entries + band_entries) * nrhs
 
 
 def traffic_entry(workload_name):
@@ -251,6 +279,8 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
     sym = info["smoother_layout"] == 1
     alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes, symmetric=sym)
     flops = 8.0 * sum(nu * no for nu, no in subs) * R
+    if info["smoother_layout"] == 3:
+        alg, flops = slab_apply_bytes(N, p, spec["l_dd"], dim, R, mat_bytes, vec_bytes)
     dd_ms, dd_n = kt["dd_apply"]
     avg_ms = dd_ms / max(dd_n, 1)
     res = {
@@ -259,7 +289,7 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         "ms_per_step": elapsed / steps * 1e3, "gmres_iters": iters[-1], "max_rel_res": worst,
         "setup_s": t_setup, "info": info,
         "kernel_ms_per_step": {k: round(v[0] / ksteps, 4) for k, v in kt.items()},
-        "layout": ["dense", "symmetric", "matrix-core"][info["smoother_layout"]],
+        "layout": ["dense", "symmetric", "matrix-core", "slab"][info["smoother_layout"]],
         "dd": {"alg_bytes": alg, "flops": flops, "avg_ms": avg_ms, "launches": dd_n,
                "gbs": alg / (avg_ms * 1e-3) / 1e9, "tflops": flops / (avg_ms * 1e-3) / 1e12},
         "desc": f"{name}: {dim}-D Q{p}, {N}^{dim} cells ({info['n_fine']} DOF), {R} RHS, "
@@ -341,7 +371,9 @@ def main():
     roof = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": {"dense": "k_dd_apply", "symmetric": "k_dd_sym + k_dd_symred",
-                       "matrix-core": "k_dd_mfma"}[prim["layout"]],
+                       "matrix-core": "k_dd_mfma",
+                       "slab": "k_slab_gather + k_slab_fwd + k_slab_bwd + k_slab_extract "
+                               "(one smoother application)"}[prim["layout"]],
             "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": round(d["avg_ms"], 4),
             "launches": d["launches"]}
     info = prim["info"]

@@ -369,9 +369,10 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return ((long long)s.nrb * (s.nrb + 1) / 2 + (long long)s.nrb * s.neb) * kSymTile * kSymTile;
   };
   const int cband = (c->dim == 3 ? (2 * P + 1) * (2 * P + 1) : 2 * P + 1) * P;
-  auto slab_elems = [&](const Sub &s) {
+  auto slab_elems = [&](const Sub &s) {  // G_t, bands, E_t
     const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
-    return (long long)(s.nsl - 1) * m * m + ml * ml + (long long)(s.nsl - 1) * s.lsz * cband;
+    return (long long)(s.nsl - 1) * m * m + ml * ml + (long long)(s.nsl - 1) * s.lsz * cband +
+           (long long)(s.nsl - 1) * s.lsz * m;
   };
   {
     long long dense = 0, sym = 0, slab = 0;
@@ -386,11 +387,11 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     const double es = d->gemm == TH_GEMM_F32 ? 8.0 : 16.0;
     const int rows = 10 * sym <= 8 * dense ? 1 : 0;
     const double t_rows = rows == 1 ? es * sym / 5.5e12 : es * dense / 6.5e12;
-    const double t_slab = 2.0 * es * slab / 4.0e12 + 2.0 * nsl * 8e-6;
-    // the sweeps keep a slab's right-hand sides in 48 KiB of LDS (complex128)
+    const double t_slab = es * slab / 4.0e12 + 2.0 * nsl * 8e-6;
+    // the sweeps keep a slab's right-hand sides and 256 partial sums in 48 KiB of LDS
     int max_lsz = 0;
     for (const Sub &s : c->subs) max_lsz = std::max(max_lsz, s.lsz);
-    const bool slab_fits = (long long)(P + 1) * max_lsz * 16 <= 48 * 1024;
+    const bool slab_fits = ((long long)(P + 1) * max_lsz + 256) * 16 <= 48 * 1024;
     if (d->gemm == TH_GEMM_BF16)
       c->layout = 2;
     else if (d->layout == TH_LAYOUT_DENSE)
@@ -414,6 +415,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     if (c->layout == 3) {
       const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
       s.coff = boff + (long long)(s.nsl - 1) * m * m + ml * ml;
+      s.ecoff = s.coff + (long long)(s.nsl - 1) * s.lsz * cband;
       boff += slab_elems(s);
       c->max_nsl = std::max(c->max_nsl, s.nsl);
       c->max_slab_rows = std::max(c->max_slab_rows, (int)ml);

@@ -38,7 +38,8 @@ struct Sub {
   // slab-factor layout: slabs of P node layers along the slowest axis (y in
   // 2-D, z in 3-D), nodes per layer, and the offset of the coupling bands
   int nsl, lsz;
-  long long coff;
+  long long coff;             // coupling bands (slab layout)
+  long long ecoff;            // backward products E_t (slab layout)
 };
 
 constexpr int kSymTile = 64;

@@ -10,14 +10,15 @@
 // (A_s^(i) is complex symmetric, so the upper coupling is L_t^T), and the
 // apply is
 //   forward   y_t = G_t (r_t - L_t y_{t-1})
-//   backward  x_t = y_t - G_t L_{t+1}^T x_{t+1}[first layer of t + 1],
+//   backward  x_t = y_t - E_t x_{t+1}[first layer of t + 1],  E_t = G_t L_{t+1}^T,
 // one launch per slab for all subdomains.  Stored per subdomain: every G_t
 // transposed (entry (b, a) at b m_t + a, so one output row per thread reads
-// consecutive entries of a row), then the couplings L_t of every slab t >= 1
-// as bands: for each first-layer node a the (2P+1)^(d-1) x P block of slab
-// t - 1 nodes within P positions of a in every in-layer direction (zero where a
-// node lies outside Omega or shares no cell with a).  The bytes per
-// application are twice the G_t (forward and backward) instead of the
+// consecutive entries of a row); the couplings L_t of every slab t >= 1 as
+// bands: for each first-layer node a the (2P+1)^(d-1) x P block of slab t - 1
+// nodes within P positions of a in every in-layer direction (zero where a node
+// lies outside Omega or shares no cell with a); and every E_t (m_t x n_layer,
+// the product the elimination forms anyway) transposed.  The bytes per
+// application are the G_t plus the E_t (a fraction 1/P of them) instead of the
 // n_U x n_Omega rows of an explicit inverse.  Elimination without pivoting is
 // stable here for the reason given for the Gauss-Jordan inverses: i A_s^(i)
 // has a positive definite Hermitian part, which every Schur complement keeps
@@ -146,6 +147,22 @@ __global__ __launch_bounds__(256) void k_slab_store(const Sub *__restrict__ subs
   }
 }
 
+// store E_{t-1} = T1 (rows of slab t - 1, columns: first layer of slab t) transposed
+template <typename TB>
+__global__ __launch_bounds__(256) void k_slab_store_e(const Sub *__restrict__ subs, int s0,
+                                                      const c64 *__restrict__ T1, int ldt,
+                                                      long long tmat, cx<TB> *__restrict__ B, int t,
+                                                      int P) {
+  const Sub s = subs[s0 + blockIdx.z];
+  if (t >= s.nsl) return;
+  const int mp = P * s.lsz;
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)s.lsz * mp) return;
+  const int cc = (int)(e / mp), r = (int)(e % mp);
+  const c64 v = T1[blockIdx.z * tmat + (long long)r * ldt + cc];
+  B[s.ecoff + (long long)(t - 1) * s.lsz * mp + e] = cx<TB>{(TB)v.re, (TB)v.im};
+}
+
 int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat, c64 *W0,
                        c64 *W1, c64 *T1, int ldw, int ldt, c64 *pws, hipStream_t s) {
   const int P = c->P;
@@ -170,6 +187,13 @@ int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long l
       hipLaunchKernelGGL(k_slab_schur, dim3((unsigned)ceil_div_ll(max_lsz * max_lsz, 256), 1, nb),
                          dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)T1, ldt,
                          tmat, W, ldw, wmat, t, P);
+      const dim3 ge((unsigned)ceil_div_ll((long long)P * max_lsz * max_lsz, 256), 1, nb);
+      if (c->desc.gemm == TH_GEMM_F32)
+        hipLaunchKernelGGL((k_slab_store_e<float>), ge, dim3(256), 0, s, c->d_subs, s0,
+                           (const c64 *)T1, ldt, tmat, (cx<float> *)c->d_B, t, P);
+      else
+        hipLaunchKernelGGL((k_slab_store_e<double>), ge, dim3(256), 0, s, c->d_subs, s0,
+                           (const c64 *)T1, ldt, tmat, (cx<double> *)c->d_B, t, P);
     }
     TH_HIP_CHECK_RET(hipGetLastError());
     int rc = gj_invert_batched(W, ldw, ldw, wmat, nb, s, pws);
@@ -205,18 +229,66 @@ __global__ __launch_bounds__(256) void k_slab_gather(const Sub *__restrict__ sub
   Z[q * xrows + s.xoff + k] = r[q * nf + om_node(s, k, P, n1)];
 }
 
+// acc[q] = sum_b G^T[b][a] x[b][q] for the output row a of the thread: g points
+// at entry (0, a) of the stored G_t^T (m x m); loads in batches of kRowsInFlight
+// rows, all issued before their use.
+constexpr int kRowsInFlight = 16;
+
+template <typename TB, typename T, int RC>
+__device__ __forceinline__ void slab_gemv_row(const cx<TB> *__restrict__ g, int m, int b0, int b1,
+                                              const cx<T> *__restrict__ x, cx<T> (&acc)[RC]) {
+  constexpr int U = kRowsInFlight;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
+  for (int b = b0; b < b1; b += U) {
+    cx<T> gv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      gv[u] = b + u < b1 ? ccast<T>(ld_stream(g + (long long)(b + u) * m)) : cx<T>{0, 0};
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (b + u < b1)
+#pragma unroll
+        for (int q = 0; q < RC; ++q) cmac(acc[q], gv[u], x[(b + u) * RC + q]);
+  }
+}
+
+// The four wavefronts of a workgroup share its 64 output rows and split the
+// rows b of G_t^T in quarters; their partial sums are added in wavefront order
+// through LDS (red: 4 x 64 x RC) by the first wavefront, which returns them in
+// acc (other wavefronts return false).
+template <typename T, int RC>
+__device__ __forceinline__ bool slab_sum_waves(cx<T> (&acc)[RC], cx<T> *__restrict__ red) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) red[(wave * 64 + lane) * RC + q] = acc[q];
+  __syncthreads();
+  if (wave != 0) return false;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) {
+    cx<T> v = red[lane * RC + q];
+    for (int w = 1; w < 4; ++w) v = v + red[(w * 64 + lane) * RC + q];
+    acc[q] = v;
+  }
+  return true;
+}
+
 // Forward step of slab t for all subdomains and RC right-hand sides: the
 // right-hand side r_t - L_t y_{t-1} is formed in LDS by every workgroup of the
-// subdomain; each thread then owns one row a of the slab (64 rows per
-// workgroup) and reads row b of the stored G_t^T for b = 0 .. m - 1.
-template <typename TB, typename T, int RC>
-__global__ __launch_bounds__(64) void k_slab_fwd(const Sub *__restrict__ subs,
+// subdomain (the band loops unrolled, so their loads are issued together);
+// a workgroup then covers 64 rows a of the slab, one per lane, its four
+// wavefronts reading a quarter each of the rows b of the stored G_t^T.
+// LDS: the slab's right-hand sides [ldx][RC], then the partial sums.
+template <typename TB, typename T, int RC, int P, int DIM>
+__global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
                                                  const cx<TB> *__restrict__ B,
                                                  const cx<T> *__restrict__ Z,
                                                  cx<T> *__restrict__ V, long long xrows,
-                                                 int nrhs, int t, int P, int dim) {
+                                                 int nrhs, int t, int ldx) {
+  constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
   extern __shared__ __align__(16) char slab_smem[];
-  cx<T> *x = (cx<T> *)slab_smem;  // [m][RC]
+  cx<T> *x = (cx<T> *)slab_smem;
+  cx<T> *red = x + (long long)ldx * RC;
   const Sub s = subs[blockIdx.x];
   if (t >= s.nsl) return;  // uniform
   const int m = slab_rows(s, t, P);
@@ -224,107 +296,82 @@ __global__ __launch_bounds__(64) void k_slab_fwd(const Sub *__restrict__ subs,
   if (a0 >= m) return;  // uniform
   const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
   const long long row0 = (long long)t * P * s.lsz;
-  const int cb = band_width(P, dim);
-  const cx<TB> *Ct = B + s.coff + (long long)(t - 1) * s.lsz * cb;
-  for (int j = threadIdx.x; j < m; j += 64) {
+  const cx<TB> *Ct = B + s.coff + (long long)(t - 1) * s.lsz * CB;
+  for (int j = threadIdx.x; j < m; j += 256) {
+    cx<T> v[RC];
 #pragma unroll
-    for (int q = 0; q < RC; ++q) {
-      cx<T> v = {0, 0};
-      if (q < nq) {
-        const long long base = (long long)(r0 + q) * xrows + s.xoff;
-        v = Z[base + row0 + j];
-        if (t > 0 && j < s.lsz) {
-          const cx<TB> *cr = Ct + (long long)j * cb;
-          for (int k = 0; k < cb; ++k) {
-            const int col = band_col(s, t, j, k, P, dim);
-            if (col >= 0) {
-              const cx<TB> l = cr[k];
-              const cx<T> y = V[base + col];
-              v.re -= (T)l.re * y.re - (T)l.im * y.im;
-              v.im -= (T)l.re * y.im + (T)l.im * y.re;
+    for (int q = 0; q < RC; ++q)
+      v[q] = q < nq ? Z[(long long)(r0 + q) * xrows + s.xoff + row0 + j] : cx<T>{0, 0};
+    if (t > 0 && j < s.lsz) {
+      const int xa = j % s.nox, ya = DIM == 3 ? j / s.nox : 0;
+      const cx<TB> *cr = Ct + (long long)j * CB;
+#pragma unroll
+      for (int jy = 0; jy < (DIM == 3 ? W2 : 1); ++jy) {
+        const int yb = DIM == 3 ? ya - P + jy : 0;
+        const bool oky = DIM == 3 ? (yb >= 0 && yb < s.noy) : true;
+#pragma unroll
+        for (int jx = 0; jx < W2; ++jx) {
+          const int xb = xa - P + jx;
+          if (!oky || xb < 0 || xb >= s.nox) continue;
+#pragma unroll
+          for (int lb = 0; lb < P; ++lb) {
+            const int col = ((t - 1) * P + lb) * s.lsz + yb * s.nox + xb;
+            const cx<TB> l = cr[(jy * W2 + jx) * P + lb];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+              if (q >= nq) continue;
+              const cx<T> y = V[(long long)(r0 + q) * xrows + s.xoff + col];
+              v[q].re -= (T)l.re * y.re - (T)l.im * y.im;
+              v[q].im -= (T)l.re * y.im + (T)l.im * y.re;
             }
           }
         }
       }
-      x[j * RC + q] = v;
     }
+#pragma unroll
+    for (int q = 0; q < RC; ++q) x[j * RC + q] = v[q];
   }
   __syncthreads();
-  const int a = a0 + threadIdx.x;
-  if (a >= m) return;
-  const cx<TB> *g = B + slab_goff(s, t, P) + a;
+  const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int bq = (m + 3) / 4;
   cx<T> acc[RC];
-#pragma unroll
-  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-#pragma unroll 8
-  for (int b = 0; b < m; ++b) {
-    const cx<T> gv = ccast<T>(ld_stream(g + (long long)b * m));
-#pragma unroll
-    for (int q = 0; q < RC; ++q) cmac(acc[q], gv, x[b * RC + q]);
-  }
+  slab_gemv_row<TB, T, RC>(B + slab_goff(s, t, P) + min(a, m - 1), m, min(wave * bq, m),
+                           min((wave + 1) * bq, m), x, acc);
+  if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
     if (q < nq) V[(long long)(r0 + q) * xrows + s.xoff + row0 + a] = acc[q];
 }
 
-// Backward step of slab t < nsl - 1: w = L_{t+1}^T x_{t+1}[first layer] in LDS
-// (for a node b of slab t the first-layer nodes of slab t + 1 within P
-// positions, read from their coupling bands), then x_t = y_t - G_t w.
+// Backward step of slab t < nsl - 1: x_t = y_t - E_t w with w = x_{t+1} on
+// the first layer of slab t + 1 (staged in LDS), the same division of work
+// as the forward step over the n_layer rows of the stored E_t^T.
 template <typename TB, typename T, int RC>
-__global__ __launch_bounds__(64) void k_slab_bwd(const Sub *__restrict__ subs,
+__global__ __launch_bounds__(256) void k_slab_bwd(const Sub *__restrict__ subs,
                                                  const cx<TB> *__restrict__ B,
                                                  cx<T> *__restrict__ V, long long xrows, int nrhs,
-                                                 int t, int P, int dim) {
+                                                 int t, int ldx, int P) {
   extern __shared__ __align__(16) char slab_smem[];
-  cx<T> *w = (cx<T> *)slab_smem;  // [m][RC]
+  cx<T> *w = (cx<T> *)slab_smem;
+  cx<T> *red = w + (long long)ldx * RC;
   const Sub s = subs[blockIdx.x];
   if (t >= s.nsl - 1) return;  // uniform
-  const int m = P * s.lsz;
+  const int m = P * s.lsz, nl = s.lsz;
   const int a0 = blockIdx.y * 64;
   if (a0 >= m) return;  // uniform
   const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
   const long long row0 = (long long)t * P * s.lsz, rn = (long long)(t + 1) * P * s.lsz;
-  const int cb = band_width(P, dim);
-  const int W2 = 2 * P + 1;
-  const cx<TB> *Cn = B + s.coff + (long long)t * s.lsz * cb;  // couplings of slab t + 1
-  for (int j = threadIdx.x; j < m; j += 64) {
-    const int lb = j / s.lsz, ib = j % s.lsz;
-    const int xb = ib % s.nox, yb = dim == 3 ? ib / s.nox : 0;
+  for (int j = threadIdx.x; j < nl; j += 256)
 #pragma unroll
-    for (int q = 0; q < RC; ++q) {
-      cx<T> v = {0, 0};
-      if (q < nq) {
-        const long long base = (long long)(r0 + q) * xrows + s.xoff + rn;
-        for (int jy = 0; jy < (dim == 3 ? W2 : 1); ++jy) {
-          const int ya = dim == 3 ? yb + P - jy : 0;  // jy = yb - ya + P
-          if (ya < 0 || (dim == 3 && ya >= s.noy)) continue;
-          for (int jx = 0; jx < W2; ++jx) {
-            const int xa = xb + P - jx;  // jx = xb - xa + P
-            if (xa < 0 || xa >= s.nox) continue;
-            const int a = ya * s.nox + xa;
-            const cx<TB> l = Cn[(long long)a * cb + (jy * W2 + jx) * P + lb];
-            const cx<T> xv = V[base + a];
-            v.re += (T)l.re * xv.re - (T)l.im * xv.im;
-            v.im += (T)l.re * xv.im + (T)l.im * xv.re;
-          }
-        }
-      }
-      w[j * RC + q] = v;
-    }
-  }
+    for (int q = 0; q < RC; ++q)
+      w[j * RC + q] = q < nq ? V[(long long)(r0 + q) * xrows + s.xoff + rn + j] : cx<T>{0, 0};
   __syncthreads();
-  const int a = a0 + threadIdx.x;
-  if (a >= m) return;
-  const cx<TB> *g = B + slab_goff(s, t, P) + a;
+  const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int cq = (nl + 3) / 4;
   cx<T> acc[RC];
-#pragma unroll
-  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-#pragma unroll 8
-  for (int b = 0; b < m; ++b) {
-    const cx<T> gv = ccast<T>(ld_stream(g + (long long)b * m));
-#pragma unroll
-    for (int q = 0; q < RC; ++q) cmac(acc[q], gv, w[b * RC + q]);
-  }
+  slab_gemv_row<TB, T, RC>(B + s.ecoff + (long long)t * nl * m + min(a, m - 1), m,
+                           min(wave * cq, nl), min((wave + 1) * cq, nl), w, acc);
+  if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
     if (q < nq) {
@@ -351,19 +398,37 @@ __global__ __launch_bounds__(256) void k_slab_extract(const Sub *__restrict__ su
   Y[q * yrows + s.yoff + j] = cx<T>{v.re * invL, v.im * invL};
 }
 
-template <typename TB, typename T, int RC>
-static int slab_sweeps_t(const th_ctx *c, int nrhs, hipStream_t s) {
+template <typename TB, typename T, int RC, int P, int DIM>
+static int slab_sweeps_pd(const th_ctx *c, int nrhs, hipStream_t s) {
   const unsigned nsub = (unsigned)c->subs.size();
-  const size_t shm = (size_t)c->max_slab_rows * RC * sizeof(cx<T>);
-  const dim3 grid(nsub, (unsigned)ceil_div(c->max_slab_rows, 64), (unsigned)ceil_div(nrhs, RC));
+  const int ldx = c->max_slab_rows;
+  const size_t shm = ((size_t)ldx + 256) * RC * sizeof(cx<T>);
+  const dim3 grid(nsub, (unsigned)ceil_div(ldx, 64), (unsigned)ceil_div(nrhs, RC));
   const cx<TB> *B = (const cx<TB> *)c->d_B;
   for (int t = 0; t < c->max_nsl; ++t)
-    hipLaunchKernelGGL((k_slab_fwd<TB, T, RC>), grid, dim3(64), shm, s, c->d_subs, B,
-                       (const cx<T> *)c->w_x, (cx<T> *)c->w_z, c->x_rows, nrhs, t, c->P, c->dim);
+    hipLaunchKernelGGL((k_slab_fwd<TB, T, RC, P, DIM>), grid, dim3(256), shm, s, c->d_subs, B,
+                       (const cx<T> *)c->w_x, (cx<T> *)c->w_z, c->x_rows, nrhs, t, ldx);
   for (int t = c->max_nsl - 2; t >= 0; --t)
-    hipLaunchKernelGGL((k_slab_bwd<TB, T, RC>), grid, dim3(64), shm, s, c->d_subs, B,
-                       (cx<T> *)c->w_z, c->x_rows, nrhs, t, c->P, c->dim);
+    hipLaunchKernelGGL((k_slab_bwd<TB, T, RC>), grid, dim3(256), shm, s, c->d_subs, B,
+                       (cx<T> *)c->w_z, c->x_rows, nrhs, t, ldx, P);
   return 0;
+}
+
+template <typename TB, typename T, int RC>
+static int slab_sweeps_t(const th_ctx *c, int nrhs, hipStream_t s) {
+  if (c->dim == 3) {
+    if (c->P == 2) return slab_sweeps_pd<TB, T, RC, 2, 3>(c, nrhs, s);
+    if (c->P == 4) return slab_sweeps_pd<TB, T, RC, 4, 3>(c, nrhs, s);
+  } else {
+    switch (c->P) {
+      case 2: return slab_sweeps_pd<TB, T, RC, 2, 2>(c, nrhs, s);
+      case 4: return slab_sweeps_pd<TB, T, RC, 4, 2>(c, nrhs, s);
+      case 6: return slab_sweeps_pd<TB, T, RC, 6, 2>(c, nrhs, s);
+      case 8: return slab_sweeps_pd<TB, T, RC, 8, 2>(c, nrhs, s);
+    }
+  }
+  set_error("unsupported order for the slab layout");
+  return TH_EUNSUPPORTED;
 }
 
 // right-hand sides per sweep pass: the slab's right-hand sides must fit in 48 KiB of LDS
@@ -373,7 +438,7 @@ static int slab_apply_t(const th_ctx *c, const void *r, void *y, int nrhs, hipSt
   hipLaunchKernelGGL((k_slab_gather<T>), dim3(ceil_div(c->max_nom, 256), nsub, nrhs), dim3(256), 0,
                      s, c->d_subs, (const cx<T> *)r, (cx<T> *)c->w_x, c->P, c->n1, c->nf,
                      c->x_rows);
-  const size_t row_bytes = (size_t)c->max_slab_rows * sizeof(cx<T>);
+  const size_t row_bytes = ((size_t)c->max_slab_rows + 256) * sizeof(cx<T>);
   int rc;
   if (nrhs >= 4 && 4 * row_bytes <= 48 * 1024)
     rc = slab_sweeps_t<TB, T, 4>(c, nrhs, s);
