@@ -369,10 +369,16 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return ((long long)s.nrb * (s.nrb + 1) / 2 + (long long)s.nrb * s.neb) * kSymTile * kSymTile;
   };
   const int cband = (c->dim == 3 ? (2 * P + 1) * (2 * P + 1) : 2 * P + 1) * P;
-  auto slab_elems = [&](const Sub &s) {  // G_t, bands, E_t
+  // G_t, bands, E_t; stored rows padded to a multiple of 8 entries, regions
+  // kept on 128-byte boundaries
+  auto pad8 = [](long long x) { return (x + 7) & ~7LL; };
+  auto slab_g = [&](const Sub &s) {
     const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
-    return (long long)(s.nsl - 1) * m * m + ml * ml + (long long)(s.nsl - 1) * s.lsz * cband +
-           (long long)(s.nsl - 1) * s.lsz * m;
+    return (long long)(s.nsl - 1) * m * pad8(m) + ml * pad8(ml);
+  };
+  auto slab_bands = [&](const Sub &s) { return pad8((long long)(s.nsl - 1) * s.lsz * cband); };
+  auto slab_elems = [&](const Sub &s) {
+    return slab_g(s) + slab_bands(s) + (long long)(s.nsl - 1) * s.lsz * pad8((long long)P * s.lsz);
   };
   {
     long long dense = 0, sym = 0, slab = 0;
@@ -413,9 +419,9 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     s.boff = boff;
     // element offsets: complex entries (F64/F32) or bf16 values (matrix-core layout)
     if (c->layout == 3) {
-      const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
-      s.coff = boff + (long long)(s.nsl - 1) * m * m + ml * ml;
-      s.ecoff = s.coff + (long long)(s.nsl - 1) * s.lsz * cband;
+      const long long ml = (long long)(P + 1) * s.lsz;
+      s.coff = boff + slab_g(s);
+      s.ecoff = s.coff + slab_bands(s);
       boff += slab_elems(s);
       c->max_nsl = std::max(c->max_nsl, s.nsl);
       c->max_slab_rows = std::max(c->max_slab_rows, (int)ml);

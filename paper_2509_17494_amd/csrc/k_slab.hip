@@ -12,12 +12,13 @@
 //   forward   y_t = G_t (r_t - L_t y_{t-1})
 //   backward  x_t = y_t - E_t x_{t+1}[first layer of t + 1],  E_t = G_t L_{t+1}^T,
 // one launch per slab for all subdomains.  Stored per subdomain: every G_t
-// transposed (entry (b, a) at b m_t + a, so one output row per thread reads
-// consecutive entries of a row); the couplings L_t of every slab t >= 1 as
+// transposed (entry (b, a) at b ld_t + a, rows padded to ld_t, a multiple of
+// 8 entries, so one output row per thread reads consecutive entries of a row
+// and every row starts on a 128-byte line); the couplings L_t of every slab t >= 1 as
 // bands: for each first-layer node a the (2P+1)^(d-1) x P block of slab t - 1
 // nodes within P positions of a in every in-layer direction (zero where a node
 // lies outside Omega or shares no cell with a); and every E_t (m_t x n_layer,
-// the product the elimination forms anyway) transposed.  The bytes per
+// the product the elimination forms anyway) transposed, likewise padded.  The bytes per
 // application are the G_t plus the E_t (a fraction 1/P of them) instead of the
 // n_U x n_Omega rows of an explicit inverse.  Elimination without pivoting is
 // stable here for the reason given for the Gauss-Jordan inverses: i A_s^(i)
@@ -33,10 +34,12 @@ __host__ __device__ __forceinline__ int slab_rows(const Sub &s, int t, int P) {
   return (t < s.nsl - 1 ? P : P + 1) * s.lsz;
 }
 
+__host__ __device__ __forceinline__ int slab_ld(int m) { return (m + 7) & ~7; }
+
 // entries of the G_t of slabs before t (all of them have P layers)
 __host__ __device__ __forceinline__ long long slab_goff(const Sub &s, int t, int P) {
-  const long long m = (long long)P * s.lsz;
-  return s.boff + (long long)t * m * m;
+  const int m = P * s.lsz;
+  return s.boff + (long long)t * m * slab_ld(m);
 }
 
 __host__ __device__ __forceinline__ int band_width(int P, int dim) {
@@ -118,7 +121,8 @@ __global__ __launch_bounds__(256) void k_slab_schur(const Sub *__restrict__ subs
   w = w - acc;
 }
 
-// store G_t = W transposed and, for t >= 1, the coupling band of slab t
+// store G_t = W transposed (rows padded to slab_ld) and, for t >= 1, the
+// coupling band of slab t
 template <typename TB>
 __global__ __launch_bounds__(256) void k_slab_store(const Sub *__restrict__ subs, int s0,
                                                     const c64 *__restrict__ A, int lda,
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(256) void k_slab_store(const Sub *__restrict__ subs
   if (e < ng) {
     const int b = (int)(e / m), a = (int)(e % m);
     const c64 v = W[blockIdx.z * wmat + (long long)a * ldw + b];
-    B[slab_goff(s, t, P) + e] = cx<TB>{(TB)v.re, (TB)v.im};
+    B[slab_goff(s, t, P) + (long long)b * slab_ld(m) + a] = cx<TB>{(TB)v.re, (TB)v.im};
   } else if (t >= 1 && e < ng + (long long)s.lsz * cb) {
     const long long f = e - ng;
     const int a = (int)(f / cb), k = (int)(f % cb);
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(256) void k_slab_store_e(const Sub *__restrict__ su
   if (e >= (long long)s.lsz * mp) return;
   const int cc = (int)(e / mp), r = (int)(e % mp);
   const c64 v = T1[blockIdx.z * tmat + (long long)r * ldt + cc];
-  B[s.ecoff + (long long)(t - 1) * s.lsz * mp + e] = cx<TB>{(TB)v.re, (TB)v.im};
+  B[s.ecoff + ((long long)(t - 1) * s.lsz + cc) * slab_ld(mp) + r] = cx<TB>{(TB)v.re, (TB)v.im};
 }
 
 int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat, c64 *W0,
@@ -229,9 +233,9 @@ __global__ __launch_bounds__(256) void k_slab_gather(const Sub *__restrict__ sub
   Z[q * xrows + s.xoff + k] = r[q * nf + om_node(s, k, P, n1)];
 }
 
-// acc[q] = sum_b G^T[b][a] x[b][q] for the output row a of the thread: g points
-// at entry (0, a) of the stored G_t^T (m x m); loads in batches of kRowsInFlight
-// rows, all issued before their use.
+// acc[q] = sum_{b0 <= b < b1} G^T[b][a] x[b][q] for the output row a of the
+// thread: g points at entry (0, a) of the stored G_t^T (rows of ld entries);
+// loads in batches of kRowsInFlight rows, all issued before their use.
 constexpr int kRowsInFlight = 16;
 
 template <typename TB, typename T, int RC>
@@ -335,7 +339,8 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
   const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
   const int bq = (m + 3) / 4;
   cx<T> acc[RC];
-  slab_gemv_row<TB, T, RC>(B + slab_goff(s, t, P) + min(a, m - 1), m, min(wave * bq, m),
+  const int ld = slab_ld(m);
+  slab_gemv_row<TB, T, RC>(B + slab_goff(s, t, P) + min(a, ld - 1), ld, min(wave * bq, m),
                            min((wave + 1) * bq, m), x, acc);
   if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
 #pragma unroll
@@ -369,7 +374,8 @@ __global__ __launch_bounds__(256) void k_slab_bwd(const Sub *__restrict__ subs,
   const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
   const int cq = (nl + 3) / 4;
   cx<T> acc[RC];
-  slab_gemv_row<TB, T, RC>(B + s.ecoff + (long long)t * nl * m + min(a, m - 1), m,
+  const int ld = slab_ld(m);
+  slab_gemv_row<TB, T, RC>(B + s.ecoff + (long long)t * nl * ld + min(a, ld - 1), ld,
                            min(wave * cq, nl), min((wave + 1) * cq, nl), w, acc);
   if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
 #pragma unroll
