@@ -104,6 +104,7 @@ struct CoarseData {
   int C = 3;                  // in-slab couplings per vertex (3 or 9)
   int nblk = 0;               // super-blocks of consecutive slabs
   int rc_chunk = 1;           // right-hand sides per sweep pass
+  int mid = -1;               // twisted elimination: meeting super-block (-1: top-down only)
   std::vector<int> line0;     // first slab of every super-block (nblk + 1 entries)
   std::vector<int> ld;        // padded leading dimension of G_J
   std::vector<long long> goff;  // element offset of G_J

@@ -10,12 +10,18 @@
 // elimination in natural order
 //   S_0 = T_0,   S_J = T_J - L_J S_{J-1}^{-1} U_{J-1},   G_J = S_J^{-1},
 // where L_J S_{J-1}^{-1} U_{J-1} only touches the first-slab block of S_J and
-// only needs the last-slab block of G_{J-1}.  Every S_J is inverted by the
+// only needs the last-slab block of G_{J-1}.  When the right-hand sides of a
+// slab fit in LDS the elimination is twisted: blocks above a middle block m
+// are eliminated downwards as above, blocks below it upwards,
+//   S_J = T_J - U_J S_{J+1}^{-1} L_{J+1}   (last-slab block only),
+// and m takes both corrections, so the two chains run side by side and a
+// solve needs about half the sequential launches.  Every S_J is inverted by the
 // same Gauss-Jordan kernels as the subdomain operators (no pivoting: natural
 // order elimination of these matrices is stable, checked against pivoted
 // sparse LU).  The solve is
-//   forward   y_J = G_J (r_J - L_J y_{J-1})
-//   backward  x_J = y_J - G_J[:, last slab] (U_J x_{J+1}[first slab]),
+//   forward   y_J = G_J (r_J - L_J y_{J-1})   (upward chain: r_J - U_J y_{J+1})
+//   backward  x_J = y_J - G_J[:, last slab] (U_J x_{J+1}[first slab])
+//             (upward chain: y_J - G_J[:, first slab] (L_J x_{J-1}[last slab])),
 // each a bandwidth-bound GEMV: for slabs whose right-hand sides fit in LDS one
 // launch per step with one wavefront per output row (coalesced row reads of
 // G_J, fixed-order wavefront reductions); for larger (3-D) slabs a GEMV that
@@ -53,14 +59,20 @@ __device__ __forceinline__ int slab_code(int a, int b, int nx, int C) {
   return (dy >= -1 && dy <= 1 && dx >= -1 && dx <= 1) ? (dy + 1) * 3 + dx + 1 : -1;
 }
 
-// S_J (ld x ld, identity padding) written over the G_J slot.
+// S_J (ld x ld, identity padding) written over the G_J slot; with rev its
+// nb x nb part in reversed node order.
 __global__ __launch_bounds__(256) void k_build_s(c64 *__restrict__ S, int ld, int nb, int nx,
                                                  int L, int C, int line0,
                                                  const c64 *__restrict__ st,
-                                                 const c64 *__restrict__ Gp, int ldp, int kp) {
+                                                 const c64 *__restrict__ Gp, int ldp, int kp,
+                                                 const c64 *__restrict__ Gn, int ldn, int rev) {
   const long long t = blockIdx.x * 256LL + threadIdx.x;
   if (t >= (long long)ld * ld) return;
-  const int a = (int)(t / ld), b = (int)(t % ld);
+  int a = (int)(t / ld), b = (int)(t % ld);
+  if (rev && a < nb && b < nb) {  // the block in reversed node order
+    a = nb - 1 - a;
+    b = nb - 1 - b;
+  }
   const int SC = 3 * C;
   c64 v = {0, 0};
   if (a >= nb || b >= nb) {
@@ -91,8 +103,39 @@ __global__ __launch_bounds__(256) void k_build_s(c64 *__restrict__ S, int ld, in
         v = v - l * sum;
       }
     }
+    const int kJ = nb / L;
+    if (Gn && la == kJ - 1 && lb == kJ - 1) {
+      // - sum_{c,d} U[ca][c] G_{J+1}[first c][first d] L[d][cb]  (L[d][cb] = U[cb][d])
+      const long long gb = (long long)(line0 + lb) * L + cb;
+      for (int c1 = 0; c1 < C; ++c1) {
+        const int c = slab_nbr(ca, c1, nx, C);
+        if (c < 0) continue;
+        const c64 u = st[SC * ga + 2 * C + c1];
+        c64 sum = {0, 0};
+        for (int c2 = 0; c2 < C; ++c2) {
+          const int d = slab_nbr(cb, c2, nx, C);
+          if (d < 0) continue;
+          cmac(sum, Gn[(long long)c * ldn + d], st[SC * gb + 2 * C + c2]);
+        }
+        v = v - u * sum;
+      }
+    }
   }
   S[t] = v;
+}
+
+// G[a][b] <-> G[nb-1-a][nb-1-b] for a, b < nb: back to natural order after the
+// inversion of a block built in reversed order
+__global__ __launch_bounds__(256) void k_reverse_block(c64 *__restrict__ G, int ld, int nb) {
+  const long long t = blockIdx.x * 256LL + threadIdx.x;
+  const long long n2 = (long long)nb * nb;
+  if (t >= n2 / 2) return;
+  const int a = (int)(t / nb), b = (int)(t % nb);
+  c64 &x = G[(long long)a * ld + b];
+  c64 &y = G[(long long)(nb - 1 - a) * ld + nb - 1 - b];
+  const c64 v = x;
+  x = y;
+  y = v;
 }
 
 __device__ __forceinline__ c64 wave_sum(c64 v) {
@@ -210,27 +253,59 @@ __global__ __launch_bounds__(256) void k_cpartsum(const c64 *__restrict__ part, 
   *p = sub ? *p - sm : sm;
 }
 
-// forward step of super-block J: y_J = G_J (r_J - L_J y_{J-1})
+// One super-block of a sweep step (small slabs).  Forward: the right-hand side
+// r_J, minus L_J y_{J-1} on the first slab when prev, minus U_J y_{J+1} on the
+// last slab when next.  Backward: x_J -= G_J[:, col slab] w with w = U_J
+// x_{J+1}[first slab] (up = 0, col slab = last) or w = L_J x_{J-1}[last slab]
+// (up = 1, col slab = first).
+struct SweepBlk {
+  const c64 *G;
+  int ld, nb, line0, kJ;
+  int prev, next, up;
+};
+
+// forward step of up to two super-blocks (blockIdx.z), one wavefront per row
+// of G_J, the right-hand side staged in LDS
 template <int RC>
-__global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int ld, int nb,
-                                                  int nx, int L, int C, int line0,
+__global__ __launch_bounds__(64 * CW) void k_cfwd(SweepBlk b0, SweepBlk b1, int nx, int L, int C,
                                                   const c64 *__restrict__ st,
                                                   const c64 *__restrict__ rc, c64 *__restrict__ uc,
-                                                  int nrhs, long long ncn, int has_prev) {
+                                                  int nrhs, long long ncn) {
   extern __shared__ c64 tsh[];  // RC x nb
+  const SweepBlk B = blockIdx.z == 0 ? b0 : b1;
+  const int nb = B.nb, line0 = B.line0;
   const int r0 = blockIdx.y * RC;
+  const int SC = 3 * C;
   const c64 *xs = tsh;
   for (int i = threadIdx.x; i < nb * RC; i += blockDim.x) {
     const int q = i / nb, a = i - q * nb;
     const int r = r0 + q;
-    tsh[q * nb + a] =
-        r < nrhs ? fwd_rhs(a, r, nx, L, C, line0, st, rc, uc, ncn, has_prev) : c64{0, 0};
+    c64 v = {0, 0};
+    if (r < nrhs) {
+      const long long g = (long long)line0 * L + a;
+      v = rc[r * ncn + g];
+      if (B.prev && a < L) {
+        for (int code = 0; code < C; ++code) {
+          const int c = slab_nbr(a, code, nx, C);
+          if (c >= 0) v = v - st[SC * g + code] * uc[r * ncn + (long long)(line0 - 1) * L + c];
+        }
+      }
+      const int al = a - (B.kJ - 1) * L;
+      if (B.next && al >= 0) {
+        for (int code = 0; code < C; ++code) {
+          const int c = slab_nbr(al, code, nx, C);
+          if (c >= 0)
+            v = v - st[SC * g + 2 * C + code] * uc[r * ncn + (long long)(line0 + B.kJ) * L + c];
+        }
+      }
+    }
+    tsh[q * nb + a] = v;
   }
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int a = blockIdx.x * CW + wave;
   if (a >= nb) return;
-  const c64 *row = G + (long long)a * ld;
+  const c64 *row = B.G + (long long)a * B.ld;
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
@@ -245,32 +320,44 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(const c64 *__restrict__ G, int
   }
 #pragma unroll
   for (int q = 0; q < RC; ++q) {
-    const c64 s = wave_sum(acc[q]);
-    if (lane == 0 && r0 + q < nrhs) uc[(r0 + q) * ncn + (long long)line0 * L + a] = s;
+    const c64 sm = wave_sum(acc[q]);
+    if (lane == 0 && r0 + q < nrhs) uc[(r0 + q) * ncn + (long long)line0 * L + a] = sm;
   }
 }
 
-// backward step of super-block J (not the last): x_J = y_J - G_J[:, last] w,
-// w = U_J x_{J+1}[first slab]
+// backward step of up to two super-blocks (blockIdx.z)
 template <int RC>
-__global__ __launch_bounds__(64 * CW) void k_cbwd(const c64 *__restrict__ G, int ld, int nb,
-                                                  int nx, int L, int C, int line0, int kJ,
-                                                  const c64 *__restrict__ st,
-                                                  c64 *__restrict__ uc, int nrhs, long long ncn) {
+__global__ __launch_bounds__(64 * CW) void k_cbwd(SweepBlk b0, SweepBlk b1, int nx, int L, int C,
+                                                  const c64 *__restrict__ st, c64 *__restrict__ uc,
+                                                  int nrhs, long long ncn) {
   extern __shared__ c64 wsh[];  // RC x L
+  const SweepBlk B = blockIdx.z == 0 ? b0 : b1;
+  const int nb = B.nb, line0 = B.line0;
   const int r0 = blockIdx.y * RC;
-  const int lend = line0 + kJ;  // first slab of J+1
+  const int SC = 3 * C;
   const c64 *ws = wsh;
   for (int i = threadIdx.x; i < L * RC; i += blockDim.x) {
     const int q = i / L, c = i - q * L;
     const int r = r0 + q;
-    wsh[q * L + c] = r < nrhs ? bwd_rhs(c, r, nx, L, C, lend, st, uc, ncn) : c64{0, 0};
+    c64 v = {0, 0};
+    if (r < nrhs) {
+      if (B.up) {  // L_J x_{J-1}[last slab] at position c of the first slab of J
+        const long long gc = (long long)line0 * L + c;
+        for (int code = 0; code < C; ++code) {
+          const int d = slab_nbr(c, code, nx, C);
+          if (d >= 0) cmac(v, st[SC * gc + code], uc[r * ncn + (long long)(line0 - 1) * L + d]);
+        }
+      } else {
+        v = bwd_rhs(c, r, nx, L, C, line0 + B.kJ, st, uc, ncn);
+      }
+    }
+    wsh[q * L + c] = v;
   }
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int a = blockIdx.x * CW + wave;
   if (a >= nb) return;
-  const c64 *row = G + (long long)a * ld + (long long)(kJ - 1) * L;
+  const c64 *row = B.G + (long long)a * B.ld + (B.up ? 0 : (long long)(B.kJ - 1) * L);
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
@@ -283,10 +370,10 @@ __global__ __launch_bounds__(64 * CW) void k_cbwd(const c64 *__restrict__ G, int
   }
 #pragma unroll
   for (int q = 0; q < RC; ++q) {
-    const c64 s = wave_sum(acc[q]);
+    const c64 sm = wave_sum(acc[q]);
     if (lane == 0 && r0 + q < nrhs) {
       c64 *p = uc + (r0 + q) * ncn + (long long)line0 * L + a;
-      *p = *p - s;
+      *p = *p - sm;
     }
   }
 }
@@ -365,18 +452,43 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   TH_HIP_CHECK_RET(hipMemcpyAsync(cd.st, st.data(), st_bytes, hipMemcpyHostToDevice, s));
   int *flag = (int *)(pws + kGJBlock * kGJBlock);
   TH_HIP_CHECK_RET(hipMemsetAsync(flag, 0, sizeof(int), s));
-  int rc = 0;
-  for (int J = 0; J < nblk && rc == 0; ++J) {
+  // twisted elimination where the small-slab sweeps apply (at least 3 blocks)
+  cd.mid = (nblk >= 3 && max_nb * cd.rc_chunk * (long long)sizeof(c64) <= 64 * 1024) ? nblk / 2 : -1;
+  // block J with the correction from the block above (prev) and/or below (next).
+  // Gauss-Jordan without pivoting eliminates in node order; a block of the
+  // upward chain (corrected on its last slab) is eliminated in reversed order,
+  // so that, as in the downward chain, the corrected slab goes first (in
+  // natural order its pivots can become small).
+  auto build = [&](int J, bool prev, bool next) -> int {
+    const bool rev = next && !prev;
     const int ld = cd.ld[J], nb = (cd.line0[J + 1] - cd.line0[J]) * L;
     c64 *GJ = cd.G + cd.goff[J];
-    const c64 *Gp = J > 0 ? cd.G + cd.goff[J - 1] : nullptr;
-    const int ldp = J > 0 ? cd.ld[J - 1] : 0;
-    const int kp = J > 0 ? cd.line0[J] - cd.line0[J - 1] : 0;
+    const c64 *Gp = prev ? cd.G + cd.goff[J - 1] : nullptr;
+    const int ldp = prev ? cd.ld[J - 1] : 0;
+    const int kp = prev ? cd.line0[J] - cd.line0[J - 1] : 0;
+    const c64 *Gn = next ? cd.G + cd.goff[J + 1] : nullptr;
+    const int ldn = next ? cd.ld[J + 1] : 0;
     const long long tot = (long long)ld * ld;
     hipLaunchKernelGGL(k_build_s, dim3((unsigned)ceil_div_ll(tot, 256)), dim3(256), 0, s, GJ, ld,
-                       nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, Gp, ldp, kp);
+                       nb, nx, L, C, cd.line0[J], (const c64 *)cd.st, Gp, ldp, kp, Gn, ldn,
+                       rev ? 1 : 0);
     TH_HIP_CHECK_RET(hipGetLastError());
-    rc = gj_invert_batched(GJ, ld, ld, tot, 1, s, pws);
+    const int rc = gj_invert_batched(GJ, ld, ld, tot, 1, s, pws);
+    if (rc == 0 && rev) {
+      hipLaunchKernelGGL(k_reverse_block, dim3((unsigned)ceil_div_ll((long long)nb * nb / 2 + 1, 256)),
+                         dim3(256), 0, s, GJ, ld, nb);
+      TH_HIP_CHECK_RET(hipGetLastError());
+    }
+    return rc;
+  };
+  int rc = 0;
+  if (cd.mid < 0) {
+    for (int J = 0; J < nblk && rc == 0; ++J) rc = build(J, J > 0, false);
+  } else {
+    const int m = cd.mid;
+    for (int J = 0; J < m && rc == 0; ++J) rc = build(J, J > 0, false);
+    for (int J = nblk - 1; J > m && rc == 0; --J) rc = build(J, false, J < nblk - 1);
+    if (rc == 0) rc = build(m, true, true);
   }
   int hflag = 0;
   TH_HIP_CHECK_RET(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -432,27 +544,64 @@ static int sweep_large_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream
 }
 
 // Small slabs: the right-hand side of a step is formed in LDS by the GEMV
-// launch itself (one launch per step).
+// launch itself (one launch per step; with the twisted elimination each
+// launch carries one super-block of each chain).
 template <int RC>
 static int sweep_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
   const CoarseData &cd = c->coarse;
   const int nx = cd.nx, L = cd.L, C = cd.C;
   const long long ncn = (long long)L * cd.ny;
   const unsigned ychunks = (unsigned)ceil_div(nrhs, RC);
-  for (int J = 0; J < cd.nblk; ++J) {
-    const int nb = (cd.line0[J + 1] - cd.line0[J]) * L;
-    const size_t shm = (size_t)nb * RC * sizeof(c64);
-    hipLaunchKernelGGL((k_cfwd<RC>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm, s,
-                       (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, nx, L, C, cd.line0[J],
-                       (const c64 *)cd.st, rcv, uc, nrhs, ncn, J > 0 ? 1 : 0);
-  }
-  for (int J = cd.nblk - 2; J >= 0; --J) {
-    const int kJ = cd.line0[J + 1] - cd.line0[J];
-    const int nb = kJ * L;
-    const size_t shm = (size_t)L * RC * sizeof(c64);
-    hipLaunchKernelGGL((k_cbwd<RC>), dim3(ceil_div(nb, CW), ychunks), dim3(64 * CW), shm, s,
-                       (const c64 *)(cd.G + cd.goff[J]), cd.ld[J], nb, nx, L, C, cd.line0[J], kJ,
-                       (const c64 *)cd.st, uc, nrhs, ncn);
+  int max_nb = 0;
+  for (int J = 0; J < cd.nblk; ++J) max_nb = std::max(max_nb, (cd.line0[J + 1] - cd.line0[J]) * L);
+  auto blk = [&](int J, int prev, int next, int up) {
+    SweepBlk b;
+    b.G = cd.G + cd.goff[J];
+    b.ld = cd.ld[J];
+    b.kJ = cd.line0[J + 1] - cd.line0[J];
+    b.nb = b.kJ * L;
+    b.line0 = cd.line0[J];
+    b.prev = prev;
+    b.next = next;
+    b.up = up;
+    return b;
+  };
+  auto fwd = [&](const SweepBlk &b0, const SweepBlk &b1, int nchain) {
+    const int nb = std::max(b0.nb, nchain > 1 ? b1.nb : 0);
+    hipLaunchKernelGGL((k_cfwd<RC>), dim3(ceil_div(nb, CW), ychunks, nchain), dim3(64 * CW),
+                       (size_t)max_nb * RC * sizeof(c64), s, b0, b1, nx, L, C, (const c64 *)cd.st,
+                       rcv, uc, nrhs, ncn);
+  };
+  auto bwd = [&](const SweepBlk &b0, const SweepBlk &b1, int nchain) {
+    const int nb = std::max(b0.nb, nchain > 1 ? b1.nb : 0);
+    hipLaunchKernelGGL((k_cbwd<RC>), dim3(ceil_div(nb, CW), ychunks, nchain), dim3(64 * CW),
+                       (size_t)L * RC * sizeof(c64), s, b0, b1, nx, L, C, (const c64 *)cd.st, uc,
+                       nrhs, ncn);
+  };
+  const int n = cd.nblk, m = cd.mid;
+  if (m < 0) {  // top-down
+    for (int J = 0; J < n; ++J) fwd(blk(J, J > 0, 0, 0), blk(J, J > 0, 0, 0), 1);
+    for (int J = n - 2; J >= 0; --J) bwd(blk(J, 0, 0, 0), blk(J, 0, 0, 0), 1);
+  } else {      // twisted: chains 0..m-1 downwards and n-1..m+1 upwards, then m
+    const int nup = n - 1 - m, steps = std::max(m, nup);
+    for (int i = 0; i < steps; ++i) {
+      if (i < m && i < nup)
+        fwd(blk(i, i > 0, 0, 0), blk(n - 1 - i, 0, i > 0, 0), 2);
+      else if (i < m)
+        fwd(blk(i, i > 0, 0, 0), blk(i, i > 0, 0, 0), 1);
+      else
+        fwd(blk(n - 1 - i, 0, i > 0, 0), blk(n - 1 - i, 0, i > 0, 0), 1);
+    }
+    fwd(blk(m, m > 0, m < n - 1, 0), blk(m, m > 0, m < n - 1, 0), 1);
+    for (int i = 0; i < steps; ++i) {
+      const int Jd = m - 1 - i, Ju = m + 1 + i;
+      if (Jd >= 0 && Ju < n)
+        bwd(blk(Jd, 0, 0, 0), blk(Ju, 0, 0, 1), 2);
+      else if (Jd >= 0)
+        bwd(blk(Jd, 0, 0, 0), blk(Jd, 0, 0, 0), 1);
+      else
+        bwd(blk(Ju, 0, 0, 1), blk(Ju, 0, 0, 1), 1);
+    }
   }
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
