@@ -257,6 +257,36 @@ __device__ __forceinline__ void slab_gemv_row(const cx<TB> *__restrict__ g, int 
   }
 }
 
+// The first kRowsAhead rows of a thread's range, loaded before the workgroup
+// forms its right-hand side (they do not depend on it), so that streaming
+// starts at once; slab_gemv_ahead then consumes them and the rest.
+constexpr int kRowsAhead = 8;
+
+template <typename TB, typename T>
+__device__ __forceinline__ void slab_rows_ahead(const cx<TB> *__restrict__ g, int m, int b0, int b1,
+                                                cx<T> (&ga)[kRowsAhead]) {
+#pragma unroll
+  for (int u = 0; u < kRowsAhead; ++u)
+    ga[u] = b0 + u < b1 ? ccast<T>(ld_stream(g + (long long)(b0 + u) * m)) : cx<T>{0, 0};
+}
+
+template <typename TB, typename T, int RC>
+__device__ __forceinline__ void slab_gemv_ahead(const cx<TB> *__restrict__ g, int m, int b0, int b1,
+                                                const cx<T> (&ga)[kRowsAhead],
+                                                const cx<T> *__restrict__ x, cx<T> (&acc)[RC]) {
+  cx<T> rest[RC];
+  slab_gemv_row<TB, T, RC>(g, m, min(b0 + kRowsAhead, b1), b1, x, rest);
+#pragma unroll
+  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
+#pragma unroll
+  for (int u = 0; u < kRowsAhead; ++u)
+    if (b0 + u < b1)
+#pragma unroll
+      for (int q = 0; q < RC; ++q) cmac(acc[q], ga[u], x[(b0 + u) * RC + q]);
+#pragma unroll
+  for (int q = 0; q < RC; ++q) acc[q] = acc[q] + rest[q];
+}
+
 // The four wavefronts of a workgroup share its 64 output rows and split the
 // rows b of G_t^T in quarters; their partial sums are added in wavefront order
 // through LDS (red: 4 x 64 x RC) by the first wavefront, which returns them in
@@ -301,34 +331,46 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
   const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
   const long long row0 = (long long)t * P * s.lsz;
   const cx<TB> *Ct = B + s.coff + (long long)(t - 1) * s.lsz * CB;
+  const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int bq = (m + 3) / 4, ld = slab_ld(m);
+  const int gb0 = min(wave * bq, m), gb1 = min((wave + 1) * bq, m);
+  const cx<TB> *gp = B + slab_goff(s, t, P) + min(a, ld - 1);
+  cx<T> ga[kRowsAhead];
+  slab_rows_ahead<TB, T>(gp, ld, gb0, gb1, ga);
   for (int j = threadIdx.x; j < m; j += 256) {
     cx<T> v[RC];
 #pragma unroll
     for (int q = 0; q < RC; ++q)
       v[q] = q < nq ? Z[(long long)(r0 + q) * xrows + s.xoff + row0 + j] : cx<T>{0, 0};
     if (t > 0 && j < s.lsz) {
+      // Branch-free band product: positions outside Omega are clamped to a
+      // node inside (its value is finite) and meet a zero band coefficient,
+      // so every load can be issued before its use.
       const int xa = j % s.nox, ya = DIM == 3 ? j / s.nox : 0;
       const cx<TB> *cr = Ct + (long long)j * CB;
+      const long long vb = (long long)r0 * xrows + s.xoff + (long long)(t - 1) * P * s.lsz;
 #pragma unroll
       for (int jy = 0; jy < (DIM == 3 ? W2 : 1); ++jy) {
-        const int yb = DIM == 3 ? ya - P + jy : 0;
-        const bool oky = DIM == 3 ? (yb >= 0 && yb < s.noy) : true;
+        const int yb = DIM == 3 ? min(max(ya - P + jy, 0), s.noy - 1) : 0;
 #pragma unroll
         for (int jx = 0; jx < W2; ++jx) {
-          const int xb = xa - P + jx;
-          if (!oky || xb < 0 || xb >= s.nox) continue;
+          const int xb = min(max(xa - P + jx, 0), s.nox - 1);
+          cx<TB> l[P];
+          cx<T> y[P][RC];
 #pragma unroll
           for (int lb = 0; lb < P; ++lb) {
-            const int col = ((t - 1) * P + lb) * s.lsz + yb * s.nox + xb;
-            const cx<TB> l = cr[(jy * W2 + jx) * P + lb];
+            l[lb] = cr[(jy * W2 + jx) * P + lb];
+#pragma unroll
+            for (int q = 0; q < RC; ++q)
+              y[lb][q] = V[vb + (long long)min(q, nq - 1) * xrows + lb * s.lsz + yb * s.nox + xb];
+          }
+#pragma unroll
+          for (int lb = 0; lb < P; ++lb)
 #pragma unroll
             for (int q = 0; q < RC; ++q) {
-              if (q >= nq) continue;
-              const cx<T> y = V[(long long)(r0 + q) * xrows + s.xoff + col];
-              v[q].re -= (T)l.re * y.re - (T)l.im * y.im;
-              v[q].im -= (T)l.re * y.im + (T)l.im * y.re;
+              v[q].re -= (T)l[lb].re * y[lb][q].re - (T)l[lb].im * y[lb][q].im;
+              v[q].im -= (T)l[lb].re * y[lb][q].im + (T)l[lb].im * y[lb][q].re;
             }
-          }
         }
       }
     }
@@ -336,12 +378,8 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
     for (int q = 0; q < RC; ++q) x[j * RC + q] = v[q];
   }
   __syncthreads();
-  const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int bq = (m + 3) / 4;
   cx<T> acc[RC];
-  const int ld = slab_ld(m);
-  slab_gemv_row<TB, T, RC>(B + slab_goff(s, t, P) + min(a, ld - 1), ld, min(wave * bq, m),
-                           min((wave + 1) * bq, m), x, acc);
+  slab_gemv_ahead<TB, T, RC>(gp, ld, gb0, gb1, ga, x, acc);
   if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
