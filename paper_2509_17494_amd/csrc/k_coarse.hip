@@ -36,7 +36,8 @@
 
 namespace th {
 
-constexpr int CW = 8;  // wavefronts (rows) per workgroup in the sweeps
+constexpr int CW = 8;      // wavefronts (rows) per workgroup in the sweeps
+constexpr int kAhead = 8;  // row entries per lane loaded before the right-hand side is staged
 constexpr int kCoarseChunk = 256;  // columns per partial sum of the large-slab GEMV
 
 // In-slab neighbourhood: C = 3 codes dx + 1 along a line (2-D), C = 9 codes
@@ -277,6 +278,18 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(SweepBlk b0, SweepBlk b1, int 
   const int r0 = blockIdx.y * RC;
   const int SC = 3 * C;
   const c64 *xs = tsh;
+  // the first kAhead entries of the wavefront's row are loaded before the
+  // right-hand side is staged (they do not depend on it)
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int arow = blockIdx.x * CW + wave;
+  const bool once = gridDim.y == 1;  // rows streamed once when one pass covers all RHS
+  const c64 *row = B.G + (long long)min(arow, nb - 1) * B.ld;
+  c64 gah[kAhead];
+#pragma unroll
+  for (int u = 0; u < kAhead; ++u) {
+    const int b = lane + 64 * u;
+    gah[u] = b < nb ? (once ? ld_stream(row + b) : row[b]) : c64{0, 0};
+  }
   for (int i = threadIdx.x; i < nb * RC; i += blockDim.x) {
     const int q = i / nb, a = i - q * nb;
     const int r = r0 + q;
@@ -302,18 +315,21 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(SweepBlk b0, SweepBlk b1, int 
     tsh[q * nb + a] = v;
   }
   __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int a = blockIdx.x * CW + wave;
+  const int a = arow;
   if (a >= nb) return;
-  const c64 *row = B.G + (long long)a * B.ld;
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-  // rows are streamed once when one pass covers all right-hand sides
-  const bool once = gridDim.y == 1;
+#pragma unroll
+  for (int u = 0; u < kAhead; ++u) {
+    const int b = lane + 64 * u;
+    if (b < nb)
+#pragma unroll
+      for (int q = 0; q < RC; ++q) cmac(acc[q], gah[u], xs[q * nb + b]);
+  }
   constexpr int UNR = RC == 1 ? 8 : 4;  // deeper unrolling only where registers allow
 #pragma unroll UNR
-  for (int b = lane; b < nb; b += 64) {
+  for (int b = lane + 64 * kAhead; b < nb; b += 64) {
     const c64 g = once ? ld_stream(row + b) : row[b];
 #pragma unroll
     for (int q = 0; q < RC; ++q) cmac(acc[q], g, xs[q * nb + b]);
@@ -336,6 +352,16 @@ __global__ __launch_bounds__(64 * CW) void k_cbwd(SweepBlk b0, SweepBlk b1, int 
   const int r0 = blockIdx.y * RC;
   const int SC = 3 * C;
   const c64 *ws = wsh;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int arow = blockIdx.x * CW + wave;
+  const bool once = gridDim.y == 1;
+  const c64 *row = B.G + (long long)min(arow, nb - 1) * B.ld + (B.up ? 0 : (long long)(B.kJ - 1) * L);
+  c64 gah[kAhead];
+#pragma unroll
+  for (int u = 0; u < kAhead; ++u) {
+    const int c = lane + 64 * u;
+    gah[u] = c < L ? (once ? ld_stream(row + c) : row[c]) : c64{0, 0};
+  }
   for (int i = threadIdx.x; i < L * RC; i += blockDim.x) {
     const int q = i / L, c = i - q * L;
     const int r = r0 + q;
@@ -354,16 +380,20 @@ __global__ __launch_bounds__(64 * CW) void k_cbwd(SweepBlk b0, SweepBlk b1, int 
     wsh[q * L + c] = v;
   }
   __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int a = blockIdx.x * CW + wave;
+  const int a = arow;
   if (a >= nb) return;
-  const c64 *row = B.G + (long long)a * B.ld + (B.up ? 0 : (long long)(B.kJ - 1) * L);
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-  const bool once = gridDim.y == 1;
+#pragma unroll
+  for (int u = 0; u < kAhead; ++u) {
+    const int c = lane + 64 * u;
+    if (c < L)
+#pragma unroll
+      for (int q = 0; q < RC; ++q) cmac(acc[q], gah[u], ws[q * L + c]);
+  }
 #pragma unroll 4
-  for (int c = lane; c < L; c += 64) {
+  for (int c = lane + 64 * kAhead; c < L; c += 64) {
     const c64 g = once ? ld_stream(row + c) : row[c];
 #pragma unroll
     for (int q = 0; q < RC; ++q) cmac(acc[q], g, ws[q * L + c]);
