@@ -409,10 +409,13 @@ __global__ __launch_bounds__(64 * CW) void k_cbwd(SweepBlk b0, SweepBlk b1, int 
 }
 
 // Number of slabs per super-block: minimise the modelled solve time
-// (K + 1) ny L^2 16 B / BW  +  2 ceil(ny / K) launches x latency, with G
-// within a memory budget; slab right-hand sides up to 64 KiB are staged in LDS.
+// (K + 1) ny L^2 16 B / BW  +  launches x latency, with G within a memory
+// budget; slab right-hand sides up to 64 KiB are staged in LDS.  With at least
+// three super-blocks the sweeps are twisted (ceil(ny / K) + 1 launches, else
+// 2 ceil(ny / K) - 1).  BW and latency are a least-squares fit of measured
+// coarse solves over K = 3..10 at ny = L = 401.
 static int choose_lines(int L, int ny, int rc_chunk, int passes) {
-  const double bw = 4.0e12, lat = 8.0e-6;
+  const double bw = 6.3e12, lat = 7.3e-6;
   const int nb_max = std::min(4096, 65536 / (16 * rc_chunk));
   const int kmax = std::max(1, std::min(ny, nb_max / L));
   int best = 1;
@@ -420,7 +423,9 @@ static int choose_lines(int L, int ny, int rc_chunk, int passes) {
   for (int K = 1; K <= kmax; ++K) {
     const double bytes = (double)(K + 1) * ny * L * (double)L * 16.0 * passes;
     if (K > 1 && (double)ny * K * L * (double)L * 16.0 > 24e9) break;
-    const double t = bytes / bw + 2.0 * std::ceil((double)ny / K) * lat;
+    const double nblk = std::ceil((double)ny / K);
+    const double launches = nblk >= 3 ? nblk + 1 : 2 * nblk - 1;
+    const double t = bytes / bw + launches * lat;
     if (t < best_t) {
       best_t = t;
       best = K;
