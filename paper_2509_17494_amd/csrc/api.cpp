@@ -363,8 +363,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
       }
   // storage layout.  Explicit inverse rows: the symmetric tiles (U x U block
   // of the symmetric inverse stored once) when they need at most 80 % of the
-  // dense bytes.  Slab factors instead when their modelled apply time (twice
-  // their bytes, plus two launches per slab) is lower.
+  // dense bytes.  Slab factors instead when their modelled apply time (their
+  // bytes at a lower rate, plus about one launch per slab) is lower.
   auto sym_elems = [](const Sub &s) {
     return ((long long)s.nrb * (s.nrb + 1) / 2 + (long long)s.nrb * s.neb) * kSymTile * kSymTile;
   };
@@ -377,8 +377,9 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     return (long long)(s.nsl - 1) * m * pad8(m) + ml * pad8(ml);
   };
   auto slab_bands = [&](const Sub &s) { return pad8((long long)(s.nsl - 1) * s.lsz * cband); };
+  // E_t of the lower chain of the twisted elimination: slabs 0 .. (nsl - 1) / 2 - 1
   auto slab_elems = [&](const Sub &s) {
-    return slab_g(s) + slab_bands(s) + (long long)(s.nsl - 1) * s.lsz * pad8((long long)P * s.lsz);
+    return slab_g(s) + slab_bands(s) + (long long)((s.nsl - 1) / 2) * s.lsz * pad8((long long)P * s.lsz);
   };
   {
     long long dense = 0, sym = 0, slab = 0;
@@ -393,7 +394,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     const double es = d->gemm == TH_GEMM_F32 ? 8.0 : 16.0;
     const int rows = 10 * sym <= 8 * dense ? 1 : 0;
     const double t_rows = rows == 1 ? es * sym / 5.5e12 : es * dense / 6.5e12;
-    const double t_slab = es * slab / 4.0e12 + 2.0 * nsl * 8e-6;
+    const double t_slab = es * slab / 4.0e12 + (2 * (nsl / 2) + 3) * 8e-6;
     // the sweeps keep a slab's right-hand sides and 256 partial sums in 48 KiB of LDS
     int max_lsz = 0;
     for (const Sub &s : c->subs) max_lsz = std::max(max_lsz, s.lsz);

@@ -239,8 +239,8 @@ int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32,
 // k_slab.hip: the slab-factor layout (apply, and its setup from the assembled
 // subdomain matrices of one batch)
 int launch_dd_slab(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);
-int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat, c64 *W0,
-                       c64 *W1, c64 *T1, int ldw, int ldt, c64 *pws, hipStream_t s);
+int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat,
+                       c64 *const W[3], c64 *T1, int ldw, int ldt, c64 *pws, hipStream_t s);
 int launch_dd_accumulate(const th_ctx *c, const void *y, void *u, int nrhs, bool f32, bool assign,
                          hipStream_t s);
 

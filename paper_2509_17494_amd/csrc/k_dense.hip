@@ -418,12 +418,12 @@ int setup_subdomain_operators(th_ctx *c) {
   const int nsub = (int)c->subs.size();
   const int npad = ceil_div(c->max_nom, GJ_BS) * GJ_BS;
   const long long mat = (long long)npad * npad;
-  // slab layout: two slab work matrices and the Schur product per subdomain
+  // slab layout: three slab work matrices and the Schur product per subdomain
   const bool slab = c->layout == 3;
   int max_lsz = 0;
   for (const Sub &sb : c->subs) max_lsz = std::max(max_lsz, sb.lsz);
   const int ldw = slab ? ceil_div(c->max_slab_rows, GJ_BS) * GJ_BS : 0;
-  const long long per_sub = mat + (slab ? 2LL * ldw * ldw + (long long)ldw * max_lsz : 0);
+  const long long per_sub = mat + (slab ? 3LL * ldw * ldw + (long long)ldw * max_lsz : 0);
   // batch: bounded by ~8 GiB of work space and by free memory
   size_t free_b = 0, total_b = 0;
   TH_HIP_CHECK_RET(hipMemGetInfo(&free_b, &total_b));
@@ -434,9 +434,9 @@ int setup_subdomain_operators(th_ctx *c) {
     set_error("cannot allocate the subdomain work space");
     return TH_ENOMEM;
   }
-  c64 *W0 = work + (long long)batch * mat;
-  c64 *W1 = W0 + (long long)batch * ldw * ldw;
-  c64 *T1 = W1 + (long long)batch * ldw * ldw;
+  c64 *const W[3] = {work + (long long)batch * mat, work + (long long)batch * (mat + ldw * ldw),
+                     work + (long long)batch * (mat + 2LL * ldw * ldw)};
+  c64 *T1 = work + (long long)batch * (mat + 3LL * ldw * ldw);
   size_t pws_bytes = (size_t)batch * GJ_BS * GJ_BS * sizeof(c64) + 64;
   if (hipMalloc(&pws, pws_bytes) != hipSuccess) {
     (void)hipFree(work);
@@ -481,7 +481,7 @@ int setup_subdomain_operators(th_ctx *c) {
     }
     TH_HIP_CHECK_RET(hipGetLastError());
     if (slab) {
-      rc = setup_slab_factors(c, s0, nb, work, npad, mat, W0, W1, T1, ldw, max_lsz, pws, s);
+      rc = setup_slab_factors(c, s0, nb, work, npad, mat, W, T1, ldw, max_lsz, pws, s);
       continue;
     }
     rc = gj_invert_batched(work, npad, npad, mat, nb, s, pws);

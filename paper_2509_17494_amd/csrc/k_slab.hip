@@ -4,26 +4,47 @@
 // A_s^(i) couples node layers only through shared cells, so grouping the
 // layers of one cell row into a slab (P layers; the last slab also takes the
 // top layer) makes it block tridiagonal: slab t couples to slab t - 1 only
-// through its first layer.  Setup runs the block elimination in natural order
-//   S_0 = T_0,  S_t = T_t - L_t S_{t-1}^{-1} L_t^T  (first-layer block only),
-//   G_t = S_t^{-1}
-// (A_s^(i) is complex symmetric, so the upper coupling is L_t^T), and the
-// apply is
-//   forward   y_t = G_t (r_t - L_t y_{t-1})
-//   backward  x_t = y_t - E_t x_{t+1}[first layer of t + 1],  E_t = G_t L_{t+1}^T,
-// one launch per slab for all subdomains.  Stored per subdomain: every G_t
-// transposed (entry (b, a) at b ld_t + a, rows padded to ld_t, a multiple of
-// 8 entries, so one output row per thread reads consecutive entries of a row
-// and every row starts on a 128-byte line); the couplings L_t of every slab t >= 1 as
-// bands: for each first-layer node a the (2P+1)^(d-1) x P block of slab t - 1
-// nodes within P positions of a in every in-layer direction (zero where a node
-// lies outside Omega or shares no cell with a); and every E_t (m_t x n_layer,
-// the product the elimination forms anyway) transposed, likewise padded.  The bytes per
-// application are the G_t plus the E_t (a fraction 1/P of them) instead of the
-// n_U x n_Omega rows of an explicit inverse.  Elimination without pivoting is
-// stable here for the reason given for the Gauss-Jordan inverses: i A_s^(i)
-// has a positive definite Hermitian part, which every Schur complement keeps
-// (Dirichlet nodes are decoupled unit rows).
+// through its first layer (A[t][t-1] is zero outside the first-layer rows,
+// and A[t-1][t] = A[t][t-1]^T since A_s^(i) is complex symmetric).
+//
+// The block elimination is twisted: with the middle slab M = (n - 1) / 2 of
+// the n slabs, the lower chain 0 .. M - 1 is eliminated upwards and the upper
+// chain n - 1 .. M + 1 downwards, both at once, and they meet in M:
+//   lower   S_0 = T_0,          S_t = T_t - A[t][t-1] G_{t-1} A[t-1][t]
+//           (first-layer block only)
+//   upper   S_{n-1} = T_{n-1},  S_t = T_t - A[t][t+1] G_{t+1} A[t+1][t]
+//           (A[t][t+1] has nonzero columns only on the first layer of t + 1,
+//           so only G_{t+1} restricted to that layer enters; a full update)
+//   middle  both corrections;   G_t = S_t^{-1} everywhere.
+// The apply is
+//   forward   y_t = G_t (r_t - A[t][t-1] y_{t-1})        lower chain
+//             y_t = G_t (r_t - A[t][t+1] y_{t+1})        upper chain
+//             y_M = G_M (r_M - both terms),  x_M = y_M
+//   backward  x_t = y_t - E_t x_{t+1}[first layer],  E_t = G_t A[t][t+1]   (lower)
+//             x_t = y_t - G_t[:, first layer] (A[t][t-1] x_{t-1})         (upper)
+// with one launch per step for all subdomains and both chains: about n + 1
+// launches instead of 2n - 1 for the one-sided elimination.  The chains of
+// all subdomains are aligned so that they reach their middles at the same step.
+//
+// Stored per subdomain: every G_t transposed (entry (b, a) at b ld_t + a, rows
+// padded to ld_t, a multiple of 8 entries, so one output row per thread reads
+// consecutive entries of a row and every row starts on a 128-byte line); the
+// couplings A[t][t-1] of every slab t >= 1 as bands: for each first-layer node
+// a the (2P+1)^(d-1) x P block of slab t - 1 nodes within P positions of a in
+// every in-layer direction (zero where a node lies outside Omega or shares no
+// cell with a), read directly by the lower chain and transposed by the upper
+// one; and the E_t of the lower chain (m_t x n_layer, the product the
+// elimination forms anyway) transposed, likewise padded.  The upper chain's
+// backward step reads the first n_layer rows of the stored G_t^T (G_t is
+// symmetric).  The bytes per application are the G_t plus a fraction 1/P of
+// them, instead of the n_U x n_Omega rows of an explicit inverse.
+//
+// Elimination without pivoting is stable here for the reason given for the
+// Gauss-Jordan inverses: i A_s^(i) has a positive definite Hermitian part,
+// which every Schur complement keeps (Dirichlet nodes are decoupled unit
+// rows).  The blocks of the upper chain, whose correction is largest on their
+// top layers, are inverted in reversed node order, so that Gauss-Jordan meets
+// the corrected rows first, as it does in the lower chain.
 #include <algorithm>
 
 #include "ctx.hpp"
@@ -46,6 +67,47 @@ __host__ __device__ __forceinline__ int band_width(int P, int dim) {
   return (dim == 3 ? (2 * P + 1) * (2 * P + 1) : (2 * P + 1)) * P;
 }
 
+// middle slab of the twisted elimination; the lower chain has slab_mid
+// slabs, the upper chain nsl - 1 - slab_mid
+__host__ __device__ __forceinline__ int slab_mid(const Sub &s) { return (s.nsl - 1) / 2; }
+
+enum { kLowerChain = 0, kUpperChain = 1, kMiddle = 2 };
+
+// The slab t of subdomain s at step i of a chain of n aligned steps (lower
+// slab t at step t + n - D, upper slab nsl - 1 - j at step j + n - U), or the
+// middle.  on: the subdomain has a slab at this step; lo / up: the correction
+// from the lower (t - 1) / upper (t + 1) neighbour applies; rev: the block is
+// handled in reversed node order during setup.
+struct SlabRole {
+  int t, on, lo, up, rev;
+};
+
+__host__ __device__ __forceinline__ SlabRole slab_role(const Sub &s, int mode, int i, int n) {
+  const int M = slab_mid(s), U = s.nsl - 1 - M;
+  SlabRole r;
+  if (mode == kLowerChain) {
+    r.t = i - (n - M);
+    r.on = r.t >= 0;
+    r.lo = r.t >= 1;
+    r.up = 0;
+    r.rev = 0;
+  } else if (mode == kUpperChain) {
+    const int j = i - (n - U);
+    r.t = s.nsl - 1 - j;
+    r.on = j >= 0;
+    r.lo = 0;
+    r.up = j >= 1;
+    r.rev = 1;
+  } else {
+    r.t = M;
+    r.on = 1;
+    r.lo = M >= 1;
+    r.up = U >= 1;
+    r.rev = 0;
+  }
+  return r;
+}
+
 // Omega-local index of band entry k of first-layer node a of slab t (t >= 1),
 // or -1 outside Omega.  k = ((jy (2P+1)) + jx) P + lb; the node sits at
 // in-layer position (xa - P + jx, ya - P + jy) in layer (t - 1) P + lb.
@@ -59,40 +121,49 @@ __device__ __forceinline__ int band_col(const Sub &s, int t, int a, int k, int P
 }
 
 // ---------------------------------------------------------------------------
-// setup (FP64), batched over subdomains s0 .. s0 + gridDim.z - 1
+// setup (FP64), batched over subdomains s0 .. s0 + gridDim.z - 1; every
+// kernel resolves the slab of its subdomain from (mode, i, n)
 
-// W = the diagonal block T_t of A (rows and columns of slab t), identity
-// padding; identity for subdomains with fewer slabs.
+// W = the diagonal block T_t of A (rows and columns of slab t, reversed for
+// the upper chain), identity padding; identity where the subdomain has no
+// slab at this step.
 __global__ __launch_bounds__(256) void k_slab_copy(const Sub *__restrict__ subs, int s0,
                                                    const c64 *__restrict__ A, int lda,
                                                    long long amat, c64 *__restrict__ W, int ldw,
-                                                   long long wmat, int t, int P) {
+                                                   long long wmat, int mode, int i, int n, int P) {
   const Sub s = subs[s0 + blockIdx.z];
+  const SlabRole r = slab_role(s, mode, i, n);
   const long long e = blockIdx.x * 256LL + threadIdx.x;
   if (e >= (long long)ldw * ldw) return;
   const int a = (int)(e / ldw), b = (int)(e % ldw);
   c64 v = a == b ? c64{1.0, 0.0} : c64{0, 0};
-  if (t < s.nsl) {
-    const int m = slab_rows(s, t, P);
-    const long long r0 = (long long)t * P * s.lsz;
-    if (a < m && b < m) v = A[blockIdx.z * amat + (r0 + a) * lda + r0 + b];
+  if (r.on) {
+    const int m = slab_rows(s, r.t, P);
+    const long long r0 = (long long)r.t * P * s.lsz;
+    if (a < m && b < m) {
+      const int ia = r.rev ? m - 1 - a : a, ib = r.rev ? m - 1 - b : b;
+      v = A[blockIdx.z * amat + (r0 + ia) * lda + r0 + ib];
+    }
   }
   W[blockIdx.z * wmat + e] = v;
 }
 
-// T1 = G_{t-1} U where U = A[slab t - 1, first layer of t] (m_{t-1} x lsz)
+// lower correction, first factor: T1 = G_{t-1} A[t-1][first layer of t]
+// (m_{t-1} x lsz), G_{t-1} in natural order in Gp
 __global__ __launch_bounds__(256) void k_slab_t1(const Sub *__restrict__ subs, int s0,
                                                  const c64 *__restrict__ A, int lda,
                                                  long long amat, const c64 *__restrict__ Gp,
                                                  int ldw, long long wmat, c64 *__restrict__ T1,
-                                                 int ldt, long long tmat, int t, int P) {
+                                                 int ldt, long long tmat, int mode, int i, int n,
+                                                 int P) {
   const Sub s = subs[s0 + blockIdx.z];
-  if (t >= s.nsl) return;
+  const SlabRole sr = slab_role(s, mode, i, n);
+  if (!sr.on || !sr.lo) return;
   const int mp = P * s.lsz;
   const long long e = blockIdx.x * 256LL + threadIdx.x;
   if (e >= (long long)mp * s.lsz) return;
   const int r = (int)(e / s.lsz), c = (int)(e % s.lsz);
-  const long long rp = (long long)(t - 1) * P * s.lsz, r0 = (long long)t * P * s.lsz;
+  const long long rp = (long long)(sr.t - 1) * P * s.lsz, r0 = (long long)sr.t * P * s.lsz;
   const c64 *g = Gp + blockIdx.z * wmat + (long long)r * ldw;
   const c64 *u = A + blockIdx.z * amat + rp * lda + r0 + c;
   c64 acc = {0, 0};
@@ -100,19 +171,22 @@ __global__ __launch_bounds__(256) void k_slab_t1(const Sub *__restrict__ subs, i
   T1[blockIdx.z * tmat + (long long)r * ldt + c] = acc;
 }
 
-// first-layer block of S_t: W[a][a'] -= sum_k A[first layer a][slab t - 1, k] T1[k][a']
+// lower correction of the first-layer block of S_t (natural order):
+// W[a][a'] -= sum_k A[first layer a][slab t - 1, k] T1[k][a']
 __global__ __launch_bounds__(256) void k_slab_schur(const Sub *__restrict__ subs, int s0,
                                                     const c64 *__restrict__ A, int lda,
                                                     long long amat, const c64 *__restrict__ T1,
                                                     int ldt, long long tmat, c64 *__restrict__ W,
-                                                    int ldw, long long wmat, int t, int P) {
+                                                    int ldw, long long wmat, int mode, int i,
+                                                    int n, int P) {
   const Sub s = subs[s0 + blockIdx.z];
-  if (t >= s.nsl) return;
+  const SlabRole sr = slab_role(s, mode, i, n);
+  if (!sr.on || !sr.lo) return;
   const long long e = blockIdx.x * 256LL + threadIdx.x;
   if (e >= (long long)s.lsz * s.lsz) return;
   const int a = (int)(e / s.lsz), a2 = (int)(e % s.lsz);
   const int mp = P * s.lsz;
-  const long long rp = (long long)(t - 1) * P * s.lsz, r0 = (long long)t * P * s.lsz;
+  const long long rp = (long long)(sr.t - 1) * P * s.lsz, r0 = (long long)sr.t * P * s.lsz;
   const c64 *l = A + blockIdx.z * amat + (r0 + a) * lda + rp;
   const c64 *t1 = T1 + blockIdx.z * tmat + a2;
   c64 acc = {0, 0};
@@ -121,24 +195,76 @@ __global__ __launch_bounds__(256) void k_slab_schur(const Sub *__restrict__ subs
   w = w - acc;
 }
 
-// store G_t = W transposed (rows padded to slab_ld) and, for t >= 1, the
-// coupling band of slab t
+// upper correction, first factor: T1 = A[t][first layer of t + 1] G_{t+1}
+// restricted to that layer (m_t x lsz); G_{t+1} in reversed order in Gn
+__global__ __launch_bounds__(256) void k_slab_t1_up(const Sub *__restrict__ subs, int s0,
+                                                    const c64 *__restrict__ A, int lda,
+                                                    long long amat, const c64 *__restrict__ Gn,
+                                                    int ldw, long long wmat,
+                                                    c64 *__restrict__ T1, int ldt, long long tmat,
+                                                    int mode, int i, int n, int P) {
+  const Sub s = subs[s0 + blockIdx.z];
+  const SlabRole sr = slab_role(s, mode, i, n);
+  if (!sr.on || !sr.up) return;
+  const int m = P * s.lsz, mn = slab_rows(s, sr.t + 1, P);
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)m * s.lsz) return;
+  const int r = (int)(e / s.lsz), c = (int)(e % s.lsz);
+  const long long r0 = (long long)sr.t * P * s.lsz, rn = (long long)(sr.t + 1) * P * s.lsz;
+  const c64 *u = A + blockIdx.z * amat + (r0 + r) * lda + rn;
+  const c64 *g = Gn + blockIdx.z * wmat + (mn - 1 - c);
+  c64 acc = {0, 0};
+  for (int k = 0; k < s.lsz; ++k) cmac(acc, u[k], g[(long long)(mn - 1 - k) * ldw]);
+  T1[blockIdx.z * tmat + (long long)r * ldt + c] = acc;
+}
+
+// upper correction of the whole block (reversed order when rev):
+// W[p][q] -= sum_k T1[row of p][k] A[row of q][first layer of t + 1, k]
+__global__ __launch_bounds__(256) void k_slab_schur_up(const Sub *__restrict__ subs, int s0,
+                                                       const c64 *__restrict__ A, int lda,
+                                                       long long amat, const c64 *__restrict__ T1,
+                                                       int ldt, long long tmat,
+                                                       c64 *__restrict__ W, int ldw,
+                                                       long long wmat, int mode, int i, int n,
+                                                       int P) {
+  const Sub s = subs[s0 + blockIdx.z];
+  const SlabRole sr = slab_role(s, mode, i, n);
+  if (!sr.on || !sr.up) return;
+  const int m = P * s.lsz;
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)m * m) return;
+  const int p = (int)(e / m), q = (int)(e % m);
+  const int rp = sr.rev ? m - 1 - p : p, rq = sr.rev ? m - 1 - q : q;
+  const long long r0 = (long long)sr.t * P * s.lsz, rn = (long long)(sr.t + 1) * P * s.lsz;
+  const c64 *t1 = T1 + blockIdx.z * tmat + (long long)rp * ldt;
+  const c64 *u = A + blockIdx.z * amat + (r0 + rq) * lda + rn;
+  c64 acc = {0, 0};
+  for (int k = 0; k < s.lsz; ++k) cmac(acc, t1[k], u[k]);
+  c64 &w = W[blockIdx.z * wmat + (long long)p * ldw + q];
+  w = w - acc;
+}
+
+// store G_t (W, reversed when rev) transposed with rows padded to slab_ld
+// and, for t >= 1, the coupling band of slab t
 template <typename TB>
 __global__ __launch_bounds__(256) void k_slab_store(const Sub *__restrict__ subs, int s0,
                                                     const c64 *__restrict__ A, int lda,
                                                     long long amat, const c64 *__restrict__ W,
                                                     int ldw, long long wmat,
-                                                    cx<TB> *__restrict__ B, int t, int P,
-                                                    int dim) {
+                                                    cx<TB> *__restrict__ B, int mode, int i, int n,
+                                                    int P, int dim) {
   const Sub s = subs[s0 + blockIdx.z];
-  if (t >= s.nsl) return;
+  const SlabRole sr = slab_role(s, mode, i, n);
+  if (!sr.on) return;
+  const int t = sr.t;
   const int m = slab_rows(s, t, P);
   const long long e = blockIdx.x * 256LL + threadIdx.x;
   const long long ng = (long long)m * m;
   const int cb = band_width(P, dim);
   if (e < ng) {
     const int b = (int)(e / m), a = (int)(e % m);
-    const c64 v = W[blockIdx.z * wmat + (long long)a * ldw + b];
+    const int wa = sr.rev ? m - 1 - a : a, wb = sr.rev ? m - 1 - b : b;
+    const c64 v = W[blockIdx.z * wmat + (long long)wa * ldw + wb];
     B[slab_goff(s, t, P) + (long long)b * slab_ld(m) + a] = cx<TB>{(TB)v.re, (TB)v.im};
   } else if (t >= 1 && e < ng + (long long)s.lsz * cb) {
     const long long f = e - ng;
@@ -151,70 +277,117 @@ __global__ __launch_bounds__(256) void k_slab_store(const Sub *__restrict__ subs
   }
 }
 
-// store E_{t-1} = T1 (rows of slab t - 1, columns: first layer of slab t) transposed
+// store E_{t-1} = T1 of the lower correction (rows of slab t - 1, columns:
+// first layer of slab t) transposed
 template <typename TB>
 __global__ __launch_bounds__(256) void k_slab_store_e(const Sub *__restrict__ subs, int s0,
                                                       const c64 *__restrict__ T1, int ldt,
-                                                      long long tmat, cx<TB> *__restrict__ B, int t,
-                                                      int P) {
+                                                      long long tmat, cx<TB> *__restrict__ B,
+                                                      int mode, int i, int n, int P) {
   const Sub s = subs[s0 + blockIdx.z];
-  if (t >= s.nsl) return;
+  const SlabRole sr = slab_role(s, mode, i, n);
+  if (!sr.on || !sr.lo) return;
   const int mp = P * s.lsz;
   const long long e = blockIdx.x * 256LL + threadIdx.x;
   if (e >= (long long)s.lsz * mp) return;
   const int cc = (int)(e / mp), r = (int)(e % mp);
   const c64 v = T1[blockIdx.z * tmat + (long long)r * ldt + cc];
-  B[s.ecoff + ((long long)(t - 1) * s.lsz + cc) * slab_ld(mp) + r] = cx<TB>{(TB)v.re, (TB)v.im};
+  B[s.ecoff + ((long long)(sr.t - 1) * s.lsz + cc) * slab_ld(mp) + r] =
+      cx<TB>{(TB)v.re, (TB)v.im};
 }
 
-int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat, c64 *W0,
-                       c64 *W1, c64 *T1, int ldw, int ldt, c64 *pws, hipStream_t s) {
+// One step of the twisted elimination for every subdomain of the batch: the
+// block in W, its corrections from the lower neighbour's inverse in Wlo and
+// the upper neighbour's in Wup (null: none at this step), inversion, store.
+static int slab_setup_step(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat,
+                           c64 *W, const c64 *Wlo, const c64 *Wup, c64 *T1, int ldw, int ldt,
+                           int max_lsz, int max_m, c64 *pws, int mode, int i, int n,
+                           hipStream_t s) {
   const int P = c->P;
   const long long wmat = (long long)ldw * ldw, tmat = (long long)ldw * ldt;
-  int max_nsl = 0, max_m = 0;
-  long long max_lsz = 0;
+  const long long ml = (long long)P * max_lsz;
+  const bool f32 = c->desc.gemm == TH_GEMM_F32;
+  hipLaunchKernelGGL(k_slab_copy, dim3((unsigned)ceil_div_ll(wmat, 256), 1, nb), dim3(256), 0, s,
+                     c->d_subs, s0, A, npad, amat, W, ldw, wmat, mode, i, n, P);
+  if (Wlo) {
+    hipLaunchKernelGGL(k_slab_t1, dim3((unsigned)ceil_div_ll(ml * max_lsz, 256), 1, nb),
+                       dim3(256), 0, s, c->d_subs, s0, A, npad, amat, Wlo, ldw, wmat, T1, ldt,
+                       tmat, mode, i, n, P);
+    hipLaunchKernelGGL(k_slab_schur, dim3((unsigned)ceil_div_ll((long long)max_lsz * max_lsz, 256),
+                                          1, nb),
+                       dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)T1, ldt, tmat,
+                       W, ldw, wmat, mode, i, n, P);
+    const dim3 ge((unsigned)ceil_div_ll(ml * max_lsz, 256), 1, nb);
+    if (f32)
+      hipLaunchKernelGGL((k_slab_store_e<float>), ge, dim3(256), 0, s, c->d_subs, s0,
+                         (const c64 *)T1, ldt, tmat, (cx<float> *)c->d_B, mode, i, n, P);
+    else
+      hipLaunchKernelGGL((k_slab_store_e<double>), ge, dim3(256), 0, s, c->d_subs, s0,
+                         (const c64 *)T1, ldt, tmat, (cx<double> *)c->d_B, mode, i, n, P);
+  }
+  if (Wup) {
+    hipLaunchKernelGGL(k_slab_t1_up, dim3((unsigned)ceil_div_ll(ml * max_lsz, 256), 1, nb),
+                       dim3(256), 0, s, c->d_subs, s0, A, npad, amat, Wup, ldw, wmat, T1, ldt,
+                       tmat, mode, i, n, P);
+    hipLaunchKernelGGL(k_slab_schur_up, dim3((unsigned)ceil_div_ll(ml * ml, 256), 1, nb),
+                       dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)T1, ldt, tmat,
+                       W, ldw, wmat, mode, i, n, P);
+  }
+  TH_HIP_CHECK_RET(hipGetLastError());
+  int rc = gj_invert_batched(W, ldw, ldw, wmat, nb, s, pws);
+  if (rc) return rc;
+  const long long nst = (long long)max_m * max_m + max_lsz * band_width(P, c->dim);
+  if (f32)
+    hipLaunchKernelGGL((k_slab_store<float>), dim3((unsigned)ceil_div_ll(nst, 256), 1, nb),
+                       dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)W, ldw, wmat,
+                       (cx<float> *)c->d_B, mode, i, n, P, c->dim);
+  else
+    hipLaunchKernelGGL((k_slab_store<double>), dim3((unsigned)ceil_div_ll(nst, 256), 1, nb),
+                       dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)W, ldw, wmat,
+                       (cx<double> *)c->d_B, mode, i, n, P, c->dim);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// The lower chain in buffers W[0] / W[1], the upper chain in the two buffers
+// its last inverse does not occupy, the middle in the remaining one.
+int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat,
+                       c64 *const W[3], c64 *T1, int ldw, int ldt, c64 *pws, hipStream_t s) {
+  const int P = c->P;
+  int max_nsl = 0, max_m = 0, max_lsz = 0;
   for (int i = s0; i < s0 + nb; ++i) {
     max_nsl = std::max(max_nsl, c->subs[i].nsl);
     max_m = std::max(max_m, slab_rows(c->subs[i], c->subs[i].nsl - 1, P));
-    max_lsz = std::max<long long>(max_lsz, c->subs[i].lsz);
+    max_lsz = std::max(max_lsz, c->subs[i].lsz);
   }
-  const int cb = band_width(P, c->dim);
-  c64 *W = W0, *Wp = W1;
-  for (int t = 0; t < max_nsl; ++t) {
-    hipLaunchKernelGGL(k_slab_copy, dim3((unsigned)ceil_div_ll(wmat, 256), 1, nb), dim3(256), 0, s,
-                       c->d_subs, s0, A, npad, amat, W, ldw, wmat, t, P);
-    if (t > 0) {
-      hipLaunchKernelGGL(k_slab_t1, dim3((unsigned)ceil_div_ll((long long)P * max_lsz * max_lsz, 256),
-                                         1, nb),
-                         dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)Wp, ldw,
-                         wmat, T1, ldt, tmat, t, P);
-      hipLaunchKernelGGL(k_slab_schur, dim3((unsigned)ceil_div_ll(max_lsz * max_lsz, 256), 1, nb),
-                         dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)T1, ldt,
-                         tmat, W, ldw, wmat, t, P);
-      const dim3 ge((unsigned)ceil_div_ll((long long)P * max_lsz * max_lsz, 256), 1, nb);
-      if (c->desc.gemm == TH_GEMM_F32)
-        hipLaunchKernelGGL((k_slab_store_e<float>), ge, dim3(256), 0, s, c->d_subs, s0,
-                           (const c64 *)T1, ldt, tmat, (cx<float> *)c->d_B, t, P);
-      else
-        hipLaunchKernelGGL((k_slab_store_e<double>), ge, dim3(256), 0, s, c->d_subs, s0,
-                           (const c64 *)T1, ldt, tmat, (cx<double> *)c->d_B, t, P);
-    }
-    TH_HIP_CHECK_RET(hipGetLastError());
-    int rc = gj_invert_batched(W, ldw, ldw, wmat, nb, s, pws);
-    if (rc) return rc;
-    const long long nst = (long long)max_m * max_m + max_lsz * cb;
-    if (c->desc.gemm == TH_GEMM_F32)
-      hipLaunchKernelGGL((k_slab_store<float>), dim3((unsigned)ceil_div_ll(nst, 256), 1, nb),
-                         dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)W, ldw, wmat,
-                         (cx<float> *)c->d_B, t, P, c->dim);
-    else
-      hipLaunchKernelGGL((k_slab_store<double>), dim3((unsigned)ceil_div_ll(nst, 256), 1, nb),
-                         dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)W, ldw, wmat,
-                         (cx<double> *)c->d_B, t, P, c->dim);
-    TH_HIP_CHECK_RET(hipGetLastError());
-    std::swap(W, Wp);
+  const int nlo = (max_nsl - 1) / 2, nup = max_nsl - 1 - nlo;
+  int prev = -1, cur = 0, rc = 0;
+  for (int i = 0; i < nlo && rc == 0; ++i) {
+    rc = slab_setup_step(c, s0, nb, A, npad, amat, W[cur], prev >= 0 ? W[prev] : nullptr,
+                         nullptr, T1, ldw, ldt, max_lsz, max_m, pws, kLowerChain, i, nlo, s);
+    prev = cur;
+    cur = 1 - cur;
   }
-  return 0;
+  const int wlo = prev;
+  int free_buf[2], nf = 0;
+  for (int k = 0; k < 3; ++k)
+    if (k != wlo && nf < 2) free_buf[nf++] = k;
+  prev = -1;
+  for (int i = 0; i < nup && rc == 0; ++i) {
+    cur = free_buf[i & 1];
+    rc = slab_setup_step(c, s0, nb, A, npad, amat, W[cur], nullptr,
+                         prev >= 0 ? W[prev] : nullptr, T1, ldw, ldt, max_lsz, max_m, pws,
+                         kUpperChain, i, nup, s);
+    prev = cur;
+  }
+  const int wup = prev;
+  int mid = 0;
+  while (mid == wlo || mid == wup) ++mid;
+  if (rc == 0)
+    rc = slab_setup_step(c, s0, nb, A, npad, amat, W[mid], wlo >= 0 ? W[wlo] : nullptr,
+                         wup >= 0 ? W[wup] : nullptr, T1, ldw, ldt, max_lsz, max_m, pws, kMiddle,
+                         0, 0, s);
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -307,30 +480,126 @@ __device__ __forceinline__ bool slab_sum_waves(cx<T> (&acc)[RC], cx<T> *__restri
   return true;
 }
 
-// Forward step of slab t for all subdomains and RC right-hand sides: the
-// right-hand side r_t - L_t y_{t-1} is formed in LDS by every workgroup of the
-// subdomain (the band loops unrolled, so their loads are issued together);
-// a workgroup then covers 64 rows a of the slab, one per lane, its four
-// wavefronts reading a quarter each of the rows b of the stored G_t^T.
-// LDS: the slab's right-hand sides [ldx][RC], then the partial sums.
+// acc[q] = sum over the band of first-layer node j of slab t (t >= 1) of
+// A[t][t-1] times v[slab t - 1] (vb: offset of slab t - 1 of right-hand side
+// r0).  Branch-free: positions outside Omega are clamped to a node inside
+// (its value is finite) and meet a zero band coefficient, so every load can
+// be issued before its use.
+template <typename TB, typename T, int RC, int P, int DIM>
+__device__ __forceinline__ void band_lower(const Sub &s, const cx<TB> *__restrict__ Ct,
+                                           const cx<T> *__restrict__ V, long long vb,
+                                           long long xrows, int nq, int j, cx<T> (&acc)[RC]) {
+  constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
+  const int xa = j % s.nox, ya = DIM == 3 ? j / s.nox : 0;
+  const cx<TB> *cr = Ct + (long long)j * CB;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
+#pragma unroll
+  for (int jy = 0; jy < (DIM == 3 ? W2 : 1); ++jy) {
+    const int yb = DIM == 3 ? min(max(ya - P + jy, 0), s.noy - 1) : 0;
+#pragma unroll
+    for (int jx = 0; jx < W2; ++jx) {
+      const int xb = min(max(xa - P + jx, 0), s.nox - 1);
+      cx<TB> l[P];
+      cx<T> y[P][RC];
+#pragma unroll
+      for (int lb = 0; lb < P; ++lb) {
+        l[lb] = cr[(jy * W2 + jx) * P + lb];
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+          y[lb][q] = V[vb + (long long)min(q, nq - 1) * xrows + lb * s.lsz + yb * s.nox + xb];
+      }
+#pragma unroll
+      for (int lb = 0; lb < P; ++lb)
+#pragma unroll
+        for (int q = 0; q < RC; ++q) cmac(acc[q], ccast<T>(l[lb]), y[lb][q]);
+    }
+  }
+}
+
+// acc[q] = (A[t][t+1] v[first layer of t + 1])[j] for node j of slab t
+// (t + 1 <= nsl - 1, so slab t has P layers): the band of slab t + 1 read
+// transposed, node j in layer lb couples to the first-layer nodes a within P
+// positions, through band entry ((2P - jy') (2P+1) + 2P - jx') P + lb of a,
+// where a sits at (xj - P + jx', yj - P + jy').  Cn: band of slab t + 1, vn:
+// offset of its first layer.  Out-of-range a are clamped and their
+// coefficient replaced by zero.
+template <typename TB, typename T, int RC, int P, int DIM>
+__device__ __forceinline__ void band_upper(const Sub &s, const cx<TB> *__restrict__ Cn,
+                                           const cx<T> *__restrict__ V, long long vn,
+                                           long long xrows, int nq, int j, cx<T> (&acc)[RC]) {
+  constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
+  const int lb = j / s.lsz, jj = j - lb * s.lsz;
+  const int xj = jj % s.nox, yj = DIM == 3 ? jj / s.nox : 0;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
+#pragma unroll
+  for (int jy = 0; jy < (DIM == 3 ? W2 : 1); ++jy) {
+    const int ya = DIM == 3 ? yj - P + jy : 0;
+    const bool iny = DIM == 3 ? (ya >= 0 && ya < s.noy) : true;
+    const int yac = DIM == 3 ? min(max(ya, 0), s.noy - 1) : 0;
+    cx<TB> l[W2];
+    cx<T> y[W2][RC];
+#pragma unroll
+    for (int jx = 0; jx < W2; ++jx) {
+      const int xa = xj - P + jx;
+      const int xac = min(max(xa, 0), s.nox - 1);
+      const int a = yac * s.nox + xac;
+      const int k = (((DIM == 3 ? 2 * P - jy : 0) * W2) + 2 * P - jx) * P + lb;
+      l[jx] = Cn[(long long)a * CB + k];
+      if (!(iny && xa >= 0 && xa < s.nox)) l[jx] = cx<TB>{0, 0};
+#pragma unroll
+      for (int q = 0; q < RC; ++q) y[jx][q] = V[vn + (long long)min(q, nq - 1) * xrows + a];
+    }
+#pragma unroll
+    for (int jx = 0; jx < W2; ++jx)
+#pragma unroll
+      for (int q = 0; q < RC; ++q) cmac(acc[q], ccast<T>(l[jx]), y[jx][q]);
+  }
+}
+
+// Forward step i of the twisted sweep (i < S: the lower chain in blockIdx.y
+// < nyb, the upper chain above; i = S: the middles) for all subdomains and RC
+// right-hand sides: the right-hand side of the slab is formed in LDS by every
+// workgroup of it (band products unrolled, so their loads are issued
+// together); a workgroup then covers 64 rows a of the slab, one per lane,
+// its four wavefronts reading a quarter each of the rows b of the stored
+// G_t^T.  LDS: the slab's right-hand sides [ldx][RC], then the partial sums.
 template <typename TB, typename T, int RC, int P, int DIM>
 __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
                                                  const cx<TB> *__restrict__ B,
                                                  const cx<T> *__restrict__ Z,
                                                  cx<T> *__restrict__ V, long long xrows,
-                                                 int nrhs, int t, int ldx) {
+                                                 int nrhs, int i, int S, int nyb, int ldx) {
   constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
   extern __shared__ __align__(16) char slab_smem[];
   cx<T> *x = (cx<T> *)slab_smem;
   cx<T> *red = x + (long long)ldx * RC;
   const Sub s = subs[blockIdx.x];
-  if (t >= s.nsl) return;  // uniform
+  const int M = slab_mid(s), U = s.nsl - 1 - M;
+  int t, lo, up, yb = blockIdx.y;
+  if (i == S) {
+    t = M;
+    lo = M >= 1;
+    up = U >= 1;
+  } else if (yb < nyb) {
+    t = i - (S - M);
+    lo = t >= 1;
+    up = 0;
+  } else {
+    yb -= nyb;
+    const int j = i - (S - U);
+    t = j >= 0 ? s.nsl - 1 - j : -1;
+    lo = 0;
+    up = j >= 1;
+  }
+  if (t < 0) return;  // uniform: no slab of this chain at this step
   const int m = slab_rows(s, t, P);
-  const int a0 = blockIdx.y * 64;
+  const int a0 = yb * 64;
   if (a0 >= m) return;  // uniform
   const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
   const long long row0 = (long long)t * P * s.lsz;
-  const cx<TB> *Ct = B + s.coff + (long long)(t - 1) * s.lsz * CB;
+  const long long vq = (long long)r0 * xrows + s.xoff;
   const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
   const int bq = (m + 3) / 4, ld = slab_ld(m);
   const int gb0 = min(wave * bq, m), gb1 = min((wave + 1) * bq, m);
@@ -341,38 +610,20 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
     cx<T> v[RC];
 #pragma unroll
     for (int q = 0; q < RC; ++q)
-      v[q] = q < nq ? Z[(long long)(r0 + q) * xrows + s.xoff + row0 + j] : cx<T>{0, 0};
-    if (t > 0 && j < s.lsz) {
-      // Branch-free band product: positions outside Omega are clamped to a
-      // node inside (its value is finite) and meet a zero band coefficient,
-      // so every load can be issued before its use.
-      const int xa = j % s.nox, ya = DIM == 3 ? j / s.nox : 0;
-      const cx<TB> *cr = Ct + (long long)j * CB;
-      const long long vb = (long long)r0 * xrows + s.xoff + (long long)(t - 1) * P * s.lsz;
+      v[q] = q < nq ? Z[vq + (long long)q * xrows + row0 + j] : cx<T>{0, 0};
+    if (lo && j < s.lsz) {
+      cx<T> w[RC];
+      band_lower<TB, T, RC, P, DIM>(s, B + s.coff + (long long)(t - 1) * s.lsz * CB, V,
+                                    vq + (long long)(t - 1) * P * s.lsz, xrows, nq, j, w);
 #pragma unroll
-      for (int jy = 0; jy < (DIM == 3 ? W2 : 1); ++jy) {
-        const int yb = DIM == 3 ? min(max(ya - P + jy, 0), s.noy - 1) : 0;
+      for (int q = 0; q < RC; ++q) v[q] = v[q] - w[q];
+    }
+    if (up) {
+      cx<T> w[RC];
+      band_upper<TB, T, RC, P, DIM>(s, B + s.coff + (long long)t * s.lsz * CB, V,
+                                    vq + (long long)(t + 1) * P * s.lsz, xrows, nq, j, w);
 #pragma unroll
-        for (int jx = 0; jx < W2; ++jx) {
-          const int xb = min(max(xa - P + jx, 0), s.nox - 1);
-          cx<TB> l[P];
-          cx<T> y[P][RC];
-#pragma unroll
-          for (int lb = 0; lb < P; ++lb) {
-            l[lb] = cr[(jy * W2 + jx) * P + lb];
-#pragma unroll
-            for (int q = 0; q < RC; ++q)
-              y[lb][q] = V[vb + (long long)min(q, nq - 1) * xrows + lb * s.lsz + yb * s.nox + xb];
-          }
-#pragma unroll
-          for (int lb = 0; lb < P; ++lb)
-#pragma unroll
-            for (int q = 0; q < RC; ++q) {
-              v[q].re -= (T)l[lb].re * y[lb][q].re - (T)l[lb].im * y[lb][q].im;
-              v[q].im -= (T)l[lb].re * y[lb][q].im + (T)l[lb].im * y[lb][q].re;
-            }
-        }
-      }
+      for (int q = 0; q < RC; ++q) v[q] = v[q] - w[q];
     }
 #pragma unroll
     for (int q = 0; q < RC; ++q) x[j * RC + q] = v[q];
@@ -383,43 +634,64 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
   if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
-    if (q < nq) V[(long long)(r0 + q) * xrows + s.xoff + row0 + a] = acc[q];
+    if (q < nq) V[vq + (long long)q * xrows + row0 + a] = acc[q];
 }
 
-// Backward step of slab t < nsl - 1: x_t = y_t - E_t w with w = x_{t+1} on
-// the first layer of slab t + 1 (staged in LDS), the same division of work
-// as the forward step over the n_layer rows of the stored E_t^T.
-template <typename TB, typename T, int RC>
+// Backward step j of the twisted sweep: the lower chain's slab M - 1 - j in
+// blockIdx.y < nyb, x_t = y_t - E_t w with w = x_{t+1} on the first layer of
+// slab t + 1; the upper chain's slab M + 1 + j above, x_t = y_t - G_t[:, first
+// layer] w with w = A[t][t-1] x_{t-1} (band product).  w is staged in LDS;
+// the same division of work as the forward step over the n_layer rows of the
+// stored E_t^T (the first n_layer rows of the stored G_t^T).
+template <typename TB, typename T, int RC, int P, int DIM>
 __global__ __launch_bounds__(256) void k_slab_bwd(const Sub *__restrict__ subs,
                                                  const cx<TB> *__restrict__ B,
                                                  cx<T> *__restrict__ V, long long xrows, int nrhs,
-                                                 int t, int ldx, int P) {
+                                                 int jstep, int nyb, int ldx) {
+  constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
   extern __shared__ __align__(16) char slab_smem[];
   cx<T> *w = (cx<T> *)slab_smem;
   cx<T> *red = w + (long long)ldx * RC;
   const Sub s = subs[blockIdx.x];
-  if (t >= s.nsl - 1) return;  // uniform
-  const int m = P * s.lsz, nl = s.lsz;
-  const int a0 = blockIdx.y * 64;
+  const int M = slab_mid(s), U = s.nsl - 1 - M;
+  int yb = blockIdx.y;
+  const bool upper = yb >= nyb;
+  if (upper) yb -= nyb;
+  if (upper ? jstep >= U : jstep >= M) return;  // uniform
+  const int t = upper ? M + 1 + jstep : M - 1 - jstep;
+  const int m = slab_rows(s, t, P), nl = s.lsz;
+  const int a0 = yb * 64;
   if (a0 >= m) return;  // uniform
   const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
-  const long long row0 = (long long)t * P * s.lsz, rn = (long long)(t + 1) * P * s.lsz;
-  for (int j = threadIdx.x; j < nl; j += 256)
+  const long long vq = (long long)r0 * xrows + s.xoff;
+  const long long row0 = (long long)t * P * s.lsz;
+  for (int c = threadIdx.x; c < nl; c += 256) {
+    cx<T> v[RC];
+    if (upper) {
+      band_lower<TB, T, RC, P, DIM>(s, B + s.coff + (long long)(t - 1) * s.lsz * CB, V,
+                                    vq + (long long)(t - 1) * P * s.lsz, xrows, nq, c, v);
+    } else {
 #pragma unroll
-    for (int q = 0; q < RC; ++q)
-      w[j * RC + q] = q < nq ? V[(long long)(r0 + q) * xrows + s.xoff + rn + j] : cx<T>{0, 0};
+      for (int q = 0; q < RC; ++q)
+        v[q] = q < nq ? V[vq + (long long)q * xrows + (long long)(t + 1) * P * s.lsz + c]
+                      : cx<T>{0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < RC; ++q) w[c * RC + q] = v[q];
+  }
   __syncthreads();
   const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
   const int cq = (nl + 3) / 4;
-  cx<T> acc[RC];
   const int ld = slab_ld(m);
-  slab_gemv_row<TB, T, RC>(B + s.ecoff + (long long)t * nl * ld + min(a, ld - 1), ld,
-                           min(wave * cq, nl), min((wave + 1) * cq, nl), w, acc);
+  const cx<TB> *g = upper ? B + slab_goff(s, t, P) : B + s.ecoff + (long long)t * nl * ld;
+  cx<T> acc[RC];
+  slab_gemv_row<TB, T, RC>(g + min(a, ld - 1), ld, min(wave * cq, nl), min((wave + 1) * cq, nl), w,
+                           acc);
   if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
     if (q < nq) {
-      cx<T> &o = V[(long long)(r0 + q) * xrows + s.xoff + row0 + a];
+      cx<T> &o = V[vq + (long long)q * xrows + row0 + a];
       o = o - acc[q];
     }
 }
@@ -447,14 +719,19 @@ static int slab_sweeps_pd(const th_ctx *c, int nrhs, hipStream_t s) {
   const unsigned nsub = (unsigned)c->subs.size();
   const int ldx = c->max_slab_rows;
   const size_t shm = ((size_t)ldx + 256) * RC * sizeof(cx<T>);
-  const dim3 grid(nsub, (unsigned)ceil_div(ldx, 64), (unsigned)ceil_div(nrhs, RC));
+  const int nyb = ceil_div(ldx, 64);
+  const unsigned nz = (unsigned)ceil_div(nrhs, RC);
+  const int S = c->max_nsl / 2;  // chain steps: the longest upper chain
   const cx<TB> *B = (const cx<TB> *)c->d_B;
-  for (int t = 0; t < c->max_nsl; ++t)
-    hipLaunchKernelGGL((k_slab_fwd<TB, T, RC, P, DIM>), grid, dim3(256), shm, s, c->d_subs, B,
-                       (const cx<T> *)c->w_x, (cx<T> *)c->w_z, c->x_rows, nrhs, t, ldx);
-  for (int t = c->max_nsl - 2; t >= 0; --t)
-    hipLaunchKernelGGL((k_slab_bwd<TB, T, RC>), grid, dim3(256), shm, s, c->d_subs, B,
-                       (cx<T> *)c->w_z, c->x_rows, nrhs, t, ldx, P);
+  for (int i = 0; i <= S; ++i)
+    hipLaunchKernelGGL((k_slab_fwd<TB, T, RC, P, DIM>),
+                       dim3(nsub, (unsigned)(i < S ? 2 * nyb : nyb), nz), dim3(256), shm, s,
+                       c->d_subs, B, (const cx<T> *)c->w_x, (cx<T> *)c->w_z, c->x_rows, nrhs, i,
+                       S, nyb, ldx);
+  for (int j = 0; j < S; ++j)
+    hipLaunchKernelGGL((k_slab_bwd<TB, T, RC, P, DIM>), dim3(nsub, (unsigned)(2 * nyb), nz),
+                       dim3(256), shm, s, c->d_subs, B, (cx<T> *)c->w_z, c->x_rows, nrhs, j, nyb,
+                       ldx);
   return 0;
 }
 
