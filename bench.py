@@ -108,9 +108,13 @@ def subdomain_sizes(N, p, l_dd, dim=2):
 
 def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes):
     """Algorithmic bytes and flops of one application in the slab-factor
-    layout: every stored G_t and coupling band read by the forward sweep, every
-    E_t (rows of slab t x first layer of slab t + 1) by the backward sweep, and
-    the patch X_i and the output rows Y_i once per right-hand side."""
+    layout with the twisted elimination (middle slab M = (nsl - 1) // 2):
+    every stored G_t read by the forward sweep; the backward sweep reads E_t
+    (rows of slab t x first layer of t + 1) for the lower slabs t < M and the
+    first-layer rows of G_t for the upper slabs t > M; the coupling bands of
+    slabs 1 .. nsl - 1 once in the forward sweep and those of the upper slabs
+    again in the backward one; the patch X_i and the output rows Y_i once per
+    right-hand side."""
     import itertools
     import math
     M = math.ceil(N / l_dd)
@@ -127,8 +131,12 @@ def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes):
         nu = [sizes[b] * p + 1 for b in idx]
         nsl, lsz = ocells[idx[-1]], math.prod(no[:-1])
         m, ml = p * lsz, (p + 1) * lsz
-        g_entries += (nsl - 1) * m * m + ml * ml + (nsl - 1) * m * lsz  # G_t, then E_t
-        band_entries += (nsl - 1) * lsz * cb
+        mid = (nsl - 1) // 2
+        nup = nsl - 1 - mid
+        g_entries += (nsl - 1) * m * m + ml * ml            # G_t, forward
+        g_entries += mid * m * lsz                           # E_t, lower chain
+        g_entries += (nup - 1) * m * lsz + ml * lsz if nup else 0  # G_t rows, upper chain
+        band_entries += (nsl - 1 + nup) * lsz * cb
         vec += math.prod(no) + math.prod(nu)
     byts = (g_entries + band_entries) * mat_bytes + vec * vec_bytes * nrhs
     return byts, 8.0 * (g_entries + band_entries) * nrhs

@@ -460,12 +460,18 @@ __device__ __forceinline__ void slab_gemv_ahead(const cx<TB> *__restrict__ g, in
   for (int q = 0; q < RC; ++q) acc[q] = acc[q] + rest[q];
 }
 
-// The four wavefronts of a workgroup share its 64 output rows and split the
-// rows b of G_t^T in quarters; their partial sums are added in wavefront order
-// through LDS (red: 4 x 64 x RC) by the first wavefront, which returns them in
-// acc (other wavefronts return false).
-template <typename T, int RC>
+// Wavefronts per workgroup of the forward and backward sweeps (measured on
+// C2: 8 and 2 take a smoother step from 1.095 to 1.076 ms against 4 and 4;
+// the backward rows, n_layer per slab, are too few for more).  The NW
+// wavefronts of a workgroup share its 64 output rows and split the rows b of
+// G_t^T (E_t^T) in NW parts; their partial sums are added in wavefront order
+// through LDS (red: NW x 64 x RC) by the first wavefront, which returns them
+// in acc (other wavefronts return false).
+constexpr int kFwdWaves = 8, kBwdWaves = 2;
+
+template <typename T, int RC, int NW>
 __device__ __forceinline__ bool slab_sum_waves(cx<T> (&acc)[RC], cx<T> *__restrict__ red) {
+  if (NW == 1) return true;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
   for (int q = 0; q < RC; ++q) red[(wave * 64 + lane) * RC + q] = acc[q];
@@ -474,7 +480,7 @@ __device__ __forceinline__ bool slab_sum_waves(cx<T> (&acc)[RC], cx<T> *__restri
 #pragma unroll
   for (int q = 0; q < RC; ++q) {
     cx<T> v = red[lane * RC + q];
-    for (int w = 1; w < 4; ++w) v = v + red[(w * 64 + lane) * RC + q];
+    for (int w = 1; w < NW; ++w) v = v + red[(w * 64 + lane) * RC + q];
     acc[q] = v;
   }
   return true;
@@ -563,10 +569,10 @@ __device__ __forceinline__ void band_upper(const Sub &s, const cx<TB> *__restric
 // right-hand sides: the right-hand side of the slab is formed in LDS by every
 // workgroup of it (band products unrolled, so their loads are issued
 // together); a workgroup then covers 64 rows a of the slab, one per lane,
-// its four wavefronts reading a quarter each of the rows b of the stored
+// its kFwdWaves wavefronts reading a part each of the rows b of the stored
 // G_t^T.  LDS: the slab's right-hand sides [ldx][RC], then the partial sums.
 template <typename TB, typename T, int RC, int P, int DIM>
-__global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
+__global__ __launch_bounds__(64 * kFwdWaves) void k_slab_fwd(const Sub *__restrict__ subs,
                                                  const cx<TB> *__restrict__ B,
                                                  const cx<T> *__restrict__ Z,
                                                  cx<T> *__restrict__ V, long long xrows,
@@ -601,12 +607,12 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
   const long long row0 = (long long)t * P * s.lsz;
   const long long vq = (long long)r0 * xrows + s.xoff;
   const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int bq = (m + 3) / 4, ld = slab_ld(m);
+  const int bq = (m + kFwdWaves - 1) / kFwdWaves, ld = slab_ld(m);
   const int gb0 = min(wave * bq, m), gb1 = min((wave + 1) * bq, m);
   const cx<TB> *gp = B + slab_goff(s, t, P) + min(a, ld - 1);
   cx<T> ga[kRowsAhead];
   slab_rows_ahead<TB, T>(gp, ld, gb0, gb1, ga);
-  for (int j = threadIdx.x; j < m; j += 256) {
+  for (int j = threadIdx.x; j < m; j += 64 * kFwdWaves) {
     cx<T> v[RC];
 #pragma unroll
     for (int q = 0; q < RC; ++q)
@@ -631,7 +637,7 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
   __syncthreads();
   cx<T> acc[RC];
   slab_gemv_ahead<TB, T, RC>(gp, ld, gb0, gb1, ga, x, acc);
-  if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
+  if (!slab_sum_waves<T, RC, kFwdWaves>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
     if (q < nq) V[vq + (long long)q * xrows + row0 + a] = acc[q];
@@ -641,10 +647,10 @@ __global__ __launch_bounds__(256) void k_slab_fwd(const Sub *__restrict__ subs,
 // blockIdx.y < nyb, x_t = y_t - E_t w with w = x_{t+1} on the first layer of
 // slab t + 1; the upper chain's slab M + 1 + j above, x_t = y_t - G_t[:, first
 // layer] w with w = A[t][t-1] x_{t-1} (band product).  w is staged in LDS;
-// the same division of work as the forward step over the n_layer rows of the
-// stored E_t^T (the first n_layer rows of the stored G_t^T).
+// 64 output rows per workgroup, its kBwdWaves wavefronts splitting the n_layer
+// rows of the stored E_t^T (the first n_layer rows of the stored G_t^T).
 template <typename TB, typename T, int RC, int P, int DIM>
-__global__ __launch_bounds__(256) void k_slab_bwd(const Sub *__restrict__ subs,
+__global__ __launch_bounds__(64 * kBwdWaves) void k_slab_bwd(const Sub *__restrict__ subs,
                                                  const cx<TB> *__restrict__ B,
                                                  cx<T> *__restrict__ V, long long xrows, int nrhs,
                                                  int jstep, int nyb, int ldx) {
@@ -665,7 +671,7 @@ __global__ __launch_bounds__(256) void k_slab_bwd(const Sub *__restrict__ subs,
   const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
   const long long vq = (long long)r0 * xrows + s.xoff;
   const long long row0 = (long long)t * P * s.lsz;
-  for (int c = threadIdx.x; c < nl; c += 256) {
+  for (int c = threadIdx.x; c < nl; c += 64 * kBwdWaves) {
     cx<T> v[RC];
     if (upper) {
       band_lower<TB, T, RC, P, DIM>(s, B + s.coff + (long long)(t - 1) * s.lsz * CB, V,
@@ -681,13 +687,13 @@ __global__ __launch_bounds__(256) void k_slab_bwd(const Sub *__restrict__ subs,
   }
   __syncthreads();
   const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int cq = (nl + 3) / 4;
+  const int cq = (nl + kBwdWaves - 1) / kBwdWaves;
   const int ld = slab_ld(m);
   const cx<TB> *g = upper ? B + slab_goff(s, t, P) : B + s.ecoff + (long long)t * nl * ld;
   cx<T> acc[RC];
   slab_gemv_row<TB, T, RC>(g + min(a, ld - 1), ld, min(wave * cq, nl), min((wave + 1) * cq, nl), w,
                            acc);
-  if (!slab_sum_waves<T, RC>(acc, red) || a >= m) return;
+  if (!slab_sum_waves<T, RC, kBwdWaves>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
     if (q < nq) {
@@ -718,19 +724,19 @@ template <typename TB, typename T, int RC, int P, int DIM>
 static int slab_sweeps_pd(const th_ctx *c, int nrhs, hipStream_t s) {
   const unsigned nsub = (unsigned)c->subs.size();
   const int ldx = c->max_slab_rows;
-  const size_t shm = ((size_t)ldx + 256) * RC * sizeof(cx<T>);
+  const size_t shm = ((size_t)ldx + 64 * std::max(kFwdWaves, kBwdWaves)) * RC * sizeof(cx<T>);
   const int nyb = ceil_div(ldx, 64);
   const unsigned nz = (unsigned)ceil_div(nrhs, RC);
   const int S = c->max_nsl / 2;  // chain steps: the longest upper chain
   const cx<TB> *B = (const cx<TB> *)c->d_B;
   for (int i = 0; i <= S; ++i)
     hipLaunchKernelGGL((k_slab_fwd<TB, T, RC, P, DIM>),
-                       dim3(nsub, (unsigned)(i < S ? 2 * nyb : nyb), nz), dim3(256), shm, s,
+                       dim3(nsub, (unsigned)(i < S ? 2 * nyb : nyb), nz), dim3(64 * kFwdWaves), shm, s,
                        c->d_subs, B, (const cx<T> *)c->w_x, (cx<T> *)c->w_z, c->x_rows, nrhs, i,
                        S, nyb, ldx);
   for (int j = 0; j < S; ++j)
     hipLaunchKernelGGL((k_slab_bwd<TB, T, RC, P, DIM>), dim3(nsub, (unsigned)(2 * nyb), nz),
-                       dim3(256), shm, s, c->d_subs, B, (cx<T> *)c->w_z, c->x_rows, nrhs, j, nyb,
+                       dim3(64 * kBwdWaves), shm, s, c->d_subs, B, (cx<T> *)c->w_z, c->x_rows, nrhs, j, nyb,
                        ldx);
   return 0;
 }
@@ -759,7 +765,8 @@ static int slab_apply_t(const th_ctx *c, const void *r, void *y, int nrhs, hipSt
   hipLaunchKernelGGL((k_slab_gather<T>), dim3(ceil_div(c->max_nom, 256), nsub, nrhs), dim3(256), 0,
                      s, c->d_subs, (const cx<T> *)r, (cx<T> *)c->w_x, c->P, c->n1, c->nf,
                      c->x_rows);
-  const size_t row_bytes = ((size_t)c->max_slab_rows + 256) * sizeof(cx<T>);
+  const size_t row_bytes =
+      ((size_t)c->max_slab_rows + 64 * std::max(kFwdWaves, kBwdWaves)) * sizeof(cx<T>);
   int rc;
   if (nrhs >= 4 && 4 * row_bytes <= 48 * 1024)
     rc = slab_sweeps_t<TB, T, 4>(c, nrhs, s);
