@@ -32,8 +32,9 @@
 // couplings A[t][t-1] of every slab t >= 1 as bands: for each first-layer node
 // a the (2P+1)^(d-1) x P block of slab t - 1 nodes within P positions of a in
 // every in-layer direction (zero where a node lies outside Omega or shares no
-// cell with a), read directly by the lower chain and transposed by the upper
-// one; and the E_t of the lower chain (m_t x n_layer, the product the
+// cell with a), stored entry-major (entry k of node a at k n_layer + a, so
+// that neighbouring nodes read neighbouring entries), read directly by the
+// lower chain and transposed by the upper one; and the E_t of the lower chain (m_t x n_layer, the product the
 // elimination forms anyway) transposed, likewise padded.  The upper chain's
 // backward step reads the first n_layer rows of the stored G_t^T (G_t is
 // symmetric).  The bytes per application are the G_t plus a fraction 1/P of
@@ -273,7 +274,8 @@ __global__ __launch_bounds__(256) void k_slab_store(const Sub *__restrict__ subs
     const long long r0 = (long long)t * P * s.lsz;
     c64 v = {0, 0};
     if (col >= 0) v = A[blockIdx.z * amat + (r0 + a) * lda + col];
-    B[s.coff + (long long)(t - 1) * s.lsz * cb + f] = cx<TB>{(TB)v.re, (TB)v.im};
+    B[s.coff + (long long)(t - 1) * s.lsz * cb + (long long)k * s.lsz + a] =
+        cx<TB>{(TB)v.re, (TB)v.im};
   }
 }
 
@@ -495,9 +497,9 @@ template <typename TB, typename T, int RC, int P, int DIM>
 __device__ __forceinline__ void band_lower(const Sub &s, const cx<TB> *__restrict__ Ct,
                                            const cx<T> *__restrict__ V, long long vb,
                                            long long xrows, int nq, int j, cx<T> (&acc)[RC]) {
-  constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
+  constexpr int W2 = 2 * P + 1;
   const int xa = j % s.nox, ya = DIM == 3 ? j / s.nox : 0;
-  const cx<TB> *cr = Ct + (long long)j * CB;
+  const cx<TB> *cr = Ct + j;
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
 #pragma unroll
@@ -510,7 +512,7 @@ __device__ __forceinline__ void band_lower(const Sub &s, const cx<TB> *__restric
       cx<T> y[P][RC];
 #pragma unroll
       for (int lb = 0; lb < P; ++lb) {
-        l[lb] = cr[(jy * W2 + jx) * P + lb];
+        l[lb] = cr[(long long)((jy * W2 + jx) * P + lb) * s.lsz];
 #pragma unroll
         for (int q = 0; q < RC; ++q)
           y[lb][q] = V[vb + (long long)min(q, nq - 1) * xrows + lb * s.lsz + yb * s.nox + xb];
@@ -534,7 +536,7 @@ template <typename TB, typename T, int RC, int P, int DIM>
 __device__ __forceinline__ void band_upper(const Sub &s, const cx<TB> *__restrict__ Cn,
                                            const cx<T> *__restrict__ V, long long vn,
                                            long long xrows, int nq, int j, cx<T> (&acc)[RC]) {
-  constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
+  constexpr int W2 = 2 * P + 1;
   const int lb = j / s.lsz, jj = j - lb * s.lsz;
   const int xj = jj % s.nox, yj = DIM == 3 ? jj / s.nox : 0;
 #pragma unroll
@@ -552,7 +554,7 @@ __device__ __forceinline__ void band_upper(const Sub &s, const cx<TB> *__restric
       const int xac = min(max(xa, 0), s.nox - 1);
       const int a = yac * s.nox + xac;
       const int k = (((DIM == 3 ? 2 * P - jy : 0) * W2) + 2 * P - jx) * P + lb;
-      l[jx] = Cn[(long long)a * CB + k];
+      l[jx] = Cn[(long long)k * s.lsz + a];
       if (!(iny && xa >= 0 && xa < s.nox)) l[jx] = cx<TB>{0, 0};
 #pragma unroll
       for (int q = 0; q < RC; ++q) y[jx][q] = V[vn + (long long)min(q, nq - 1) * xrows + a];
