@@ -36,7 +36,9 @@
 
 namespace th {
 
-constexpr int CW = 8;      // wavefronts (rows) per workgroup in the sweeps
+constexpr int CW = 16;     // wavefronts (rows) per workgroup in the sweeps (each workgroup
+                           // stages the block's right-hand side; 16 halves that redundancy
+                           // against 8: 1.43 -> 1.35 ms per C2 coarse solve)
 constexpr int kAhead = 8;  // row entries per lane loaded before the right-hand side is staged
 constexpr int kCoarseChunk = 256;  // columns per partial sum of the large-slab GEMV
 
@@ -413,7 +415,8 @@ __global__ __launch_bounds__(64 * CW) void k_cbwd(SweepBlk b0, SweepBlk b1, int 
 // budget; slab right-hand sides up to 64 KiB are staged in LDS.  With at least
 // three super-blocks the sweeps are twisted (ceil(ny / K) + 1 launches, else
 // 2 ceil(ny / K) - 1).  BW and latency are a least-squares fit of measured
-// coarse solves over K = 3..10 at ny = L = 401.
+// coarse solves over K = 3..10 at ny = L = 401 (8 wavefronts per workgroup;
+// with 16 the measured optimum stays at K = 4).
 static int choose_lines(int L, int ny, int rc_chunk, int passes) {
   const double bw = 6.3e12, lat = 7.3e-6;
   const int nb_max = std::min(4096, 65536 / (16 * rc_chunk));

@@ -435,7 +435,7 @@ __device__ __forceinline__ void slab_gemv_row(const cx<TB> *__restrict__ g, int 
 // The first kRowsAhead rows of a thread's range, loaded before the workgroup
 // forms its right-hand side (they do not depend on it), so that streaming
 // starts at once; slab_gemv_ahead then consumes them and the rest.
-constexpr int kRowsAhead = 8;
+constexpr int kRowsAhead = 6;
 
 template <typename TB, typename T>
 __device__ __forceinline__ void slab_rows_ahead(const cx<TB> *__restrict__ g, int m, int b0, int b1,
