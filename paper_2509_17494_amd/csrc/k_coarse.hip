@@ -36,9 +36,12 @@
 
 namespace th {
 
-constexpr int CW = 16;     // wavefronts (rows) per workgroup in the sweeps (each workgroup
-                           // stages the block's right-hand side; 16 halves that redundancy
-                           // against 8: 1.43 -> 1.35 ms per C2 coarse solve)
+// wavefronts (rows) per workgroup in the small-slab sweeps for RC right-hand
+// sides per pass: every workgroup stages the block's right-hand side, and 16
+// halve that redundancy against 8 (1.43 -> 1.35 ms per C2 coarse solve, one
+// right-hand side); with 4 right-hand sides the larger register footprint
+// makes 16 slower (C3: 1.81 -> 2.09 ms of coarse sweeps per solve)
+__host__ __device__ constexpr int sweep_waves(int rc) { return rc == 1 ? 16 : 8; }
 constexpr int kAhead = 8;  // row entries per lane loaded before the right-hand side is staged
 constexpr int kCoarseChunk = 256;  // columns per partial sum of the large-slab GEMV
 
@@ -270,7 +273,7 @@ struct SweepBlk {
 // forward step of up to two super-blocks (blockIdx.z), one wavefront per row
 // of G_J, the right-hand side staged in LDS
 template <int RC>
-__global__ __launch_bounds__(64 * CW) void k_cfwd(SweepBlk b0, SweepBlk b1, int nx, int L, int C,
+__global__ __launch_bounds__(64 * sweep_waves(RC)) void k_cfwd(SweepBlk b0, SweepBlk b1, int nx, int L, int C,
                                                   const c64 *__restrict__ st,
                                                   const c64 *__restrict__ rc, c64 *__restrict__ uc,
                                                   int nrhs, long long ncn) {
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(SweepBlk b0, SweepBlk b1, int 
   // the first kAhead entries of the wavefront's row are loaded before the
   // right-hand side is staged (they do not depend on it)
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int arow = blockIdx.x * CW + wave;
+  const int arow = blockIdx.x * sweep_waves(RC) + wave;
   const bool once = gridDim.y == 1;  // rows streamed once when one pass covers all RHS
   const c64 *row = B.G + (long long)min(arow, nb - 1) * B.ld;
   c64 gah[kAhead];
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(64 * CW) void k_cfwd(SweepBlk b0, SweepBlk b1, int 
 
 // backward step of up to two super-blocks (blockIdx.z)
 template <int RC>
-__global__ __launch_bounds__(64 * CW) void k_cbwd(SweepBlk b0, SweepBlk b1, int nx, int L, int C,
+__global__ __launch_bounds__(64 * sweep_waves(RC)) void k_cbwd(SweepBlk b0, SweepBlk b1, int nx, int L, int C,
                                                   const c64 *__restrict__ st, c64 *__restrict__ uc,
                                                   int nrhs, long long ncn) {
   extern __shared__ c64 wsh[];  // RC x L
@@ -355,7 +358,7 @@ __global__ __launch_bounds__(64 * CW) void k_cbwd(SweepBlk b0, SweepBlk b1, int 
   const int SC = 3 * C;
   const c64 *ws = wsh;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int arow = blockIdx.x * CW + wave;
+  const int arow = blockIdx.x * sweep_waves(RC) + wave;
   const bool once = gridDim.y == 1;
   const c64 *row = B.G + (long long)min(arow, nb - 1) * B.ld + (B.up ? 0 : (long long)(B.kJ - 1) * L);
   c64 gah[kAhead];
@@ -606,13 +609,15 @@ static int sweep_t(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) 
   };
   auto fwd = [&](const SweepBlk &b0, const SweepBlk &b1, int nchain) {
     const int nb = std::max(b0.nb, nchain > 1 ? b1.nb : 0);
-    hipLaunchKernelGGL((k_cfwd<RC>), dim3(ceil_div(nb, CW), ychunks, nchain), dim3(64 * CW),
+    hipLaunchKernelGGL((k_cfwd<RC>), dim3(ceil_div(nb, sweep_waves(RC)), ychunks, nchain),
+                       dim3(64 * sweep_waves(RC)),
                        (size_t)max_nb * RC * sizeof(c64), s, b0, b1, nx, L, C, (const c64 *)cd.st,
                        rcv, uc, nrhs, ncn);
   };
   auto bwd = [&](const SweepBlk &b0, const SweepBlk &b1, int nchain) {
     const int nb = std::max(b0.nb, nchain > 1 ? b1.nb : 0);
-    hipLaunchKernelGGL((k_cbwd<RC>), dim3(ceil_div(nb, CW), ychunks, nchain), dim3(64 * CW),
+    hipLaunchKernelGGL((k_cbwd<RC>), dim3(ceil_div(nb, sweep_waves(RC)), ychunks, nchain),
+                       dim3(64 * sweep_waves(RC)),
                        (size_t)L * RC * sizeof(c64), s, b0, b1, nx, L, C, (const c64 *)cd.st, uc,
                        nrhs, ncn);
   };
