@@ -87,7 +87,8 @@ def grf_speed(n_cells: int, dim: int, ell: float, cmin: float, cmax: float,
     sl = tuple(slice(pad, pad + n_cells) for _ in range(dim))
     field = field[sl]
     lo, hi = field.min(), field.max()
-    out = cmin + (field - lo) * ((cmax - cmin) / (hi - lo))
+    scale = (cmax - cmin) / (hi - lo) if hi > lo else 0.0  # a single cell: cmax below
+    out = cmin + (field - lo) * scale
     out[np.unravel_index(np.argmin(field), field.shape)] = cmin
     out[np.unravel_index(np.argmax(field), field.shape)] = cmax
     return np.ascontiguousarray(out)

@@ -46,8 +46,10 @@ def solver(k, p, l_dd, **kw):
 
 # (N, p, l_dd): several subdomain sizes, ragged blocks, every order; l_dd = 1
 # gives subdomains of 2 and 3 slabs (a middle slab with one or two chains of
-# a single slab), l_dd = 8 at N = 37 up to 10 slabs
-CASES_2D = [(19, 4, 6), (33, 4, 8), (7, 6, 3), (5, 8, 2), (37, 2, 8), (12, 2, 5), (9, 4, 1)]
+# a single slab), N = 1 a single subdomain of one slab (the middle alone, no
+# chain), l_dd = 8 at N = 37 up to 10 slabs
+CASES_2D = [(19, 4, 6), (33, 4, 8), (7, 6, 3), (5, 8, 2), (37, 2, 8), (12, 2, 5), (9, 4, 1),
+            (1, 4, 1), (1, 2, 1)]
 
 
 @pytest.mark.parametrize("N,p,l_dd", CASES_2D)
