@@ -21,6 +21,10 @@ the scaling N keeps sigma(0) = -eta^2 (eq. scaling_factor_QSFEM).  Reading of
 the "shift" input: the damping ratio delta = eps / k^2, entering through the
 real wavenumber of the damped medium, k Re sqrt(1 + i delta).  With
 xi_f = k the fit is exactly QSFEM.
+
+Parity unpinned: the "shift" reading (delta > 0).  No passage of the paper
+fixes how damping enters the fitted stencil, so nothing but this definition
+checks the delta > 0 branch; the tests pin delta = 0 only.
 """
 from __future__ import annotations
 
