@@ -67,21 +67,29 @@ typedef enum { TH_GEMM_F64 = 0, TH_GEMM_F32 = 1, TH_GEMM_BF16 = 2 } th_gemm;
 typedef enum {
   TH_COARSE_QSFEM = 0,    /* per-cell QSFEM weights q(h_c k(c)), Sec. 3.3; in 3-D the
                              27-point stencil exact at k (see th_plain_fit3d) */
-  TH_COARSE_WEIGHTS = 1,  /* caller-supplied per-coarse-cell (q0, q_edge, q_diag), or
+  TH_COARSE_PLAINFIT = 1, /* per-cell plain dispersion-matching fit (th_plain_fit, or
+                             th_plain_fit3d in 3-D) */
+  TH_COARSE_MLP = 2,      /* per-cell surrogate network with fallback to the plain fit
+                             (network family matching the dimension) */
+  TH_COARSE_WEIGHTS = 3   /* caller-supplied per-coarse-cell (q0, q_edge, q_diag), or
                              (q0, q_face, q_edge, q_corner) in 3-D; weights are on the
                              2-D element scale (symbol -eta^2 at 0), a 3-D cell
                              contributes h_c q */
-  TH_COARSE_PLAINFIT = 2, /* per-cell plain dispersion-matching fit (th_plain_fit, or
-                             th_plain_fit3d in 3-D) */
-  TH_COARSE_MLP = 3       /* per-cell surrogate network with fallback to the plain fit
-                             (network family matching the dimension) */
 } th_coarse_scheme;
 
 typedef struct th_mlp th_mlp;
 
+/* Outer iteration around the preconditioner f -> TwoGridStep(0, f) (Sec. 4,
+ * Alg. 1).  The paper leaves the Krylov method open.  GMRES_RIGHT and FGMRES
+ * run the same code: right-preconditioned GMRES from x0 = 0 that stores the
+ * preconditioned directions z_j = B(v_j) and forms x = x0 + sum y_j z_j, which
+ * is flexible GMRES (needed when the preconditioner runs in complex64 and
+ * varies with rounding) and equals plain right-preconditioned GMRES for the
+ * FP64 preconditioner. */
 typedef enum {
-  TH_KRYLOV_GMRES = 0,      /* right-preconditioned (flexible) GMRES, x0 = 0 */
-  TH_KRYLOV_STATIONARY = 1  /* u <- TwoGridStep(u, f) repeated */
+  TH_KRYLOV_GMRES_RIGHT = 0,  /* right-preconditioned GMRES (preconditioned directions stored) */
+  TH_KRYLOV_FGMRES = 1,       /* flexible GMRES: the same iteration */
+  TH_KRYLOV_STATIONARY = 2    /* u <- TwoGridStep(u, f) repeated from u = 0 */
 } th_krylov;
 
 /* Layout of the FP64/FP32 subdomain solves (th_fine_desc.layout).
@@ -128,9 +136,14 @@ typedef struct {
 
 typedef struct {
   th_krylov krylov;
-  double rtol;          /* stop when ||f - A u||_2 / ||f||_2 <= rtol (per RHS) */
-  int maxit;            /* preconditioner applications per RHS */
-  int restart;          /* GMRES restart length (<= 0: maxit) */
+  double rtol;          /* per right-hand side, converged when the TRUE FP64 residual
+                           satisfies ||f - A u||_2 / ||f||_2 <= rtol.  GMRES leaves a
+                           cycle on its recurrence residual, then forms f - A u; a
+                           right-hand side still above rtol restarts from it */
+  int maxit;            /* two-grid preconditioner applications (iterations) per RHS */
+  int restart;          /* GMRES cycle length; <= 0: no restart (the Krylov basis grows
+                           in blocks of 8 vectors of max_rhs x n_fine as the iteration
+                           reaches them) */
   th_dtype precond_dtype; /* TH_C128: FP64 preconditioner; TH_C64: complex64 */
   int use_graph;        /* 1: capture the two-grid preconditioner once in a HIP graph and
                            replay it every iteration (needs a non-NULL stream; ignored
@@ -142,6 +155,9 @@ typedef struct {
   double rel_res;       /* largest true relative residual ||f - A u|| / ||f|| (FP64) */
   double t_solve_s;     /* wall time of the solve */
   long long n_precond;  /* two-grid preconditioner applications (summed over RHS) */
+  double t_cycle_s;     /* t_solve_s / iters: wall time of one iteration (one two-grid
+                           cycle for all RHS with its matvec and orthogonalisation) */
+  int n_fallback_cells; /* TH_COARSE_MLP: coarse cells that fell back to the plain fit */
 } th_solve_stats;
 
 typedef struct {
@@ -213,10 +229,18 @@ th_status th_coarse_solve(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dt
 /* u <- TwoGridStep(u, f) (Alg. 1).  Stream-ordered. */
 th_status th_twogrid(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt);
 
-/* Solve A u = f for nrhs right-hand sides (TH_C128 device vectors) with the
- * two-grid preconditioner: GMRES in FP64 (residual, orthogonalisation,
- * Hessenberg) or the stationary iteration.  Blocking.  Returns TH_ENOTCONV
- * when maxit is reached (u holds the last iterate, stats filled). */
+/* Solve A u = f (eq. bilin_form, Sec. 2-3.1) for nrhs right-hand sides
+ * (TH_C128 device vectors, u overwritten, x0 = 0) with the two-grid
+ * preconditioner f -> TwoGridStep(0, f) of Sec. 4 (Alg. 1: n_s smoothing steps
+ * of Alg. 2, coarse-grid correction with omega_c, n_s smoothing steps) inside
+ * the outer iteration of opts->krylov: GMRES in FP64 (matvec, residual,
+ * orthogonalisation, Hessenberg) or the stationary iteration.  Blocking.
+ * Returns TH_OK only when every RHS meets opts->rtol on its true FP64
+ * residual; TH_ENOTCONV when maxit is reached first (u holds the last
+ * iterate, stats filled, stats->rel_res > rtol); TH_EINVAL (rtol <= 0,
+ * maxit < 1, unknown method or dtype, nrhs > max_rhs); TH_ESTATE (no coarse
+ * setup); TH_ENOMEM (Krylov basis); TH_ENUMERIC (NaN/Inf in f, the Arnoldi
+ * process or the residual). */
 th_status th_solve(th_ctx *ctx, const void *f, void *u, int nrhs,
                    const th_solve_opts *opts, th_solve_stats *stats);
 

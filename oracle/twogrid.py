@@ -10,7 +10,10 @@ Readings (the outer Krylov method is not specified in the paper):
     with the Hermitian inner product, Givens rotations, no restart unless
     asked; the preconditioned directions z_j are stored and x = sum y_j z_j
     (identical to GMRES for a fixed preconditioner, and to FGMRES);
-  * stop when the recurrence residual |g_{j+1}| / ||f|| <= rtol.
+  * a cycle ends when the recurrence residual |g_{j+1}| / ||f|| <= rtol; the
+    iterate is then converged only if its true residual satisfies
+    ||f - A x|| / ||f|| <= rtol, otherwise a new cycle starts from that
+    residual (until maxit).
 The coarse solve is a sparse LU of the quasi-FE QSFEM matrix.
 
 Dirichlet sides (eq. Helmholtz_eq): their nodes are eliminated on both levels
@@ -96,7 +99,7 @@ def gmres_right(matvec, precond, f, rtol=1e-6, maxit=300, restart=None, callback
     """Right-preconditioned GMRES (stored preconditioned directions), x0 = 0.
 
     Returns (x, iters, rel_res_history).  iters counts Arnoldi steps, i.e.
-    preconditioner applications.
+    preconditioner applications; converged means the true residual meets rtol.
     """
     f = np.asarray(f, dtype=np.complex128)
     n = f.shape[0]
@@ -152,9 +155,9 @@ def gmres_right(matvec, precond, f, rtol=1e-6, maxit=300, restart=None, callback
         for i in reversed(range(j_end)):
             y[i] = (g[i] - H[i, i + 1:j_end] @ y[i + 1:j_end]) / H[i, i]
         x = x + y @ Z[:j_end]
-        if done:
-            return x, total, hist
         r = f - matvec(x)
+        if np.linalg.norm(r) <= rtol * fnorm or total >= maxit:
+            return x, total, hist
 
 
 def givens(a, b):

@@ -38,6 +38,8 @@ class SolveStats:
     t_solve_s: float
     n_precond: int
     status: int
+    t_cycle_s: float = 0.0
+    n_fallback_cells: int = 0
 
 
 def load_library():
@@ -284,15 +286,22 @@ class TwoGridSolver:
               method="gmres", raise_on_notconv=False, graph=False):
         """Solve A u = f (complex128 vectors) with the two-grid preconditioner.
 
-        precond: "c128" (FP64 two-grid step) or "c64" (complex64 step under
-        FP64 flexible GMRES).  graph: replay the preconditioner from a HIP
+        Converged means ||f - A u|| / ||f|| <= rtol on the true FP64 residual
+        of every right-hand side.  restart <= 0: no restart.
+        method: "gmres" / "fgmres" (the same flexible iteration) or
+        "stationary".  precond: "c128" (FP64 two-grid step) or "c64"
+        (complex64 step under FP64 flexible GMRES).  graph: replay the preconditioner from a HIP
         graph (needs the solver to run on a non-default stream).
         Returns (u, SolveStats)."""
         nrhs = self._vec(f, self.n_fine, "f", torch.complex128)
         u = torch.empty_like(f) if u is None else u
         self._vec(u, self.n_fine, "u", torch.complex128)
         o = L.SolveOpts()
-        o.krylov = L.TH_KRYLOV_GMRES if method == "gmres" else L.TH_KRYLOV_STATIONARY
+        methods = {"gmres": L.TH_KRYLOV_GMRES_RIGHT, "fgmres": L.TH_KRYLOV_FGMRES,
+                   "stationary": L.TH_KRYLOV_STATIONARY}
+        if method not in methods:
+            raise ValueError(f"method must be one of {sorted(methods)}")
+        o.krylov = methods[method]
         o.rtol, o.maxit, o.restart = float(rtol), int(maxit), int(restart)
         o.precond_dtype = L.TH_C128 if precond == "c128" else L.TH_C64
         o.use_graph = 1 if graph else 0
@@ -300,7 +309,8 @@ class TwoGridSolver:
         status = self._ordered(self._lib.th_solve, self._h, self._p(f), self._p(u), nrhs, C.byref(o), C.byref(st))
         if status not in (0, L.TH_ENOTCONV) or (status and raise_on_notconv):
             self._check(status)
-        return u, SolveStats(st.iters, st.rel_res, st.t_solve_s, st.n_precond, status)
+        return u, SolveStats(st.iters, st.rel_res, st.t_solve_s, st.n_precond, status,
+                             st.t_cycle_s, st.n_fallback_cells)
 
 
 def plain_fit(samples):

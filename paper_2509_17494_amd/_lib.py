@@ -17,8 +17,8 @@ TH_BC_ROBIN, TH_BC_NEUMANN, TH_BC_DIRICHLET = 0, 1, 2
 TH_LAYOUT_AUTO, TH_LAYOUT_DENSE, TH_LAYOUT_SYMMETRIC, TH_LAYOUT_SLAB = 0, 1, 2, 3
 TH_C128, TH_C64 = 0, 1
 TH_GEMM_F64, TH_GEMM_F32, TH_GEMM_BF16 = 0, 1, 2
-TH_COARSE_QSFEM, TH_COARSE_WEIGHTS, TH_COARSE_PLAINFIT, TH_COARSE_MLP = 0, 1, 2, 3
-TH_KRYLOV_GMRES, TH_KRYLOV_STATIONARY = 0, 1
+TH_COARSE_QSFEM, TH_COARSE_PLAINFIT, TH_COARSE_MLP, TH_COARSE_WEIGHTS = 0, 1, 2, 3
+TH_KRYLOV_GMRES_RIGHT, TH_KRYLOV_FGMRES, TH_KRYLOV_STATIONARY = 0, 1, 2
 KERNEL_CLASSES = ["dd_apply", "dd_accum", "operator", "restrict", "prolong", "coarse", "krylov"]
 
 
@@ -42,7 +42,8 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("rel_res", C.c_double), ("t_solve_s", C.c_double),
-                ("n_precond", C.c_longlong)]
+                ("n_precond", C.c_longlong), ("t_cycle_s", C.c_double),
+                ("n_fallback_cells", C.c_int)]
 
 
 class Info(C.Structure):

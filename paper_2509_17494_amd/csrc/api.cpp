@@ -146,6 +146,11 @@ static void free_solver(th_ctx *c) {
   if (c->s_buf) (void)hipFree(c->s_buf);
   c->s_buf = nullptr;
   c->s_bytes = 0;
+  for (auto *L : {&c->kv_V, &c->kv_Z}) {
+    for (void *p : *L) (void)hipFree(p);
+    L->clear();
+  }
+  c->kv_vec_bytes = 0;
 }
 
 extern "C" {
@@ -261,6 +266,12 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
       return fail(ctx, TH_EINVAL, "k must be finite and > 0 in every cell");
     if (d->eps && (!(d->eps[i] >= 0.0) || !std::isfinite(d->eps[i])))
       return fail(ctx, TH_EINVAL, "eps must be finite and >= 0 in every cell");
+    // the subdomain factorisations run without pivoting; that rests on the
+    // positive definite Hermitian part of i A_s^(i), which needs a positive
+    // imaginary volume coefficient alpha_s k^2 + eps in every cell (Sec. 4.1)
+    if (!(d->alpha_s * d->k[i] * d->k[i] + (d->eps ? d->eps[i] : 0.0) > 0.0))
+      return fail(ctx, TH_EINVAL,
+                  "alpha_s = 0 needs eps > 0 in every cell (shifted operator without pivoting)");
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TH_EHIP, "hipSetDevice failed");
   auto t0 = std::chrono::steady_clock::now();
@@ -903,21 +914,42 @@ namespace th {
 using zc = std::complex<double>;
 
 struct SolverWS {
-  c64 *V, *Z, *partial, *hd, *tmp32a, *tmp32b, *coef, *fx;
+  c64 *partial, *hd, *tmp32a, *tmp32b, *coef, *res;
   double *scal;
   c64 *hcol;    // device: one Hessenberg column, (m + 2) x nrhs
   c64 *hcol_h;  // pinned host copy of it
 };
 
+// Vectors per block of the Krylov basis (V or Z).
+static const int KV_CHUNK = 8;
+
+// Basis vector j of V or Z (nrhs vectors of n_fine, consecutive), its block
+// allocated on first use.
+static int basis_vec(th_ctx *c, std::vector<void *> &blocks, int j, c64 **out) {
+  while ((int)blocks.size() <= j / KV_CHUNK) {
+    void *p = nullptr;
+    if (hipMalloc(&p, (size_t)KV_CHUNK * c->kv_vec_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("cannot allocate Krylov basis vectors (" + std::to_string(j + 1) +
+                " needed); lower th_solve_opts.restart");
+      return TH_ENOMEM;
+    }
+    blocks.push_back(p);
+  }
+  *out = (c64 *)((char *)blocks[j / KV_CHUNK] + (size_t)(j % KV_CHUNK) * c->kv_vec_bytes);
+  return 0;
+}
+
 static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
   const size_t vec = (size_t)nrhs * c->nf * sizeof(c64);
-  size_t need = (size_t)(m + 1) * vec + (size_t)m * vec;   // V, Z
+  size_t need = 0;
   need += (size_t)nrhs * 256 * sizeof(c64);                 // partial sums
   need += (size_t)nrhs * sizeof(c64) * 2;                   // dot outputs
-  need += 2 * (size_t)nrhs * c->nf * sizeof(c64);          // preconditioner staging
+  need += 2 * vec;                                          // preconditioner staging
   need += (size_t)nrhs * (m + 1) * sizeof(c64);             // lincomb coefficients
   need += (size_t)nrhs * sizeof(double) * 2;                // scalars
   need += (size_t)nrhs * (m + 2) * sizeof(c64);             // Hessenberg column
+  need += vec;                                              // true residual
   const size_t pinned = (size_t)nrhs * (m + 2) * sizeof(c64);
   if (pinned > c->h_pinned_bytes) {
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
@@ -930,13 +962,15 @@ static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
     c->h_pinned_bytes = pinned;
   }
   need += 4096;
-  if (need > c->s_bytes) {
+  const size_t kv_vec = (size_t)c->desc.max_rhs * c->nf * sizeof(c64);
+  if (need > c->s_bytes || kv_vec != c->kv_vec_bytes) {
     free_solver(c);
     if (hipMalloc(&c->s_buf, need) != hipSuccess) {
       set_error("cannot allocate the Krylov work space");
       return TH_ENOMEM;
     }
     c->s_bytes = need;
+    c->kv_vec_bytes = kv_vec;
   }
   char *p = (char *)c->s_buf;
   auto take = [&](size_t bytes) {
@@ -944,18 +978,17 @@ static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
     p += (bytes + 255) / 256 * 256;
     return q;
   };
-  w.V = (c64 *)take((size_t)(m + 1) * vec);
-  w.Z = (c64 *)take((size_t)m * vec);
   w.partial = (c64 *)take((size_t)nrhs * 256 * sizeof(c64));
   w.hd = (c64 *)take((size_t)nrhs * sizeof(c64) * 2);
   // staging of the preconditioner input/output (complex64 copies, or FP64
   // copies at fixed addresses for graph replay)
-  w.tmp32a = (c64 *)take((size_t)nrhs * c->nf * sizeof(c64));
-  w.tmp32b = (c64 *)take((size_t)nrhs * c->nf * sizeof(c64));
+  w.tmp32a = (c64 *)take(vec);
+  w.tmp32b = (c64 *)take(vec);
   (void)f32;
   w.coef = (c64 *)take((size_t)nrhs * (m + 1) * sizeof(c64));
   w.scal = (double *)take((size_t)nrhs * sizeof(double) * 2);
   w.hcol = (c64 *)take((size_t)nrhs * (m + 2) * sizeof(c64));
+  w.res = (c64 *)take(vec);
   w.hcol_h = (c64 *)c->h_pinned;
   return 0;
 }
@@ -1041,6 +1074,13 @@ static void givens(zc a, zc b, zc &cs, zc &sn, zc &rr) {
   rr = ph * t;
 }
 
+// Right-preconditioned GMRES storing the preconditioned directions (flexible
+// GMRES), x0 = 0, modified Gram-Schmidt, complex Givens rotations, all
+// right-hand sides advancing together.  A right-hand side leaves the current
+// cycle when its recurrence residual |g_{j+1}| / ||f|| reaches rtol; at the
+// end of every cycle the true FP64 residual f - A x is formed and decides:
+// a right-hand side is converged only when ||f - A x|| / ||f|| <= rtol, the
+// others start a new cycle from that residual until maxit.
 static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve_opts *o,
                        th_solve_stats *stats) {
   hipStream_t s = c->stream;
@@ -1052,8 +1092,19 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
   if (rc) return rc;
   const size_t vbytes = (size_t)nrhs * c->nf * sizeof(c64);
   const long long nf = c->nf;
-  auto Vj = [&](int j) { return w.V + (size_t)j * nrhs * nf; };
-  auto Zj = [&](int j) { return w.Z + (size_t)j * nrhs * nf; };
+  const long long ldj = (long long)(c->kv_vec_bytes / sizeof(c64));  // stride between basis vectors
+  std::vector<c64 *> Vp, Zp;  // basis vectors reached so far
+  auto Vj = [&](int j) { return Vp[j]; };
+  auto Zj = [&](int j) { return Zp[j]; };
+  auto reach = [&](std::vector<c64 *> &P, std::vector<void *> &blocks, int j) -> int {
+    while ((int)P.size() <= j) {
+      c64 *q = nullptr;
+      int e = basis_vec(c, blocks, (int)P.size(), &q);
+      if (e) return e;
+      P.push_back(q);
+    }
+    return 0;
+  };
 
   std::vector<zc> fn2;
   rc = dot_to_host(c, f, f, nrhs, w, fn2);
@@ -1067,32 +1118,27 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
     }
   }
   TH_HIP_CHECK_RET(hipMemsetAsync(u, 0, vbytes, s));
-  std::vector<int> conv(nrhs, 0), it_r(nrhs, 0);
-  for (int r = 0; r < nrhs; ++r)
-    if (fnorm[r] == 0.0) conv[r] = 1;
+  // x0 = 0: the first residual is f itself
+  TH_HIP_CHECK_RET(hipMemcpyAsync(w.res, f, vbytes, hipMemcpyDeviceToDevice, s));
+  std::vector<double> beta(fnorm);        // true residual norms of the current iterate
+  std::vector<int> done(nrhs, 0), it_r(nrhs, 0);
+  for (int r = 0; r < nrhs; ++r) done[r] = fnorm[r] == 0.0 || beta[r] <= o->rtol * fnorm[r];
   int total = 0;
   long long nprec = 0;
-  bool first_cycle = true;
   std::vector<double> hscal(nrhs);
-  while (true) {
-    // r0 = f - A x into V_0
-    if (first_cycle) {
-      TH_HIP_CHECK_RET(hipMemcpyAsync(Vj(0), f, vbytes, hipMemcpyDeviceToDevice, s));
-    } else {
-      rc = launch_apply(make_op(c, false), c->ref, u, f, Vj(0), nrhs, false, -1.0, s);
-      if (rc) return rc;
-    }
-    std::vector<zc> bb;
-    rc = dot_to_host(c, Vj(0), Vj(0), nrhs, w, bb);
+  auto all_done = [&]() {
+    for (int r = 0; r < nrhs; ++r)
+      if (!done[r]) return false;
+    return true;
+  };
+  while (!all_done() && total < maxit) {
+    rc = reach(Vp, c->kv_V, 0);
     if (rc) return rc;
-    std::vector<double> beta(nrhs);
-    for (int r = 0; r < nrhs; ++r) {
-      beta[r] = std::sqrt(std::max(bb[r].real(), 0.0));
-      hscal[r] = (beta[r] > 0.0) ? 1.0 / beta[r] : 0.0;
-    }
+    // V_0 = r / beta for the right-hand sides still running, 0 for the others
+    for (int r = 0; r < nrhs; ++r) hscal[r] = (!done[r] && beta[r] > 0.0) ? 1.0 / beta[r] : 0.0;
     TH_HIP_CHECK_RET(hipMemcpyAsync(w.scal, hscal.data(), nrhs * sizeof(double),
                                     hipMemcpyHostToDevice, s));
-    rc = launch_scale_dev(Vj(0), Vj(0), w.scal, nf, nrhs, nf, nf, s);
+    rc = launch_scale_dev(Vj(0), w.res, w.scal, nf, nrhs, nf, nf, s);
     if (rc) return rc;
     // rotated Hessenberg (upper triangular R) stored by columns as they grow:
     // H[r][q][i] = R(i, q), i <= q
@@ -1102,15 +1148,14 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
     std::vector<int> jend(nrhs, 0), active(nrhs);
     for (int r = 0; r < nrhs; ++r) {
       g[r][0] = beta[r];
-      active[r] = !conv[r];
-      if (beta[r] == 0.0 && !conv[r]) {
-        conv[r] = 1;
-        active[r] = 0;
-      }
+      active[r] = !done[r];
     }
     int j = 0;
     bool cycle_done = false;
     for (j = 0; j < m && !cycle_done; ++j) {
+      rc = reach(Vp, c->kv_V, j + 1);
+      if (!rc) rc = reach(Zp, c->kv_Z, j);
+      if (rc) return rc;
       rc = precond(c, Vj(j), Zj(j), nrhs, f32, w, o->use_graph != 0);
       if (rc) return rc;
       nprec += nrhs;
@@ -1150,7 +1195,7 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
         hcol[r][j + 1] = std::sqrt(std::max(w.hcol_h[(size_t)(j + 1) * nrhs + r].re, 0.0));
       }
       ++total;
-      bool all_done = true;
+      bool cycle_finished = true;
       for (int r = 0; r < nrhs; ++r) {
         if (!active[r]) continue;
         std::vector<zc> &h = hcol[r];
@@ -1174,16 +1219,14 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
         jend[r] = j + 1;
         it_r[r] = total;
         const double rel = std::abs(g[r][j + 1]) / fnorm[r];
-        if (rel <= o->rtol || hsub == 0.0) {
-          conv[r] = 1;
-          active[r] = 0;
-        } else {
-          all_done = false;
-        }
+        if (rel <= o->rtol || hsub == 0.0)
+          active[r] = 0;  // leaves this cycle; the true residual decides below
+        else
+          cycle_finished = false;
       }
-      if (all_done || total >= maxit) cycle_done = true;
+      if (cycle_finished || total >= maxit) cycle_done = true;
     }
-    // x += Z y for every RHS
+    // x += Z y for every right-hand side of this cycle
     std::vector<c64> coef((size_t)nrhs * m, c64{0, 0});
     for (int r = 0; r < nrhs; ++r) {
       const int je = jend[r];
@@ -1197,36 +1240,40 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
     }
     TH_HIP_CHECK_RET(hipMemcpyAsync(w.coef, coef.data(), coef.size() * sizeof(c64),
                                     hipMemcpyHostToDevice, s));
-    rc = launch_lincomb(u, w.Z, w.coef, j, m, nf, nrhs, (long long)nrhs * nf, nf, s);
+    for (int b = 0; b * KV_CHUNK < j; ++b) {
+      const int cnt = std::min(KV_CHUNK, j - b * KV_CHUNK);
+      rc = launch_lincomb(u, Zj(b * KV_CHUNK), w.coef + b * KV_CHUNK, cnt, m, nf, nrhs, ldj, nf, s);
+      if (rc) return rc;
+    }
+    // true FP64 residual of the new iterate: the convergence test and the
+    // start of the next cycle
+    rc = launch_apply(make_op(c, false), c->ref, u, f, w.res, nrhs, false, -1.0, s);
     if (rc) return rc;
-    TH_HIP_CHECK_RET(hipStreamSynchronize(s));
-    first_cycle = false;
-    bool all_conv = true;
-    for (int r = 0; r < nrhs; ++r) all_conv &= conv[r] != 0;
-    if (all_conv || total >= maxit) break;
+    std::vector<zc> rn;
+    rc = dot_to_host(c, w.res, w.res, nrhs, w, rn);
+    if (rc) return rc;
+    for (int r = 0; r < nrhs; ++r) {
+      beta[r] = std::sqrt(std::max(rn[r].real(), 0.0));
+      if (!std::isfinite(beta[r])) {
+        set_error("NaN or Inf in the residual");
+        return TH_ENUMERIC;
+      }
+      done[r] = fnorm[r] == 0.0 || beta[r] <= o->rtol * fnorm[r];
+    }
   }
-  // true FP64 residual
-  rc = launch_apply(make_op(c, false), c->ref, u, f, w.V, nrhs, false, -1.0, s);
-  if (rc) return rc;
-  std::vector<zc> rn;
-  rc = dot_to_host(c, w.V, w.V, nrhs, w, rn);
-  if (rc) return rc;
   double worst = 0.0;
   int maxits = 0;
-  bool all_conv = true;
   for (int r = 0; r < nrhs; ++r) {
-    const double rel = (fnorm[r] > 0) ? std::sqrt(std::max(rn[r].real(), 0.0)) / fnorm[r] : 0.0;
-    worst = std::max(worst, rel);
+    worst = std::max(worst, fnorm[r] > 0 ? beta[r] / fnorm[r] : 0.0);
     maxits = std::max(maxits, it_r[r]);
-    all_conv &= conv[r] != 0;
   }
   if (stats) {
     stats->iters = maxits;
     stats->rel_res = worst;
     stats->n_precond = nprec;
   }
-  if (!all_conv) {
-    set_error("GMRES reached maxit before the tolerance");
+  if (!all_done()) {
+    set_error("GMRES reached maxit before the true residual met the tolerance");
     return TH_ENOTCONV;
   }
   return 0;
@@ -1241,6 +1288,9 @@ static int solve_stationary(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_
   if (rc) return rc;
   const long long nf = c->nf;
   const size_t vbytes = (size_t)nrhs * nf * sizeof(c64);
+  c64 *zdir = nullptr;
+  rc = basis_vec(c, c->kv_Z, 0, &zdir);
+  if (rc) return rc;
   std::vector<zc> fn2;
   rc = dot_to_host(c, f, f, nrhs, w, fn2);
   if (rc) return rc;
@@ -1257,19 +1307,19 @@ static int solve_stationary(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_
   double worst = 0.0;
   while (it < o->maxit) {
     // u <- u + B (f - A u)  (= TwoGridStep(u, f) for the linear two-grid map)
-    rc = launch_apply(make_op(c, false), c->ref, u, f, w.V, nrhs, false, -1.0, s);
-    if (!rc) rc = precond(c, w.V, w.Z, nrhs, f32, w, o->use_graph != 0);
+    rc = launch_apply(make_op(c, false), c->ref, u, f, w.res, nrhs, false, -1.0, s);
+    if (!rc) rc = precond(c, w.res, zdir, nrhs, f32, w, o->use_graph != 0);
     if (rc) return rc;
     c64 one = {1.0, 0.0};
     std::vector<c64> ones(nrhs, one);
     TH_HIP_CHECK_RET(hipMemcpyAsync(w.hd, ones.data(), nrhs * sizeof(c64), hipMemcpyHostToDevice, s));
-    rc = launch_axpy_dev(u, w.Z, w.hd, 1.0, nf, nrhs, nf, nf, s);
+    rc = launch_axpy_dev(u, zdir, w.hd, 1.0, nf, nrhs, nf, nf, s);
     if (rc) return rc;
     ++it;
-    rc = launch_apply(make_op(c, false), c->ref, u, f, w.V, nrhs, false, -1.0, s);
+    rc = launch_apply(make_op(c, false), c->ref, u, f, w.res, nrhs, false, -1.0, s);
     if (rc) return rc;
     std::vector<zc> rn;
-    rc = dot_to_host(c, w.V, w.V, nrhs, w, rn);
+    rc = dot_to_host(c, w.res, w.res, nrhs, w, rn);
     if (rc) return rc;
     worst = 0.0;
     for (int r = 0; r < nrhs; ++r)
@@ -1305,14 +1355,17 @@ extern "C" th_status th_solve(th_ctx *ctx, const void *f, void *u, int nrhs,
   if (stats) std::memset(stats, 0, sizeof(*stats));
   auto t0 = std::chrono::steady_clock::now();
   int rc;
-  if (opts->krylov == TH_KRYLOV_GMRES)
+  if (opts->krylov == TH_KRYLOV_GMRES_RIGHT || opts->krylov == TH_KRYLOV_FGMRES)
     rc = solve_gmres(ctx, (const c64 *)f, (c64 *)u, nrhs, opts, stats);
   else if (opts->krylov == TH_KRYLOV_STATIONARY)
     rc = solve_stationary(ctx, (const c64 *)f, (c64 *)u, nrhs, opts, stats);
   else
     return fail(ctx, TH_EINVAL, "unknown Krylov method");
   if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == 0) rc = TH_EHIP;
-  if (stats)
+  if (stats) {
     stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->t_cycle_s = stats->iters > 0 ? stats->t_solve_s / stats->iters : 0.0;
+    stats->n_fallback_cells = ctx->n_fallback;
+  }
   return finish(ctx, rc);
 }

@@ -175,6 +175,11 @@ struct th_ctx {
   size_t s_bytes = 0;
   void *h_pinned = nullptr;    // pinned host staging of the Hessenberg column
   size_t h_pinned_bytes = 0;
+  // Krylov basis V and preconditioned directions Z: blocks of a fixed number
+  // of vectors (max_rhs x n_fine complex128 each), allocated as the Arnoldi
+  // process reaches them and kept for later solves
+  std::vector<void *> kv_V, kv_Z;
+  size_t kv_vec_bytes = 0;
 
   // captured preconditioner graphs: (nrhs, f32, input, output) -> executable
   struct PrecGraph {
@@ -270,7 +275,14 @@ int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const doubl
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);
 int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s);
 int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStream_t s,
-                      c64 *pbuf);
+                      c64 *ws);
+// work space of gj_invert_batched for batches of up to `batch` matrices of size <= n:
+// status words, inverted diagonal blocks, check vectors
+size_t gj_ws_bytes(int batch, int n);
+int gj_ws_reset(c64 *ws, hipStream_t s);   // clears the status words (before the first call)
+// synchronises; TH_ENUMERIC (with the message naming `what`) when a pivot was zero, not
+// finite or relatively small, or an inverse failed its one-vector check
+int gj_ws_status(const c64 *ws, hipStream_t s, const char *what);
 
 // k_blas.hip
 int launch_convert(const void *in, void *out, long long n, bool in_f32, bool out_f32, hipStream_t s);

@@ -475,8 +475,11 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
     set_error("coarse stencil has the wrong size");
     return TH_EINVAL;
   }
-  int max_nb = 0;
-  for (int J = 0; J < nblk; ++J) max_nb = std::max(max_nb, (cd.line0[J + 1] - cd.line0[J]) * L);
+  int max_nb = 0, max_ld = 0;
+  for (int J = 0; J < nblk; ++J) {
+    max_nb = std::max(max_nb, (cd.line0[J + 1] - cd.line0[J]) * L);
+    max_ld = std::max(max_ld, cd.ld[J]);
+  }
   const size_t t_bytes = (size_t)max_nb * R * sizeof(c64);
   const size_t p_bytes = (size_t)ceil_div(max_nb, kCoarseChunk) * t_bytes;
   cd.bytes = cd.goff[nblk] * (long long)sizeof(c64) + (long long)st_bytes;
@@ -485,14 +488,16 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
       hipMalloc(&cd.st, st_bytes) != hipSuccess ||
       hipMalloc(&cd.tbuf, t_bytes) != hipSuccess ||
       hipMalloc(&cd.pbuf, p_bytes) != hipSuccess ||
-      hipMalloc(&pws, kGJBlock * kGJBlock * sizeof(c64) + 64) != hipSuccess) {
+      hipMalloc(&pws, gj_ws_bytes(1, max_ld)) != hipSuccess) {
     if (pws) (void)hipFree(pws);
     set_error("cannot allocate the coarse factors");
     return TH_ENOMEM;
   }
   TH_HIP_CHECK_RET(hipMemcpyAsync(cd.st, st.data(), st_bytes, hipMemcpyHostToDevice, s));
-  int *flag = (int *)(pws + kGJBlock * kGJBlock);
-  TH_HIP_CHECK_RET(hipMemsetAsync(flag, 0, sizeof(int), s));
+  if (int e = gj_ws_reset(pws, s)) {
+    (void)hipFree(pws);
+    return e;
+  }
   // twisted elimination where the small-slab sweeps apply (at least 3 blocks)
   cd.mid = (nblk >= 3 && max_nb * cd.rc_chunk * (long long)sizeof(c64) <= 64 * 1024) ? nblk / 2 : -1;
   // block J with the correction from the block above (prev) and/or below (next).
@@ -531,16 +536,10 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
     for (int J = nblk - 1; J > m && rc == 0; --J) rc = build(J, false, J < nblk - 1);
     if (rc == 0) rc = build(m, true, true);
   }
-  int hflag = 0;
-  TH_HIP_CHECK_RET(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  TH_HIP_CHECK_RET(hipStreamSynchronize(s));
+  if (rc == 0) rc = gj_ws_status(pws, s, "the coarse factorisation");
+  (void)hipStreamSynchronize(s);
   (void)hipFree(pws);
-  if (rc) return rc;
-  if (hflag) {
-    set_error("zero or non-finite pivot in the coarse factorisation");
-    return TH_ENUMERIC;
-  }
-  return 0;
+  return rc;
 }
 
 // Large slabs: per step one staging launch, one GEMV over column chunks and one

@@ -18,10 +18,18 @@
 // and after the last block A holds A^{-1}.  Matrices are padded with an
 // identity block to a multiple of 64, which leaves the inverse unchanged on
 // the leading block.
+//
+// Guards (every batched inversion): a pivot that is zero or not finite, or
+// smaller than kPivotRel times the largest entry of its 64 x 64 diagonal block
+// at the time it is eliminated, sets a flag; and every inverse is checked on
+// one vector: b = A x is formed before the elimination for a fixed probe x of
+// unit-modulus entries, and max_i |(A^{-1} b)_i - x_i| after it must stay
+// below kCheckTol.  Either failure makes the setup return TH_ENUMERIC.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "ctx.hpp"
@@ -32,6 +40,8 @@ constexpr int GJ_BS = kGJBlock;  // block width of the elimination (64)
 constexpr int GJ_T = 64;         // tile edge of the update kernel
 constexpr int GJ_KH = 32;        // k-slice of the update staged in LDS at a time
 constexpr int GJ_PT = 32;        // tile width of the panel kernels
+constexpr double kPivotRel = 1e-12;  // smallest accepted |pivot| / largest |entry| of its block
+constexpr double kCheckTol = 1e-6;   // largest accepted error of the one-vector inverse check
 
 // ---------------------------------------------------------------------------
 // Gauss-Jordan kernels.  Matrix b of the batch starts at A + b * stride and is
@@ -42,17 +52,29 @@ constexpr int GJ_PT = 32;        // tile width of the panel kernels
 __global__ __launch_bounds__(256) void k_gj_diag(c64 *A, int ld, long long stride, int kb,
                                                  c64 *pbuf, int *flag) {
   __shared__ c64 a[GJ_BS][GJ_BS + 1];
+  __shared__ double red[256];
   c64 *Ab = A + blockIdx.x * stride + (long long)kb * GJ_BS * ld + kb * GJ_BS;
+  double mx = 0.0;
   for (int t = threadIdx.x; t < GJ_BS * GJ_BS; t += blockDim.x) {
     int i = t / GJ_BS, j = t % GJ_BS;
-    a[i][j] = Ab[(long long)i * ld + j];
+    const c64 v = Ab[(long long)i * ld + j];
+    a[i][j] = v;
+    mx = fmax(mx, v.re * v.re + v.im * v.im);
   }
+  red[threadIdx.x] = mx;
   __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double small2 = kPivotRel * kPivotRel * red[0];  // squared threshold
   for (int kk = 0; kk < GJ_BS; ++kk) {
     const c64 d = a[kk][kk];
     const double den = d.re * d.re + d.im * d.im;
     if (!(den > 0.0) || !isfinite(den)) {
-      if (threadIdx.x == 0) flag[0] = 1;
+      if (threadIdx.x == 0) flag[0] |= 1;
+    } else if (den < small2) {
+      if (threadIdx.x == 0) flag[0] |= 2;
     }
     const c64 piv = {d.re / den, -d.im / den};
     __syncthreads();
@@ -77,6 +99,75 @@ __global__ __launch_bounds__(256) void k_gj_diag(c64 *A, int ld, long long strid
     Ab[(long long)i * ld + j] = a[i][j];
     pb[t] = a[i][j];
   }
+}
+
+// Probe vector of the inverse check: unit-modulus entries with no structure
+// that a subdomain or coarse block could share.
+__device__ inline c64 gj_probe(int j) {
+  double sn, cs;
+  sincos(0.7548776662466927 * (double)j + 0.25 * (double)(j % 7), &sn, &cs);
+  return c64{cs, sn};
+}
+
+// b = A x (before the elimination; before == 1) or the check of A^{-1} b
+// against x (after it; A then holds the inverse): one wavefront per row,
+// lanes over the columns, fixed-order reductions.  Grid (ceil(n / 4), batch).
+__global__ __launch_bounds__(256) void k_gj_probe(const c64 *A, int ld, long long stride, int n,
+                                                  c64 *chk, int before,
+                                                  unsigned long long *errbits) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;  // wavefront-uniform
+  const c64 *Ar = A + blockIdx.y * stride + (long long)row * ld;
+  c64 *cb = chk + (long long)blockIdx.y * n;
+  c64 acc = {0, 0};
+  for (int j = lane; j < n; j += 64) cmac(acc, Ar[j], before ? gj_probe(j) : cb[j]);
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.re += __shfl_xor(acc.re, o);
+    acc.im += __shfl_xor(acc.im, o);
+  }
+  if (lane != 0) return;
+  if (before) {
+    cb[row] = acc;
+    return;
+  }
+  const c64 x = gj_probe(row);
+  const double dr = acc.re - x.re, di = acc.im - x.im;
+  const double e = sqrt(dr * dr + di * di);
+  // non-negative doubles order like their bit patterns; NaN sorts above them
+  atomicMax(errbits, (unsigned long long)__double_as_longlong(isnan(e) ? __longlong_as_double(0x7ff8000000000000LL) : e));
+}
+
+size_t gj_ws_bytes(int batch, int n) {
+  return 256 + (size_t)batch * GJ_BS * GJ_BS * sizeof(c64) + (size_t)batch * n * sizeof(c64);
+}
+
+int gj_ws_reset(c64 *ws, hipStream_t s) {
+  TH_HIP_CHECK_RET(hipMemsetAsync(ws, 0, 16, s));
+  return 0;
+}
+
+int gj_ws_status(const c64 *ws, hipStream_t s, const char *what) {
+  unsigned long long h[2] = {0, 0};
+  TH_HIP_CHECK_RET(hipMemcpyAsync(h, ws, 16, hipMemcpyDeviceToHost, s));
+  TH_HIP_CHECK_RET(hipStreamSynchronize(s));
+  const int flag = (int)(h[0] & 0xffffffffu);
+  double err;
+  std::memcpy(&err, &h[1], sizeof(err));
+  char msg[256];
+  if (flag & 1) {
+    std::snprintf(msg, sizeof msg, "zero or non-finite pivot in %s", what);
+  } else if (flag & 2) {
+    std::snprintf(msg, sizeof msg, "pivot below %.0e of its block's largest entry in %s", kPivotRel,
+                  what);
+  } else if (!(err <= kCheckTol)) {
+    std::snprintf(msg, sizeof msg, "inverse check failed in %s: |A^-1 (A x) - x| = %.3e > %.0e",
+                  what, err, kCheckTol);
+  } else {
+    return 0;
+  }
+  set_error(msg);
+  return TH_ENUMERIC;
 }
 
 // A_kj <- P A_kj for the GJ_PT-column tile blockIdx.x (columns of block k skipped)
@@ -187,17 +278,21 @@ __global__ __launch_bounds__(256) void k_gj_update(c64 *A, int ld, long long str
 }
 
 int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStream_t s,
-                      c64 *pbuf_flag_ws) {
-  // pbuf_flag_ws: batch * GJ_BS * GJ_BS complex for the inverted diagonal
-  // blocks, followed by one int flag (zeroed by the caller)
+                      c64 *ws) {
+  // ws: gj_ws_bytes(batch, >= n) bytes, status words cleared by gj_ws_reset
   if (n % GJ_BS) {
     set_error("gauss-jordan size must be a multiple of the block width");
     return TH_EINVAL;
   }
-  c64 *pbuf = pbuf_flag_ws;
-  int *flag = (int *)(pbuf + (long long)batch * GJ_BS * GJ_BS);
+  int *flag = (int *)ws;
+  unsigned long long *errbits = (unsigned long long *)((char *)ws + 8);
+  c64 *pbuf = (c64 *)((char *)ws + 256);
+  c64 *chk = pbuf + (long long)batch * GJ_BS * GJ_BS;
   const int nbk = n / GJ_BS;
   const int nt = ceil_div(n, GJ_T), np = ceil_div(n, GJ_PT);
+  const dim3 gprobe(ceil_div(n, 4), batch);
+  hipLaunchKernelGGL(k_gj_probe, gprobe, dim3(256), 0, s, (const c64 *)A, ld, stride, n, chk, 1,
+                     errbits);
   for (int kb = 0; kb < nbk; ++kb) {
     hipLaunchKernelGGL(k_gj_diag, dim3(batch), dim3(256), 0, s, A, ld, stride, kb, pbuf, flag);
     hipLaunchKernelGGL(k_gj_rowpanel, dim3(np, batch), dim3(256), 0, s, A, ld, stride, n, kb,
@@ -207,6 +302,9 @@ int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStr
                        (const c64 *)pbuf);
     TH_HIP_CHECK_RET(hipGetLastError());
   }
+  hipLaunchKernelGGL(k_gj_probe, gprobe, dim3(256), 0, s, (const c64 *)A, ld, stride, n, chk, 0,
+                     errbits);
+  TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
 
@@ -437,15 +535,12 @@ int setup_subdomain_operators(th_ctx *c) {
   c64 *const W[3] = {work + (long long)batch * mat, work + (long long)batch * (mat + ldw * ldw),
                      work + (long long)batch * (mat + 2LL * ldw * ldw)};
   c64 *T1 = work + (long long)batch * (mat + 3LL * ldw * ldw);
-  size_t pws_bytes = (size_t)batch * GJ_BS * GJ_BS * sizeof(c64) + 64;
-  if (hipMalloc(&pws, pws_bytes) != hipSuccess) {
+  if (hipMalloc(&pws, gj_ws_bytes(batch, npad)) != hipSuccess) {
     (void)hipFree(work);
     set_error("cannot allocate the pivot work space");
     return TH_ENOMEM;
   }
-  int *flag = (int *)(pws + (long long)batch * GJ_BS * GJ_BS);
-  int rc = 0;
-  TH_HIP_CHECK_RET(hipMemsetAsync(flag, 0, sizeof(int), s));
+  int rc = gj_ws_reset(pws, s);
   // optional progress lines on stderr for long setups (environment TH_PROGRESS
   // set): the stream is synchronised after a batch at most every 10 s
   const bool progress = std::getenv("TH_PROGRESS") != nullptr;
@@ -509,19 +604,11 @@ int setup_subdomain_operators(th_ctx *c) {
                          (const c64 *)work, npad, mat, c->d_nblk, (cx<double> *)c->d_B, c->P);
     TH_HIP_CHECK_RET(hipGetLastError());
   }
-  int hflag = 0;
-  if (rc == 0) {
-    TH_HIP_CHECK_RET(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    TH_HIP_CHECK_RET(hipStreamSynchronize(s));
-  }
+  if (rc == 0) rc = gj_ws_status(pws, s, slab ? "a subdomain slab factor" : "a subdomain inverse");
+  (void)hipStreamSynchronize(s);
   (void)hipFree(work);
   (void)hipFree(pws);
-  if (rc) return rc;
-  if (hflag) {
-    set_error("zero or non-finite pivot in a subdomain inverse");
-    return TH_ENUMERIC;
-  }
-  return 0;
+  return rc;
 }
 
 }  // namespace th

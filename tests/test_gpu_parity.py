@@ -281,3 +281,28 @@ def test_graph_replay_matches_eager(precond, gemm):
             assert st_g.iters == st_e.iters
             assert np.array_equal(got, ref)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precond,gemm,restart", [("c128", "f64", 2), ("c64", "bf16", 3), ("c64", "bf16", 0)])
+def test_solve_status_means_true_residual_met(precond, gemm, restart):
+    """th_solve returns TH_OK only when every right-hand side meets rtol on
+    its true FP64 residual (short restart cycles, complex64 preconditioner);
+    at maxit it returns TH_ENOTCONV with the true residual above rtol."""
+    cfg = syn.config("C1")
+    p, N = cfg["p"], cfg["n"]
+    f = syn.gaussian_load(N, p, syn.gaussian_centres_grid(2, 2), cfg["sigma"])
+    print(f"contract {precond}/{gemm} restart {restart}", flush=True)
+    s = make_solver(cfg["k"], p, cfg["l_dd"], max_rhs=4, gemm=gemm)
+    fd = to_dev(f)
+    for rtol in (1e-6, 1e-9):
+        u, st = s.solve(fd, rtol=rtol, restart=restart, precond=precond)
+        r = to_np(s.residual(u, fd))
+        true_res = max(np.linalg.norm(r[i]) / np.linalg.norm(f[i]) for i in range(4))
+        print(f"  rtol {rtol:.0e}: status {st.status} iters {st.iters} rel_res {st.rel_res:.2e} "
+              f"(here {true_res:.2e})", flush=True)
+        assert st.status == 0 and st.rel_res <= rtol and true_res <= rtol * (1 + 1e-9)
+        assert abs(st.rel_res - true_res) <= 1e-3 * true_res
+    from paper_2509_17494_amd import _lib as L
+    u, st = s.solve(fd, rtol=1e-12, maxit=3, restart=restart, precond=precond)
+    assert st.status == L.TH_ENOTCONV and st.rel_res > 1e-12 and st.iters == 3
+    s.close()

@@ -30,7 +30,7 @@ def iters(p, ppw, **kw):
     s = TwoGridSolver(k, order=p, max_rhs=1, **kw)
     _, st = s.solve(torch.from_numpy(f).to("cuda"), rtol=1e-6, maxit=400)
     s.close()
-    assert st.status == 0
+    assert st.status == 0 and st.rel_res <= 1e-6
     return st.iters
 
 

@@ -303,6 +303,24 @@ def test_gmres_matches_krylov_least_squares():
     assert np.linalg.norm(x - Kr @ y) / np.linalg.norm(x) < 1e-9
 
 
+def test_gmres_converged_iterate_meets_rtol_on_the_true_residual():
+    """With short restarts and a preconditioner that varies from call to call
+    (rounded to single precision, as the complex64 two-grid step is), the
+    returned iterate meets rtol on f - A x itself."""
+    rng = np.random.default_rng(3)
+    n = 60
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 4 * np.eye(n)
+    Minv = np.linalg.inv(A + 0.3 * rng.standard_normal((n, n)))
+    f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    prec = lambda v: (Minv.astype(np.complex64) @ v.astype(np.complex64)).astype(np.complex128)
+    for restart in (2, 3, None):
+        for rtol in (1e-6, 1e-10):
+            x, it, _ = twogrid.gmres_right(lambda v: A @ v, prec, f, rtol=rtol, maxit=400,
+                                           restart=restart)
+            assert it < 400
+            assert np.linalg.norm(f - A @ x) <= rtol * np.linalg.norm(f)
+
+
 def test_givens_zeroes_second_component():
     for a, b in [(1 + 2j, 3 - 1j), (0.0, 2j), (1.5, 0.0)]:
         c, s, r = twogrid.givens(a, b)
