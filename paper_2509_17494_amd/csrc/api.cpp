@@ -118,7 +118,7 @@ static void free_graphs(th_ctx *c) {
 static void free_fine(th_ctx *c) {
   void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,  c->d_subs, c->d_nblk, c->d_B, c->w_r,
                   c->w_v,   c->w_rr,   c->w_y,  c->w_rc,   c->w_uc,   c->w_t, c->w_rc32,
-                  c->d_eidx, c->w_p, c->w_x, c->w_z};
+                  c->d_eidx, c->w_p, c->w_x, c->w_z, c->w_yc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_kap = c->d_kaps = nullptr;
@@ -127,7 +127,8 @@ static void free_fine(th_ctx *c) {
   c->d_nblk = nullptr;
   c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = c->w_rc32 = nullptr;
   c->d_eidx = nullptr;
-  c->w_p = c->w_x = c->w_z = nullptr;
+  c->w_p = c->w_x = c->w_z = c->w_yc = nullptr;
+  c->mfx_max_nrb = 0;
   c->max_nsl = c->max_slab_rows = 0;
   c->fine_ready = false;
 }
@@ -496,6 +497,14 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   if (ok && d->n_dd > 1)
     ok = alloc(&c->w_v, R * c->nf * sizeof(c64)) && alloc(&c->w_rr, R * c->nf * sizeof(c64));
   if (ok && c->layout == 3) ok = alloc(&c->w_z, R * c->x_rows * sizeof(c64));
+  if (ok && c->layout == 2 && mfx_fits(d->max_rhs, max_nom)) {
+    // colour planes of the staged matrix-core kernel, sized for complex128 vectors
+    const size_t yc = ((size_t)1 << c->dim) * R * c->nf * sizeof(c64);
+    if (yc <= ((size_t)4 << 30)) {
+      ok = alloc(&c->w_yc, yc);
+      for (const Sub &sb : c->subs) c->mfx_max_nrb = std::max(c->mfx_max_nrb, (sb.nU + 15) / 16);
+    }
+  }
   if (!ok) {
     free_fine(c);
     return fail(ctx, TH_ENOMEM, "device allocation failed in setup_fine");

@@ -3,7 +3,8 @@
 // events on the real subdomain operators and max_rhs right-hand sides, and the
 // fastest is kept.  Results are cached per problem shape and device in the
 // text file named by the environment variable TH_AUTOTUNE_CACHE (if set), one
-// line "key cfg grid ms" per shape.
+// line "key cfg grid ms" per shape.  TH_MFMA_CFG=<index>[,<grid>] skips the
+// search and takes that configuration when it applies to the problem.
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -56,19 +57,38 @@ static void cache_store(const std::string &key, int cfg, int grid, double ms) {
   out << key << " " << cfg << " " << grid << " " << ms << "\n";
 }
 
+// Every candidate is timed as the smoother's subdomain step: the batched
+// apply followed by the averaged update that reads its output (the staged
+// kernel writes colour planes, the chunked kernels the packed Y rows).
 int autotune_mfma(th_ctx *c) {
   hipStream_t s = c->stream;
   const int nrhs = c->desc.max_rhs;
   const std::string key = shape_key(c);
   int cfg = 0, grid = 0;
   double best = 0;
-  if (cache_lookup(key, cfg, grid, best)) {
+  // TH_MFMA_CFG=<index>[,<grid>] forces a configuration (tests and measurements)
+  if (const char *force = std::getenv("TH_MFMA_CFG")) {
+    int f = -1, g = 0;
+    if (std::sscanf(force, "%d,%d", &f, &g) >= 1 && f >= 0 && f < mfma_num_configs() && g >= 0 &&
+        (!mfma_cfg_staged(f) || c->w_yc)) {
+      c->mfma_cfg = f;
+      c->mfma_grid = mfma_cfg_staged(f) ? 0 : g;
+      c->tune_report = "forced";
+      return 0;
+    }
+  }
+  if (cache_lookup(key, cfg, grid, best) && (!mfma_cfg_staged(cfg) || c->w_yc)) {
     c->mfma_cfg = cfg;
     c->mfma_grid = grid;
     c->tune_report = "cache " + key;
     return 0;
   }
   TH_HIP_CHECK_RET(hipMemsetAsync(c->w_r, 0, (size_t)nrhs * c->nf * sizeof(c32), s));
+  void *uout = nullptr;
+  if (hipMalloc(&uout, (size_t)nrhs * c->nf * sizeof(c32)) != hipSuccess) {
+    set_error("cannot allocate the autotuner's output vector");
+    return TH_ENOMEM;
+  }
   hipDeviceProp_t prop{};
   TH_HIP_CHECK_RET(hipGetDeviceProperties(&prop, c->device));
   const int cu = prop.multiProcessorCount;
@@ -80,13 +100,22 @@ int autotune_mfma(th_ctx *c) {
   std::ostringstream rep;
   rep << key << ":";
   int rc = 0;
-  for (int cf = 0; cf < mfma_num_configs() && rc == 0; ++cf)
+  const int saved = c->mfma_cfg;
+  auto step = [&](int cf, int g) {
+    c->mfma_cfg = cf;  // selects the matching averaged update
+    int e = launch_dd_mfma(c, c->w_r, c->w_y, nrhs, true, cf, g, s);
+    if (!e) e = launch_dd_accumulate(c, c->w_y, uout, nrhs, true, true, s);
+    return e;
+  };
+  for (int cf = 0; cf < mfma_num_configs() && rc == 0; ++cf) {
+    if (mfma_cfg_staged(cf) && !c->w_yc) continue;
     for (int g : grids) {
-      rc = launch_dd_mfma(c, c->w_r, c->w_y, nrhs, true, cf, g, s);  // warm-up
+      if (mfma_cfg_staged(cf) && g != 0) continue;  // one workgroup per item, no grid choice
+      rc = step(cf, g);  // warm-up
       if (rc) break;
       (void)hipEventRecord(e0, s);
       const int reps = 3;
-      for (int i = 0; i < reps && rc == 0; ++i) rc = launch_dd_mfma(c, c->w_r, c->w_y, nrhs, true, cf, g, s);
+      for (int i = 0; i < reps && rc == 0; ++i) rc = step(cf, g);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) {
         rc = TH_EHIP;
@@ -103,8 +132,12 @@ int autotune_mfma(th_ctx *c) {
         grid = g;
       }
     }
+  }
+  c->mfma_cfg = saved;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(uout);
   if (rc) return rc;
   c->mfma_cfg = cfg;
   c->mfma_grid = grid;

@@ -166,6 +166,8 @@ struct th_ctx {
   void *w_rc32 = nullptr;      // coarse rhs in working precision
   void *w_p = nullptr;         // transposed-tile partial sums (symmetric layout)
   void *w_x = nullptr;         // gathered patches X_i (symmetric layout)
+  void *w_yc = nullptr;        // colour planes [2^d][rhs][n_fine] of the staged matrix-core kernel
+  int mfx_max_nrb = 0;         // most 16-row blocks of a subdomain (staged matrix-core kernel)
   size_t ws_bytes = 0;
 
   th::CoarseData coarse;
@@ -257,6 +259,10 @@ int launch_extract_b_mfma(const th_ctx *c, int s0, int nb, const c64 *work, int 
                           long long stride, hipStream_t s);
 long long mfma_store_elems(const Sub &s);
 int mfma_num_configs();
+bool mfma_cfg_staged(int cfg);          // configuration of the staged kernel (colour-plane output)
+int mfx_rhs_group(int max_rhs);         // right-hand sides staged together by the staged kernel
+bool mfx_fits(int max_rhs, int max_nom);  // patches small enough for the staged kernel
+int launch_dd_accum_col(const th_ctx *c, void *u, int nrhs, bool f32, bool assign, hipStream_t s);
 int launch_dd_mfma(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, int cfg, int grid,
                    hipStream_t s);
 

@@ -313,6 +313,9 @@ int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32,
 
 int launch_dd_accumulate(const th_ctx *c, const void *y, void *u, int nrhs, bool f32, bool assign,
                          hipStream_t s) {
+  // the staged matrix-core kernel leaves its results in the colour planes
+  if (c->layout == 2 && mfma_cfg_staged(c->mfma_cfg))
+    return launch_dd_accum_col(c, u, nrhs, f32, assign, s);
   int blocks = (int)std::min<long long>(ceil_div_ll(c->nf, 256), 65535);
   if (f32)
     hipLaunchKernelGGL((k_dd_accumulate<float>), dim3(blocks, nrhs), dim3(256), 0, s, c->d_subs,

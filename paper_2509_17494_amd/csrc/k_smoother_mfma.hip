@@ -16,6 +16,21 @@
 // row blocks) work items, so the launch holds all subdomains and all
 // right-hand sides; the waves per workgroup, the column chunk and the grid
 // size are tunables chosen by the setup autotuner.
+//
+// Staged form (k_dd_mfx, for patches small enough to sit in LDS whole: n_Omega
+// up to 448 columns with 64 right-hand sides, 896 with 32, 1792 with 16): one
+// workgroup per (subdomain, group of row blocks).  Each wavefront first
+// issues the loads of its first operand fragments, then the whole workgroup
+// gathers the patch X_i once (node offsets from an LDS table, two columns per
+// thread, rounded to BF16) into LDS planes [plane][rhs][k] (row stride
+// n_Omega + 8: conflict-free 16-byte fragment reads), and after one barrier
+// every wavefront streams its row blocks' fragments from memory, four deep in
+// registers, through the MFMAs.  The workgroups of one subdomain are g * nsub
+// + si, so with nsub a multiple of 8 they land on the same XCD and share its
+// L2 for the patch.  Results go to the colour planes of the Y scratch: plane
+// c = parity of the subdomain's block index per direction, at the global node
+// position, so that subdomains of one colour never share a node and the
+// averaged update reads every contribution with coalesced loads.
 #include "ctx.hpp"
 
 namespace th {
@@ -143,6 +158,162 @@ __global__ __launch_bounds__(64 * WAVES) void k_dd_mfma(const Sub *__restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Staged form.
+constexpr int MFX_LDS_ELEMS = 2 * 64 * 456;  // bf16 elements of the staged patch planes
+constexpr int MFX_KMAX = 1792;               // largest staged patch (columns)
+constexpr int MFX_PF = 4;                    // operand fragments in flight per wavefront
+
+// Columns of the largest patch the staged form holds for RHSG right-hand sides.
+__host__ __device__ constexpr int mfx_kcap(int rhsg) {
+  return ((MFX_LDS_ELEMS / (2 * rhsg) - 8) / MF_KB) * MF_KB < MFX_KMAX
+             ? ((MFX_LDS_ELEMS / (2 * rhsg) - 8) / MF_KB) * MF_KB
+             : MFX_KMAX;
+}
+
+template <typename T, int WAVES, int RHSG>
+__global__ __launch_bounds__(64 * WAVES) void k_dd_mfx(const Sub *__restrict__ subs, int nsub,
+                                                       int rbg, int M,
+                                                       const unsigned short *__restrict__ B,
+                                                       const cx<T> *__restrict__ r,
+                                                       cx<T> *__restrict__ Yc, int P, int n1,
+                                                       long long nf, int nrhs) {
+  constexpr int NT = 64 * WAVES, NTILE = RHSG / MF_NT;
+  __shared__ __attribute__((aligned(16))) unsigned short Xs[MFX_LDS_ELEMS];
+  __shared__ int gofs[MFX_KMAX];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int si = blockIdx.x % nsub, grp = blockIdx.x / nsub;
+  const Sub s = subs[si];
+  const int nrb = (s.nU + MF_RB - 1) / MF_RB;
+  const int rb0 = grp * rbg, rb1 = min(nrb, rb0 + rbg);
+  if (rb0 >= rb1) return;  // uniform over the workgroup
+  const int nkb = (s.nOm + MF_KB - 1) / MF_KB, K = nkb * MF_KB, LD = K + 8;
+  const long long base = om_node(s, 0, P, n1);
+  for (int k = threadIdx.x; k < K; k += NT)
+    gofs[k] = k < s.nOm ? (int)(om_node(s, k, P, n1) - base) : -1;
+  const int bx = si % M, by = (si / M) % M, bz = si / (M * M);
+  const int color = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
+  // this wavefront's row blocks rb0 + wave + j WAVES, flattened with the column blocks
+  const int nmine = (rb0 + wave < rb1) ? (rb1 - rb0 - wave + WAVES - 1) / WAVES : 0;
+  const int nit = nmine * nkb;
+  auto frag = [&](int it, int plane) {
+    const int rb = rb0 + wave + (it / nkb) * WAVES, kb = it % nkb;
+    return (const u32x4 *)(B + mf_frag(s, rb, kb, plane) + lane * 8);
+  };
+  for (int r0 = 0; r0 < nrhs; r0 += RHSG) {
+    const int nr = min(RHSG, nrhs - r0);
+    u32x4 fr[MFX_PF], fi[MFX_PF];
+#pragma unroll
+    for (int j = 0; j < MFX_PF; ++j)
+      if (j < nit) {
+        fr[j] = __builtin_nontemporal_load(frag(j, 0));
+        fi[j] = __builtin_nontemporal_load(frag(j, 1));
+      }
+    __syncthreads();  // offset table written; the previous group's reads of Xs done
+    // gather X_i: two consecutive columns per thread, right-hand sides slowest
+    const cx<T> *rg = r + (long long)r0 * nf + base;
+    for (int t = threadIdx.x; t < (K / 2) * RHSG; t += NT) {
+      const int k = 2 * (t % (K / 2)), q = t / (K / 2);
+      unsigned int vr = 0, vi = 0;
+      if (q < nr) {
+        const int g0 = gofs[k], g1 = gofs[k + 1];
+        const cx<T> a = g0 >= 0 ? rg[(long long)q * nf + g0] : cx<T>{0, 0};
+        const cx<T> b = g1 >= 0 ? rg[(long long)q * nf + g1] : cx<T>{0, 0};
+        vr = (unsigned int)f2bf((float)a.re) | ((unsigned int)f2bf((float)b.re) << 16);
+        vi = (unsigned int)f2bf((float)a.im) | ((unsigned int)f2bf((float)b.im) << 16);
+      }
+      *(unsigned int *)&Xs[(long long)q * LD + k] = vr;
+      *(unsigned int *)&Xs[(long long)(RHSG + q) * LD + k] = vi;
+    }
+    __syncthreads();
+    f32x4 are[NTILE], aim[NTILE];
+    for (int it0 = 0; it0 < nit; it0 += MFX_PF) {
+#pragma unroll
+      for (int j = 0; j < MFX_PF; ++j) {
+        const int it = it0 + j;
+        if (it < nit) {  // uniform per wavefront
+          const int kb = it % nkb;
+          if (kb == 0) {
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t) {
+              are[t] = f32x4{0, 0, 0, 0};
+              aim[t] = f32x4{0, 0, 0, 0};
+            }
+          }
+          const u32x4 uin = fi[j] ^ u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+          const bf16x8 br = __builtin_bit_cast(bf16x8, fr[j]);
+          const bf16x8 bi = __builtin_bit_cast(bf16x8, fi[j]);
+          const bf16x8 bin = __builtin_bit_cast(bf16x8, uin);
+          const int kl = kb * MF_KB + (lane / 16) * 8;
+#pragma unroll
+          for (int t = 0; t < NTILE; ++t) {
+            const int q = t * MF_NT + lane % 16;
+            const bf16x8 xr = __builtin_bit_cast(bf16x8, *(const u32x4 *)&Xs[(long long)q * LD + kl]);
+            const bf16x8 xi =
+                __builtin_bit_cast(bf16x8, *(const u32x4 *)&Xs[(long long)(RHSG + q) * LD + kl]);
+            are[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, xr, are[t], 0, 0, 0);
+            are[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bin, xi, are[t], 0, 0, 0);
+            aim[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, xi, aim[t], 0, 0, 0);
+            aim[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi, xr, aim[t], 0, 0, 0);
+          }
+          if (it + MFX_PF < nit) {
+            fr[j] = __builtin_nontemporal_load(frag(it + MFX_PF, 0));
+            fi[j] = __builtin_nontemporal_load(frag(it + MFX_PF, 1));
+          }
+          if (kb == nkb - 1) {
+            const int rb = rb0 + wave + (it / nkb) * WAVES;
+            long long gn[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = rb * MF_RB + (lane / 16) * 4 + i;
+              gn[i] = row < s.nU ? u_global(s, row, P, n1) : -1;
+            }
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t) {
+              const int q = t * MF_NT + lane % 16;
+              if (q < nr) {
+                cx<T> *yq = Yc + ((long long)color * nrhs + r0 + q) * nf;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  if (gn[i] >= 0) yq[gn[i]] = cx<T>{(T)are[t][i], (T)aim[t][i]};
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Averaged update from the colour planes: v_j (assign) or u_j += sum over the
+// closed U^(i) containing node j of (Y_i)_j, subdomains in ascending order (the
+// order of k_dd_accumulate, so both give the same bits).
+template <typename T>
+__global__ __launch_bounds__(256) void k_dd_accum_col(const int *__restrict__ nblk,
+                                                      const cx<T> *__restrict__ Yc,
+                                                      cx<T> *__restrict__ u, int n1, long long nf,
+                                                      int nrhs, int assign) {
+  const long long rhs = blockIdx.y;
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < nf;
+       g += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(g % n1);
+    const long long t = g / n1;
+    const int iy = (int)(t % n1), iz = (int)(t / n1);  // iz = 0 in 2-D
+    const int bx0 = nblk[2 * ix], nbx = nblk[2 * ix + 1];
+    const int by0 = nblk[2 * iy], nby = nblk[2 * iy + 1];
+    const int bz0 = nblk[2 * iz], nbz = nblk[2 * iz + 1];
+    cx<T> acc = {0, 0};
+    for (int bz = bz0; bz < bz0 + nbz; ++bz)
+      for (int by = by0; by < by0 + nby; ++by)
+        for (int bx = bx0; bx < bx0 + nbx; ++bx) {
+          const int color = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
+          acc = acc + Yc[((long long)color * nrhs + rhs) * nf + g];
+        }
+    cx<T> *up = u + rhs * nf + g;
+    *up = assign ? acc : *up + acc;
+  }
+}
+
 // Setup: B_i in the MFMA layout from the FP64 inverse (row-major, ld), the
 // weights 1/L_j applied, rounded to BF16.  One thread per (rb, kb, lane).
 __global__ __launch_bounds__(256) void k_extract_b_mfma(const Sub *__restrict__ subs, int s0,
@@ -211,20 +382,79 @@ static int launch_mfma_t(const th_ctx *c, const void *r, void *y, int nrhs, int 
   return 0;
 }
 
-// tunable configurations: (waves per workgroup, column blocks per chunk)
+template <typename T, int WAVES>
+static int launch_mfx_t(const th_ctx *c, const void *r, int nrhs, int groups, hipStream_t s) {
+  const int nsub = (int)c->subs.size();
+  const int rbg = ceil_div(c->mfx_max_nrb, groups);
+  const dim3 grid(nsub * groups);
+  cx<T> *yc = (cx<T> *)c->w_yc;
+  const unsigned short *B = (const unsigned short *)c->d_B;
+  const cx<T> *rr = (const cx<T> *)r;
+  const int rhsg = mfx_rhs_group(c->desc.max_rhs);
+  if (rhsg == 16)
+    hipLaunchKernelGGL((k_dd_mfx<T, WAVES, 16>), grid, dim3(64 * WAVES), 0, s, c->d_subs, nsub, rbg,
+                       c->M, B, rr, yc, c->P, c->n1, c->nf, nrhs);
+  else if (rhsg == 32)
+    hipLaunchKernelGGL((k_dd_mfx<T, WAVES, 32>), grid, dim3(64 * WAVES), 0, s, c->d_subs, nsub, rbg,
+                       c->M, B, rr, yc, c->P, c->n1, c->nf, nrhs);
+  else
+    hipLaunchKernelGGL((k_dd_mfx<T, WAVES, 64>), grid, dim3(64 * WAVES), 0, s, c->d_subs, nsub, rbg,
+                       c->M, B, rr, yc, c->P, c->n1, c->nf, nrhs);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+int mfx_rhs_group(int max_rhs) { return max_rhs <= 16 ? 16 : (max_rhs <= 32 ? 32 : 64); }
+
+bool mfx_fits(int max_rhs, int max_nom) {
+  return ceil_div(max_nom, MF_KB) * MF_KB <= mfx_kcap(mfx_rhs_group(max_rhs));
+}
+
+// tunable configurations: persistent chunked kernel (waves per workgroup,
+// column blocks per chunk), then the staged kernel (waves per workgroup,
+// workgroups per subdomain)
 static const int kMfmaCfg[][2] = {{4, 4}, {4, 8}, {2, 4}, {8, 4}, {2, 8}};
-int mfma_num_configs() { return (int)(sizeof(kMfmaCfg) / sizeof(kMfmaCfg[0])); }
+static const int kMfxCfg[][2] = {{4, 4}, {8, 4}, {8, 2}, {4, 5}, {8, 3}, {4, 8}, {8, 1}};
+constexpr int kNumChunked = (int)(sizeof(kMfmaCfg) / sizeof(kMfmaCfg[0]));
+int mfma_num_configs() { return kNumChunked + (int)(sizeof(kMfxCfg) / sizeof(kMfxCfg[0])); }
+bool mfma_cfg_staged(int cfg) { return cfg >= kNumChunked; }
 
 int launch_dd_mfma(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, int cfg, int grid,
                    hipStream_t s) {
+  if (cfg >= kNumChunked && cfg < mfma_num_configs()) {
+    if (!c->w_yc) {
+      set_error("staged matrix-core smoother selected without its colour planes");
+      return TH_EINVAL;
+    }
+    const int w = kMfxCfg[cfg - kNumChunked][0], g = kMfxCfg[cfg - kNumChunked][1];
+#define TH_MX(W)                                                                         \
+  if (w == W) return f32 ? launch_mfx_t<float, W>(c, r, nrhs, g, s)                     \
+                         : launch_mfx_t<double, W>(c, r, nrhs, g, s);
+    TH_MX(4) TH_MX(8)
+#undef TH_MX
+  }
 #define TH_MF(W, K)                                                                         \
-  if (kMfmaCfg[cfg][0] == W && kMfmaCfg[cfg][1] == K)                                     \
+  if (cfg < kNumChunked && kMfmaCfg[cfg][0] == W && kMfmaCfg[cfg][1] == K)                \
     return f32 ? launch_mfma_t<float, W, K>(c, r, y, nrhs, grid, s)                       \
                : launch_mfma_t<double, W, K>(c, r, y, nrhs, grid, s);
   TH_MF(4, 4) TH_MF(4, 8) TH_MF(2, 4) TH_MF(8, 4) TH_MF(2, 8)
 #undef TH_MF
   set_error("bad matrix-core smoother configuration");
   return TH_EINVAL;
+}
+
+int launch_dd_accum_col(const th_ctx *c, void *u, int nrhs, bool f32, bool assign, hipStream_t s) {
+  int blocks = (int)std::min<long long>(ceil_div_ll(c->nf, 256), 65535);
+  if (f32)
+    hipLaunchKernelGGL((k_dd_accum_col<float>), dim3(blocks, nrhs), dim3(256), 0, s, c->d_nblk,
+                       (const cx<float> *)c->w_yc, (cx<float> *)u, c->n1, c->nf, nrhs,
+                       assign ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_dd_accum_col<double>), dim3(blocks, nrhs), dim3(256), 0, s, c->d_nblk,
+                       (const cx<double> *)c->w_yc, (cx<double> *)u, c->n1, c->nf, nrhs,
+                       assign ? 1 : 0);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
 }
 
 }  // namespace th

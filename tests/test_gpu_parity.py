@@ -214,6 +214,41 @@ def test_smooth_bf16_matrix_cores(N, p, l_dd, nrhs):
         assert err < 5e-2
 
 
+@pytest.mark.parametrize("N,p,l_dd,nrhs", [(37, 2, 8, 64), (19, 4, 6, 5), (64, 2, 8, 70),
+                                            (12, 2, 4, 20)])
+def test_matrix_core_configurations_agree_bitwise(N, p, l_dd, nrhs, monkeypatch):
+    """Every matrix-core smoother configuration (the persistent chunked kernel
+    with its tile choices and the staged kernel with its workgroup splits,
+    forced through TH_MFMA_CFG) gives bitwise the same smoother output: the
+    same MFMAs in the same order, and the averaged update from the packed Y
+    rows or from the colour planes in the same subdomain order.  Covers
+    staged right-hand-side groups of 16, 32 and 64, a ragged last group
+    (70 = 64 + 6) and ragged row blocks."""
+    from paper_2509_17494_amd import _lib as L
+    print(f"case mfma configs N={N} p={p} nrhs={nrhs}", flush=True)
+    k = hetero_k(N, p, seed=31)
+    n = (N * p + 1) ** 2
+    u0 = syn.random_complex((nrhs, n), seed=32)
+    f = syn.random_complex((nrhs, n), seed=33)
+    out = {}
+    n_cfg = 12  # 5 chunked + 7 staged configurations
+    for cfg in range(n_cfg):
+        monkeypatch.setenv("TH_MFMA_CFG", str(cfg))
+        s = make_solver(k, p, l_dd, max_rhs=nrhs, coarse=None, gemm="bf16")
+        got_cfg = s.info()["smoother_cfg"]
+        if got_cfg != cfg:  # a staged configuration on patches too large for it
+            s.close()
+            continue
+        u = to_dev(u0, torch.complex64)
+        s.smooth(u, to_dev(f, torch.complex64))
+        out[cfg] = to_np(u)
+        s.close()
+    print(f"  configurations run: {sorted(out)}", flush=True)
+    assert 0 in out and len(out) >= 6
+    for cfg, v in out.items():
+        assert np.array_equal(v, out[0]), f"configuration {cfg} differs"
+
+
 @pytest.mark.parametrize("N,p,l_dd,layout", [(19, 4, 6, 0), (33, 4, 8, 1)])
 def test_operator_layout_choice(N, p, l_dd, layout):
     """Dense rows below, symmetric tiles above the 80 % storage threshold."""
