@@ -124,6 +124,23 @@ typedef struct {
                            BF16 storage has the matrix-core layout only */
 } th_fine_desc;
 
+/* Direct solver of the coarse system (th_coarse_desc.solver).  Both are exact
+ * FP64 factorisations computed once on the device at setup; they differ in
+ * the order of elimination, hence in bytes streamed and launches per solve.
+ * ND eliminates interior separator blocks that can be nearly singular (real
+ * indefinite Helmholtz blocks), so setup adds iterative-refinement steps (up
+ * to 3, th_info.coarse_refine) until the probe solve is within 1e-13.
+ *   LINES:  block elimination over super-blocks of grid lines (planes in 3-D),
+ *           explicit inverses of the Schur blocks (twisted when the slab
+ *           right-hand sides fit in LDS).
+ *   ND:     nested dissection of the vertex grid by separator lines (planes),
+ *           multifrontal elimination with explicit inverses of every
+ *           separator's frontal block; two launches per tree level.
+ *   AUTO:   ND, unless its setup runs out of memory or its probe check (a
+ *           solve against A_c x for a vector of unit-modulus entries, reported
+ *           in th_info.coarse_check) misses 1e-9; then LINES. */
+typedef enum { TH_CSOLVE_AUTO = 0, TH_CSOLVE_LINES = 1, TH_CSOLVE_ND = 2 } th_coarse_solver;
+
 typedef struct {
   th_coarse_scheme scheme;
   const double *q;      /* HOST, (pN/2)^d x 3 (2-D) or x 4 (3-D) weights, x fastest;
@@ -132,6 +149,7 @@ typedef struct {
   double fallback_tau;  /* TH_COARSE_MLP: a cell falls back to the plain fit when the
                            network's dispersion errors differ from the fine ones by more
                            than this (relative wavenumber); 0 = every cell falls back */
+  th_coarse_solver solver; /* coarse factorisation (0 = automatic) */
 } th_coarse_desc;
 
 typedef struct {
@@ -177,6 +195,12 @@ typedef struct {
                              1 symmetric tiles (FP64/FP32; the U x U block of the symmetric
                              inverse stored once), 2 matrix-core fragments (BF16),
                              3 slab factors (FP64/FP32) */
+  int coarse_solver;      /* factorisation in use: TH_CSOLVE_LINES or TH_CSOLVE_ND */
+  int coarse_levels;      /* ND: levels of the dissection tree (two launches each per solve) */
+  int coarse_refine;      /* ND: iterative-refinement steps per coarse solve (each one more
+                             solve with the factors and a stencil residual) */
+  double coarse_check;    /* max |A_c^{-1} (A_c x) - x| over the coarse vertices for the setup
+                             probe x (unit-modulus entries) */
 } th_info;
 
 /* Create a context on HIP device `hip_device`, ordering work on `hip_stream`
@@ -200,10 +224,11 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *desc);
 
 /* Build the coarse QSFEM quasi-FE matrix (Sec. 3.3, eq. element_wise_qsfem;
  * 27-point in 3-D) on the coarse vertex grid and factorise it once in FP64 on
- * the device (block-tridiagonal elimination over grid lines, or planes in
- * 3-D, with explicit inverses of the diagonal Schur blocks).  Needs
+ * the device (th_coarse_solver: nested dissection, or block elimination over
+ * grid lines or planes; explicit inverses of the eliminated blocks).  Needs
  * th_setup_fine.  Blocking.  Errors: TH_EINVAL (also: surrogate network of the
- * other dimension's family), TH_ENOMEM, TH_ENUMERIC. */
+ * other dimension's family, unknown solver), TH_ENOMEM, TH_ENUMERIC (a pivot
+ * guard, or with TH_CSOLVE_ND a probe check above 1e-6). */
 th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *desc);
 
 /* r = f - A u (fine Galerkin matrix, eq. bilin_form).  Stream-ordered. */

@@ -48,6 +48,8 @@ def load_library():
 
 _BC = {"robin": L.TH_BC_ROBIN, "neumann": L.TH_BC_NEUMANN, "dirichlet": L.TH_BC_DIRICHLET}
 _GEMM = {"f64": L.TH_GEMM_F64, "f32": L.TH_GEMM_F32, "bf16": L.TH_GEMM_BF16}
+_CSOLVE = {None: L.TH_CSOLVE_AUTO, "auto": L.TH_CSOLVE_AUTO, "lines": L.TH_CSOLVE_LINES,
+           "nd": L.TH_CSOLVE_ND}
 _LAYOUT = {None: L.TH_LAYOUT_AUTO, "auto": L.TH_LAYOUT_AUTO, "dense": L.TH_LAYOUT_DENSE,
            "symmetric": L.TH_LAYOUT_SYMMETRIC, "slab": L.TH_LAYOUT_SLAB}
 LAYOUT_NAMES = {0: "dense", 1: "symmetric", 2: "matrix-core", 3: "slab"}
@@ -75,7 +77,8 @@ class TwoGridSolver:
     def __init__(self, k, eps=None, order: int = 2, alpha_s: float = 0.5, l_dd: int = 8,
                  n_dd: int = 1, n_s: int = 1, omega_c: float = 1.0, bc=None,
                  gemm: str = "f64", max_rhs: int = 1, device: int | None = None,
-                 coarse: str | None = "qsfem", coarse_q=None, layout: str | None = None):
+                 coarse: str | None = "qsfem", coarse_q=None, layout: str | None = None,
+                 coarse_solver: str | None = None):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
@@ -120,7 +123,7 @@ class TwoGridSolver:
             d.layout = _LAYOUT[layout]
             self._check(self._lib.th_setup_fine(self._h, C.byref(d)))
             if coarse is not None:
-                self.setup_coarse(coarse, coarse_q)
+                self.setup_coarse(coarse, coarse_q, solver=coarse_solver)
 
     # ------------------------------------------------------------------
     def _check(self, st: int):
@@ -139,8 +142,12 @@ class TwoGridSolver:
         except Exception:
             pass
 
-    def setup_coarse(self, scheme: str = "qsfem", q=None):
+    def setup_coarse(self, scheme: str = "qsfem", q=None, solver: str | None = None):
+        """Coarse operator and its factorisation; solver: "nd" (nested
+        dissection), "lines" (block elimination over grid lines or planes) or
+        None (automatic)."""
         d = L.CoarseDesc()
+        d.solver = _CSOLVE[solver]
         if scheme == "qsfem":
             d.scheme = L.TH_COARSE_QSFEM
             d.q = C.POINTER(C.c_double)()

@@ -19,6 +19,7 @@ TH_C128, TH_C64 = 0, 1
 TH_GEMM_F64, TH_GEMM_F32, TH_GEMM_BF16 = 0, 1, 2
 TH_COARSE_QSFEM, TH_COARSE_PLAINFIT, TH_COARSE_MLP, TH_COARSE_WEIGHTS = 0, 1, 2, 3
 TH_KRYLOV_GMRES_RIGHT, TH_KRYLOV_FGMRES, TH_KRYLOV_STATIONARY = 0, 1, 2
+TH_CSOLVE_AUTO, TH_CSOLVE_LINES, TH_CSOLVE_ND = 0, 1, 2
 KERNEL_CLASSES = ["dd_apply", "dd_accum", "operator", "restrict", "prolong", "coarse", "krylov"]
 
 
@@ -32,7 +33,7 @@ class FineDesc(C.Structure):
 
 class CoarseDesc(C.Structure):
     _fields_ = [("scheme", C.c_int), ("q", C.POINTER(C.c_double)), ("mlp", C.c_void_p),
-                ("fallback_tau", C.c_double)]
+                ("fallback_tau", C.c_double), ("solver", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -53,7 +54,9 @@ class Info(C.Structure):
                 ("t_setup_coarse_s", C.c_double), ("smoother_cfg", C.c_int),
                 ("smoother_grid", C.c_int), ("coarse_lines", C.c_int),
                 ("n_fallback_cells", C.c_int), ("t_stencil_s", C.c_double),
-                ("smoother_layout", C.c_int)]
+                ("smoother_layout", C.c_int), ("coarse_solver", C.c_int),
+                ("coarse_levels", C.c_int), ("coarse_refine", C.c_int),
+                ("coarse_check", C.c_double)]
 
 
 _lib = None

@@ -133,11 +133,17 @@ static void free_fine(th_ctx *c) {
   c->fine_ready = false;
 }
 
+// nested-dissection coarse solve: probe error below which no further
+// refinement step is taken, and the most steps
+constexpr double kCoarseRefineTol = 1e-13;
+constexpr int kCoarseMaxRefine = 3;
+
 static void free_coarse(th_ctx *c) {
   free_graphs(c);  // graphs reference the coarse factors and workspaces
   void *ptrs[] = {c->coarse.G, c->coarse.st, c->coarse.tbuf, c->coarse.pbuf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  free_nd(c->coarse.nd);
   c->coarse = CoarseData{};
   c->coarse_ready = false;
 }
@@ -234,6 +240,10 @@ th_status th_get_info(const th_ctx *ctx, th_info *info) {
   info->n_fallback_cells = ctx->n_fallback;
   info->t_stencil_s = ctx->t_stencil;
   info->smoother_layout = ctx->layout;
+  info->coarse_solver = ctx->coarse.kind == 1 ? TH_CSOLVE_ND : TH_CSOLVE_LINES;
+  info->coarse_levels = ctx->coarse.nd.levels;
+  info->coarse_refine = ctx->coarse.nd.refine;
+  info->coarse_check = ctx->coarse.check_err;
   return TH_OK;
 }
 
@@ -725,6 +735,8 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
   if (d->scheme != TH_COARSE_QSFEM && d->scheme != TH_COARSE_WEIGHTS &&
       d->scheme != TH_COARSE_PLAINFIT && d->scheme != TH_COARSE_MLP)
     return fail(ctx, TH_EINVAL, "unknown coarse scheme");
+  if (d->solver != TH_CSOLVE_AUTO && d->solver != TH_CSOLVE_LINES && d->solver != TH_CSOLVE_ND)
+    return fail(ctx, TH_EINVAL, "unknown coarse solver");
   if (d->scheme == TH_COARSE_WEIGHTS && !d->q) return fail(ctx, TH_EINVAL, "q is NULL");
   if (d->scheme == TH_COARSE_MLP && !d->mlp) return fail(ctx, TH_EINVAL, "mlp is NULL");
   if (d->scheme == TH_COARSE_MLP && !(d->fallback_tau >= 0.0))
@@ -739,7 +751,46 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
     if (sc) return sc;
     eliminate_dirichlet(c, st);
   }
-  int rc = setup_coarse_factors(c, st);
+  // nested dissection first (unless the caller asked for the line elimination);
+  // AUTO falls back to the line elimination when it fails its probe check or
+  // cannot get its memory
+  int rc = 0;
+  bool have = false;
+  if (d->solver != TH_CSOLVE_LINES) {
+    rc = setup_coarse_nd(c, st);
+    double err = -1.0;
+    if (rc == 0) rc = coarse_probe_check(c, st, &err);
+    // refinement steps until the probe solve is at the rounding level
+    while (rc == 0 && !(err <= kCoarseRefineTol) && c->coarse.nd.refine < kCoarseMaxRefine) {
+      ++c->coarse.nd.refine;
+      rc = coarse_probe_check(c, st, &err);
+    }
+    c->coarse.check_err = err;
+    const double tol = d->solver == TH_CSOLVE_ND ? 1e-6 : 1e-9;
+    if (rc == 0 && err <= tol) {
+      have = true;
+    } else if (d->solver == TH_CSOLVE_ND) {
+      if (rc == 0) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "nested-dissection coarse factors fail the probe check "
+                      "(%.3e > %.0e)", err, tol);
+        set_error(msg);
+        rc = TH_ENUMERIC;
+      }
+    } else if (rc == 0 || rc == TH_ENOMEM || rc == TH_ENUMERIC) {
+      rc = 0;  // AUTO: the line elimination instead
+    }
+    if (!have) {
+      free_nd(c->coarse.nd);
+      c->coarse = CoarseData{};
+    }
+  }
+  if (!have && rc == 0) {
+    rc = setup_coarse_factors(c, st);
+    double err = -1.0;
+    if (rc == 0) rc = coarse_probe_check(c, st, &err);
+    c->coarse.check_err = err;
+  }
   if (rc) {
     free_coarse(c);
     return finish(ctx, rc);

@@ -93,6 +93,43 @@ struct FineOp {
   const double *kr;           // per cell k for the absorbing term
 };
 
+// Nested-dissection coarse solve: one tree node (device descriptor).  The
+// node's vertex list holds I (nI entries) followed by B (nB); its front
+// positions (I, then B) carry two extend-add sources (update-vector entries of
+// its two children, or -1); [G; -T] is stored column-major with leading
+// dimension ldm (rows nI + nB), -W column-major over B with leading dimension
+// ldw (rows nI); its own update vector has nB entries at uoff.
+struct NDNode {
+  int nI, nB, ldm, ldw;
+  long long ioff, soff, moff, woff, uoff;
+};
+
+// Nodes of one tree level (equal height) and their workgroup tasks.
+struct NDLevel {
+  int n0 = 0, n1 = 0;     // nodes [n0, n1) in level order
+  int f0 = 0, f1 = 0;     // forward tasks (node, first row)
+  int b0 = 0, b1 = 0;     // backward tasks
+  int maxI = 0, maxB = 0;
+};
+
+struct NDData {
+  int levels = 0, nodes = 0;
+  std::vector<NDLevel> lv;
+  NDNode *d_nodes = nullptr;
+  int *d_idx = nullptr;       // vertex lists (I then B per node)
+  int *d_src = nullptr;       // extend-add sources, two per front position
+  int2 *d_ftask = nullptr, *d_btask = nullptr;
+  c64 *M = nullptr;           // [G; -T] per node
+  c64 *Wm = nullptr;          // -W per node
+  c64 *uvec = nullptr;        // update vectors [max_rhs][ulen]
+  long long ulen = 0, bytes = 0, fwd_bytes = 0, bwd_bytes = 0;
+  // iterative refinement: x += A_c^{-1}(r - A_c x) repeated `refine` times,
+  // with the stencil kept on the device and two coarse work vectors per RHS
+  int refine = 0;
+  c64 *st = nullptr;
+  c64 *t = nullptr, *d = nullptr;
+};
+
 // The coarse grid is ordered in slabs along the slowest axis (lines of
 // constant y in 2-D, planes of constant z in 3-D).  Every vertex couples to
 // the previous / same / next slab through C = 3^(d-1) in-slab offsets.
@@ -113,6 +150,9 @@ struct CoarseData {
   c64 *tbuf = nullptr;        // staging of slab right-hand sides for large slabs
   c64 *pbuf = nullptr;        // column-chunk partial sums of the large-slab GEMV
   long long bytes = 0;
+  int kind = 0;               // 0: block elimination over slabs, 1: nested dissection
+  NDData nd;
+  double check_err = -1.0;    // max |A_c^{-1} (A_c x) - x| of the setup probe (unit entries)
 };
 
 }  // namespace th
@@ -280,6 +320,15 @@ int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const doubl
 // k_coarse.hip
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);
 int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s);
+// k_nd.hip: nested-dissection factorisation of the coarse stencil matrix, its
+// solve, and the probe check of whichever coarse factorisation is set up
+int setup_coarse_nd(th_ctx *c, const std::vector<c64> &stencil);
+int launch_coarse_nd(const th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s);
+void free_nd(NDData &nd);
+int coarse_probe_check(th_ctx *c, const std::vector<c64> &stencil, double *err);
+// modelled solve times (s) of both coarse factorisations for the context's grid
+double coarse_model_lines(const th_ctx *c);
+double coarse_model_nd(const th_ctx *c);
 int gj_invert_batched(c64 *A, int n, int ld, long long stride, int batch, hipStream_t s,
                       c64 *ws);
 // work space of gj_invert_batched for batches of up to `batch` matrices of size <= n:

@@ -657,6 +657,7 @@ static bool small_slabs_fit(const CoarseData &cd, int RC) {
 }
 
 int launch_coarse_solve(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+  if (c->coarse.kind == 1) return launch_coarse_nd(c, rcv, uc, nrhs, s);
   if (!small_slabs_fit(c->coarse, c->coarse.rc_chunk)) {
     if (nrhs >= 8) return sweep_large_t<8>(c, rcv, uc, nrhs, s);
     if (nrhs >= 4) return sweep_large_t<4>(c, rcv, uc, nrhs, s);
