@@ -136,7 +136,9 @@ typedef struct {
  *   ND:     nested dissection of the vertex grid by separator lines (planes),
  *           multifrontal elimination with explicit inverses of every
  *           separator's frontal block; two launches per tree level.
- *   AUTO:   ND, unless its setup runs out of memory or its probe check (a
+ *   AUTO:   ND, unless its modelled solve time (factor bytes over bandwidth
+ *           and a latency per launch, for max_rhs right-hand sides) exceeds
+ *           that of LINES, its setup runs out of memory or its probe check (a
  *           solve against A_c x for a vector of unit-modulus entries, reported
  *           in th_info.coarse_check) misses 1e-9; then LINES. */
 typedef enum { TH_CSOLVE_AUTO = 0, TH_CSOLVE_LINES = 1, TH_CSOLVE_ND = 2 } th_coarse_solver;

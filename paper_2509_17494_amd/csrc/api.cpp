@@ -767,7 +767,8 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
     }
     c->coarse.check_err = err;
     const double tol = d->solver == TH_CSOLVE_ND ? 1e-6 : 1e-9;
-    if (rc == 0 && err <= tol) {
+    if (rc == 0 && err <= tol &&
+        (d->solver == TH_CSOLVE_ND || coarse_model_nd(c) <= coarse_model_lines(c))) {
       have = true;
     } else if (d->solver == TH_CSOLVE_ND) {
       if (rc == 0) {
@@ -871,7 +872,7 @@ static int coarse_solve_impl(th_ctx *c, const void *rc_in, void *uc_out, int nrh
   int rc;
   {
     KTimer kt(c, TH_KT_COARSE);
-    rc = launch_coarse_solve(c, r64, u64, nrhs, s);
+    rc = launch_coarse_solve(c, r64, u64, nrhs, s, !f32);
   }
   if (rc) return rc;
   if (f32) return launch_convert(u64, uc_out, (long long)nrhs * c->nc, false, true, s);

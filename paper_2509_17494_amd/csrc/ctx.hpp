@@ -110,6 +110,7 @@ struct NDLevel {
   int f0 = 0, f1 = 0;     // forward tasks (node, first row)
   int b0 = 0, b1 = 0;     // backward tasks
   int maxI = 0, maxB = 0;
+  long long fbytes = 0, bbytes = 0;  // factor bytes read by the level's forward / backward step
 };
 
 struct NDData {
@@ -319,11 +320,13 @@ int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const doubl
 
 // k_coarse.hip
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);
-int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s);
+// exact: the result is used in FP64 (with false, nested dissection skips its
+// refinement steps: the result is rounded to complex64 afterwards)
+int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact);
 // k_nd.hip: nested-dissection factorisation of the coarse stencil matrix, its
 // solve, and the probe check of whichever coarse factorisation is set up
 int setup_coarse_nd(th_ctx *c, const std::vector<c64> &stencil);
-int launch_coarse_nd(const th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s);
+int launch_coarse_nd(const th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact);
 void free_nd(NDData &nd);
 int coarse_probe_check(th_ctx *c, const std::vector<c64> &stencil, double *err);
 // modelled solve times (s) of both coarse factorisations for the context's grid

@@ -440,6 +440,20 @@ static int choose_lines(int L, int ny, int rc_chunk, int passes) {
   return best;
 }
 
+// Modelled time of one coarse solve by the line elimination (the model above
+// at the K it chooses).
+double coarse_model_lines(const th_ctx *c) {
+  const int dim = c->dim, nx = c->nc1;
+  const int L = dim == 3 ? nx * nx : nx, ny = nx;
+  const int R = c->desc.max_rhs;
+  const int rc_chunk = (R >= 4) ? 4 : (R >= 2 ? 2 : 1);
+  const int passes = (R + rc_chunk - 1) / rc_chunk;
+  const int K = choose_lines(L, ny, rc_chunk, passes);
+  const double nblk = std::ceil((double)ny / K);
+  const double launches = nblk >= 3 ? nblk + 1 : 2 * nblk - 1;
+  return (double)(K + 1) * ny * L * (double)L * 16.0 * passes / 6.3e12 + launches * 7.3e-6;
+}
+
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &st) {
   hipStream_t s = c->stream;
   CoarseData &cd = c->coarse;
@@ -656,8 +670,8 @@ static bool small_slabs_fit(const CoarseData &cd, int RC) {
   return (size_t)max_nb * RC * sizeof(c64) <= 64 * 1024;
 }
 
-int launch_coarse_solve(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
-  if (c->coarse.kind == 1) return launch_coarse_nd(c, rcv, uc, nrhs, s);
+int launch_coarse_solve(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s, bool exact) {
+  if (c->coarse.kind == 1) return launch_coarse_nd(c, rcv, uc, nrhs, s, exact);
   if (!small_slabs_fit(c->coarse, c->coarse.rc_chunk)) {
     if (nrhs >= 8) return sweep_large_t<8>(c, rcv, uc, nrhs, s);
     if (nrhs >= 4) return sweep_large_t<4>(c, rcv, uc, nrhs, s);

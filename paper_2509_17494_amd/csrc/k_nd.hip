@@ -571,6 +571,8 @@ int setup_coarse_nd(th_ctx *c, const std::vector<c64> &stencil) {
         for (int r = 0; r < hn[i].nI; r += kNDRows) bt.push_back(make_int2(i, r));
       L.maxI = std::max(L.maxI, hn[i].nI);
       L.maxB = std::max(L.maxB, hn[i].nB);
+      L.fbytes += (long long)hn[i].nI * (hn[i].nI + hn[i].nB) * (long long)sizeof(c64);
+      L.bbytes += (long long)hn[i].nI * hn[i].nB * (long long)sizeof(c64);
     }
     L.f1 = (int)ft.size();
     L.b1 = (int)bt.size();
@@ -787,7 +789,7 @@ int coarse_probe_check(th_ctx *c, const std::vector<c64> &stencil, double *err) 
                      dim3(256), 0, s, (const c64 *)dst, dim, nx, (const c64 *)nullptr,
                      (const c64 *)xp, bp);
   TH_HIP_CHECK_RET(hipGetLastError());
-  if (int e = launch_coarse_solve(c, bp, xs, 1, s)) return e;
+  if (int e = launch_coarse_solve(c, bp, xs, 1, s, true)) return e;
   std::vector<c64> hs(ncn);
   TH_HIP_CHECK_RET(hipMemcpyAsync(hs.data(), xs, ncn * sizeof(c64), hipMemcpyDeviceToHost, s));
   TH_HIP_CHECK_RET(hipStreamSynchronize(s));
@@ -801,51 +803,97 @@ int coarse_probe_check(th_ctx *c, const std::vector<c64> &stencil, double *err) 
   return 0;
 }
 
-template <int RC, int W>
-static void nd_solve_t(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+// Modelled time of one coarse solve for max_rhs right-hand sides: every level
+// streams its factor bytes once per pass of RC right-hand sides at 6.5 TB/s
+// and takes at least 7 us (its launch and a few dependent memory round trips,
+// measured on the C2 tree); refinement steps (FP64 operators only: the
+// complex64 preconditioner skips them) add a solve and two short launches.
+double coarse_model_nd(const th_ctx *c) {
   const NDData &nd = c->coarse.nd;
-  const long long ncn = c->nc;
-  const dim3 blk(64 * W);
-  const unsigned gy = (unsigned)ceil_div(nrhs, RC);
+  const int R = c->desc.max_rhs;
+  const int RC = R >= 8 ? 8 : (R >= 4 ? 4 : (R >= 2 ? 2 : 1));
+  const double passes = (double)ceil_div(R, RC);
+  double t = 0.0;
+  for (const NDLevel &L : nd.lv) {
+    t += std::max(7e-6, (double)L.fbytes * passes / 6.5e12);
+    if (L.bbytes > 0) t += std::max(7e-6, (double)L.bbytes * passes / 6.5e12);
+  }
+  const int refine = c->desc.gemm == TH_GEMM_F64 ? nd.refine : 0;
+  return t * (1 + refine) + refine * 17e-6;
+}
+
+// Wavefronts per workgroup of a level: 4 where the level has enough tasks to
+// fill the chip, more (16 for one or two right-hand sides per pass, 8 beyond)
+// where few long nodes near the root would leave each wavefront a long
+// sequential column loop.
+constexpr int kNDFewTasks = 256;
+
+template <int RC, int W>
+static void nd_fwd_level(const th_ctx *c, const NDLevel &L, const c64 *rcv, c64 *uc, int nrhs,
+                         hipStream_t s) {
+  const NDData &nd = c->coarse.nd;
+  hipLaunchKernelGGL((k_nd_fwd<RC, W>), dim3(L.f1 - L.f0, (unsigned)ceil_div(nrhs, RC)), dim3(64 * W),
+                     0, s, (const NDNode *)nd.d_nodes, (const int2 *)nd.d_ftask + L.f0,
+                     (const int *)nd.d_idx, (const int *)nd.d_src, (const c64 *)nd.M, rcv, uc,
+                     nd.uvec, c->nc, nd.ulen, nrhs);
+}
+
+template <int RC, int W>
+static void nd_bwd_level(const th_ctx *c, const NDLevel &L, c64 *uc, int nrhs, hipStream_t s) {
+  const NDData &nd = c->coarse.nd;
+  hipLaunchKernelGGL((k_nd_bwd<RC, W>), dim3(L.b1 - L.b0, (unsigned)ceil_div(nrhs, RC)), dim3(64 * W),
+                     0, s, (const NDNode *)nd.d_nodes, (const int2 *)nd.d_btask + L.b0,
+                     (const int *)nd.d_idx, (const c64 *)nd.Wm, uc, c->nc, nrhs);
+}
+
+template <int RC>
+static void nd_solve_t(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+  constexpr int WB = RC <= 2 ? 16 : 8;
+  const NDData &nd = c->coarse.nd;
+  const int gy = ceil_div(nrhs, RC);
   for (int h = 0; h < nd.levels; ++h) {
     const NDLevel &L = nd.lv[h];
-    if (L.f1 > L.f0)
-      hipLaunchKernelGGL((k_nd_fwd<RC, W>), dim3(L.f1 - L.f0, gy), blk, 0, s,
-                         (const NDNode *)nd.d_nodes, (const int2 *)nd.d_ftask + L.f0,
-                         (const int *)nd.d_idx, (const int *)nd.d_src, (const c64 *)nd.M, rcv, uc,
-                         nd.uvec, ncn, nd.ulen, nrhs);
+    if (L.f1 <= L.f0) continue;
+    if ((long long)(L.f1 - L.f0) * gy < kNDFewTasks)
+      nd_fwd_level<RC, WB>(c, L, rcv, uc, nrhs, s);
+    else
+      nd_fwd_level<RC, 4>(c, L, rcv, uc, nrhs, s);
   }
   for (int h = nd.levels - 1; h >= 0; --h) {
     const NDLevel &L = nd.lv[h];
-    if (L.b1 > L.b0)
-      hipLaunchKernelGGL((k_nd_bwd<RC, W>), dim3(L.b1 - L.b0, gy), blk, 0, s,
-                         (const NDNode *)nd.d_nodes, (const int2 *)nd.d_btask + L.b0,
-                         (const int *)nd.d_idx, (const c64 *)nd.Wm, uc, ncn, nrhs);
+    if (L.b1 <= L.b0) continue;
+    if ((long long)(L.b1 - L.b0) * gy < kNDFewTasks)
+      nd_bwd_level<RC, WB>(c, L, uc, nrhs, s);
+    else
+      nd_bwd_level<RC, 4>(c, L, uc, nrhs, s);
   }
 }
 
 static void nd_solve(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
   if (nrhs >= 8)
-    nd_solve_t<8, 4>(c, rcv, uc, nrhs, s);
+    nd_solve_t<8>(c, rcv, uc, nrhs, s);
   else if (nrhs >= 4)
-    nd_solve_t<4, 4>(c, rcv, uc, nrhs, s);
+    nd_solve_t<4>(c, rcv, uc, nrhs, s);
   else if (nrhs >= 2)
-    nd_solve_t<2, 4>(c, rcv, uc, nrhs, s);
+    nd_solve_t<2>(c, rcv, uc, nrhs, s);
   else
-    nd_solve_t<1, 4>(c, rcv, uc, nrhs, s);
+    nd_solve_t<1>(c, rcv, uc, nrhs, s);
 }
 
 // uc = A_c^{-1} rc: one solve with the factors, then `refine` steps of
 // iterative refinement against the stencil matrix (FP64 residuals).  The
 // separator blocks of interior boxes are real indefinite Helmholtz blocks that
 // can be close to singular, which costs digits in the factors; refinement
-// brings the solve back to the rounding level of the residual.
-int launch_coarse_nd(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+// brings the solve back to the rounding level of the residual.  Without
+// `exact` (a result rounded to complex64 afterwards) no refinement is done:
+// the factors alone are far more accurate than that rounding.
+int launch_coarse_nd(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s,
+                     bool exact) {
   const NDData &nd = c->coarse.nd;
   nd_solve(c, rcv, uc, nrhs, s);
   const long long ncn = c->nc;
   const unsigned gx = (unsigned)std::min<long long>(ceil_div_ll(ncn, 256), 4096);
-  for (int it = 0; it < nd.refine; ++it) {
+  for (int it = 0; exact && it < nd.refine; ++it) {
     hipLaunchKernelGGL(k_cstencil_apply, dim3(gx, nrhs), dim3(256), 0, s, (const c64 *)nd.st,
                        c->dim, c->nc1, rcv, (const c64 *)uc, nd.t);
     nd_solve(c, nd.t, nd.d, nrhs, s);

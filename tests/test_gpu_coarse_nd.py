@@ -99,23 +99,37 @@ def test_coarse_solvers_3d(N, p, l_dd, nrhs, bc, solver):
     s.close()
 
 
-def test_automatic_choice_and_solve_iterations():
-    """The automatic choice takes nested dissection; a full C1 solve with it
-    and with the line elimination takes the same iterations and agrees to
-    1e-10."""
+def test_nd_and_lines_solve_c1_alike():
+    """A full C1 solve with nested dissection and with the line elimination
+    takes the same iterations and agrees to 1e-10."""
     from paper_2509_17494_amd import TwoGridSolver
     cfg = syn.config("C1")
     f = syn.gaussian_load(cfg["n"], cfg["p"], cfg["centres"], cfg["sigma"])
     out = {}
-    for solver in (None, "lines"):
+    for solver in ("nd", "lines"):
         s = TwoGridSolver(cfg["k"], order=cfg["p"], l_dd=cfg["l_dd"], alpha_s=cfg["alpha_s"],
                           coarse_solver=solver)
-        out[solver] = (s.info()["coarse_solver"],) + tuple(s.solve(to_dev(f)))
-        torch.cuda.synchronize()
+        u, st = s.solve(to_dev(f))
+        out[solver] = (s.info()["coarse_solver"], to_np(u), st)
         s.close()
-    assert out[None][0] == 2 and out["lines"][0] == 1
-    u_nd, st_nd = out[None][1], out[None][2]
-    u_ln, st_ln = out["lines"][1], out["lines"][2]
+    assert out["nd"][0] == 2 and out["lines"][0] == 1
+    st_nd, st_ln = out["nd"][2], out["lines"][2]
     assert st_nd.status == 0 and st_ln.status == 0
     assert st_nd.iters == st_ln.iters
-    assert rel(to_np(u_nd), to_np(u_ln)) < 1e-10
+    assert rel(out["nd"][1], out["lines"][1]) < 1e-10
+
+
+def test_automatic_choice_follows_the_time_model():
+    """The automatic choice: the line elimination for C1's small grid and one
+    right-hand side (a few launches beat the dissection tree's levels), nested
+    dissection for C3's 64 right-hand sides (complex64 preconditioner, no
+    refinement) and for C2's large grid."""
+    from paper_2509_17494_amd import TwoGridSolver
+    got = {}
+    for name, kw in (("C1", {}), ("C3", dict(max_rhs=64, gemm="bf16")), ("C2", {})):
+        cfg = syn.config(name)
+        s = TwoGridSolver(cfg["k"], order=cfg["p"], l_dd=cfg["l_dd"], alpha_s=cfg["alpha_s"], **kw)
+        got[name] = s.info()["coarse_solver"]
+        s.close()
+    print(f"automatic coarse solver: {got}", flush=True)
+    assert got == {"C1": 1, "C3": 2, "C2": 2}
