@@ -253,6 +253,22 @@ th_status th_prolong(th_ctx *ctx, const void *uc, void *u, double omega_c,
  * TH_C64 vectors are promoted to FP64 for the sweeps.  Stream-ordered. */
 th_status th_coarse_solve(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt);
 
+/* th_coarse_solve for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve, with every work vector (the nested-dissection update vectors, the
+ * refinement residual and correction, the FP64 staging of TH_C64 vectors)
+ * in a fixed 64 MiB device array per GPU that the library holds until the
+ * process ends, instead of the context's buffers.  It allocates and frees
+ * nothing.  Calls on one GPU share that array: calls that overlap in time on
+ * one GPU (other streams, other contexts) race; nothing in it needs to start
+ * at zero.  Results equal th_coarse_solve's.  Errors: those of
+ * th_coarse_solve; TH_EINVAL when nrhs right-hand sides need more than 64 MiB
+ * (nested dissection: nrhs x (update-vector length + 2 n_coarse) x 16 bytes,
+ * plus 2 nrhs n_coarse x 16 bytes for TH_C64); TH_EUNSUPPORTED for the line
+ * elimination of grids whose slabs it stages in context buffers (3-D).
+ * Stream-ordered. */
+th_status th_coarse_solve_noalloc(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt);
+
 /* u <- TwoGridStep(u, f) (Alg. 1).  Stream-ordered. */
 th_status th_twogrid(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt);
 

@@ -280,6 +280,17 @@ class TwoGridSolver:
         self._check(self._ordered(self._lib.th_coarse_solve, self._h, self._p(rc), self._p(uc), nrhs, _dt(rc)))
         return uc
 
+    def coarse_solve_noalloc(self, rc, uc):
+        """uc = A_c^{-1} rc with the library's fixed per-GPU scratch array
+        instead of the context's work buffers (allocates nothing)."""
+        nrhs = self._vec(rc, self.n_coarse, "rc")
+        self._vec(uc, self.n_coarse, "uc", rc.dtype)
+        if uc.data_ptr() == rc.data_ptr():
+            raise ValueError("rc and uc must not alias")
+        self._check(self._ordered(self._lib.th_coarse_solve_noalloc, self._h, self._p(rc),
+                                  self._p(uc), nrhs, _dt(rc)))
+        return uc
+
     def twogrid(self, u, f):
         """u <- TwoGridStep(u, f) in place."""
         nrhs = self._vec(u, self.n_fine, "u")

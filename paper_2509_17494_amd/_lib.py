@@ -91,6 +91,7 @@ def load():
         "th_restrict": ([vp, vp, vp, i, i], i),
         "th_prolong": ([vp, vp, vp, d, i, i], i),
         "th_coarse_solve": ([vp, vp, vp, i, i], i),
+        "th_coarse_solve_noalloc": ([vp, vp, vp, i, i], i),
         "th_twogrid": ([vp, vp, vp, i, i], i),
         "th_solve": ([vp, vp, vp, i, C.POINTER(SolveOpts), C.POINTER(SolveStats)], i),
         "th_timing_enable": ([vp, i], i),

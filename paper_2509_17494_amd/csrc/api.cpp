@@ -5,6 +5,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -160,6 +161,32 @@ static void free_solver(th_ctx *c) {
   c->kv_vec_bytes = 0;
 }
 
+// Device scratch of th_coarse_solve_noalloc: one fixed array per GPU, held
+// until the process ends.  Host code never passes the array's name to a kernel
+// (on the host it is a stand-in, not a device address); th_create looks up
+// each device's address once, with that device current, and the entry point
+// uses only that address.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) c64 scratch[kNoAllocBytes / sizeof(c64)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device `dev`, looked up once
+static hipError_t scratch_address(int dev, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 extern "C" {
 
 th_status th_create(th_ctx **out, int hip_device, void *hip_stream) {
@@ -170,6 +197,7 @@ th_status th_create(th_ctx **out, int hip_device, void *hip_stream) {
   c->device = hip_device;
   c->stream = (hipStream_t)hip_stream;
   hipError_t e = hipSetDevice(hip_device);
+  if (e == hipSuccess) e = scratch_address(hip_device, &c->noalloc_scratch);
   if (e != hipSuccess) {
     delete c;
     return TH_EHIP;
@@ -957,6 +985,48 @@ th_status th_coarse_solve(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dt
   th_status st = check_vec_call(ctx, rc, uc, nrhs, dt, true);
   if (st) return st;
   return finish(ctx, coarse_solve_impl(ctx, rc, uc, nrhs, is_f32(dt)));
+}
+
+th_status th_coarse_solve_noalloc(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt) {
+  th_status st = check_vec_call(ctx, rc, uc, nrhs, dt, true);
+  if (st) return st;
+  th_ctx *c = ctx;
+  const bool f32 = is_f32(dt);
+  const long long ncn = c->nc;
+  // scratch: [FP64 staging of rc and uc (complex64 only)][update vectors][t][d]
+  long long need = f32 ? 2LL * nrhs * ncn : 0;
+  const bool nd = c->coarse.kind == 1;
+  if (nd) need += (long long)nrhs * (c->coarse.nd.ulen + 2 * ncn);
+  else if (coarse_lines_need_staging(c))
+    return fail(ctx, TH_EUNSUPPORTED, "th_coarse_solve_noalloc: the line elimination of this "
+                "grid stages slabs in context buffers; set up the nested-dissection solver");
+  if (need * (long long)sizeof(c64) > (long long)kNoAllocBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg, "th_coarse_solve_noalloc: needs %lld bytes of scratch, the "
+                  "limit is %zu (fewer right-hand sides per call)",
+                  need * (long long)sizeof(c64), kNoAllocBytes);
+    return fail(ctx, TH_EINVAL, msg);
+  }
+  c64 *w = (c64 *)c->noalloc_scratch;
+  hipStream_t s = c->stream;
+  const c64 *r64 = (const c64 *)rc;
+  c64 *u64 = (c64 *)uc;
+  int rcode = 0;
+  if (f32) {
+    rcode = launch_convert(rc, w, (long long)nrhs * ncn, true, false, s);
+    r64 = w;
+    u64 = w + (long long)nrhs * ncn;
+    w += 2LL * nrhs * ncn;
+  }
+  CoarseScratch ws;
+  if (nd) {
+    ws.uvec = w;
+    ws.t = w + (long long)nrhs * c->coarse.nd.ulen;
+    ws.d = ws.t + (long long)nrhs * ncn;
+  }
+  if (!rcode) rcode = launch_coarse_solve(c, r64, u64, nrhs, s, !f32, &ws);
+  if (!rcode && f32) rcode = launch_convert(u64, uc, (long long)nrhs * ncn, false, true, s);
+  return finish(ctx, rcode);
 }
 
 th_status th_twogrid(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt) {

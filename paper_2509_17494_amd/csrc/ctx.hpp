@@ -212,6 +212,7 @@ struct th_ctx {
   size_t ws_bytes = 0;
 
   th::CoarseData coarse;
+  void *noalloc_scratch = nullptr;  // this device's address of the no-allocation scratch array
 
   // solver workspaces (allocated lazily by th_solve)
   void *s_buf = nullptr;
@@ -320,13 +321,23 @@ int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const doubl
 
 // k_coarse.hip
 int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);
+// Work vectors of a nested-dissection solve for nrhs right-hand sides: update
+// vectors (nrhs x ulen) and the refinement residual and correction (nrhs x
+// n_coarse each); null members mean the context's own.
+struct CoarseScratch {
+  c64 *uvec = nullptr, *t = nullptr, *d = nullptr;
+};
 // exact: the result is used in FP64 (with false, nested dissection skips its
 // refinement steps: the result is rounded to complex64 afterwards)
-int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact);
+int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact,
+                        const CoarseScratch *ws = nullptr);
+// true when the line elimination's solve needs its large-slab staging buffers
+bool coarse_lines_need_staging(const th_ctx *c);
 // k_nd.hip: nested-dissection factorisation of the coarse stencil matrix, its
 // solve, and the probe check of whichever coarse factorisation is set up
 int setup_coarse_nd(th_ctx *c, const std::vector<c64> &stencil);
-int launch_coarse_nd(const th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact);
+int launch_coarse_nd(const th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact,
+                     const CoarseScratch *ws);
 void free_nd(NDData &nd);
 int coarse_probe_check(th_ctx *c, const std::vector<c64> &stencil, double *err);
 // modelled solve times (s) of both coarse factorisations for the context's grid

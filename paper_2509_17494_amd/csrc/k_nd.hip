@@ -829,13 +829,13 @@ double coarse_model_nd(const th_ctx *c) {
 constexpr int kNDFewTasks = 256;
 
 template <int RC, int W>
-static void nd_fwd_level(const th_ctx *c, const NDLevel &L, const c64 *rcv, c64 *uc, int nrhs,
-                         hipStream_t s) {
+static void nd_fwd_level(const th_ctx *c, const NDLevel &L, const c64 *rcv, c64 *uc, c64 *uvec,
+                         int nrhs, hipStream_t s) {
   const NDData &nd = c->coarse.nd;
   hipLaunchKernelGGL((k_nd_fwd<RC, W>), dim3(L.f1 - L.f0, (unsigned)ceil_div(nrhs, RC)), dim3(64 * W),
                      0, s, (const NDNode *)nd.d_nodes, (const int2 *)nd.d_ftask + L.f0,
                      (const int *)nd.d_idx, (const int *)nd.d_src, (const c64 *)nd.M, rcv, uc,
-                     nd.uvec, c->nc, nd.ulen, nrhs);
+                     uvec, c->nc, nd.ulen, nrhs);
 }
 
 template <int RC, int W>
@@ -847,7 +847,8 @@ static void nd_bwd_level(const th_ctx *c, const NDLevel &L, c64 *uc, int nrhs, h
 }
 
 template <int RC>
-static void nd_solve_t(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+static void nd_solve_t(const th_ctx *c, const c64 *rcv, c64 *uc, c64 *uvec, int nrhs,
+                       hipStream_t s) {
   constexpr int WB = RC <= 2 ? 16 : 8;
   const NDData &nd = c->coarse.nd;
   const int gy = ceil_div(nrhs, RC);
@@ -855,9 +856,9 @@ static void nd_solve_t(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipSt
     const NDLevel &L = nd.lv[h];
     if (L.f1 <= L.f0) continue;
     if ((long long)(L.f1 - L.f0) * gy < kNDFewTasks)
-      nd_fwd_level<RC, WB>(c, L, rcv, uc, nrhs, s);
+      nd_fwd_level<RC, WB>(c, L, rcv, uc, uvec, nrhs, s);
     else
-      nd_fwd_level<RC, 4>(c, L, rcv, uc, nrhs, s);
+      nd_fwd_level<RC, 4>(c, L, rcv, uc, uvec, nrhs, s);
   }
   for (int h = nd.levels - 1; h >= 0; --h) {
     const NDLevel &L = nd.lv[h];
@@ -869,15 +870,15 @@ static void nd_solve_t(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipSt
   }
 }
 
-static void nd_solve(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s) {
+static void nd_solve(const th_ctx *c, const c64 *rcv, c64 *uc, c64 *uvec, int nrhs, hipStream_t s) {
   if (nrhs >= 8)
-    nd_solve_t<8>(c, rcv, uc, nrhs, s);
+    nd_solve_t<8>(c, rcv, uc, uvec, nrhs, s);
   else if (nrhs >= 4)
-    nd_solve_t<4>(c, rcv, uc, nrhs, s);
+    nd_solve_t<4>(c, rcv, uc, uvec, nrhs, s);
   else if (nrhs >= 2)
-    nd_solve_t<2>(c, rcv, uc, nrhs, s);
+    nd_solve_t<2>(c, rcv, uc, uvec, nrhs, s);
   else
-    nd_solve_t<1>(c, rcv, uc, nrhs, s);
+    nd_solve_t<1>(c, rcv, uc, uvec, nrhs, s);
 }
 
 // uc = A_c^{-1} rc: one solve with the factors, then `refine` steps of
@@ -888,16 +889,19 @@ static void nd_solve(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStre
 // `exact` (a result rounded to complex64 afterwards) no refinement is done:
 // the factors alone are far more accurate than that rounding.
 int launch_coarse_nd(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s,
-                     bool exact) {
+                     bool exact, const CoarseScratch *ws) {
   const NDData &nd = c->coarse.nd;
-  nd_solve(c, rcv, uc, nrhs, s);
+  c64 *uvec = ws && ws->uvec ? ws->uvec : nd.uvec;
+  c64 *t = ws && ws->t ? ws->t : nd.t;
+  c64 *d = ws && ws->d ? ws->d : nd.d;
+  nd_solve(c, rcv, uc, uvec, nrhs, s);
   const long long ncn = c->nc;
   const unsigned gx = (unsigned)std::min<long long>(ceil_div_ll(ncn, 256), 4096);
   for (int it = 0; exact && it < nd.refine; ++it) {
     hipLaunchKernelGGL(k_cstencil_apply, dim3(gx, nrhs), dim3(256), 0, s, (const c64 *)nd.st,
-                       c->dim, c->nc1, rcv, (const c64 *)uc, nd.t);
-    nd_solve(c, nd.t, nd.d, nrhs, s);
-    if (int e = launch_add(uc, nd.d, (long long)nrhs * ncn, false, s)) return e;
+                       c->dim, c->nc1, rcv, (const c64 *)uc, t);
+    nd_solve(c, t, d, uvec, nrhs, s);
+    if (int e = launch_add(uc, d, (long long)nrhs * ncn, false, s)) return e;
   }
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
