@@ -500,8 +500,9 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
       poff += (long long)s.nrb * (s.nrb + 1) / 2 * kSymTile;
       xoff += s.nOm;
       c->max_pairs = std::max(c->max_pairs, (s.nrb + 1) / 2);
-    } else if (c->layout == 3) {
-      xoff += s.nOm;
+    } else if (c->layout == 3 || (c->layout == 0 && d->gemm == TH_GEMM_F64 &&
+                                    dd_mfma64_rhs_pad(d->max_rhs) > 0)) {
+      xoff += s.nOm;  // gathered patches (slab sweeps, FP64 matrix-core apply)
     }
   }
   c->p_rows = poff;
@@ -524,7 +525,8 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   const size_t R = (size_t)d->max_rhs;
   bool ok = alloc((void **)&c->d_eidx, eidx.size() * sizeof(int)) &&
             alloc(&c->w_p, R * c->p_rows * sizeof(c64)) &&
-            alloc(&c->w_x, R * c->x_rows * sizeof(c64)) &&
+            alloc(&c->w_x, std::max<size_t>(R, dd_mfma64_rhs_pad(d->max_rhs)) * c->x_rows *
+                               sizeof(c64)) &&
             alloc((void **)&c->d_kap, ncell * sizeof(c64)) &&
             alloc((void **)&c->d_kaps, ncell * sizeof(c64)) &&
             alloc((void **)&c->d_k, ncell * sizeof(double)) &&

@@ -285,6 +285,9 @@ int launch_prolong(int dim, int N, int P, int dir, const Ref1D &ref, const void 
 
 // k_smoother.hip
 int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);
+// right-hand sides of the gathered patches of the FP64 matrix-core apply (dense
+// layout), 0 when max_rhs is below its threshold
+int dd_mfma64_rhs_pad(int max_rhs);
 // k_slab.hip: the slab-factor layout (apply, and its setup from the assembled
 // subdomain matrices of one batch)
 int launch_dd_slab(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);

@@ -14,6 +14,9 @@
 // of a wavefront is 1 KiB (FP64) of consecutive entries, and one wavefront
 // streams one contiguous n_Omega x 64 region.  The gathered X chunk sits in LDS
 // and is read as a broadcast.  No atomics: results are bitwise reproducible.
+#include <algorithm>
+#include <type_traits>
+
 #include "ctx.hpp"
 
 namespace th {
@@ -265,8 +268,122 @@ __global__ __launch_bounds__(256) void k_dd_accumulate(const Sub *__restrict__ s
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 operators with many right-hand sides: Y_i = B_i X_i as a complex GEMM
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64, four real products per
+// complex one).  The patches X_i are first gathered into [subdomain][k][Rp]
+// (right-hand sides fastest, Rp a multiple of 16), so both MFMA operands are
+// read straight from memory: the B_i fragment (16 rows x 4 columns) as four
+// 256-byte row segments of the dense 64-row-block layout, the X fragment (4
+// columns x 16 right-hand sides) as four 256-byte segments of the gathered
+// patch.  A workgroup owns one 16-row block of one subdomain, its wavefronts
+// one block of 16 right-hand sides each (the B_i fragment is shared through
+// the cache); workgroups of one subdomain sit on one XCD so that its patch
+// stays in one L2.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kXgTileK = 64;  // patch rows per workgroup of the gather
+
+__global__ __launch_bounds__(256) void k_dd_gatherx(const Sub *__restrict__ subs,
+                                                    const c64 *__restrict__ r,
+                                                    c64 *__restrict__ Xg, int P, int n1,
+                                                    long long nf, int nrhs, int Rp) {
+  __shared__ c64 T[16][kXgTileK + 1];
+  const Sub s = subs[blockIdx.y];
+  const int k0 = blockIdx.x * kXgTileK;
+  if (k0 >= s.nOm) return;  // uniform
+  c64 *xo = Xg + s.xoff * Rp;
+  for (int q0 = 0; q0 < Rp; q0 += 16) {
+    // read 16 right-hand sides x 64 patch nodes, coalesced along the nodes
+    for (int t = threadIdx.x; t < 16 * kXgTileK; t += 256) {
+      const int kk = t % kXgTileK, qq = t / kXgTileK;
+      const int k = k0 + kk, q = q0 + qq;
+      T[qq][kk] = (k < s.nOm && q < nrhs) ? r[(long long)q * nf + om_node(s, k, P, n1)] : c64{0, 0};
+    }
+    __syncthreads();
+    // write them right-hand sides fastest
+    for (int t = threadIdx.x; t < 16 * kXgTileK; t += 256) {
+      const int qq = t % 16, kk = t / 16;
+      if (k0 + kk < s.nOm) xo[(long long)(k0 + kk) * Rp + q0 + qq] = T[qq][kk];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dd_mfma64(const Sub *__restrict__ subs, int nsub,
+                                                   int nrb, const c64 *__restrict__ B,
+                                                   const c64 *__restrict__ Xg,
+                                                   c64 *__restrict__ Y, long long yrows,
+                                                   int nrhs, int Rp) {
+  // XCD-aware mapping: workgroup b runs on XCD b % 8; subdomain si on XCD si % 8
+  const int b = blockIdx.x;
+  const int si = (b & 7) + 8 * ((b >> 3) / nrb), rb = (b >> 3) % nrb;
+  if (si >= nsub) return;
+  const Sub s = subs[si];
+  if (rb * 16 >= s.nU) return;  // uniform
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kl = lane >> 4, cl = lane & 15;
+  const c64 *Ab = B + s.boff + (long long)(rb >> 2) * s.nOm * 64 + (rb & 3) * 16 + cl;
+  const c64 *Xi = Xg + s.xoff * Rp;
+  for (int cb = wave; cb * 16 < nrhs; cb += 4) {
+    f64x4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    const c64 *Xb = Xi + cb * 16 + cl;
+    // four k-steps per pass: their eight operand loads are issued before the
+    // sixteen MFMAs that use them
+    for (int k0 = 0; k0 < s.nOm; k0 += 16) {
+      c64 a[4], x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + kl;
+        const bool ok = k < s.nOm;
+        a[u] = ok ? Ab[(long long)k * 64] : c64{0, 0};
+        x[u] = ok ? Xb[(long long)k * Rp] : c64{0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].re, x[u].re, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].im, x[u].im, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].re, x[u].im, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].im, x[u].re, cim, 0, 0, 0);
+      }
+    }
+    // lane: right-hand side cb * 16 + cl; its value i is row rb * 16 + 4 i + kl
+    // (the FP64 16x16 result interleaves rows over the lane quarters)
+    const int q = cb * 16 + cl;
+    if (q < nrhs) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rb * 16 + 4 * i + kl;
+        if (row < s.nU) Y[(long long)q * yrows + s.yoff + row] = c64{cre[i], cim[i]};
+      }
+    }
+  }
+}
+
+// right-hand sides from which the FP64 dense apply runs on the matrix cores
+constexpr int kMfma64MinRhs = 16;
+
+int dd_mfma64_rhs_pad(int max_rhs) { return max_rhs >= kMfma64MinRhs ? ceil_div(max_rhs, 16) * 16 : 0; }
+
+static int dd_apply_mfma64(const th_ctx *c, const void *r, void *y, int nrhs, hipStream_t s) {
+  const int nsub = (int)c->subs.size();
+  const int Rp = dd_mfma64_rhs_pad(c->desc.max_rhs);
+  int nrb = 0;
+  for (const Sub &sb : c->subs) nrb = std::max(nrb, ceil_div(sb.nU, 16));
+  hipLaunchKernelGGL(k_dd_gatherx, dim3(ceil_div(c->max_nom, kXgTileK), nsub), dim3(256), 0, s,
+                     c->d_subs, (const c64 *)r, (c64 *)c->w_x, c->P, c->n1, c->nf, nrhs, Rp);
+  const int groups = ceil_div(nsub, 8);
+  hipLaunchKernelGGL(k_dd_mfma64, dim3(8 * groups * nrb), dim3(256), 0, s, c->d_subs, nsub, nrb,
+                     (const c64 *)c->d_B, (const c64 *)c->w_x, (c64 *)y, c->y_rows, nrhs, Rp);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
 template <typename TB, typename T>
 static int dd_apply_t(const th_ctx *c, const void *r, void *y, int nrhs, hipStream_t s) {
+  if (std::is_same<TB, double>::value && std::is_same<T, double>::value && c->layout == 0 &&
+      nrhs >= kMfma64MinRhs && dd_mfma64_rhs_pad(c->desc.max_rhs) > 0)
+    return dd_apply_mfma64(c, r, y, nrhs, s);
   dim3 grid(c->max_rowblocks, (unsigned)c->subs.size());
   const Sub *ds = c->d_subs;
   const cx<TB> *B = (const cx<TB> *)c->d_B;
