@@ -148,9 +148,10 @@ typedef struct {
   const double *q;      /* HOST, (pN/2)^d x 3 (2-D) or x 4 (3-D) weights, x fastest;
                            TH_COARSE_WEIGHTS only */
   const th_mlp *mlp;    /* trained surrogate; TH_COARSE_MLP only */
-  double fallback_tau;  /* TH_COARSE_MLP: a cell falls back to the plain fit when the
-                           network's dispersion errors differ from the fine ones by more
-                           than this (relative wavenumber); 0 = every cell falls back */
+  double fallback_tau;  /* TH_COARSE_MLP: a cell falls back to the plain fit when the zero
+                           set of the network's stencil lies farther than this (relative
+                           to eta) from the fine dispersion curve anywhere in the sector of
+                           wave directions (th_mlp_stencils); 0 = every cell falls back */
   th_coarse_solver solver; /* coarse factorisation (0 = automatic) */
 } th_coarse_desc;
 
@@ -379,6 +380,20 @@ th_status th_mlp_train(th_mlp *m, const double *samples, int n, const th_mlp_tra
                        th_mlp_train_stats *stats);
 /* Device inference for n HOST samples: e_out (HOST n x n_out) = predicted e_m. */
 th_status th_mlp_predict(th_mlp *m, const double *samples, int n, int bf16, double *e_out);
+/* Coarse stencils from the network for n HOST samples of one order p, all on
+ * the device: inference (BF16 weights), weights q_out (HOST n x 3 for the
+ * 9-point family, n x 4 for the 27-point family) from the predicted e_m by
+ * the plain-fit formulas, and mismatch_out (HOST n): the largest distance,
+ * relative to eta, between the stencil's zero set and the fine Q_p
+ * dispersion curve over the symmetry sector of wave directions (the curve
+ * traced through the separation mu(theta_x) + mu(theta_y) [+ mu(theta_z)] =
+ * (kh)^2 of the tensor-product symbol at 16 points in 2-D, 21 in 3-D; one
+ * Newton step of the coarse symbol along each point's ray).  Infinite where
+ * the curve leaves the acoustic branch.  TH_COARSE_MLP sends a cell back to
+ * the plain fit when its mismatch exceeds fallback_tau.  Errors: TH_EINVAL
+ * (samples of several orders), TH_ESTATE (no weights). */
+th_status th_mlp_stencils(th_mlp *m, const double *samples, int n, double *q_out,
+                          double *mismatch_out);
 
 #ifdef __cplusplus
 }

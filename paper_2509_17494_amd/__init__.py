@@ -456,3 +456,14 @@ class CoarseStencilMLP:
         self._check(self._lib.th_mlp_predict(self._h, x.ctypes.data, x.shape[0],
                                              1 if bf16 else 0, e.ctypes.data))
         return e
+
+    def stencils(self, samples):
+        """(q, mismatch): per-sample coarse weights from the network and the
+        distance (relative to eta) of their zero set from the fine dispersion
+        curve over the sector of wave directions, computed on the device."""
+        x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64))
+        q = np.zeros((x.shape[0], 4 if self.n_out == 3 else 3))
+        mis = np.zeros(x.shape[0])
+        self._check(self._lib.th_mlp_stencils(self._h, x.ctypes.data, x.shape[0], q.ctypes.data,
+                                              mis.ctypes.data))
+        return q, mis

@@ -134,6 +134,7 @@ def load_mlp(lib):
         "th_mlp_loss_grad": ([vp, vp, vp, i, i, C.POINTER(d), vp], i),
         "th_mlp_train": ([vp, vp, i, C.POINTER(MlpTrainOpts), C.POINTER(MlpTrainStats)], i),
         "th_mlp_predict": ([vp, vp, i, i, vp], i),
+        "th_mlp_stencils": ([vp, vp, i, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

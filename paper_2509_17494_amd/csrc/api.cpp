@@ -445,10 +445,11 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     const int rows = 10 * sym <= 8 * dense ? 1 : 0;
     const double t_rows = rows == 1 ? es * sym / 5.5e12 : es * dense / 6.5e12;
     const double t_slab = es * slab / 4.0e12 + (2 * (nsl / 2) + 3) * 8e-6;
-    // the sweeps keep a slab's right-hand sides and up to 512 partial sums in 48 KiB of LDS
+    // the sweeps keep a slab's right-hand side (then, in the same space, up to
+    // 512 partial sums) in 48 KiB of LDS
     int max_lsz = 0;
     for (const Sub &s : c->subs) max_lsz = std::max(max_lsz, s.lsz);
-    const bool slab_fits = ((long long)(P + 1) * max_lsz + 512) * 16 <= 48 * 1024;
+    const bool slab_fits = std::max<long long>((long long)(P + 1) * max_lsz, 512) * 16 <= 48 * 1024;
     if (d->gemm == TH_GEMM_BF16)
       c->layout = 2;
     else if (d->layout == TH_LAYOUT_DENSE)

@@ -475,6 +475,7 @@ template <typename T, int RC, int NW>
 __device__ __forceinline__ bool slab_sum_waves(cx<T> (&acc)[RC], cx<T> *__restrict__ red) {
   if (NW == 1) return true;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();  // red overlays the staged right-hand side: every wavefront is done with it
 #pragma unroll
   for (int q = 0; q < RC; ++q) red[(wave * 64 + lane) * RC + q] = acc[q];
   __syncthreads();
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_slab_fwd(const Sub *__restri
   constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
   extern __shared__ __align__(16) char slab_smem[];
   cx<T> *x = (cx<T> *)slab_smem;
-  cx<T> *red = x + (long long)ldx * RC;
+  cx<T> *red = x;  // the partial sums reuse the staged right-hand side's LDS
   const Sub s = subs[blockIdx.x];
   const int M = slab_mid(s), U = s.nsl - 1 - M;
   int t, lo, up, yb = blockIdx.y;
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_slab_bwd(const Sub *__restri
   constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
   extern __shared__ __align__(16) char slab_smem[];
   cx<T> *w = (cx<T> *)slab_smem;
-  cx<T> *red = w + (long long)ldx * RC;
+  cx<T> *red = w;  // the partial sums reuse the staged right-hand side's LDS
   const Sub s = subs[blockIdx.x];
   const int M = slab_mid(s), U = s.nsl - 1 - M;
   int yb = blockIdx.y;
@@ -722,11 +723,17 @@ __global__ __launch_bounds__(256) void k_slab_extract(const Sub *__restrict__ su
   Y[q * yrows + s.yoff + j] = cx<T>{v.re * invL, v.im * invL};
 }
 
+// LDS entries per right-hand side of the sweeps: the staged slab right-hand
+// side, whose space the wavefronts' partial sums take over afterwards
+static size_t slab_lds_rows(const th_ctx *c) {
+  return std::max<size_t>((size_t)c->max_slab_rows, 64 * (size_t)std::max(kFwdWaves, kBwdWaves));
+}
+
 template <typename TB, typename T, int RC, int P, int DIM>
 static int slab_sweeps_pd(const th_ctx *c, int nrhs, hipStream_t s) {
   const unsigned nsub = (unsigned)c->subs.size();
   const int ldx = c->max_slab_rows;
-  const size_t shm = ((size_t)ldx + 64 * std::max(kFwdWaves, kBwdWaves)) * RC * sizeof(cx<T>);
+  const size_t shm = slab_lds_rows(c) * RC * sizeof(cx<T>);
   const int nyb = ceil_div(ldx, 64);
   const unsigned nz = (unsigned)ceil_div(nrhs, RC);
   const int S = c->max_nsl / 2;  // chain steps: the longest upper chain
@@ -767,8 +774,7 @@ static int slab_apply_t(const th_ctx *c, const void *r, void *y, int nrhs, hipSt
   hipLaunchKernelGGL((k_slab_gather<T>), dim3(ceil_div(c->max_nom, 256), nsub, nrhs), dim3(256), 0,
                      s, c->d_subs, (const cx<T> *)r, (cx<T> *)c->w_x, c->P, c->n1, c->nf,
                      c->x_rows);
-  const size_t row_bytes =
-      ((size_t)c->max_slab_rows + 64 * std::max(kFwdWaves, kBwdWaves)) * sizeof(cx<T>);
+  const size_t row_bytes = slab_lds_rows(c) * sizeof(cx<T>);
   int rc;
   if (nrhs >= 4 && 4 * row_bytes <= 48 * 1024)
     rc = slab_sweeps_t<TB, T, 4>(c, nrhs, s);

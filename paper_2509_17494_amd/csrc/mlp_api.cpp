@@ -13,6 +13,9 @@
 
 namespace th {
 void plain_fit_batch(const double *x, int n, double *e_out, double *q_out);
+int stencil_check_launch(int dim, int p, const double *d_samples, const float *d_y, int n,
+                         const double out_mean[3], const double out_std[3], double floor_,
+                         double *d_q, double *d_mis, hipStream_t s);
 void fit_from_errors(double eta, const double e[2], double qw[3]);
 double effective_eta(double eta_c, double shift);
 int mlp_num_params(int n_out);
@@ -361,11 +364,47 @@ int mlp_predict_impl(const th_mlp *m, const double *samples, int n, bool bf16, d
   return 0;
 }
 
+// Device: network inference, the stencil weights from the predicted errors
+// and each stencil's dispersion mismatch (k_stencil.hip); all cells of one
+// call share the order p.  q_out: n x 3 (2-D) or n x 4 (3-D), mis: n.
+int mlp_stencils_impl(const th_mlp *m, int dim, const double *samples, int n, double *q_out,
+                      double *mis) {
+  const int no = m->n_out, nq = dim == 3 ? 4 : 3;
+  const int p = (int)std::lround(samples[1]);
+  for (int i = 0; i < n; ++i)
+    if ((int)std::lround(samples[3 * i + 1]) != p) {
+      set_error("cells of one problem must share the order");
+      return TH_EINVAL;
+    }
+  std::vector<float> xs((size_t)n * 3);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c)
+      xs[3 * i + c] = (float)((samples[3 * i + c] - m->in_mean[c]) / m->in_std[c]);
+  DevBuf b;
+  float *dx = b.alloc<float>((size_t)n * 3), *dy = b.alloc<float>((size_t)n * no);
+  double *ds = b.alloc<double>((size_t)n * 3), *dq = b.alloc<double>((size_t)n * nq);
+  double *dm = b.alloc<double>(n);
+  if (!dx || !dy || !ds || !dq || !dm) {
+    set_error("device allocation failed");
+    return TH_ENOMEM;
+  }
+  hipStream_t s = m->stream;
+  TH_HIP_CHECK_RET(hipMemcpyAsync(dx, xs.data(), xs.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  TH_HIP_CHECK_RET(hipMemcpyAsync(ds, samples, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+  int rc = mlp_infer_launch(no, m->d_master, m->d_bf, true, dx, dy, n, s);
+  if (!rc) rc = stencil_check_launch(dim, p, ds, dy, n, m->out_mean, m->out_std, kEFloor, dq, dm, s);
+  if (rc) return rc;
+  TH_HIP_CHECK_RET(hipMemcpyAsync(q_out, dq, (size_t)n * nq * sizeof(double), hipMemcpyDeviceToHost, s));
+  TH_HIP_CHECK_RET(hipMemcpyAsync(mis, dm, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+  TH_HIP_CHECK_RET(hipStreamSynchronize(s));
+  return 0;
+}
+
 // Per-cell weights for the coarse schemes PLAINFIT / MLP of a dim-dimensional
 // problem.  samples: n x 3 (eta_c, p, shift); q_out: n x 3 (2-D) or n x 4
-// (3-D).  For MLP, the network's e_m are compared with the fine dispersion
-// errors interpolated from a table of exact values (256 nodes in eta, cubic
-// Lagrange in log space); cells beyond tau get the exact plain fit.
+// (3-D).  For MLP, the network's stencils are computed and checked on the
+// device: a cell whose zero-set mismatch against the fine dispersion curve
+// exceeds tau (or is not finite) gets the exact plain fit.
 int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const double *samples, int n,
                    double *q_out, int *n_fallback) {
   *n_fallback = 0;
@@ -389,50 +428,12 @@ int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const doubl
     set_error("the surrogate network's stencil family does not match the problem dimension");
     return TH_EINVAL;
   }
-  std::vector<double> e((size_t)n * no);
-  int rc = mlp_predict_impl(m, samples, n, true, e.data());
+  std::vector<double> mis(n);
+  int rc = mlp_stencils_impl(m, dim, samples, n, q_out, mis.data());
   if (rc) return rc;
-  // table of exact fine errors over the range of effective eta (per order)
-  double lo = 1e300, hi = 0;
-  std::vector<double> eta_eff(n);
-  int p = (int)std::lround(samples[1]);
-  for (int i = 0; i < n; ++i) {
-    eta_eff[i] = effective_eta(samples[3 * i], samples[3 * i + 2]);
-    lo = std::min(lo, eta_eff[i]);
-    hi = std::max(hi, eta_eff[i]);
-    if ((int)std::lround(samples[3 * i + 1]) != p) {
-      set_error("cells of one problem must share the order");
-      return TH_EINVAL;
-    }
-  }
-  const int NT = 256;
-  const double a = lo * 0.98, bnd = std::min(hi * 1.02, 0.999 * 2.0 * M_PI / p);
-  const double dx = (bnd - a) / (NT - 1);
-  std::vector<double> tab_in((size_t)NT * 3), tab_e((size_t)NT * no);
-  for (int i = 0; i < NT; ++i) {
-    tab_in[3 * i] = a + dx * i;
-    tab_in[3 * i + 1] = p;
-    tab_in[3 * i + 2] = 0.0;
-  }
-  family_errors(no, tab_in.data(), NT, tab_e.data());
   std::vector<int> bad;
-  for (int i = 0; i < n; ++i) {
-    const double xq = (eta_eff[i] - a) / dx;
-    int j0 = std::max(0, std::min(NT - 4, (int)std::floor(xq) - 1));
-    double mismatch = 0.0;
-    for (int c = 0; c < no; ++c) {
-      double v = 0.0;  // cubic Lagrange in log space
-      for (int j = j0; j < j0 + 4; ++j) {
-        double w = 1.0;
-        for (int l = j0; l < j0 + 4; ++l)
-          if (l != j) w *= (xq - l) / (double)(j - l);
-        v += w * std::log(std::max(-tab_e[(size_t)no * j + c], 0.0) + kEFloor);
-      }
-      const double e_tab = -(std::exp(v) - kEFloor);
-      mismatch = std::max(mismatch, std::fabs(e[(size_t)no * i + c] - e_tab));
-    }
-    if (!(mismatch <= tau)) bad.push_back(i);
-  }
+  for (int i = 0; i < n; ++i)
+    if (!(mis[i] <= tau)) bad.push_back(i);
   // exact plain fit for the flagged cells
   if (!bad.empty()) {
     std::vector<double> sb(bad.size() * 3), eb(bad.size() * no);
@@ -440,9 +441,9 @@ int coarse_weights(int dim, int scheme, const th_mlp *m, double tau, const doubl
       for (int c = 0; c < 3; ++c) sb[3 * k + c] = samples[3 * bad[k] + c];
     family_errors(no, sb.data(), (int)bad.size(), eb.data());
     for (size_t k = 0; k < bad.size(); ++k)
-      for (int c = 0; c < no; ++c) e[(size_t)no * bad[k] + c] = eb[(size_t)no * k + c];
+      weights_from(bad[k], effective_eta(samples[3 * bad[k]], samples[3 * bad[k] + 2]),
+                   &eb[(size_t)no * k]);
   }
-  for (int i = 0; i < n; ++i) weights_from(i, eta_eff[i], &e[(size_t)no * i]);
   *n_fallback = (int)bad.size();
   return 0;
 }
@@ -458,6 +459,19 @@ extern "C" th_status th_mlp_predict(th_mlp *m, const double *samples, int n, int
   if (!m->has_weights) return mfail(m, TH_ESTATE, "weights not set");
   if (hipSetDevice(m->device) != hipSuccess) return mfail(m, TH_EHIP, "hipSetDevice failed");
   int rc = mlp_predict_impl(m, samples, n, bf16 != 0, e_out);
+  if (rc) return mfail(m, (th_status)rc, get_error());
+  return TH_OK;
+}
+
+extern "C" th_status th_mlp_stencils(th_mlp *m, const double *samples, int n, double *q_out,
+                                     double *mismatch_out) {
+  if (!m) return TH_EINVAL;
+  std::string msg;
+  if (check_samples(samples, n, msg) != TH_OK) return mfail(m, TH_EINVAL, msg);
+  if (!q_out || !mismatch_out) return mfail(m, TH_EINVAL, "output array is NULL");
+  if (!m->has_weights) return mfail(m, TH_ESTATE, "weights not set");
+  if (hipSetDevice(m->device) != hipSuccess) return mfail(m, TH_EHIP, "hipSetDevice failed");
+  int rc = mlp_stencils_impl(m, m->n_out == 3 ? 3 : 2, samples, n, q_out, mismatch_out);
   if (rc) return mfail(m, (th_status)rc, get_error());
   return TH_OK;
 }
