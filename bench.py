@@ -30,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense matrix cores
+FP64_PEAK_TFLOPS = 78.6     # matrix and vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dd_apply_traffic.json")
 # sources of the batched subdomain apply kernel (its file and the headers it uses)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2509_17494_amd", "csrc", f)
@@ -54,6 +56,9 @@ def parse():
                     help="smoother shift alpha_s (default: the workload's, 0.5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="leave the 3-D C4 variant out")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="no HIP-graph replay of the preconditioner (profiling runs)")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--study", default=None, choices=["table1"],
                     help="instead of the benchmark, print the iteration counts of a parameter "
@@ -68,8 +73,8 @@ def workload(name):
                 coarse="qsfem")
     if name == "C3":
         spec.update(gemm="bf16", precond="c64")
-    if name == "C4":  # BF16 operators, complex64 preconditioner, dispersion-matched 27-point
-        spec.update(gemm="bf16", precond="c64", coarse="plainfit")
+    if name == "C4":  # FP32 slab factors, complex64 preconditioner, dispersion-matched 27-point
+        spec.update(gemm="f32", precond="c64", coarse="plainfit", restart=30)
     return cfg, spec
 
 
@@ -157,6 +162,58 @@ def traffic_entry(workload_name):
         return None
 
 
+def host_description():
+    """The host the oracle runs on: usable cores and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"nproc": nproc, "logical_cpus": os.cpu_count(), "cpu_model": model}
+
+
+def timed_oracle_solves(tg, f, threads, min_seconds=8.0):
+    """Repeat the oracle's GMRES solve for about min_seconds of CPU work with
+    the BLAS thread pools limited to `threads` (the sparse LU solves of the
+    coarse level are serial either way)."""
+    from threadpoolctl import threadpool_limits
+    its = reps = 0
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        while True:
+            _, k, _ = tg.gmres(f, 1e-6)
+            its += k
+            reps += 1
+            if time.perf_counter() - t0 >= min_seconds:
+                break
+        t = time.perf_counter() - t0
+    return its, t, reps
+
+
+def _baseline(tg, f, ndof, t_setup, what):
+    host = host_description()
+    runs = {}
+    for threads in (1, host["nproc"]):
+        its, t, reps = timed_oracle_solves(tg, f, threads)
+        runs[threads] = (ndof * its / t, its, t, reps)
+    best = max(runs, key=lambda k: runs[k][0])
+    v, its, t, reps = runs[best]
+    return {"value": v, "unit": "DOF*cycles/s", "cores": best, "kind": "oracle",
+            "sample": f"{what}: oracle GMRES to 1e-6 repeated {reps} times, {its} cycles in "
+                      f"{t:.2f} s with {best} BLAS thread(s) (setup {t_setup:.1f} s excluded); "
+                      f"numpy/scipy FP64",
+            "single_thread_value": runs[1][0], "all_cores_value": runs[host["nproc"]][0],
+            "host": host}
+
+
 def cpu_baseline_3d():
     """The oracle on the reduced 3-D cube: C4's recipe (GRF correlation 0.1,
     speeds 1.5..4, 10 points per minimum wavelength, Q2, 8-cell subdomains,
@@ -169,36 +226,17 @@ def cpu_baseline_3d():
     tg = TwoGrid(p, k, alpha_s=0.5, l_dd=8)
     t_setup = time.perf_counter() - t0
     f = syn.gaussian_load(n, p, [[0.25, 0.25, 0.25]], 2.0 / n, dim=3)[0]
-    its, t_solve, reps = timed_oracle_solves(tg, f)
     ndof = (n * p + 1) ** 3
-    return {"value": ndof * its / t_solve, "unit": "DOF*cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"C4 recipe on a 16^3-cell cube ({ndof} DOF), Q2, l_dd=8, one source, "
-                      f"exact-wavenumber 27-point coarse stencil, oracle GMRES to 1e-6 repeated "
-                      f"{reps} times: {its} cycles in {t_solve:.2f} s (setup {t_setup:.1f} s "
-                      f"excluded), single-threaded numpy/scipy"}
-
-
-def timed_oracle_solves(tg, f, min_seconds=10.0):
-    """Repeat the oracle's GMRES solve until about min_seconds of CPU work, with
-    the BLAS thread pools limited to one thread (sparse LU solves are serial)."""
-    from threadpoolctl import threadpool_limits
-    its = reps = 0
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        while True:
-            _, k, _ = tg.gmres(f, 1e-6)
-            its += k
-            reps += 1
-            if time.perf_counter() - t0 >= min_seconds:
-                break
-        t = time.perf_counter() - t0
-    return its, t, reps
+    return _baseline(tg, f, ndof, t_setup,
+                     f"C4 recipe on a 16^3-cell cube ({ndof} DOF), Q2, l_dd=8, one source, "
+                     f"exact-wavenumber 27-point coarse stencil")
 
 
 def cpu_baseline(cfg_name):
     """The FP64 oracle timed on this host on a bounded sample: a 96x96-cell
     window of the same medium, order and k h with the same subdomain size,
-    solved to 1e-6 by the oracle's GMRES; rate = DOF x cycles / solve time."""
+    solved to 1e-6 by the oracle's GMRES; rate = DOF x cycles / solve time,
+    with one BLAS thread and with all usable cores (the faster is the value)."""
     if cfg_name == "C4":
         return cpu_baseline_3d()
     import numpy as np
@@ -213,17 +251,14 @@ def cpu_baseline(cfg_name):
     tg = TwoGrid(p, k, alpha_s=cfg["alpha_s"], l_dd=cfg["l_dd"])
     t_setup = time.perf_counter() - t0
     f = syn.gaussian_load(n, p, [[0.5, 0.5]], 2.0 / n)[0]
-    its, t_solve, reps = timed_oracle_solves(tg, f)
     ndof = (n * p + 1) ** 2
-    return {"value": ndof * its / t_solve, "unit": "DOF*cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cfg_name} medium, order and k*h on a {n}x{n}-cell window ({ndof} DOF), "
-                      f"l_dd={cfg['l_dd']}, oracle GMRES to 1e-6 repeated {reps} times: {its} "
-                      f"cycles in {t_solve:.2f} s (setup {t_setup:.1f} s excluded), "
-                      f"single-threaded numpy/scipy"}
+    return _baseline(tg, f, ndof, t_setup,
+                     f"{cfg_name} medium, order and k*h on a {n}x{n}-cell window ({ndof} DOF), "
+                     f"l_dd={cfg['l_dd']}")
 
 
 def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, verbose=False,
-                 gemm=None, alpha_s=None):
+                 gemm=None, alpha_s=None, coarse=None, coarse_q=None):
     """Set up one workload, then time `steps` solves to 1e-6 after `warmup`
     untimed ones.  With timing, HIP events record every kernel class over the
     timed region (graph replay is off then); without it a separate one-solve
@@ -239,6 +274,8 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         spec["gemm"] = gemm
     if alpha_s is not None:
         spec["alpha_s"] = alpha_s
+    if coarse is not None:
+        spec["coarse"] = coarse
     N, p, dim = cfg["n"], cfg["p"], cfg.get("dim", 2)
     f_host = syn.gaussian_load(N, p, cfg["centres"], cfg["sigma"], dim=dim)
     R = f_host.shape[0]
@@ -246,7 +283,7 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
     with torch.cuda.stream(stream):
         t0 = time.perf_counter()
         s = TwoGridSolver(cfg["k"], order=p, alpha_s=spec["alpha_s"], l_dd=spec["l_dd"],
-                          gemm=spec["gemm"], max_rhs=R, coarse=spec["coarse"])
+                          gemm=spec["gemm"], max_rhs=R, coarse=spec["coarse"], coarse_q=coarse_q)
         t_setup = time.perf_counter() - t0
         info = s.info()
         f = torch.from_numpy(f_host).to("cuda")
@@ -290,6 +327,19 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         alg, flops = slab_apply_bytes(N, p, spec["l_dd"], dim, R, mat_bytes, vec_bytes)
     dd_ms, dd_n = kt["dd_apply"]
     avg_ms = dd_ms / max(dd_n, 1)
+    # coarse solve: one per two-grid cycle; bytes streamed per solve by the
+    # nested dissection (factors once per solve and refinement step, the
+    # refinement residual reads the stencil) or the line elimination (its
+    # factors once per pass of right-hand sides)
+    c_ms, _ = kt["coarse"]
+    c_avg = c_ms / max(sum(iters) if timing else iters[-1], 1)  # one coarse solve per iteration
+    S = 27 if dim == 3 else 9
+    st_bytes = info["n_coarse"] * S * 16
+    refine = info["coarse_refine"] if precond == "c128" else 0
+    if info["coarse_solver"] == 2:
+        c_bytes = (info["coarse_bytes"] - st_bytes) * (1 + refine) + refine * st_bytes
+    else:
+        c_bytes = info["coarse_bytes"]
     res = {
         "name": name, "precond": precond, "gemm": spec["gemm"], "graph": graph, "R": R,
         "n_fine": info["n_fine"], "value": info["n_fine"] * cycles / elapsed,
@@ -299,6 +349,11 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
         "layout": ["dense", "symmetric", "matrix-core", "slab"][info["smoother_layout"]],
         "dd": {"alg_bytes": alg, "flops": flops, "avg_ms": avg_ms, "launches": dd_n,
                "gbs": alg / (avg_ms * 1e-3) / 1e9, "tflops": flops / (avg_ms * 1e-3) / 1e12},
+        "coarse": {"solver": {1: "lines", 2: "nested dissection"}[info["coarse_solver"]],
+                   "levels": info["coarse_levels"], "refine_steps": refine,
+                   "probe_error": info["coarse_check"], "factor_bytes": info["coarse_bytes"],
+                   "bytes_per_solve": c_bytes, "avg_ms_per_solve": round(c_avg, 4),
+                   "gbs": c_bytes / max(c_avg * 1e-3, 1e-12) / 1e9},
         "desc": f"{name}: {dim}-D Q{p}, {N}^{dim} cells ({info['n_fine']} DOF), {R} RHS, "
                 f"l_dd={spec['l_dd']}, alpha_s={spec['alpha_s']}, B_i {spec['gemm']}, "
                 f"preconditioner {precond}, coarse {spec['coarse']}"
@@ -359,6 +414,76 @@ def study_table1(wavelengths=16.0, rtol=1e-6):
                       "wavelengths": wavelengths, "rtol": rtol, "iters": part_b}), flush=True)
 
 
+def roofline_hbm(v, kernel, mfma_peak=None):
+    """Roofline object of a variant's smoother application (HBM bound):
+    algorithmic bytes per launch over the average launch time from HIP
+    events; with mfma_peak, the matrix-core rate of the same launch too."""
+    d = v["dd"]
+    r = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+         "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": round(d["avg_ms"], 4),
+         "launches": d["launches"]}
+    if mfma_peak:
+        r["mfma_TFLOPs"] = round(d["tflops"], 2)
+        r["mfma_frac"] = round(d["tflops"] / mfma_peak, 4)
+    return r
+
+
+def roofline_fp64(v):
+    """The FP64 batched smoother is a dense complex GEMM (arithmetic intensity
+    above the FP64 ridge of 9.8 flop/B): bound by the FP64 matrix cores."""
+    d = v["dd"]
+    return {"bound": "mfma", "achieved": round(d["tflops"], 2), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(d["tflops"] / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "k_dd_gatherx + k_dd_mfma64 (FP64 matrix cores, v_mfma_f64_16x16x4f64)",
+            "flops_per_launch": d["flops"], "avg_launch_ms": round(d["avg_ms"], 4),
+            "launches": d["launches"]}
+
+
+def coarse_roofline(v):
+    c = v["coarse"]
+    return {"bound": "hbm", "achieved": round(c["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(c["gbs"] / HBM_PEAK_GBS, 4),
+            "kernel": "coarse solve (" + c["solver"] + ")",
+            "alg_bytes_per_solve": c["bytes_per_solve"], "avg_ms_per_solve": c["avg_ms_per_solve"]}
+
+
+def variant_entry(v, roof):
+    return {"workload": v["desc"], "value": v["value"], "unit": "DOF*cycles/s",
+            "time_to_1e-6_ms": v["ms_per_step"], "gmres_iters": v["gmres_iters"],
+            "max_rel_res": v["max_rel_res"], "setup_s": round(v["setup_s"], 3),
+            "kernel_ms_per_step": v["kernel_ms_per_step"], "coarse": v["coarse"],
+            "roofline": roof}
+
+
+def c5_variant(steps, verbose):
+    """C5: the surrogate network trained on the device (1e5 seeded samples of
+    the plain fit, 30 epochs), then the C5 solve with per-cell network
+    stencils (fallback threshold 1e-3 on the zero-set mismatch) against the
+    plain fit computed per cell on the host."""
+    import synthetic as syn
+    from paper_2509_17494_amd import CoarseStencilMLP
+    t0 = time.perf_counter()
+    net = CoarseStencilMLP(syn.mlp_init(seed=2))
+    st = net.train(syn.mlp_samples(100_000, seed=1), epochs=30, batch=1024, lr=2e-3, bf16=True)
+    t_train = time.perf_counter() - t0
+    out = {"training": {"samples": 100000, "epochs": 30, "steps": st.steps,
+                        "loss_first": st.loss_first, "loss_last": st.loss_last,
+                        "t_targets_s": round(st.t_targets_s, 3),
+                        "t_device_train_s": round(st.t_train_s, 3), "t_total_s": round(t_train, 3)}}
+    for key, coarse, q in (("plainfit", "plainfit", None), ("mlp", "mlp", (net, 1e-3))):
+        v = run_workload("C5", steps, 1, graph=False, timing=True, verbose=verbose,
+                         coarse=coarse, coarse_q=q)
+        out[key] = {"workload": v["desc"], "value": v["value"], "unit": "DOF*cycles/s",
+                    "time_to_1e-6_ms": v["ms_per_step"], "gmres_iters": v["gmres_iters"],
+                    "max_rel_res": v["max_rel_res"],
+                    "stencil_time_ms": round(v["info"]["t_stencil_s"] * 1e3, 3),
+                    "fallback_cells": v["info"]["n_fallback_cells"],
+                    "coarse_setup_s": round(v["info"]["t_setup_coarse_s"], 3)}
+    net.close()
+    return out
+
+
 def main():
     a = parse()
     if a.verbose:
@@ -371,8 +496,9 @@ def main():
         study_table1()
         return
     mixed = a.workload in ("C3", "C4")
-    prim = run_workload(a.workload, a.steps, a.warmup, precond=a.precond, graph=mixed,
-                        timing=not mixed, verbose=a.verbose, alpha_s=a.alpha_s)
+    prim = run_workload(a.workload, a.steps, a.warmup, precond=a.precond,
+                        graph=mixed and not a.no_graph, timing=not mixed, verbose=a.verbose,
+                        alpha_s=a.alpha_s)
     d = prim["dd"]
     traffic = traffic_entry(a.workload)
     roof = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -407,20 +533,31 @@ def main():
                    "kernel_ms_per_step": prim["kernel_ms_per_step"]},
         "roofline": roof,
     }
+    out["config"]["coarse"] = prim["coarse"]
+    out["coarse_roofline"] = coarse_roofline(prim)
     if not a.no_variants and a.workload == "C2":
         variants = {}
-        for key, kw in [("C3_mixed_bf16_batched64_graph", dict(name="C3", graph=True, timing=False)),
-                        ("C3_fp64_batched64_control", dict(name="C3", precond="c128", gemm="f64",
-                                                           graph=False, timing=True)),
-                        ("C1_fp64", dict(name="C1", graph=False, timing=True))]:
-            v = run_workload(steps=max(3, a.steps), warmup=1, verbose=a.verbose, **kw)
-            variants[key] = {"workload": v["desc"], "value": v["value"],
-                             "unit": "DOF*cycles/s", "time_to_1e-6_ms": v["ms_per_step"],
-                             "gmres_iters": v["gmres_iters"], "max_rel_res": v["max_rel_res"],
-                             "smoother_kernel_ms": round(v["dd"]["avg_ms"], 4),
-                             "smoother_alg_GBps": round(v["dd"]["gbs"], 1),
-                             "smoother_TFLOPs": round(v["dd"]["tflops"], 3),
-                             "kernel_ms_per_step": v["kernel_ms_per_step"]}
+        v_mixed = run_workload("C3", max(3, a.steps), 1, graph=True, timing=False,
+                               verbose=a.verbose)
+        variants["C3_mixed_bf16_batched64_graph"] = variant_entry(
+            v_mixed, roofline_hbm(v_mixed, "k_dd_mfx (staged matrix-core smoother, BF16 B_i, "
+                                           "FP32 accumulation)", mfma_peak=BF16_PEAK_TFLOPS))
+        v_fp64 = run_workload("C3", max(3, a.steps), 1, precond="c128", gemm="f64", graph=False,
+                              timing=True, verbose=a.verbose)
+        variants["C3_fp64_batched64_control"] = variant_entry(v_fp64, roofline_fp64(v_fp64))
+        variants["C3_mixed_vs_fp64"] = {
+            "value_ratio": v_mixed["value"] / v_fp64["value"],
+            "time_ratio": v_fp64["ms_per_step"] / v_mixed["ms_per_step"],
+            "note": "the same 64 sources; FP64 control runs its subdomain GEMMs on the FP64 "
+                    "matrix cores"}
+        v1 = run_workload("C1", max(3, a.steps), 1, graph=False, timing=True, verbose=a.verbose)
+        variants["C1_fp64"] = variant_entry(v1, roofline_hbm(v1, "k_dd_apply (dense rows)"))
+        variants["C5_learned_stencils"] = c5_variant(max(3, a.steps), a.verbose)
+        if not a.no_c4:
+            v4 = run_workload("C4", 2, 1, graph=True, timing=False, verbose=a.verbose)
+            variants["C4_3d_mixed_f32slab_8rhs_graph"] = variant_entry(
+                v4, roofline_hbm(v4, "k_slab_gather + k_slab_fwd + k_slab_bwd + k_slab_extract "
+                                     "(one smoother application, FP32 slab factors)"))
         out["config"]["variants"] = variants
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline("C2" if a.workload == "C2" else a.workload)

@@ -119,7 +119,7 @@ static void free_graphs(th_ctx *c) {
 static void free_fine(th_ctx *c) {
   void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,  c->d_subs, c->d_nblk, c->d_B, c->w_r,
                   c->w_v,   c->w_rr,   c->w_y,  c->w_rc,   c->w_uc,   c->w_t, c->w_rc32,
-                  c->d_eidx, c->w_p, c->w_x, c->w_z, c->w_yc};
+                  c->d_eidx, c->w_p, c->w_x, c->w_z, c->w_yc, c->w_xp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   c->d_kap = c->d_kaps = nullptr;
@@ -128,8 +128,9 @@ static void free_fine(th_ctx *c) {
   c->d_nblk = nullptr;
   c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = c->w_rc32 = nullptr;
   c->d_eidx = nullptr;
-  c->w_p = c->w_x = c->w_z = c->w_yc = nullptr;
+  c->w_p = c->w_x = c->w_z = c->w_yc = c->w_xp = nullptr;
   c->mfx_max_nrb = 0;
+  c->mfx_ok = false;
   c->max_nsl = c->max_slab_rows = 0;
   c->fine_ready = false;
 }
@@ -504,10 +505,13 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
     } else if (c->layout == 3 || (c->layout == 0 && d->gemm == TH_GEMM_F64 &&
                                     dd_mfma64_rhs_pad(d->max_rhs) > 0)) {
       xoff += s.nOm;  // gathered patches (slab sweeps, FP64 matrix-core apply)
+    } else if (c->layout == 2) {
+      s.xoff = xoff;  // first 32-column block of the patch fragments (two-pass BF16 apply)
+      xoff += (s.nOm + 31) / 32;
     }
   }
   c->p_rows = poff;
-  c->x_rows = xoff;
+  c->x_rows = c->layout == 2 ? 0 : xoff;  // layout 2 counts column blocks, kept in the Subs
   c->max_ldb = max_ldb;
   c->max_nom = max_nom;
   c->max_rowblocks = (max_ldb + 255) / 256;
@@ -538,12 +542,17 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   if (ok && d->n_dd > 1)
     ok = alloc(&c->w_v, R * c->nf * sizeof(c64)) && alloc(&c->w_rr, R * c->nf * sizeof(c64));
   if (ok && c->layout == 3) ok = alloc(&c->w_z, R * c->x_rows * sizeof(c64));
-  if (ok && c->layout == 2 && mfx_fits(d->max_rhs, max_nom)) {
-    // colour planes of the staged matrix-core kernel, sized for complex128 vectors
+  if (ok && c->layout == 2) {
+    // colour planes of the staged and two-pass matrix-core kernels (sized for
+    // complex128 vectors) and the two-pass kernel's BF16 patch fragments
     const size_t yc = ((size_t)1 << c->dim) * R * c->nf * sizeof(c64);
+    long long xp = 0;
+    for (const Sub &sb : c->subs) xp += mfp_patch_elems(sb, d->max_rhs);
     if (yc <= ((size_t)4 << 30)) {
       ok = alloc(&c->w_yc, yc);
+      c->mfx_ok = mfx_fits(d->max_rhs, max_nom);
       for (const Sub &sb : c->subs) c->mfx_max_nrb = std::max(c->mfx_max_nrb, (sb.nU + 15) / 16);
+      if (ok && xp * 2 <= ((long long)4 << 30)) ok = alloc(&c->w_xp, (size_t)xp * 2);
     }
   }
   if (!ok) {

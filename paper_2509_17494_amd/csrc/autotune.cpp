@@ -69,15 +69,14 @@ int autotune_mfma(th_ctx *c) {
   // TH_MFMA_CFG=<index>[,<grid>] forces a configuration (tests and measurements)
   if (const char *force = std::getenv("TH_MFMA_CFG")) {
     int f = -1, g = 0;
-    if (std::sscanf(force, "%d,%d", &f, &g) >= 1 && f >= 0 && f < mfma_num_configs() && g >= 0 &&
-        (!mfma_cfg_staged(f) || c->w_yc)) {
+    if (std::sscanf(force, "%d,%d", &f, &g) >= 1 && g >= 0 && mfma_cfg_usable(c, f)) {
       c->mfma_cfg = f;
       c->mfma_grid = mfma_cfg_staged(f) ? 0 : g;
       c->tune_report = "forced";
       return 0;
     }
   }
-  if (cache_lookup(key, cfg, grid, best) && (!mfma_cfg_staged(cfg) || c->w_yc)) {
+  if (cache_lookup(key, cfg, grid, best) && mfma_cfg_usable(c, cfg)) {
     c->mfma_cfg = cfg;
     c->mfma_grid = grid;
     c->tune_report = "cache " + key;
@@ -108,7 +107,7 @@ int autotune_mfma(th_ctx *c) {
     return e;
   };
   for (int cf = 0; cf < mfma_num_configs() && rc == 0; ++cf) {
-    if (mfma_cfg_staged(cf) && !c->w_yc) continue;
+    if (!mfma_cfg_usable(c, cf)) continue;
     for (int g : grids) {
       if (mfma_cfg_staged(cf) && g != 0) continue;  // one workgroup per item, no grid choice
       rc = step(cf, g);  // warm-up

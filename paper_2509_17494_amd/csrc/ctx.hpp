@@ -208,7 +208,9 @@ struct th_ctx {
   void *w_p = nullptr;         // transposed-tile partial sums (symmetric layout)
   void *w_x = nullptr;         // gathered patches X_i (symmetric layout)
   void *w_yc = nullptr;        // colour planes [2^d][rhs][n_fine] of the staged matrix-core kernel
+  void *w_xp = nullptr;        // BF16 patch fragments of the two-pass matrix-core kernel
   int mfx_max_nrb = 0;         // most 16-row blocks of a subdomain (staged matrix-core kernel)
+  bool mfx_ok = false;         // patches fit the staged kernel's LDS
   size_t ws_bytes = 0;
 
   th::CoarseData coarse;
@@ -304,7 +306,11 @@ int launch_extract_b_mfma(const th_ctx *c, int s0, int nb, const c64 *work, int 
                           long long stride, hipStream_t s);
 long long mfma_store_elems(const Sub &s);
 int mfma_num_configs();
-bool mfma_cfg_staged(int cfg);          // configuration of the staged kernel (colour-plane output)
+bool mfma_cfg_staged(int cfg);          // staged or two-pass form (colour-plane output)
+bool mfma_cfg_twopass(int cfg);         // two-pass form (patch fragments gathered first)
+bool mfma_cfg_usable(const th_ctx *c, int cfg);  // its workspaces exist and its limits hold
+int mfp_tiles(int max_rhs);             // tiles of 16 right-hand sides of the patch fragments
+long long mfp_patch_elems(const Sub &s, int max_rhs);  // bf16 elements of one patch's fragments
 int mfx_rhs_group(int max_rhs);         // right-hand sides staged together by the staged kernel
 bool mfx_fits(int max_rhs, int max_nom);  // patches small enough for the staged kernel
 int launch_dd_accum_col(const th_ctx *c, void *u, int nrhs, bool f32, bool assign, hipStream_t s);

@@ -285,6 +285,224 @@ __global__ __launch_bounds__(64 * WAVES) void k_dd_mfx(const Sub *__restrict__ s
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-pass form (any patch size): a gather pass rounds every patch X_i to BF16
+// once and stores it in the B-operand layout of v_mfma_f32_16x16x32_bf16 --
+// for every subdomain, 32-column block kb and tile of 16 right-hand sides,
+// re and im planes of 64 lanes x 8 values, lane l holding right-hand side
+// 16 t + l % 16 and patch columns 32 kb + 8 (l / 16) + [0, 8) -- with one
+// thread per (column block, tile, lane) and eight independent loads per
+// thread.  The product pass then streams both operands from memory with no
+// LDS and no barrier: a workgroup owns one 16-row block of one subdomain, its
+// wavefronts one tile of right-hand sides each (the B_i fragment is shared
+// through the cache), fragments prefetched PF column blocks ahead; workgroups
+// of one subdomain sit on one XCD (its patch stays in one L2).  Results go to
+// the colour planes, as in the staged form, in the same MFMA order, so every
+// form gives the same bits.
+// Gather pass: workgroup (column block kb, subdomain); the 32 patch columns
+// of every right-hand side are read with consecutive lanes on consecutive
+// columns (coalesced along the patch's grid lines), transposed through LDS,
+// rounded to BF16 and written as whole 1 KiB fragment planes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mfp_gather(const Sub *__restrict__ subs,
+                                                    const cx<T> *__restrict__ r,
+                                                    unsigned short *__restrict__ Xp, int P,
+                                                    int n1, long long nf, int nrhs, int ntmax) {
+  constexpr int QP = 64;  // right-hand sides staged per pass (four tiles)
+  __shared__ cx<T> tile[QP][MF_KB + 1];
+  __shared__ long long gofs[MF_KB];
+  const Sub s = subs[blockIdx.y];
+  const int kb = blockIdx.x;
+  const int nkb = (s.nOm + MF_KB - 1) / MF_KB;
+  if (kb >= nkb) return;  // uniform
+  if (threadIdx.x < MF_KB) {
+    const int k = kb * MF_KB + threadIdx.x;
+    gofs[threadIdx.x] = k < s.nOm ? om_node(s, k, P, n1) : -1;
+  }
+  const int ntile = (nrhs + MF_NT - 1) / MF_NT;
+  for (int q0 = 0; q0 < nrhs; q0 += QP) {
+    __syncthreads();  // offsets written; the previous pass's reads of the tile done
+    for (int t = threadIdx.x; t < QP * MF_KB; t += 256) {
+      const int kk = t % MF_KB, qq = t / MF_KB, q = q0 + qq;
+      const long long g = gofs[kk];
+      tile[qq][kk] = (q < nrhs && g >= 0) ? r[(long long)q * nf + g] : cx<T>{0, 0};
+    }
+    __syncthreads();
+    // fragment planes of the tiles of this pass: one thread per (tile, lane)
+    const int nt = min(QP / MF_NT, ntile - q0 / MF_NT);
+    for (int t = threadIdx.x; t < nt * 64; t += 256) {
+      const int lane = t % 64, tt = t / 64;
+      const int qq = tt * MF_NT + lane % 16, k0 = (lane / 16) * 8;
+      u32x4 pr, pi;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const cx<T> a = tile[qq][k0 + 2 * h], c = tile[qq][k0 + 2 * h + 1];
+        pr[h] = (unsigned int)f2bf((float)a.re) | ((unsigned int)f2bf((float)c.re) << 16);
+        pi[h] = (unsigned int)f2bf((float)a.im) | ((unsigned int)f2bf((float)c.im) << 16);
+      }
+      unsigned short *o = Xp + (((s.xoff + kb) * ntmax + q0 / MF_NT + tt) * 2) * 512 + lane * 8;
+      *(u32x4 *)o = pr;
+      *(u32x4 *)(o + 512) = pi;
+    }
+  }
+}
+
+template <typename T, int PF>
+__global__ __launch_bounds__(256) void k_mfp_gemm(const Sub *__restrict__ subs, int nsub, int nrb,
+                                                  const unsigned short *__restrict__ B,
+                                                  const unsigned short *__restrict__ Xp,
+                                                  cx<T> *__restrict__ Yc, int P, int n1, int M,
+                                                  long long nf, int nrhs, int ntmax) {
+  // XCD-aware mapping: workgroup b runs on XCD b % 8; subdomain si on XCD si % 8
+  const int b = blockIdx.x;
+  const int si = (b & 7) + 8 * ((b >> 3) / nrb), rb = (b >> 3) % nrb;
+  if (si >= nsub) return;
+  const Sub s = subs[si];
+  if (rb * MF_RB >= s.nU) return;  // uniform
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nkb = (s.nOm + MF_KB - 1) / MF_KB, ntile = (nrhs + MF_NT - 1) / MF_NT;
+  const int bx = si % M, by = (si / M) % M, bz = si / (M * M);
+  const int color = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
+  const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  long long gn[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = rb * MF_RB + (lane / 16) * 4 + i;
+    gn[i] = row < s.nU ? u_global(s, row, P, n1) : -1;
+  }
+  for (int t = wave; t < ntile; t += nw) {
+    const unsigned short *xb = Xp + ((s.xoff * ntmax + t) * 2) * 512 + lane * 8;
+    const long long xstep = (long long)ntmax * 2 * 512;  // next column block
+    u32x4 fr[PF], fi[PF], xr[PF], xi[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+      if (j < nkb) {
+        fr[j] = *(const u32x4 *)(B + mf_frag(s, rb, j, 0) + lane * 8);
+        fi[j] = *(const u32x4 *)(B + mf_frag(s, rb, j, 1) + lane * 8);
+        xr[j] = *(const u32x4 *)(xb + j * xstep);
+        xi[j] = *(const u32x4 *)(xb + j * xstep + 512);
+      }
+    f32x4 are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < nkb; k0 += PF) {
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        const int kb = k0 + j;
+        if (kb < nkb) {  // uniform
+          const bf16x8 br = __builtin_bit_cast(bf16x8, fr[j]);
+          const bf16x8 bi = __builtin_bit_cast(bf16x8, fi[j]);
+          const bf16x8 bin = __builtin_bit_cast(bf16x8, fi[j] ^ sgn);
+          const bf16x8 vr = __builtin_bit_cast(bf16x8, xr[j]);
+          const bf16x8 vi = __builtin_bit_cast(bf16x8, xi[j]);
+          are = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, vr, are, 0, 0, 0);
+          are = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bin, vi, are, 0, 0, 0);
+          aim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, vi, aim, 0, 0, 0);
+          aim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi, vr, aim, 0, 0, 0);
+          const int kn = kb + PF;
+          if (kn < nkb) {
+            fr[j] = *(const u32x4 *)(B + mf_frag(s, rb, kn, 0) + lane * 8);
+            fi[j] = *(const u32x4 *)(B + mf_frag(s, rb, kn, 1) + lane * 8);
+            xr[j] = *(const u32x4 *)(xb + kn * xstep);
+            xi[j] = *(const u32x4 *)(xb + kn * xstep + 512);
+          }
+        }
+      }
+    }
+    const int q = t * MF_NT + lane % 16;
+    if (q < nrhs) {
+      cx<T> *yq = Yc + ((long long)color * nrhs + q) * nf;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (gn[i] >= 0) yq[gn[i]] = cx<T>{(T)are[i], (T)aim[i]};
+    }
+  }
+}
+
+// Two-pass product, one wavefront per 16-row block with all tiles of right-hand
+// sides (up to four per pass): the B_i fragment is loaded once and used for
+// every tile; a workgroup holds four row blocks of one subdomain.
+template <typename T, int PF>
+__global__ __launch_bounds__(256) void k_mfp_gemm_all(const Sub *__restrict__ subs, int nsub,
+                                                      int ng, const unsigned short *__restrict__ B,
+                                                      const unsigned short *__restrict__ Xp,
+                                                      cx<T> *__restrict__ Yc, int P, int n1,
+                                                      int M, long long nf, int nrhs, int ntmax) {
+  constexpr int TT = 4;  // tiles per pass
+  const int b = blockIdx.x;
+  const int si = (b & 7) + 8 * ((b >> 3) / ng), g = (b >> 3) % ng;
+  if (si >= nsub) return;
+  const Sub s = subs[si];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb = 4 * g + wave;
+  if (rb * MF_RB >= s.nU) return;  // uniform per wavefront; no barrier follows
+  const int nkb = (s.nOm + MF_KB - 1) / MF_KB, ntile = (nrhs + MF_NT - 1) / MF_NT;
+  const int bx = si % M, by = (si / M) % M, bz = si / (M * M);
+  const int color = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
+  const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  long long gn[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = rb * MF_RB + (lane / 16) * 4 + i;
+    gn[i] = row < s.nU ? u_global(s, row, P, n1) : -1;
+  }
+  const long long xstep = (long long)ntmax * 2 * 512;
+  for (int t0 = 0; t0 < ntile; t0 += TT) {
+    const int nt = min(TT, ntile - t0);
+    const unsigned short *xb = Xp + ((s.xoff * ntmax + t0) * 2) * 512 + lane * 8;
+    u32x4 fr[PF], fi[PF], xr[PF][TT], xi[PF][TT];
+    auto load = [&](int j, int kb) {
+      fr[j] = __builtin_nontemporal_load((const u32x4 *)(B + mf_frag(s, rb, kb, 0) + lane * 8));
+      fi[j] = __builtin_nontemporal_load((const u32x4 *)(B + mf_frag(s, rb, kb, 1) + lane * 8));
+#pragma unroll
+      for (int t = 0; t < TT; ++t)
+        if (t < nt) {
+          xr[j][t] = *(const u32x4 *)(xb + kb * xstep + t * 1024);
+          xi[j][t] = *(const u32x4 *)(xb + kb * xstep + t * 1024 + 512);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+      if (j < nkb) load(j, j);
+    f32x4 are[TT], aim[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      are[t] = f32x4{0, 0, 0, 0};
+      aim[t] = f32x4{0, 0, 0, 0};
+    }
+    for (int k0 = 0; k0 < nkb; k0 += PF) {
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        const int kb = k0 + j;
+        if (kb < nkb) {  // uniform
+          const bf16x8 br = __builtin_bit_cast(bf16x8, fr[j]);
+          const bf16x8 bi = __builtin_bit_cast(bf16x8, fi[j]);
+          const bf16x8 bin = __builtin_bit_cast(bf16x8, fi[j] ^ sgn);
+#pragma unroll
+          for (int t = 0; t < TT; ++t)
+            if (t < nt) {
+              const bf16x8 vr = __builtin_bit_cast(bf16x8, xr[j][t]);
+              const bf16x8 vi = __builtin_bit_cast(bf16x8, xi[j][t]);
+              are[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, vr, are[t], 0, 0, 0);
+              are[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bin, vi, are[t], 0, 0, 0);
+              aim[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, vi, aim[t], 0, 0, 0);
+              aim[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi, vr, aim[t], 0, 0, 0);
+            }
+          if (kb + PF < nkb) load(j, kb + PF);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      const int q = (t0 + t) * MF_NT + lane % 16;
+      if (t < nt && q < nrhs) {
+        cx<T> *yq = Yc + ((long long)color * nrhs + q) * nf;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (gn[i] >= 0) yq[gn[i]] = cx<T>{(T)are[t][i], (T)aim[t][i]};
+      }
+    }
+  }
+}
+
 // Averaged update from the colour planes: v_j (assign) or u_j += sum over the
 // closed U^(i) containing node j of (Y_i)_j, subdomains in ascending order (the
 // order of k_dd_accumulate, so both give the same bits).
@@ -404,6 +622,43 @@ static int launch_mfx_t(const th_ctx *c, const void *r, int nrhs, int groups, hi
   return 0;
 }
 
+template <typename T, int PF, bool ALL>
+static int launch_mfp_t(const th_ctx *c, const void *r, int nrhs, hipStream_t s) {
+  const int nsub = (int)c->subs.size();
+  const int ntmax = mfp_tiles(c->desc.max_rhs), ntile = ceil_div(nrhs, MF_NT);
+  int max_nkb = 0, nrb = 0;
+  for (const Sub &sb : c->subs) {
+    max_nkb = std::max(max_nkb, (sb.nOm + MF_KB - 1) / MF_KB);
+    nrb = std::max(nrb, (sb.nU + MF_RB - 1) / MF_RB);
+  }
+  const int nw = std::min(4, ntile);
+  unsigned short *xp = (unsigned short *)c->w_xp;
+  hipLaunchKernelGGL((k_mfp_gather<T>), dim3(max_nkb, nsub), dim3(256), 0, s, c->d_subs,
+                     (const cx<T> *)r, xp, c->P, c->n1, c->nf, nrhs, ntmax);
+  const int groups = ceil_div(nsub, 8);
+  if (ALL) {
+    const int ng = ceil_div(nrb, 4);
+    hipLaunchKernelGGL((k_mfp_gemm_all<T, PF>), dim3(8 * groups * ng), dim3(256), 0, s,
+                       c->d_subs, nsub, ng, (const unsigned short *)c->d_B,
+                       (const unsigned short *)xp, (cx<T> *)c->w_yc, c->P, c->n1, c->M, c->nf,
+                       nrhs, ntmax);
+  } else {
+    hipLaunchKernelGGL((k_mfp_gemm<T, PF>), dim3(8 * groups * nrb), dim3(64 * nw), 0, s,
+                       c->d_subs, nsub, nrb, (const unsigned short *)c->d_B,
+                       (const unsigned short *)xp, (cx<T> *)c->w_yc, c->P, c->n1, c->M, c->nf,
+                       nrhs, ntmax);
+  }
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+int mfp_tiles(int max_rhs) { return (max_rhs + MF_NT - 1) / MF_NT; }
+
+// BF16 patch fragments of the two-pass form (bf16 elements)
+long long mfp_patch_elems(const Sub &s, int max_rhs) {
+  return (long long)((s.nOm + MF_KB - 1) / MF_KB) * mfp_tiles(max_rhs) * 2 * 512;
+}
+
 int mfx_rhs_group(int max_rhs) { return max_rhs <= 16 ? 16 : (max_rhs <= 32 ? 32 : 64); }
 
 bool mfx_fits(int max_rhs, int max_nom) {
@@ -415,15 +670,37 @@ bool mfx_fits(int max_rhs, int max_nom) {
 // workgroups per subdomain)
 static const int kMfmaCfg[][2] = {{4, 4}, {4, 8}, {2, 4}, {8, 4}, {2, 8}};
 static const int kMfxCfg[][2] = {{4, 4}, {8, 4}, {8, 2}, {4, 5}, {8, 3}, {4, 8}, {8, 1}};
+// two-pass form: column blocks prefetched; 0: one wavefront per tile, 1: all tiles per wavefront
+static const int kMfpCfg[][2] = {{2, 0}, {4, 0}, {2, 1}};
 constexpr int kNumChunked = (int)(sizeof(kMfmaCfg) / sizeof(kMfmaCfg[0]));
-int mfma_num_configs() { return kNumChunked + (int)(sizeof(kMfxCfg) / sizeof(kMfxCfg[0])); }
+constexpr int kNumStaged = (int)(sizeof(kMfxCfg) / sizeof(kMfxCfg[0]));
+int mfma_num_configs() { return kNumChunked + kNumStaged + (int)(sizeof(kMfpCfg) / sizeof(kMfpCfg[0])); }
 bool mfma_cfg_staged(int cfg) { return cfg >= kNumChunked; }
+bool mfma_cfg_twopass(int cfg) { return cfg >= kNumChunked + kNumStaged; }
+bool mfma_cfg_usable(const th_ctx *c, int cfg) {
+  if (cfg < 0 || cfg >= mfma_num_configs()) return false;
+  if (mfma_cfg_twopass(cfg)) return c->w_yc && c->w_xp;
+  if (mfma_cfg_staged(cfg)) return c->w_yc && c->mfx_ok;
+  return true;
+}
 
 int launch_dd_mfma(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, int cfg, int grid,
                    hipStream_t s) {
+  if (mfma_cfg_twopass(cfg) && cfg < mfma_num_configs()) {
+    if (!c->w_yc || !c->w_xp) {
+      set_error("two-pass matrix-core smoother selected without its colour planes");
+      return TH_EINVAL;
+    }
+    const int pf = kMfpCfg[cfg - kNumChunked - kNumStaged][0];
+    const bool all = kMfpCfg[cfg - kNumChunked - kNumStaged][1] != 0;
+    if (all) return f32 ? launch_mfp_t<float, 2, true>(c, r, nrhs, s) : launch_mfp_t<double, 2, true>(c, r, nrhs, s);
+    if (pf == 2) return f32 ? launch_mfp_t<float, 2, false>(c, r, nrhs, s) : launch_mfp_t<double, 2, false>(c, r, nrhs, s);
+    return f32 ? launch_mfp_t<float, 4, false>(c, r, nrhs, s) : launch_mfp_t<double, 4, false>(c, r, nrhs, s);
+  }
   if (cfg >= kNumChunked && cfg < mfma_num_configs()) {
-    if (!c->w_yc) {
-      set_error("staged matrix-core smoother selected without its colour planes");
+    if (!c->w_yc || !c->mfx_ok) {
+      set_error("staged matrix-core smoother selected without its colour planes or for patches "
+                "too large for it");
       return TH_EINVAL;
     }
     const int w = kMfxCfg[cfg - kNumChunked][0], g = kMfxCfg[cfg - kNumChunked][1];

@@ -241,8 +241,9 @@ def test_smooth_bf16_matrix_cores(N, p, l_dd, nrhs):
                                             (12, 2, 4, 20)])
 def test_matrix_core_configurations_agree_bitwise(N, p, l_dd, nrhs, monkeypatch):
     """Every matrix-core smoother configuration (the persistent chunked kernel
-    with its tile choices and the staged kernel with its workgroup splits,
-    forced through TH_MFMA_CFG) gives bitwise the same smoother output: the
+    with its tile choices, the staged kernel with its workgroup splits and the
+    two-pass kernel with its prefetch depths, forced through TH_MFMA_CFG) gives
+    bitwise the same smoother output: the
     same MFMAs in the same order, and the averaged update from the packed Y
     rows or from the colour planes in the same subdomain order.  Covers
     staged right-hand-side groups of 16, 32 and 64, a ragged last group
@@ -254,7 +255,7 @@ def test_matrix_core_configurations_agree_bitwise(N, p, l_dd, nrhs, monkeypatch)
     u0 = syn.random_complex((nrhs, n), seed=32)
     f = syn.random_complex((nrhs, n), seed=33)
     out = {}
-    n_cfg = 12  # 5 chunked + 7 staged configurations
+    n_cfg = 15  # 5 chunked, 7 staged and 3 two-pass configurations
     for cfg in range(n_cfg):
         monkeypatch.setenv("TH_MFMA_CFG", str(cfg))
         s = make_solver(k, p, l_dd, max_rhs=nrhs, coarse=None, gemm="bf16")
@@ -267,7 +268,7 @@ def test_matrix_core_configurations_agree_bitwise(N, p, l_dd, nrhs, monkeypatch)
         out[cfg] = to_np(u)
         s.close()
     print(f"  configurations run: {sorted(out)}", flush=True)
-    assert 0 in out and len(out) >= 6
+    assert 0 in out and 12 in out and 13 in out and 14 in out and len(out) >= 9
     for cfg, v in out.items():
         assert np.array_equal(v, out[0]), f"configuration {cfg} differs"
 
