@@ -32,16 +32,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense matrix cores
 FP64_PEAK_TFLOPS = 78.6     # matrix and vector
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dd_apply_traffic.json")
-# sources of the batched subdomain apply kernel (its file and the headers it uses)
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2509_17494_amd", "csrc", f)
-               for f in ("k_smoother.hip", "k_slab.hip", "common.hpp", "ctx.hpp")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
-def kernel_sources_sha256():
+def sources_sha256(files):
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()
 
 
@@ -146,18 +143,17 @@ def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes):
     return byts, 8.0 * (g_entries + band_entries) * nrhs
 
 
-def traffic_entry(workload_name):
-    """HBM bytes per dd_apply launch from the committed rocprofv3 counter run,
-    or None when the kernel source changed since the counters were taken."""
+def traffic_entry(key):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE counter runs scaled by
+    a device copy of known size) from the committed summary, or None when the
+    kernel sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
-        d = json.load(open(TRAFFIC_FILE))
-        src_hash = kernel_sources_sha256()
-        e = d.get(workload_name)
-        if not e or e.get("kernel_sha256") != src_hash:
+        e = json.load(open(TRAFFIC_FILE)).get(key)
+        if not e or e.get("kernel_sha256") != sources_sha256(e["sources"]):
             return None
-        return e.get("hbm_bytes_per_launch")
+        return e.get("hbm_bytes_per_launch", e.get("hbm_bytes_per_solve"))
     except Exception:
         return None
 
@@ -414,19 +410,30 @@ def study_table1(wavelengths=16.0, rtol=1e-6):
                       "wavelengths": wavelengths, "rtol": rtol, "iters": part_b}), flush=True)
 
 
-def roofline_hbm(v, kernel, mfma_peak=None):
+def roofline_hbm(v, kernel, mfma_peak=None, traffic_key=None):
     """Roofline object of a variant's smoother application (HBM bound):
     algorithmic bytes per launch over the average launch time from HIP
     events; with mfma_peak, the matrix-core rate of the same launch too."""
     d = v["dd"]
     r = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+         "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+         "traffic": traffic_entry(traffic_key) if traffic_key else None, "kernel": kernel,
          "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": round(d["avg_ms"], 4),
          "launches": d["launches"]}
     if mfma_peak:
         r["mfma_TFLOPs"] = round(d["tflops"], 2)
         r["mfma_frac"] = round(d["tflops"] / mfma_peak, 4)
     return r
+
+
+def mfma_kernel_name(cfg):
+    """The BF16 matrix-core smoother form of an autotuner configuration."""
+    if cfg < 5:
+        return f"k_dd_mfma (persistent, configuration {cfg}; BF16 B_i, FP32 accumulation)"
+    if cfg < 12:
+        return f"k_dd_mfx (staged patch in LDS, configuration {cfg}; BF16 B_i, FP32 accumulation)"
+    return (f"k_mfp_gather + k_mfp_gemm (two-pass, configuration {cfg}; BF16 B_i, FP32 "
+            f"accumulation)")
 
 
 def roofline_fp64(v):
@@ -440,10 +447,11 @@ def roofline_fp64(v):
             "launches": d["launches"]}
 
 
-def coarse_roofline(v):
+def coarse_roofline(v, traffic_key=None):
     c = v["coarse"]
     return {"bound": "hbm", "achieved": round(c["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(c["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic_entry(traffic_key) if traffic_key else None,
             "kernel": "coarse solve (" + c["solver"] + ")",
             "alg_bytes_per_solve": c["bytes_per_solve"], "avg_ms_per_solve": c["avg_ms_per_solve"]}
 
@@ -534,14 +542,18 @@ def main():
         "roofline": roof,
     }
     out["config"]["coarse"] = prim["coarse"]
-    out["coarse_roofline"] = coarse_roofline(prim)
+    out["coarse_roofline"] = coarse_roofline(
+        prim, traffic_key="C2_coarse" if a.workload == "C2" and prim["coarse"]["solver"] ==
+        "nested dissection" else None)
     if not a.no_variants and a.workload == "C2":
         variants = {}
         v_mixed = run_workload("C3", max(3, a.steps), 1, graph=True, timing=False,
                                verbose=a.verbose)
         variants["C3_mixed_bf16_batched64_graph"] = variant_entry(
-            v_mixed, roofline_hbm(v_mixed, "k_dd_mfx (staged matrix-core smoother, BF16 B_i, "
-                                           "FP32 accumulation)", mfma_peak=BF16_PEAK_TFLOPS))
+            v_mixed, roofline_hbm(v_mixed, mfma_kernel_name(v_mixed["info"]["smoother_cfg"]),
+                                  mfma_peak=BF16_PEAK_TFLOPS,
+                                  traffic_key="C3" if v_mixed["info"]["smoother_cfg"] == 12
+                                  else None))
         v_fp64 = run_workload("C3", max(3, a.steps), 1, precond="c128", gemm="f64", graph=False,
                               timing=True, verbose=a.verbose)
         variants["C3_fp64_batched64_control"] = variant_entry(v_fp64, roofline_fp64(v_fp64))
