@@ -54,7 +54,12 @@ constexpr int kGemmK = 16;       // GEMM k-slice staged in LDS
 // Forward step of one tree level.  Task (node, row0): rows row0 .. row0 + 63 of
 // the node's [G; -T] (rows < nI give y_I, written to uc at I; rows nI.. give
 // the node's update vector u = w_B - T w_I).  The W wavefronts split the
-// columns; their partial sums are added in wavefront order.
+// columns; their partial sums are added in wavefront order.  A level is
+// short, so the loads that do not depend on the staged w (the output row's
+// extend-add sources and values, and the first kNDPre columns of every
+// wavefront) are issued before the staging.
+constexpr int kNDPre = 4;
+
 template <int RC, int W>
 __global__ __launch_bounds__(64 * W) void k_nd_fwd(const NDNode *__restrict__ nodes,
                                                    const int2 *__restrict__ tasks,
@@ -74,10 +79,33 @@ __global__ __launch_bounds__(64 * W) void k_nd_fwd(const NDNode *__restrict__ no
   const int q0 = blockIdx.y * RC, nq = min(RC, nrhs - q0);
   const int *I = idx + nd.ioff;
   const int *S = src + nd.soff;
+  const bool live = r < rows;
+  // output side: the vertex of row r (r < nI) or its two extend-add values
+  long long gout = 0;
+  c64 e0[RC], e1[RC];
+  if (wave == 0 && live) {
+    if (r < nd.nI) {
+      gout = I[r];
+    } else {
+      const int s0 = S[2 * r], s1 = S[2 * r + 1];
+#pragma unroll
+      for (int q = 0; q < RC; ++q) {
+        const long long qq = q0 + min(q, nq - 1);
+        e0[q] = s0 >= 0 ? uvec[qq * ulen + s0] : c64{0, 0};
+        e1[q] = s1 >= 0 ? uvec[qq * ulen + s1] : c64{0, 0};
+      }
+    }
+  }
+  const c64 *Mr = M + nd.moff + r;
+  c64 pre[kNDPre];
+#pragma unroll
+  for (int u = 0; u < kNDPre; ++u) {
+    const int j = wave + u * W;
+    pre[u] = (live && j < min(KC, nd.nI)) ? ld_stream(Mr + (long long)j * nd.ldm) : c64{0, 0};
+  }
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = c64{0, 0};
-  const c64 *Mr = M + nd.moff + r;
   for (int c0 = 0; c0 < nd.nI; c0 += KC) {
     const int kc = min(KC, nd.nI - c0);
     if (c0) __syncthreads();
@@ -96,9 +124,18 @@ __global__ __launch_bounds__(64 * W) void k_nd_fwd(const NDNode *__restrict__ no
       ws[q * KC + j] = v;
     }
     __syncthreads();
-    if (r < rows) {
+    if (live) {
+      int j = wave;
+      if (c0 == 0) {
+#pragma unroll
+        for (int u = 0; u < kNDPre; ++u, j += W)
+          if (j < kc) {
+#pragma unroll
+            for (int q = 0; q < RC; ++q) cmac(acc[q], pre[u], ws[q * KC + j]);
+          }
+      }
 #pragma unroll 4
-      for (int j = wave; j < kc; j += W) {
+      for (; j < kc; j += W) {
         const c64 g = ld_stream(Mr + (long long)(c0 + j) * nd.ldm);
 #pragma unroll
         for (int q = 0; q < RC; ++q) cmac(acc[q], g, ws[q * KC + j]);
@@ -112,33 +149,26 @@ __global__ __launch_bounds__(64 * W) void k_nd_fwd(const NDNode *__restrict__ no
     }
     __syncthreads();
   }
-  if (wave != 0 || r >= rows) return;
+  if (wave != 0 || !live) return;
   for (int w = 1; w < W; ++w) {
 #pragma unroll
     for (int q = 0; q < RC; ++q) acc[q] = acc[q] + red[((w - 1) * RC + q) * 64 + lane];
   }
   if (r < nd.nI) {
-    const long long g = I[r];
 #pragma unroll
     for (int q = 0; q < RC; ++q)
-      if (q < nq) uc[(q0 + q) * ncn + g] = acc[q];
+      if (q < nq) uc[(q0 + q) * ncn + gout] = acc[q];
   } else {
-    const int j = r - nd.nI, p = r;
-    const int s0 = S[2 * p], s1 = S[2 * p + 1];
+    const int j = r - nd.nI;
 #pragma unroll
-    for (int q = 0; q < RC; ++q) {
-      if (q >= nq) continue;
-      const long long qq = q0 + q;
-      c64 v = acc[q];
-      if (s0 >= 0) v = v + uvec[qq * ulen + s0];
-      if (s1 >= 0) v = v + uvec[qq * ulen + s1];
-      uvec[qq * ulen + nd.uoff + j] = v;
-    }
+    for (int q = 0; q < RC; ++q)
+      if (q < nq) uvec[(q0 + q) * ulen + nd.uoff + j] = acc[q] + e0[q] + e1[q];
   }
 }
 
 // Backward step of one tree level: x_I = y_I + (-W) x_B for rows row0 ..
-// row0 + 63 of I; x_B read from uc at the node's B vertices (ancestors).
+// row0 + 63 of I; x_B read from uc at the node's B vertices (ancestors).  The
+// row's y_I and the first columns of -W are loaded before x_B is staged.
 template <int RC, int W>
 __global__ __launch_bounds__(64 * W) void k_nd_bwd(const NDNode *__restrict__ nodes,
                                                    const int2 *__restrict__ tasks,
@@ -152,13 +182,27 @@ __global__ __launch_bounds__(64 * W) void k_nd_bwd(const NDNode *__restrict__ no
   const NDNode nd = nodes[tk.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = tk.y + lane;
+  const bool live = i < nd.nI;
   const int q0 = blockIdx.y * RC, nq = min(RC, nrhs - q0);
   const int *I = idx + nd.ioff;
   const int *B = I + nd.nI;
+  long long g = 0;
+  c64 yv[RC];
+  if (wave == 0 && live) {
+    g = I[i];
+#pragma unroll
+    for (int q = 0; q < RC; ++q) yv[q] = uc[(q0 + min(q, nq - 1)) * ncn + g];
+  }
+  const c64 *Wr = Wm + nd.woff + i;
+  c64 pre[kNDPre];
+#pragma unroll
+  for (int u = 0; u < kNDPre; ++u) {
+    const int j = wave + u * W;
+    pre[u] = (live && j < min(KC, nd.nB)) ? ld_stream(Wr + (long long)j * nd.ldw) : c64{0, 0};
+  }
   c64 acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = c64{0, 0};
-  const c64 *Wr = Wm + nd.woff + i;
   for (int c0 = 0; c0 < nd.nB; c0 += KC) {
     const int kc = min(KC, nd.nB - c0);
     if (c0) __syncthreads();
@@ -167,12 +211,21 @@ __global__ __launch_bounds__(64 * W) void k_nd_bwd(const NDNode *__restrict__ no
       ws[q * KC + j] = q < nq ? uc[(q0 + q) * ncn + B[c0 + j]] : c64{0, 0};
     }
     __syncthreads();
-    if (i < nd.nI) {
-#pragma unroll 4
-      for (int j = wave; j < kc; j += W) {
-        const c64 g = ld_stream(Wr + (long long)(c0 + j) * nd.ldw);
+    if (live) {
+      int j = wave;
+      if (c0 == 0) {
 #pragma unroll
-        for (int q = 0; q < RC; ++q) cmac(acc[q], g, ws[q * KC + j]);
+        for (int u = 0; u < kNDPre; ++u, j += W)
+          if (j < kc) {
+#pragma unroll
+            for (int q = 0; q < RC; ++q) cmac(acc[q], pre[u], ws[q * KC + j]);
+          }
+      }
+#pragma unroll 4
+      for (; j < kc; j += W) {
+        const c64 gw = ld_stream(Wr + (long long)(c0 + j) * nd.ldw);
+#pragma unroll
+        for (int q = 0; q < RC; ++q) cmac(acc[q], gw, ws[q * KC + j]);
       }
     }
   }
@@ -183,18 +236,14 @@ __global__ __launch_bounds__(64 * W) void k_nd_bwd(const NDNode *__restrict__ no
     }
     __syncthreads();
   }
-  if (wave != 0 || i >= nd.nI) return;
+  if (wave != 0 || !live) return;
   for (int w = 1; w < W; ++w) {
 #pragma unroll
     for (int q = 0; q < RC; ++q) acc[q] = acc[q] + red[((w - 1) * RC + q) * 64 + lane];
   }
-  const long long g = I[i];
 #pragma unroll
   for (int q = 0; q < RC; ++q)
-    if (q < nq) {
-      c64 *p = uc + (q0 + q) * ncn + g;
-      *p = *p + acc[q];
-    }
+    if (q < nq) uc[(q0 + q) * ncn + g] = yv[q] + acc[q];
 }
 
 // ---------------------------------------------------------------------------

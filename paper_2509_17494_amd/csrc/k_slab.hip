@@ -567,7 +567,25 @@ __device__ __forceinline__ void band_upper(const Sub &s, const cx<TB> *__restric
   }
 }
 
-// Forward step i of the twisted sweep (i < S: the lower chain in blockIdx.y
+// Workgroup -> (subdomain, row block, right-hand-side chunk) of the sweep
+// launches, XCD-aware: workgroup b runs on XCD b % 8, and all row blocks of a
+// subdomain get consecutive b with the same remainder, so the workgroups that
+// each stage the same slab right-hand side (band products included) share one
+// L2.  Returns false for the padding workgroups of the last group.
+struct SweepItem {
+  int si, yb, z;
+};
+__device__ __forceinline__ bool sweep_item(int nsub, int ny, SweepItem &it) {
+  const int b = blockIdx.x, t = b >> 3;
+  const int groups = (nsub + 7) >> 3;
+  it.yb = t % ny;
+  const int g = (t / ny) % groups;
+  it.z = t / (ny * groups);
+  it.si = 8 * g + (b & 7);
+  return it.si < nsub;
+}
+
+// Forward step i of the twisted sweep (i < S: the lower chain in row blocks yb
 // < nyb, the upper chain above; i = S: the middles) for all subdomains and RC
 // right-hand sides: the right-hand side of the slab is formed in LDS by every
 // workgroup of it (band products unrolled, so their loads are issued
@@ -579,14 +597,17 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_slab_fwd(const Sub *__restri
                                                  const cx<TB> *__restrict__ B,
                                                  const cx<T> *__restrict__ Z,
                                                  cx<T> *__restrict__ V, long long xrows,
-                                                 int nrhs, int i, int S, int nyb, int ldx) {
+                                                 int nrhs, int i, int S, int nyb, int ldx,
+                                                 int nsub) {
   constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
   extern __shared__ __align__(16) char slab_smem[];
   cx<T> *x = (cx<T> *)slab_smem;
   cx<T> *red = x;  // the partial sums reuse the staged right-hand side's LDS
-  const Sub s = subs[blockIdx.x];
+  SweepItem it;
+  if (!sweep_item(nsub, i < S ? 2 * nyb : nyb, it)) return;  // uniform
+  const Sub s = subs[it.si];
   const int M = slab_mid(s), U = s.nsl - 1 - M;
-  int t, lo, up, yb = blockIdx.y;
+  int t, lo, up, yb = it.yb;
   if (i == S) {
     t = M;
     lo = M >= 1;
@@ -606,7 +627,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_slab_fwd(const Sub *__restri
   const int m = slab_rows(s, t, P);
   const int a0 = yb * 64;
   if (a0 >= m) return;  // uniform
-  const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
+  const int r0 = it.z * RC, nq = min(RC, nrhs - r0);
   const long long row0 = (long long)t * P * s.lsz;
   const long long vq = (long long)r0 * xrows + s.xoff;
   const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -647,7 +668,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_slab_fwd(const Sub *__restri
 }
 
 // Backward step j of the twisted sweep: the lower chain's slab M - 1 - j in
-// blockIdx.y < nyb, x_t = y_t - E_t w with w = x_{t+1} on the first layer of
+// row blocks yb < nyb, x_t = y_t - E_t w with w = x_{t+1} on the first layer of
 // slab t + 1; the upper chain's slab M + 1 + j above, x_t = y_t - G_t[:, first
 // layer] w with w = A[t][t-1] x_{t-1} (band product).  w is staged in LDS;
 // 64 output rows per workgroup, its kBwdWaves wavefronts splitting the n_layer
@@ -656,14 +677,16 @@ template <typename TB, typename T, int RC, int P, int DIM>
 __global__ __launch_bounds__(64 * kBwdWaves) void k_slab_bwd(const Sub *__restrict__ subs,
                                                  const cx<TB> *__restrict__ B,
                                                  cx<T> *__restrict__ V, long long xrows, int nrhs,
-                                                 int jstep, int nyb, int ldx) {
+                                                 int jstep, int nyb, int ldx, int nsub) {
   constexpr int W2 = 2 * P + 1, CB = (DIM == 3 ? W2 * W2 : W2) * P;
   extern __shared__ __align__(16) char slab_smem[];
   cx<T> *w = (cx<T> *)slab_smem;
   cx<T> *red = w;  // the partial sums reuse the staged right-hand side's LDS
-  const Sub s = subs[blockIdx.x];
+  SweepItem it;
+  if (!sweep_item(nsub, 2 * nyb, it)) return;  // uniform
+  const Sub s = subs[it.si];
   const int M = slab_mid(s), U = s.nsl - 1 - M;
-  int yb = blockIdx.y;
+  int yb = it.yb;
   const bool upper = yb >= nyb;
   if (upper) yb -= nyb;
   if (upper ? jstep >= U : jstep >= M) return;  // uniform
@@ -671,7 +694,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_slab_bwd(const Sub *__restri
   const int m = slab_rows(s, t, P), nl = s.lsz;
   const int a0 = yb * 64;
   if (a0 >= m) return;  // uniform
-  const int r0 = blockIdx.z * RC, nq = min(RC, nrhs - r0);
+  const int r0 = it.z * RC, nq = min(RC, nrhs - r0);
   const long long vq = (long long)r0 * xrows + s.xoff;
   const long long row0 = (long long)t * P * s.lsz;
   for (int c = threadIdx.x; c < nl; c += 64 * kBwdWaves) {
@@ -738,15 +761,16 @@ static int slab_sweeps_pd(const th_ctx *c, int nrhs, hipStream_t s) {
   const unsigned nz = (unsigned)ceil_div(nrhs, RC);
   const int S = c->max_nsl / 2;  // chain steps: the longest upper chain
   const cx<TB> *B = (const cx<TB> *)c->d_B;
+  const unsigned groups8 = 8 * (unsigned)ceil_div((int)nsub, 8);  // XCD-aware 1-D grids
   for (int i = 0; i <= S; ++i)
     hipLaunchKernelGGL((k_slab_fwd<TB, T, RC, P, DIM>),
-                       dim3(nsub, (unsigned)(i < S ? 2 * nyb : nyb), nz), dim3(64 * kFwdWaves), shm, s,
-                       c->d_subs, B, (const cx<T> *)c->w_x, (cx<T> *)c->w_z, c->x_rows, nrhs, i,
-                       S, nyb, ldx);
+                       dim3(groups8 * (unsigned)(i < S ? 2 * nyb : nyb) * nz), dim3(64 * kFwdWaves),
+                       shm, s, c->d_subs, B, (const cx<T> *)c->w_x, (cx<T> *)c->w_z, c->x_rows, nrhs,
+                       i, S, nyb, ldx, (int)nsub);
   for (int j = 0; j < S; ++j)
-    hipLaunchKernelGGL((k_slab_bwd<TB, T, RC, P, DIM>), dim3(nsub, (unsigned)(2 * nyb), nz),
-                       dim3(64 * kBwdWaves), shm, s, c->d_subs, B, (cx<T> *)c->w_z, c->x_rows, nrhs, j, nyb,
-                       ldx);
+    hipLaunchKernelGGL((k_slab_bwd<TB, T, RC, P, DIM>), dim3(groups8 * (unsigned)(2 * nyb) * nz),
+                       dim3(64 * kBwdWaves), shm, s, c->d_subs, B, (cx<T> *)c->w_z, c->x_rows, nrhs, j,
+                       nyb, ldx, (int)nsub);
   return 0;
 }
 
