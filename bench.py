@@ -107,10 +107,11 @@ def subdomain_sizes(N, p, l_dd, dim=2):
     return out
 
 
-def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes):
+def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes, packed=False):
     """Algorithmic bytes and flops of one application in the slab-factor
     layout with the twisted elimination (middle slab M = (nsl - 1) // 2):
-    every stored G_t read by the forward sweep; the backward sweep reads E_t
+    every G_t read by the forward sweep (whole, or with packed storage its
+    m (m + 1) / 2 distinct entries, G_t being symmetric); the backward sweep reads E_t
     (rows of slab t x first layer of t + 1) for the lower slabs t < M and the
     first-layer rows of G_t for the upper slabs t > M; the coupling bands of
     slabs 1 .. nsl - 1 once in the forward sweep and those of the upper slabs
@@ -126,7 +127,7 @@ def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes):
         starts.append(starts[-1] + x)
     ocells = [min(starts[b + 1] + 1, N) - max(starts[b] - 1, 0) for b in range(M)]
     cb = ((2 * p + 1) ** (dim - 1)) * p
-    g_entries, band_entries, vec = 0, 0, 0
+    g_entries, band_entries, vec, mul_entries = 0, 0, 0, 0
     for idx in itertools.product(range(M), repeat=dim):
         no = [ocells[b] * p + 1 for b in idx]      # x first
         nu = [sizes[b] * p + 1 for b in idx]
@@ -134,13 +135,17 @@ def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes):
         m, ml = p * lsz, (p + 1) * lsz
         mid = (nsl - 1) // 2
         nup = nsl - 1 - mid
-        g_entries += (nsl - 1) * m * m + ml * ml            # G_t, forward
+        full = (nsl - 1) * m * m + ml * ml                   # G_t, forward
+        g_entries += (nsl - 1) * m * (m + 1) // 2 + ml * (ml + 1) // 2 if packed else full
+        mul_entries += full - ((nsl - 1) * m * (m + 1) // 2 + ml * (ml + 1) // 2 if packed else full)
         g_entries += mid * m * lsz                           # E_t, lower chain
         g_entries += (nup - 1) * m * lsz + ml * lsz if nup else 0  # G_t rows, upper chain
         band_entries += (nsl - 1 + nup) * lsz * cb
         vec += math.prod(no) + math.prod(nu)
     byts = (g_entries + band_entries) * mat_bytes + vec * vec_bytes * nrhs
-    return byts, 8.0 * (g_entries + band_entries) * nrhs
+    # flops: every entry of every G_t multiplies once (a stored off-diagonal
+    # entry of a packed G_t twice)
+    return byts, 8.0 * (g_entries + mul_entries + band_entries) * nrhs
 
 
 def traffic_entry(key):
@@ -320,7 +325,8 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
     alg = dd_apply_bytes(subs, R, mat_bytes, vec_bytes, symmetric=sym)
     flops = 8.0 * sum(nu * no for nu, no in subs) * R
     if info["smoother_layout"] == 3:
-        alg, flops = slab_apply_bytes(N, p, spec["l_dd"], dim, R, mat_bytes, vec_bytes)
+        alg, flops = slab_apply_bytes(N, p, spec["l_dd"], dim, R, mat_bytes, vec_bytes,
+                                      packed=bool(info["slab_packed"]))
     dd_ms, dd_n = kt["dd_apply"]
     avg_ms = dd_ms / max(dd_n, 1)
     # coarse solve: one per two-grid cycle; bytes streamed per solve by the

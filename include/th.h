@@ -204,6 +204,10 @@ typedef struct {
                              solve with the factors and a stencil residual) */
   double coarse_check;    /* max |A_c^{-1} (A_c x) - x| over the coarse vertices for the setup
                              probe x (unit-modulus entries) */
+  int slab_packed;        /* slab factors: 1 when each symmetric G_t is stored once (the lower
+                             block triangle as skewed 64 x 64 tiles plus a dense strip of its
+                             last m mod 64 rows), 0 when stored whole; the environment variable
+                             TH_SLAB_PACKED=0 or 1 at setup overrides the choice */
 } th_info;
 
 /* Create a context on HIP device `hip_device`, ordering work on `hip_stream`

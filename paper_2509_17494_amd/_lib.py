@@ -56,7 +56,8 @@ class Info(C.Structure):
                 ("n_fallback_cells", C.c_int), ("t_stencil_s", C.c_double),
                 ("smoother_layout", C.c_int), ("coarse_solver", C.c_int),
                 ("coarse_levels", C.c_int), ("coarse_refine", C.c_int),
-                ("coarse_check", C.c_double)]
+                ("coarse_check", C.c_double),
+                ("slab_packed", C.c_int)]
 
 
 _lib = None

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -132,6 +133,7 @@ static void free_fine(th_ctx *c) {
   c->mfx_max_nrb = 0;
   c->mfx_ok = false;
   c->max_nsl = c->max_slab_rows = 0;
+  c->slab_pk = 0;
   c->fine_ready = false;
 }
 
@@ -273,6 +275,7 @@ th_status th_get_info(const th_ctx *ctx, th_info *info) {
   info->coarse_levels = ctx->coarse.nd.levels;
   info->coarse_refine = ctx->coarse.nd.refine;
   info->coarse_check = ctx->coarse.check_err;
+  info->slab_packed = ctx->layout == 3 ? ctx->slab_pk : 0;
   return TH_OK;
 }
 
@@ -423,14 +426,42 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
   // G_t, bands, E_t; stored rows padded to a multiple of 8 entries, regions
   // kept on 128-byte boundaries
   auto pad8 = [](long long x) { return (x + 7) & ~7LL; };
+  // Packed G_t (each symmetric G_t stored once: skewed 64 x 64 tiles of the
+  // lower block triangle plus a dense strip of the last m mod 64 rows) when
+  // the largest slab is one work unit of the packed forward sweep and its LDS
+  // holds a chunk of min(max_rhs, 4) FP64 right-hand sides (TH_SLAB_PACKED=0
+  // or 1 overrides: whole G_t, or packed with one right-hand side per chunk).
+  {
+    int max_lsz = 0;
+    for (const Sub &s : c->subs) max_lsz = std::max(max_lsz, s.lsz);
+    const long long ml = (long long)(P + 1) * max_lsz;
+    const int rc = d->max_rhs >= 4 ? 4 : (d->max_rhs >= 2 ? 2 : 1);
+    auto lds = [&](int r) {
+      return (size_t)std::max<long long>(2 * ml + 512 * ((ml + 63) / 64), 512) * r * sizeof(c64);
+    };
+    const char *env = std::getenv("TH_SLAB_PACKED");
+    const bool want = env ? std::atoi(env) != 0 : true;
+    c->slab_pk = want && ml <= slab_pk_max_rows() &&
+                 lds(env ? 1 : rc) <= kSlabPkLds;
+  }
+  auto pk_size = [](long long m) {
+    const long long nf = m / 64;
+    return 64 * (33 * nf + 32 * nf * (nf - 1)) + (m - 64 * nf) * ((m + 7) & ~7LL);
+  };
   auto slab_g = [&](const Sub &s) {
     const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
+    if (c->slab_pk) return (long long)(s.nsl - 1) * pk_size(m) + pk_size(ml);
     return (long long)(s.nsl - 1) * m * pad8(m) + ml * pad8(ml);
   };
   auto slab_bands = [&](const Sub &s) { return pad8((long long)(s.nsl - 1) * s.lsz * cband); };
-  // E_t of the lower chain of the twisted elimination: slabs 0 .. (nsl - 1) / 2 - 1
+  // E_t of the lower chain of the twisted elimination (slabs 0 .. (nsl - 1) / 2 - 1);
+  // packed: also G_t[:, first layer] of the upper chain, indexed by slab
   auto slab_elems = [&](const Sub &s) {
-    return slab_g(s) + slab_bands(s) + (long long)((s.nsl - 1) / 2) * s.lsz * pad8((long long)P * s.lsz);
+    const long long m = (long long)P * s.lsz, ml = (long long)(P + 1) * s.lsz;
+    if (c->slab_pk)
+      return slab_g(s) + slab_bands(s) + (long long)(s.nsl - 1) * s.lsz * pad8(m) +
+             s.lsz * pad8(ml);
+    return slab_g(s) + slab_bands(s) + (long long)((s.nsl - 1) / 2) * s.lsz * pad8(m);
   };
   {
     long long dense = 0, sym = 0, slab = 0;
@@ -464,6 +495,7 @@ th_status th_setup_fine(th_ctx *ctx, const th_fine_desc *d) {
       c->layout = 3;
     else
       c->layout = slab_fits && t_slab < t_rows ? 3 : rows;
+    if (c->layout != 3) c->slab_pk = 0;
   }
   std::vector<int> eidx;
   long long poff = 0, xoff = 0;

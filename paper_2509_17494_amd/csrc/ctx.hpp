@@ -180,6 +180,7 @@ struct th_ctx {
   int dir = 0;                 // bit s: Dirichlet on global side s
   int max_nsl = 0;             // slab layout: most slabs of a subdomain
   int max_slab_rows = 0;       // slab layout: largest slab
+  int slab_pk = 0;             // slab layout: G_t stored packed (lower block triangle)
   void *w_z = nullptr;         // slab layout: per-subdomain solutions [R][x_rows]
   int M = 0;                   // blocks per direction
   std::vector<int> blk_start;  // M+1 cell starts
@@ -293,6 +294,11 @@ int dd_mfma64_rhs_pad(int max_rhs);
 // k_slab.hip: the slab-factor layout (apply, and its setup from the assembled
 // subdomain matrices of one batch)
 int launch_dd_slab(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);
+// packed slab factors: LDS bytes of the forward sweep for rhs_bytes bytes of
+// right-hand sides per row (at most kSlabPkLds), and the largest slab
+constexpr size_t kSlabPkLds = 64 * 1024;
+size_t slab_pk_lds(const th_ctx *c, size_t rhs_bytes);
+int slab_pk_max_rows();
 int setup_slab_factors(th_ctx *c, int s0, int nb, const c64 *A, int npad, long long amat,
                        c64 *const W[3], c64 *T1, int ldw, int ldt, c64 *pws, hipStream_t s);
 int launch_dd_accumulate(const th_ctx *c, const void *y, void *u, int nrhs, bool f32, bool assign,

@@ -25,6 +25,9 @@
 // with one launch per step for all subdomains and both chains: about n + 1
 // launches instead of 2n - 1 for the one-sided elimination.  The chains of
 // all subdomains are aligned so that they reach their middles at the same step.
+// With G_t stored packed (each symmetric G_t once, k_slab_pk.hip) the sweeps
+// take three launches instead: every chain's forward sweep, the middles, every
+// chain's backward sweep.
 //
 // Stored per subdomain: every G_t transposed (entry (b, a) at b ld_t + a, rows
 // padded to ld_t, a multiple of 8 entries, so one output row per thread reads
@@ -37,7 +40,7 @@
 // lower chain and transposed by the upper one; and the E_t of the lower chain (m_t x n_layer, the product the
 // elimination forms anyway) transposed, likewise padded.  The upper chain's
 // backward step reads the first n_layer rows of the stored G_t^T (G_t is
-// symmetric).  The bytes per application are the G_t plus a fraction 1/P of
+// symmetric); with packed G_t those rows are stored apart, beside the E_t.  The bytes per application are the G_t plus a fraction 1/P of
 // them, instead of the n_U x n_Omega rows of an explicit inverse.
 //
 // Elimination without pivoting is stable here for the reason given for the
@@ -48,78 +51,9 @@
 // the corrected rows first, as it does in the lower chain.
 #include <algorithm>
 
-#include "ctx.hpp"
+#include "k_slab.hpp"
 
 namespace th {
-
-__host__ __device__ __forceinline__ int slab_rows(const Sub &s, int t, int P) {
-  return (t < s.nsl - 1 ? P : P + 1) * s.lsz;
-}
-
-__host__ __device__ __forceinline__ int slab_ld(int m) { return (m + 7) & ~7; }
-
-// entries of the G_t of slabs before t (all of them have P layers)
-__host__ __device__ __forceinline__ long long slab_goff(const Sub &s, int t, int P) {
-  const int m = P * s.lsz;
-  return s.boff + (long long)t * m * slab_ld(m);
-}
-
-__host__ __device__ __forceinline__ int band_width(int P, int dim) {
-  return (dim == 3 ? (2 * P + 1) * (2 * P + 1) : (2 * P + 1)) * P;
-}
-
-// middle slab of the twisted elimination; the lower chain has slab_mid
-// slabs, the upper chain nsl - 1 - slab_mid
-__host__ __device__ __forceinline__ int slab_mid(const Sub &s) { return (s.nsl - 1) / 2; }
-
-enum { kLowerChain = 0, kUpperChain = 1, kMiddle = 2 };
-
-// The slab t of subdomain s at step i of a chain of n aligned steps (lower
-// slab t at step t + n - D, upper slab nsl - 1 - j at step j + n - U), or the
-// middle.  on: the subdomain has a slab at this step; lo / up: the correction
-// from the lower (t - 1) / upper (t + 1) neighbour applies; rev: the block is
-// handled in reversed node order during setup.
-struct SlabRole {
-  int t, on, lo, up, rev;
-};
-
-__host__ __device__ __forceinline__ SlabRole slab_role(const Sub &s, int mode, int i, int n) {
-  const int M = slab_mid(s), U = s.nsl - 1 - M;
-  SlabRole r;
-  if (mode == kLowerChain) {
-    r.t = i - (n - M);
-    r.on = r.t >= 0;
-    r.lo = r.t >= 1;
-    r.up = 0;
-    r.rev = 0;
-  } else if (mode == kUpperChain) {
-    const int j = i - (n - U);
-    r.t = s.nsl - 1 - j;
-    r.on = j >= 0;
-    r.lo = 0;
-    r.up = j >= 1;
-    r.rev = 1;
-  } else {
-    r.t = M;
-    r.on = 1;
-    r.lo = M >= 1;
-    r.up = U >= 1;
-    r.rev = 0;
-  }
-  return r;
-}
-
-// Omega-local index of band entry k of first-layer node a of slab t (t >= 1),
-// or -1 outside Omega.  k = ((jy (2P+1)) + jx) P + lb; the node sits at
-// in-layer position (xa - P + jx, ya - P + jy) in layer (t - 1) P + lb.
-__device__ __forceinline__ int band_col(const Sub &s, int t, int a, int k, int P, int dim) {
-  const int lb = k % P, j = k / P;
-  const int jx = j % (2 * P + 1), jy = j / (2 * P + 1);
-  const int xa = a % s.nox, ya = dim == 3 ? a / s.nox : 0;
-  const int xb = xa - P + jx, yb = dim == 3 ? ya - P + jy : 0;
-  if (xb < 0 || xb >= s.nox || yb < 0 || (dim == 3 && yb >= s.noy)) return -1;
-  return ((t - 1) * P + lb) * s.lsz + yb * s.nox + xb;
-}
 
 // ---------------------------------------------------------------------------
 // setup (FP64), batched over subdomains s0 .. s0 + gridDim.z - 1; every
@@ -245,30 +179,67 @@ __global__ __launch_bounds__(256) void k_slab_schur_up(const Sub *__restrict__ s
   w = w - acc;
 }
 
-// store G_t (W, reversed when rev) transposed with rows padded to slab_ld
-// and, for t >= 1, the coupling band of slab t
+// store G_t (W, reversed when rev) transposed with rows padded to slab_ld,
+// or packed (pk); with pk, the upper chain also stores G_t[:, first layer]
+// transposed (n_layer rows of slab_ld(m) entries) in the backward region,
+// which its backward step reads; for t >= 1, the coupling band of slab t
 template <typename TB>
 __global__ __launch_bounds__(256) void k_slab_store(const Sub *__restrict__ subs, int s0,
                                                     const c64 *__restrict__ A, int lda,
                                                     long long amat, const c64 *__restrict__ W,
                                                     int ldw, long long wmat,
                                                     cx<TB> *__restrict__ B, int mode, int i, int n,
-                                                    int P, int dim) {
+                                                    int P, int dim, int pk) {
   const Sub s = subs[s0 + blockIdx.z];
   const SlabRole sr = slab_role(s, mode, i, n);
   if (!sr.on) return;
   const int t = sr.t;
   const int m = slab_rows(s, t, P);
-  const long long e = blockIdx.x * 256LL + threadIdx.x;
-  const long long ng = (long long)m * m;
-  const int cb = band_width(P, dim);
-  if (e < ng) {
-    const int b = (int)(e / m), a = (int)(e % m);
+  long long e = blockIdx.x * 256LL + threadIdx.x;
+  const c64 *w = W + blockIdx.z * wmat;
+  // G_t[a][b] in natural order
+  auto g = [&](int a, int b) {
     const int wa = sr.rev ? m - 1 - a : a, wb = sr.rev ? m - 1 - b : b;
-    const c64 v = W[blockIdx.z * wmat + (long long)wa * ldw + wb];
-    B[slab_goff(s, t, P) + (long long)b * slab_ld(m) + a] = cx<TB>{(TB)v.re, (TB)v.im};
-  } else if (t >= 1 && e < ng + (long long)s.lsz * cb) {
-    const long long f = e - ng;
+    const c64 v = w[(long long)wa * ldw + wb];
+    return cx<TB>{(TB)v.re, (TB)v.im};
+  };
+  const int cb = band_width(P, dim);
+  if (pk) {
+    const int nf = m / 64;
+    const long long nt = 64 * pk_tile_steps(nf), ng = pk_elems(m);
+    if (e < nt) {
+      int R, C, k;
+      pk_step(nf, e / 64, R, C, k);
+      const int l = (int)(e % 64);
+      B[pk_goff(s, t, P) + e] = g(64 * R + ((l + k) & 63), 64 * C + l);
+      return;
+    }
+    if (e < ng) {
+      const long long f = e - nt;
+      const int j = (int)(f / slab_ld(m)), b = (int)(f % slab_ld(m));
+      B[pk_goff(s, t, P) + e] = b < m ? g(64 * nf + j, b) : cx<TB>{0, 0};
+      return;
+    }
+    e -= ng;
+    const long long nfl = mode == kUpperChain ? (long long)s.lsz * m : 0;
+    if (e < nfl) {
+      const int c = (int)(e / m), a = (int)(e % m);
+      const long long off = s.ecoff + (long long)t * s.lsz * slab_ld(P * s.lsz);
+      B[off + (long long)c * slab_ld(m) + a] = g(a, c);
+      return;
+    }
+    e -= nfl;
+  } else {
+    const long long ng = (long long)m * m;
+    if (e < ng) {
+      const int b = (int)(e / m), a = (int)(e % m);
+      B[slab_goff(s, t, P) + (long long)b * slab_ld(m) + a] = g(a, b);
+      return;
+    }
+    e -= ng;
+  }
+  if (t >= 1 && e < (long long)s.lsz * cb) {
+    const long long f = e;
     const int a = (int)(f / cb), k = (int)(f % cb);
     const int col = band_col(s, t, a, k, P, dim);
     const long long r0 = (long long)t * P * s.lsz;
@@ -338,15 +309,17 @@ static int slab_setup_step(th_ctx *c, int s0, int nb, const c64 *A, int npad, lo
   TH_HIP_CHECK_RET(hipGetLastError());
   int rc = gj_invert_batched(W, ldw, ldw, wmat, nb, s, pws);
   if (rc) return rc;
-  const long long nst = (long long)max_m * max_m + max_lsz * band_width(P, c->dim);
+  // G_t (whole or packed), G_t[:, first layer] (packed, upper chain), band
+  const long long nst = (long long)max_m * slab_ld(max_m) + (long long)max_lsz * max_m +
+                        (long long)max_lsz * band_width(P, c->dim);
   if (f32)
     hipLaunchKernelGGL((k_slab_store<float>), dim3((unsigned)ceil_div_ll(nst, 256), 1, nb),
                        dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)W, ldw, wmat,
-                       (cx<float> *)c->d_B, mode, i, n, P, c->dim);
+                       (cx<float> *)c->d_B, mode, i, n, P, c->dim, c->slab_pk);
   else
     hipLaunchKernelGGL((k_slab_store<double>), dim3((unsigned)ceil_div_ll(nst, 256), 1, nb),
                        dim3(256), 0, s, c->d_subs, s0, A, npad, amat, (const c64 *)W, ldw, wmat,
-                       (cx<double> *)c->d_B, mode, i, n, P, c->dim);
+                       (cx<double> *)c->d_B, mode, i, n, P, c->dim, c->slab_pk);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
@@ -489,102 +462,6 @@ __device__ __forceinline__ bool slab_sum_waves(cx<T> (&acc)[RC], cx<T> *__restri
   return true;
 }
 
-// acc[q] = sum over the band of first-layer node j of slab t (t >= 1) of
-// A[t][t-1] times v[slab t - 1] (vb: offset of slab t - 1 of right-hand side
-// r0).  Branch-free: positions outside Omega are clamped to a node inside
-// (its value is finite) and meet a zero band coefficient, so every load can
-// be issued before its use.
-template <typename TB, typename T, int RC, int P, int DIM>
-__device__ __forceinline__ void band_lower(const Sub &s, const cx<TB> *__restrict__ Ct,
-                                           const cx<T> *__restrict__ V, long long vb,
-                                           long long xrows, int nq, int j, cx<T> (&acc)[RC]) {
-  constexpr int W2 = 2 * P + 1;
-  const int xa = j % s.nox, ya = DIM == 3 ? j / s.nox : 0;
-  const cx<TB> *cr = Ct + j;
-#pragma unroll
-  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-#pragma unroll
-  for (int jy = 0; jy < (DIM == 3 ? W2 : 1); ++jy) {
-    const int yb = DIM == 3 ? min(max(ya - P + jy, 0), s.noy - 1) : 0;
-#pragma unroll
-    for (int jx = 0; jx < W2; ++jx) {
-      const int xb = min(max(xa - P + jx, 0), s.nox - 1);
-      cx<TB> l[P];
-      cx<T> y[P][RC];
-#pragma unroll
-      for (int lb = 0; lb < P; ++lb) {
-        l[lb] = cr[(long long)((jy * W2 + jx) * P + lb) * s.lsz];
-#pragma unroll
-        for (int q = 0; q < RC; ++q)
-          y[lb][q] = V[vb + (long long)min(q, nq - 1) * xrows + lb * s.lsz + yb * s.nox + xb];
-      }
-#pragma unroll
-      for (int lb = 0; lb < P; ++lb)
-#pragma unroll
-        for (int q = 0; q < RC; ++q) cmac(acc[q], ccast<T>(l[lb]), y[lb][q]);
-    }
-  }
-}
-
-// acc[q] = (A[t][t+1] v[first layer of t + 1])[j] for node j of slab t
-// (t + 1 <= nsl - 1, so slab t has P layers): the band of slab t + 1 read
-// transposed, node j in layer lb couples to the first-layer nodes a within P
-// positions, through band entry ((2P - jy') (2P+1) + 2P - jx') P + lb of a,
-// where a sits at (xj - P + jx', yj - P + jy').  Cn: band of slab t + 1, vn:
-// offset of its first layer.  Out-of-range a are clamped and their
-// coefficient replaced by zero.
-template <typename TB, typename T, int RC, int P, int DIM>
-__device__ __forceinline__ void band_upper(const Sub &s, const cx<TB> *__restrict__ Cn,
-                                           const cx<T> *__restrict__ V, long long vn,
-                                           long long xrows, int nq, int j, cx<T> (&acc)[RC]) {
-  constexpr int W2 = 2 * P + 1;
-  const int lb = j / s.lsz, jj = j - lb * s.lsz;
-  const int xj = jj % s.nox, yj = DIM == 3 ? jj / s.nox : 0;
-#pragma unroll
-  for (int q = 0; q < RC; ++q) acc[q] = {0, 0};
-#pragma unroll
-  for (int jy = 0; jy < (DIM == 3 ? W2 : 1); ++jy) {
-    const int ya = DIM == 3 ? yj - P + jy : 0;
-    const bool iny = DIM == 3 ? (ya >= 0 && ya < s.noy) : true;
-    const int yac = DIM == 3 ? min(max(ya, 0), s.noy - 1) : 0;
-    cx<TB> l[W2];
-    cx<T> y[W2][RC];
-#pragma unroll
-    for (int jx = 0; jx < W2; ++jx) {
-      const int xa = xj - P + jx;
-      const int xac = min(max(xa, 0), s.nox - 1);
-      const int a = yac * s.nox + xac;
-      const int k = (((DIM == 3 ? 2 * P - jy : 0) * W2) + 2 * P - jx) * P + lb;
-      l[jx] = Cn[(long long)k * s.lsz + a];
-      if (!(iny && xa >= 0 && xa < s.nox)) l[jx] = cx<TB>{0, 0};
-#pragma unroll
-      for (int q = 0; q < RC; ++q) y[jx][q] = V[vn + (long long)min(q, nq - 1) * xrows + a];
-    }
-#pragma unroll
-    for (int jx = 0; jx < W2; ++jx)
-#pragma unroll
-      for (int q = 0; q < RC; ++q) cmac(acc[q], ccast<T>(l[jx]), y[jx][q]);
-  }
-}
-
-// Workgroup -> (subdomain, row block, right-hand-side chunk) of the sweep
-// launches, XCD-aware: workgroup b runs on XCD b % 8, and all row blocks of a
-// subdomain get consecutive b with the same remainder, so the workgroups that
-// each stage the same slab right-hand side (band products included) share one
-// L2.  Returns false for the padding workgroups of the last group.
-struct SweepItem {
-  int si, yb, z;
-};
-__device__ __forceinline__ bool sweep_item(int nsub, int ny, SweepItem &it) {
-  const int b = blockIdx.x, t = b >> 3;
-  const int groups = (nsub + 7) >> 3;
-  it.yb = t % ny;
-  const int g = (t / ny) % groups;
-  it.z = t / (ny * groups);
-  it.si = 8 * g + (b & 7);
-  return it.si < nsub;
-}
-
 // Forward step i of the twisted sweep (i < S: the lower chain in row blocks yb
 // < nyb, the upper chain above; i = S: the middles) for all subdomains and RC
 // right-hand sides: the right-hand side of the slab is formed in LDS by every
@@ -697,6 +574,18 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_slab_bwd(const Sub *__restri
   const int r0 = it.z * RC, nq = min(RC, nrhs - r0);
   const long long vq = (long long)r0 * xrows + s.xoff;
   const long long row0 = (long long)t * P * s.lsz;
+  const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int cq = (nl + kBwdWaves - 1) / kBwdWaves;
+  const int ld = slab_ld(m);
+  // lower: E_t^T; upper: the first n_layer rows of G_t^T
+  const cx<TB> *g = upper ? B + slab_goff(s, t, P) : B + s.ecoff + (long long)t * nl * ld;
+  const int c0 = min(wave * cq, nl), c1 = min((wave + 1) * cq, nl);
+  // the rows and y_t do not depend on w: their loads go out before w is formed
+  cx<T> ga[kRowsAhead], yo[RC];
+  slab_rows_ahead<TB, T>(g + min(a, ld - 1), ld, c0, c1, ga);
+#pragma unroll
+  for (int q = 0; q < RC; ++q)
+    yo[q] = q < nq && a < m ? V[vq + (long long)q * xrows + row0 + a] : cx<T>{0, 0};
   for (int c = threadIdx.x; c < nl; c += 64 * kBwdWaves) {
     cx<T> v[RC];
     if (upper) {
@@ -712,20 +601,12 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_slab_bwd(const Sub *__restri
     for (int q = 0; q < RC; ++q) w[c * RC + q] = v[q];
   }
   __syncthreads();
-  const int a = a0 + threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int cq = (nl + kBwdWaves - 1) / kBwdWaves;
-  const int ld = slab_ld(m);
-  const cx<TB> *g = upper ? B + slab_goff(s, t, P) : B + s.ecoff + (long long)t * nl * ld;
   cx<T> acc[RC];
-  slab_gemv_row<TB, T, RC>(g + min(a, ld - 1), ld, min(wave * cq, nl), min((wave + 1) * cq, nl), w,
-                           acc);
+  slab_gemv_ahead<TB, T, RC>(g + min(a, ld - 1), ld, c0, c1, ga, w, acc);
   if (!slab_sum_waves<T, RC, kBwdWaves>(acc, red) || a >= m) return;
 #pragma unroll
   for (int q = 0; q < RC; ++q)
-    if (q < nq) {
-      cx<T> &o = V[vq + (long long)q * xrows + row0 + a];
-      o = o - acc[q];
-    }
+    if (q < nq) V[vq + (long long)q * xrows + row0 + a] = yo[q] - acc[q];
 }
 
 // Y_i[j] = x[U node j] / L_j
@@ -800,7 +681,13 @@ static int slab_apply_t(const th_ctx *c, const void *r, void *y, int nrhs, hipSt
                      c->x_rows);
   const size_t row_bytes = slab_lds_rows(c) * sizeof(cx<T>);
   int rc;
-  if (nrhs >= 4 && 4 * row_bytes <= 48 * 1024)
+  if (c->slab_pk) {
+    // packed: the largest chunk whose LDS fits in 64 KiB (two workgroups
+    // per compute unit)
+    auto fits = [&](int r) { return slab_pk_lds(c, r * sizeof(cx<T>)) <= kSlabPkLds; };
+    rc = slab_pk_sweeps<TB, T>(c, nrhs, nrhs >= 4 && fits(4) ? 4 : (nrhs >= 2 && fits(2) ? 2 : 1),
+                               s);
+  } else if (nrhs >= 4 && 4 * row_bytes <= 48 * 1024)
     rc = slab_sweeps_t<TB, T, 4>(c, nrhs, s);
   else if (nrhs >= 2 && 2 * row_bytes <= 48 * 1024)
     rc = slab_sweeps_t<TB, T, 2>(c, nrhs, s);

@@ -52,12 +52,17 @@ CASES_2D = [(19, 4, 6), (33, 4, 8), (7, 6, 3), (5, 8, 2), (37, 2, 8), (12, 2, 5)
             (1, 4, 1), (1, 2, 1)]
 
 
+@pytest.mark.parametrize("packed", ["1", "0"])
 @pytest.mark.parametrize("N,p,l_dd", CASES_2D)
-def test_smooth_slab_2d(N, p, l_dd):
-    print(f"case slab smooth N={N} p={p} l_dd={l_dd}", flush=True)
+def test_smooth_slab_2d(N, p, l_dd, packed, monkeypatch):
+    """Both storages of G_t: packed (lower block triangle as skewed tiles and
+    a dense strip; slabs of fewer than 64 rows are all strip) and whole."""
+    print(f"case slab smooth N={N} p={p} l_dd={l_dd} packed={packed}", flush=True)
+    monkeypatch.setenv("TH_SLAB_PACKED", packed)
     k = medium(N, p, 2, seed=N)
     sm = CSDDSmoother(p, k, None, 0.5, l_dd)
     s = solver(k, p, l_dd, max_rhs=3, coarse=None)
+    assert s.info()["slab_packed"] == int(packed)
     u0 = syn.random_complex((3, sm.n_nodes), seed=1)
     f = syn.random_complex((3, sm.n_nodes), seed=2)
     ref = np.stack([sm.apply(u0[i], f[i]) for i in range(3)])
@@ -90,12 +95,20 @@ def test_smooth_slab_ndd2_neumann_and_f32():
     s32.close()
 
 
-@pytest.mark.parametrize("N,p,l_dd", [(6, 2, 3), (5, 4, 2), (7, 2, 4)])
-def test_smooth_slab_3d(N, p, l_dd):
-    print(f"case slab smooth 3-D N={N} p={p}", flush=True)
+@pytest.mark.parametrize("N,p,l_dd,packed", [(6, 2, 3, "1"), (6, 2, 3, "0"), (5, 4, 2, None),
+                                              (7, 2, 4, None)])
+def test_smooth_slab_3d(N, p, l_dd, packed, monkeypatch):
+    """3-D slabs; (6, 2, 3) also with packed G_t (slabs of 162 and 243 rows:
+    two and three 64-row blocks of tiles, strips of 34 and 51 rows; one
+    right-hand side per chunk)."""
+    print(f"case slab smooth 3-D N={N} p={p} packed={packed}", flush=True)
+    if packed is not None:
+        monkeypatch.setenv("TH_SLAB_PACKED", packed)
     k = medium(N, p, 3, seed=N + 1)
     sm = CSDDSmoother(p, k, None, 0.5, l_dd)
     s = solver(k, p, l_dd, max_rhs=2, coarse=None)
+    if packed is not None:
+        assert s.info()["slab_packed"] == int(packed)
     u0 = syn.random_complex((2, sm.n_nodes), seed=6)
     f = syn.random_complex((2, sm.n_nodes), seed=7)
     ref = np.stack([sm.apply(u0[i], f[i]) for i in range(2)])
