@@ -353,7 +353,8 @@ def run_workload(name, steps, warmup, precond=None, graph=False, timing=True, ve
                "gbs": alg / (avg_ms * 1e-3) / 1e9, "tflops": flops / (avg_ms * 1e-3) / 1e12},
         "coarse": {"solver": {1: "lines", 2: "nested dissection"}[info["coarse_solver"]],
                    "levels": info["coarse_levels"], "refine_steps": refine,
-                   "probe_error": info["coarse_check"], "factor_bytes": info["coarse_bytes"],
+                   "probe_error": info["coarse_check_pc"] if precond == "c128" else None,
+                   "factor_bytes": info["coarse_bytes"],
                    "bytes_per_solve": c_bytes, "avg_ms_per_solve": round(c_avg, 4),
                    "gbs": c_bytes / max(c_avg * 1e-3, 1e-12) / 1e9},
         "desc": f"{name}: {dim}-D Q{p}, {N}^{dim} cells ({info['n_fine']} DOF), {R} RHS, "

@@ -129,7 +129,9 @@ typedef struct {
  * the order of elimination, hence in bytes streamed and launches per solve.
  * ND eliminates interior separator blocks that can be nearly singular (real
  * indefinite Helmholtz blocks), so setup adds iterative-refinement steps (up
- * to 3, th_info.coarse_refine) until the probe solve is within 1e-13.
+ * to 3) until the probe solve is within 1e-13 for th_coarse_solve
+ * (th_info.coarse_refine_exact), within 1e-10 inside the FP64 two-grid
+ * preconditioner (th_info.coarse_refine).
  *   LINES:  block elimination over super-blocks of grid lines (planes in 3-D),
  *           explicit inverses of the Schur blocks (twisted when the slab
  *           right-hand sides fit in LDS).
@@ -200,14 +202,19 @@ typedef struct {
                              3 slab factors (FP64/FP32) */
   int coarse_solver;      /* factorisation in use: TH_CSOLVE_LINES or TH_CSOLVE_ND */
   int coarse_levels;      /* ND: levels of the dissection tree (two launches each per solve) */
-  int coarse_refine;      /* ND: iterative-refinement steps per coarse solve (each one more
-                             solve with the factors and a stencil residual) */
+  int coarse_refine;      /* ND: iterative-refinement steps per coarse solve inside the FP64
+                             preconditioner (each one more solve with the factors and a
+                             stencil residual): as many as bring the probe error to 1e-10 */
   double coarse_check;    /* max |A_c^{-1} (A_c x) - x| over the coarse vertices for the setup
                              probe x (unit-modulus entries) */
   int slab_packed;        /* slab factors: 1 when each symmetric G_t is stored once (the lower
                              block triangle as skewed 64 x 64 tiles plus a dense strip of its
                              last m mod 64 rows), 0 when stored whole; the environment variable
                              TH_SLAB_PACKED=0 or 1 at setup overrides the choice */
+  int coarse_refine_exact;  /* ND: refinement steps of th_coarse_solve (FP64): as many as bring
+                               the probe error to 1e-13, at most 3 */
+  double coarse_check_pc;   /* the probe error at coarse_refine steps (coarse_check: at
+                               coarse_refine_exact) */
 } th_info;
 
 /* Create a context on HIP device `hip_device`, ordering work on `hip_stream`

@@ -57,7 +57,9 @@ class Info(C.Structure):
                 ("smoother_layout", C.c_int), ("coarse_solver", C.c_int),
                 ("coarse_levels", C.c_int), ("coarse_refine", C.c_int),
                 ("coarse_check", C.c_double),
-                ("slab_packed", C.c_int)]
+                ("slab_packed", C.c_int),
+                ("coarse_refine_exact", C.c_int),
+                ("coarse_check_pc", C.c_double)]
 
 
 _lib = None

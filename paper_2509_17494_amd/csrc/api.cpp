@@ -138,8 +138,12 @@ static void free_fine(th_ctx *c) {
 }
 
 // nested-dissection coarse solve: probe error below which no further
-// refinement step is taken, and the most steps
+// refinement step is taken for an exact solve, the same inside the FP64
+// preconditioner (four orders below the rounding of a complex64 one, six
+// below the tightest GMRES tolerance in use; whatever it perturbs, the solve
+// stops only on the true FP64 residual), and the most steps
 constexpr double kCoarseRefineTol = 1e-13;
+constexpr double kCoarsePrecondTol = 1e-10;
 constexpr int kCoarseMaxRefine = 3;
 
 static void free_coarse(th_ctx *c) {
@@ -273,8 +277,10 @@ th_status th_get_info(const th_ctx *ctx, th_info *info) {
   info->smoother_layout = ctx->layout;
   info->coarse_solver = ctx->coarse.kind == 1 ? TH_CSOLVE_ND : TH_CSOLVE_LINES;
   info->coarse_levels = ctx->coarse.nd.levels;
-  info->coarse_refine = ctx->coarse.nd.refine;
+  info->coarse_refine = ctx->coarse.nd.refine_pc;
+  info->coarse_refine_exact = ctx->coarse.nd.refine;
   info->coarse_check = ctx->coarse.check_err;
+  info->coarse_check_pc = ctx->coarse.check_err_pc;
   info->slab_packed = ctx->layout == 3 ? ctx->slab_pk : 0;
   return TH_OK;
 }
@@ -832,12 +838,21 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
     rc = setup_coarse_nd(c, st);
     double err = -1.0;
     if (rc == 0) rc = coarse_probe_check(c, st, &err);
-    // refinement steps until the probe solve is at the rounding level
+    // refinement steps until the probe solve is at the rounding level (exact
+    // solves) or within kCoarsePrecondTol (the FP64 preconditioner)
+    int pc = err <= kCoarsePrecondTol ? 0 : -1;
+    double err_pc = err;
     while (rc == 0 && !(err <= kCoarseRefineTol) && c->coarse.nd.refine < kCoarseMaxRefine) {
       ++c->coarse.nd.refine;
       rc = coarse_probe_check(c, st, &err);
+      if (pc < 0 && err <= kCoarsePrecondTol) {
+        pc = c->coarse.nd.refine;
+        err_pc = err;
+      }
     }
+    c->coarse.nd.refine_pc = pc < 0 ? c->coarse.nd.refine : pc;
     c->coarse.check_err = err;
+    c->coarse.check_err_pc = pc < 0 ? err : err_pc;
     const double tol = d->solver == TH_CSOLVE_ND ? 1e-6 : 1e-9;
     if (rc == 0 && err <= tol &&
         (d->solver == TH_CSOLVE_ND || coarse_model_nd(c) <= coarse_model_lines(c))) {
@@ -862,7 +877,7 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
     rc = setup_coarse_factors(c, st);
     double err = -1.0;
     if (rc == 0) rc = coarse_probe_check(c, st, &err);
-    c->coarse.check_err = err;
+    c->coarse.check_err = c->coarse.check_err_pc = err;
   }
   if (rc) {
     free_coarse(c);
@@ -931,7 +946,10 @@ static int smooth_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, bo
   return add_inplace(c, u, c->w_v, nrhs, f32);
 }
 
-static int coarse_solve_impl(th_ctx *c, const void *rc_in, void *uc_out, int nrhs, bool f32) {
+// accuracy: kCoarseExact (th_coarse_solve) or kCoarsePrecond (inside the
+// two-grid preconditioner); a complex64 solve is always rounded
+static int coarse_solve_impl(th_ctx *c, const void *rc_in, void *uc_out, int nrhs, bool f32,
+                             int accuracy) {
   hipStream_t s = c->stream;
   const c64 *r64 = (const c64 *)rc_in;
   c64 *u64 = (c64 *)uc_out;
@@ -944,7 +962,7 @@ static int coarse_solve_impl(th_ctx *c, const void *rc_in, void *uc_out, int nrh
   int rc;
   {
     KTimer kt(c, TH_KT_COARSE);
-    rc = launch_coarse_solve(c, r64, u64, nrhs, s, !f32);
+    rc = launch_coarse_solve(c, r64, u64, nrhs, s, f32 ? kCoarseRounded : accuracy);
   }
   if (rc) return rc;
   if (f32) return launch_convert(u64, uc_out, (long long)nrhs * c->nc, false, true, s);
@@ -968,7 +986,7 @@ static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, b
     KTimer kt(c, TH_KT_RESTRICT);
     rc = launch_restrict(c->dim, c->N, c->P, c->dir, c->ref, c->w_r, rcv, nrhs, f32, s);
   }
-  if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32);
+  if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32, kCoarsePrecond);
   if (!rc) {
     KTimer kt(c, TH_KT_PROLONG);
     rc = launch_prolong(c->dim, c->N, c->P, c->dir, c->ref, ucv, u, c->desc.omega_c, nrhs, f32,
@@ -1028,7 +1046,7 @@ th_status th_prolong(th_ctx *ctx, const void *uc, void *u, double omega_c, int n
 th_status th_coarse_solve(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt) {
   th_status st = check_vec_call(ctx, rc, uc, nrhs, dt, true);
   if (st) return st;
-  return finish(ctx, coarse_solve_impl(ctx, rc, uc, nrhs, is_f32(dt)));
+  return finish(ctx, coarse_solve_impl(ctx, rc, uc, nrhs, is_f32(dt), kCoarseExact));
 }
 
 th_status th_coarse_solve_noalloc(th_ctx *ctx, const void *rc, void *uc, int nrhs, th_dtype dt) {
@@ -1068,7 +1086,7 @@ th_status th_coarse_solve_noalloc(th_ctx *ctx, const void *rc, void *uc, int nrh
     ws.t = w + (long long)nrhs * c->coarse.nd.ulen;
     ws.d = ws.t + (long long)nrhs * ncn;
   }
-  if (!rcode) rcode = launch_coarse_solve(c, r64, u64, nrhs, s, !f32, &ws);
+  if (!rcode) rcode = launch_coarse_solve(c, r64, u64, nrhs, s, f32 ? kCoarseRounded : kCoarseExact, &ws);
   if (!rcode && f32) rcode = launch_convert(u64, uc, (long long)nrhs * ncn, false, true, s);
   return finish(ctx, rcode);
 }

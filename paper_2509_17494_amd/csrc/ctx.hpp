@@ -124,9 +124,11 @@ struct NDData {
   c64 *Wm = nullptr;          // -W per node
   c64 *uvec = nullptr;        // update vectors [max_rhs][ulen]
   long long ulen = 0, bytes = 0, fwd_bytes = 0, bwd_bytes = 0;
-  // iterative refinement: x += A_c^{-1}(r - A_c x) repeated `refine` times,
-  // with the stencil kept on the device and two coarse work vectors per RHS
-  int refine = 0;
+  // iterative refinement: x += A_c^{-1}(r - A_c x) repeated `refine` times
+  // for an exact solve (th_coarse_solve), `refine_pc` times inside the FP64
+  // preconditioner, with the stencil kept on the device and two coarse work
+  // vectors per RHS
+  int refine = 0, refine_pc = 0;
   c64 *st = nullptr;
   c64 *t = nullptr, *d = nullptr;
 };
@@ -154,6 +156,7 @@ struct CoarseData {
   int kind = 0;               // 0: block elimination over slabs, 1: nested dissection
   NDData nd;
   double check_err = -1.0;    // max |A_c^{-1} (A_c x) - x| of the setup probe (unit entries)
+  double check_err_pc = -1.0; // the same at the preconditioner's refinement
 };
 
 }  // namespace th
@@ -342,16 +345,19 @@ int setup_coarse_factors(th_ctx *c, const std::vector<c64> &stencil);
 struct CoarseScratch {
   c64 *uvec = nullptr, *t = nullptr, *d = nullptr;
 };
-// exact: the result is used in FP64 (with false, nested dissection skips its
-// refinement steps: the result is rounded to complex64 afterwards)
-int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact,
+// Accuracy asked of a coarse solve: rounded to complex64 afterwards (nested
+// dissection skips its refinement), inside the FP64 preconditioner (refined
+// to a probe error of 1e-10), or exact (th_coarse_solve: refined to the
+// rounding level)
+enum CoarseAccuracy { kCoarseRounded = 0, kCoarsePrecond = 1, kCoarseExact = 2 };
+int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, int accuracy,
                         const CoarseScratch *ws = nullptr);
 // true when the line elimination's solve needs its large-slab staging buffers
 bool coarse_lines_need_staging(const th_ctx *c);
 // k_nd.hip: nested-dissection factorisation of the coarse stencil matrix, its
 // solve, and the probe check of whichever coarse factorisation is set up
 int setup_coarse_nd(th_ctx *c, const std::vector<c64> &stencil);
-int launch_coarse_nd(const th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, bool exact,
+int launch_coarse_nd(const th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, int accuracy,
                      const CoarseScratch *ws);
 void free_nd(NDData &nd);
 int coarse_probe_check(th_ctx *c, const std::vector<c64> &stencil, double *err);

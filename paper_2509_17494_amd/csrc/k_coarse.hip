@@ -674,9 +674,9 @@ bool coarse_lines_need_staging(const th_ctx *c) {
   return !small_slabs_fit(c->coarse, c->coarse.rc_chunk);
 }
 
-int launch_coarse_solve(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s, bool exact,
+int launch_coarse_solve(th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s, int accuracy,
                         const CoarseScratch *ws) {
-  if (c->coarse.kind == 1) return launch_coarse_nd(c, rcv, uc, nrhs, s, exact, ws);
+  if (c->coarse.kind == 1) return launch_coarse_nd(c, rcv, uc, nrhs, s, accuracy, ws);
   if (!small_slabs_fit(c->coarse, c->coarse.rc_chunk)) {
     if (nrhs >= 8) return sweep_large_t<8>(c, rcv, uc, nrhs, s);
     if (nrhs >= 4) return sweep_large_t<4>(c, rcv, uc, nrhs, s);

@@ -838,7 +838,7 @@ int coarse_probe_check(th_ctx *c, const std::vector<c64> &stencil, double *err) 
                      dim3(256), 0, s, (const c64 *)dst, dim, nx, (const c64 *)nullptr,
                      (const c64 *)xp, bp);
   TH_HIP_CHECK_RET(hipGetLastError());
-  if (int e = launch_coarse_solve(c, bp, xs, 1, s, true)) return e;
+  if (int e = launch_coarse_solve(c, bp, xs, 1, s, kCoarseExact)) return e;
   std::vector<c64> hs(ncn);
   TH_HIP_CHECK_RET(hipMemcpyAsync(hs.data(), xs, ncn * sizeof(c64), hipMemcpyDeviceToHost, s));
   TH_HIP_CHECK_RET(hipStreamSynchronize(s));
@@ -867,7 +867,7 @@ double coarse_model_nd(const th_ctx *c) {
     t += std::max(7e-6, (double)L.fbytes * passes / 6.5e12);
     if (L.bbytes > 0) t += std::max(7e-6, (double)L.bbytes * passes / 6.5e12);
   }
-  const int refine = c->desc.gemm == TH_GEMM_F64 ? nd.refine : 0;
+  const int refine = c->desc.gemm == TH_GEMM_F64 ? nd.refine_pc : 0;
   return t * (1 + refine) + refine * 17e-6;
 }
 
@@ -934,11 +934,12 @@ static void nd_solve(const th_ctx *c, const c64 *rcv, c64 *uc, c64 *uvec, int nr
 // iterative refinement against the stencil matrix (FP64 residuals).  The
 // separator blocks of interior boxes are real indefinite Helmholtz blocks that
 // can be close to singular, which costs digits in the factors; refinement
-// brings the solve back to the rounding level of the residual.  Without
-// `exact` (a result rounded to complex64 afterwards) no refinement is done:
-// the factors alone are far more accurate than that rounding.
+// brings the solve back to the rounding level of the residual (exact
+// accuracy), or to a probe error of 1e-10 inside the FP64 preconditioner.  For
+// a result rounded to complex64 afterwards no refinement is done: the factors
+// alone are far more accurate than that rounding.
 int launch_coarse_nd(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s,
-                     bool exact, const CoarseScratch *ws) {
+                     int accuracy, const CoarseScratch *ws) {
   const NDData &nd = c->coarse.nd;
   c64 *uvec = ws && ws->uvec ? ws->uvec : nd.uvec;
   c64 *t = ws && ws->t ? ws->t : nd.t;
@@ -946,7 +947,10 @@ int launch_coarse_nd(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStre
   nd_solve(c, rcv, uc, uvec, nrhs, s);
   const long long ncn = c->nc;
   const unsigned gx = (unsigned)std::min<long long>(ceil_div_ll(ncn, 256), 4096);
-  for (int it = 0; exact && it < nd.refine; ++it) {
+  const int steps = accuracy == kCoarseExact    ? nd.refine
+                    : accuracy == kCoarsePrecond ? nd.refine_pc
+                                                 : 0;
+  for (int it = 0; it < steps; ++it) {
     hipLaunchKernelGGL(k_cstencil_apply, dim3(gx, nrhs), dim3(256), 0, s, (const c64 *)nd.st,
                        c->dim, c->nc1, rcv, (const c64 *)uc, t);
     nd_solve(c, t, d, uvec, nrhs, s);
