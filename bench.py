@@ -520,8 +520,11 @@ def main():
             "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": {"dense": "k_dd_apply", "symmetric": "k_dd_sym + k_dd_symred",
                        "matrix-core": "k_dd_mfma",
-                       "slab": "k_slab_gather + k_slab_fwd + k_slab_bwd + k_slab_extract "
-                               "(one smoother application)"}[prim["layout"]],
+                       "slab": ("k_slab_gather + k_slab_fwd_chain + k_slab_fwd_pk (middles) + "
+                                "k_slab_bwd_chain + k_slab_extract (one smoother application, "
+                                "packed G_t)" if prim["info"]["slab_packed"] else
+                                "k_slab_gather + k_slab_fwd + k_slab_bwd + k_slab_extract "
+                                "(one smoother application)")}[prim["layout"]],
             "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": round(d["avg_ms"], 4),
             "launches": d["launches"]}
     info = prim["info"]

@@ -129,9 +129,10 @@ typedef struct {
  * the order of elimination, hence in bytes streamed and launches per solve.
  * ND eliminates interior separator blocks that can be nearly singular (real
  * indefinite Helmholtz blocks), so setup adds iterative-refinement steps (up
- * to 3) until the probe solve is within 1e-13 for th_coarse_solve
- * (th_info.coarse_refine_exact), within 1e-10 inside the FP64 two-grid
- * preconditioner (th_info.coarse_refine).
+ * to 3) until the probe solve is within 1e-13 for th_coarse_solve and
+ * th_twogrid (th_info.coarse_refine_exact), within 1e-8 inside the FP64
+ * preconditioner of th_solve (th_info.coarse_refine), where Sec. 1 allows an
+ * approximate coarse solve and the true-residual stopping rule decides.
  *   LINES:  block elimination over super-blocks of grid lines (planes in 3-D),
  *           explicit inverses of the Schur blocks (twisted when the slab
  *           right-hand sides fit in LDS).
@@ -203,8 +204,8 @@ typedef struct {
   int coarse_solver;      /* factorisation in use: TH_CSOLVE_LINES or TH_CSOLVE_ND */
   int coarse_levels;      /* ND: levels of the dissection tree (two launches each per solve) */
   int coarse_refine;      /* ND: iterative-refinement steps per coarse solve inside the FP64
-                             preconditioner (each one more solve with the factors and a
-                             stencil residual): as many as bring the probe error to 1e-10 */
+                             preconditioner of th_solve (each one more solve with the factors
+                             and a stencil residual): as many as bring the probe error to 1e-8 */
   double coarse_check;    /* max |A_c^{-1} (A_c x) - x| over the coarse vertices for the setup
                              probe x (unit-modulus entries) */
   int slab_packed;        /* slab factors: 1 when each symmetric G_t is stored once (the lower

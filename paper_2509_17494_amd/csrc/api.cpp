@@ -138,12 +138,13 @@ static void free_fine(th_ctx *c) {
 }
 
 // nested-dissection coarse solve: probe error below which no further
-// refinement step is taken for an exact solve, the same inside the FP64
-// preconditioner (four orders below the rounding of a complex64 one, six
-// below the tightest GMRES tolerance in use; whatever it perturbs, the solve
-// stops only on the true FP64 residual), and the most steps
+// refinement step is taken for an exact solve (th_coarse_solve, th_twogrid),
+// the same for the preconditioner inside th_solve, where the coarse solve may
+// be approximate (Sec. 1): an order below the rounding of a complex64
+// preconditioner, which takes no refinement at all, and whatever it perturbs,
+// the solve stops only on the true FP64 residual; and the most steps
 constexpr double kCoarseRefineTol = 1e-13;
-constexpr double kCoarsePrecondTol = 1e-10;
+constexpr double kCoarsePrecondTol = 1e-8;
 constexpr int kCoarseMaxRefine = 3;
 
 static void free_coarse(th_ctx *c) {
@@ -970,7 +971,10 @@ static int coarse_solve_impl(th_ctx *c, const void *rc_in, void *uc_out, int nrh
 }
 
 // u <- TwoGridStep(u, f) (Alg. 1)
-static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, bool u_zero) {
+// accuracy of the coarse solve: kCoarseExact for th_twogrid, kCoarsePrecond
+// for the preconditioner of th_solve
+static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, bool u_zero,
+                        int accuracy) {
   hipStream_t s = c->stream;
   int rc = 0;
   for (int i = 0; i < c->desc.n_s && rc == 0; ++i) rc = smooth_impl(c, u, f, nrhs, f32, u_zero && i == 0);
@@ -986,7 +990,7 @@ static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, b
     KTimer kt(c, TH_KT_RESTRICT);
     rc = launch_restrict(c->dim, c->N, c->P, c->dir, c->ref, c->w_r, rcv, nrhs, f32, s);
   }
-  if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32, kCoarsePrecond);
+  if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32, accuracy);
   if (!rc) {
     KTimer kt(c, TH_KT_PROLONG);
     rc = launch_prolong(c->dim, c->N, c->P, c->dir, c->ref, ucv, u, c->desc.omega_c, nrhs, f32,
@@ -1094,7 +1098,7 @@ th_status th_coarse_solve_noalloc(th_ctx *ctx, const void *rc, void *uc, int nrh
 th_status th_twogrid(th_ctx *ctx, void *u, const void *f, int nrhs, th_dtype dt) {
   th_status st = check_vec_call(ctx, u, f, nrhs, dt, true);
   if (st) return st;
-  return finish(ctx, twogrid_impl(ctx, u, f, nrhs, is_f32(dt), false));
+  return finish(ctx, twogrid_impl(ctx, u, f, nrhs, is_f32(dt), false, kCoarseExact));
 }
 
 }  // extern "C"
@@ -1198,7 +1202,7 @@ static int twogrid_graph(th_ctx *c, void *out, const void *in, int nrhs, bool f3
     }
   hipGraph_t graph = nullptr;
   TH_HIP_CHECK_RET(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-  int rc = twogrid_impl(c, out, in, nrhs, f32, true);
+  int rc = twogrid_impl(c, out, in, nrhs, f32, true, kCoarsePrecond);
   hipError_t e = hipStreamEndCapture(c->stream, &graph);
   if (rc) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -1220,7 +1224,7 @@ static int precond(th_ctx *c, const c64 *v, c64 *z, int nrhs, bool f32, SolverWS
   const bool graph = use_graph && c->stream != nullptr && !c->timing;
   const long long n = (long long)nrhs * c->nf;
   if (!f32) {
-    if (!graph) return twogrid_impl(c, z, v, nrhs, false, true);
+    if (!graph) return twogrid_impl(c, z, v, nrhs, false, true, kCoarsePrecond);
     TH_HIP_CHECK_RET(hipMemcpyAsync(w.tmp32a, v, n * sizeof(c64), hipMemcpyDeviceToDevice, c->stream));
     int rc = twogrid_graph(c, w.tmp32b, w.tmp32a, nrhs, false);
     if (rc) return rc;
@@ -1229,7 +1233,7 @@ static int precond(th_ctx *c, const c64 *v, c64 *z, int nrhs, bool f32, SolverWS
   }
   int rc = launch_convert(v, w.tmp32a, n, false, true, c->stream);
   if (!rc) rc = graph ? twogrid_graph(c, w.tmp32b, w.tmp32a, nrhs, true)
-                      : twogrid_impl(c, w.tmp32b, w.tmp32a, nrhs, true, true);
+                      : twogrid_impl(c, w.tmp32b, w.tmp32a, nrhs, true, true, kCoarsePrecond);
   if (!rc) rc = launch_convert(w.tmp32b, z, n, true, false, c->stream);
   return rc;
 }

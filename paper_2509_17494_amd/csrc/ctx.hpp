@@ -125,9 +125,9 @@ struct NDData {
   c64 *uvec = nullptr;        // update vectors [max_rhs][ulen]
   long long ulen = 0, bytes = 0, fwd_bytes = 0, bwd_bytes = 0;
   // iterative refinement: x += A_c^{-1}(r - A_c x) repeated `refine` times
-  // for an exact solve (th_coarse_solve), `refine_pc` times inside the FP64
-  // preconditioner, with the stencil kept on the device and two coarse work
-  // vectors per RHS
+  // for an exact solve (th_coarse_solve, th_twogrid), `refine_pc` times inside
+  // the FP64 preconditioner of th_solve, with the stencil kept on the device
+  // and two coarse work vectors per RHS
   int refine = 0, refine_pc = 0;
   c64 *st = nullptr;
   c64 *t = nullptr, *d = nullptr;
@@ -346,9 +346,9 @@ struct CoarseScratch {
   c64 *uvec = nullptr, *t = nullptr, *d = nullptr;
 };
 // Accuracy asked of a coarse solve: rounded to complex64 afterwards (nested
-// dissection skips its refinement), inside the FP64 preconditioner (refined
-// to a probe error of 1e-10), or exact (th_coarse_solve: refined to the
-// rounding level)
+// dissection skips its refinement), inside the FP64 preconditioner of
+// th_solve (refined to a probe error of 1e-8), or exact (th_coarse_solve,
+// th_twogrid: refined to the rounding level)
 enum CoarseAccuracy { kCoarseRounded = 0, kCoarsePrecond = 1, kCoarseExact = 2 };
 int launch_coarse_solve(th_ctx *c, const c64 *rc, c64 *uc, int nrhs, hipStream_t s, int accuracy,
                         const CoarseScratch *ws = nullptr);

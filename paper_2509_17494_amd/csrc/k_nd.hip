@@ -935,7 +935,7 @@ static void nd_solve(const th_ctx *c, const c64 *rcv, c64 *uc, c64 *uvec, int nr
 // separator blocks of interior boxes are real indefinite Helmholtz blocks that
 // can be close to singular, which costs digits in the factors; refinement
 // brings the solve back to the rounding level of the residual (exact
-// accuracy), or to a probe error of 1e-10 inside the FP64 preconditioner.  For
+// accuracy), or to a probe error of 1e-8 inside the FP64 preconditioner.  For
 // a result rounded to complex64 afterwards no refinement is done: the factors
 // alone are far more accurate than that rounding.
 int launch_coarse_nd(const th_ctx *c, const c64 *rcv, c64 *uc, int nrhs, hipStream_t s,

@@ -65,9 +65,9 @@ def test_coarse_solvers_2d(N, p, l_dd, nrhs, bc, solver):
     print(f"  rel err {err:.2e}, check {info['coarse_check']:.2e}, levels {info['coarse_levels']} "
           f"refine {info['coarse_refine_exact']} (preconditioner {info['coarse_refine']}, "
           f"{info['coarse_check_pc']:.2e})", flush=True)
-    if solver == "nd":  # the preconditioner's refinement reaches 1e-10 or stops at 3 steps
+    if solver == "nd":  # the preconditioner's refinement reaches 1e-8 or stops at 3 steps
         assert info["coarse_refine"] <= info["coarse_refine_exact"]
-        assert 0.0 <= info["coarse_check_pc"] <= 1e-10 or info["coarse_refine"] == 3
+        assert 0.0 <= info["coarse_check_pc"] <= 1e-8 or info["coarse_refine"] == 3
     assert err < 1e-11
     s.close()
 
