@@ -1363,22 +1363,22 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
       if (rc) return rc;
       // modified Gram-Schmidt: coefficients stay on the device (column j of
       // the Hessenberg matrix in w.hcol), the new vector is normalised by a
-      // device-computed 1/norm, and one copy brings the column to the host
+      // device-computed 1/norm, and one copy brings the column to the host;
+      // each projection is two launches (partial dot products, then the axpy
+      // that finishes their fixed-order sum itself)
       std::vector<std::vector<zc>> hcol(nrhs, std::vector<zc>(j + 2, 0.0));
       {
         KTimer kt(c, TH_KT_KRYLOV);
         for (int i = 0; i <= j && rc == 0; ++i) {
-          rc = launch_dot(Vj(i), Vj(j + 1), nf, nrhs, nf, nf, w.hcol + (size_t)i * nrhs,
-                          w.partial, s);
+          rc = launch_dot_partial(Vj(i), Vj(j + 1), nf, nrhs, nf, nf, w.partial, s);
           if (!rc)
-            rc = launch_axpy_dev(Vj(j + 1), Vj(i), w.hcol + (size_t)i * nrhs, -1.0, nf, nrhs, nf,
-                                 nf, s);
+            rc = launch_axpy_partials(Vj(j + 1), Vj(i), w.partial, w.hcol + (size_t)i * nrhs, -1.0,
+                                      nf, nrhs, nf, nf, s);
         }
+        if (!rc) rc = launch_dot_partial(Vj(j + 1), Vj(j + 1), nf, nrhs, nf, nf, w.partial, s);
         if (!rc)
-          rc = launch_dot(Vj(j + 1), Vj(j + 1), nf, nrhs, nf, nf, w.hcol + (size_t)(j + 1) * nrhs,
-                          w.partial, s);
-        if (!rc) rc = launch_inv_norm(w.hcol + (size_t)(j + 1) * nrhs, w.scal, nrhs, s);
-        if (!rc) rc = launch_scale_dev(Vj(j + 1), Vj(j + 1), w.scal, nf, nrhs, nf, nf, s);
+          rc = launch_scale_partials(Vj(j + 1), w.partial, w.hcol + (size_t)(j + 1) * nrhs, nf,
+                                     nrhs, nf, s);
       }
       if (rc) return rc;
       TH_HIP_CHECK_RET(hipMemcpyAsync(w.hcol_h, w.hcol, (size_t)(j + 2) * nrhs * sizeof(c64),

@@ -376,6 +376,14 @@ int gj_ws_status(const c64 *ws, hipStream_t s, const char *what);
 
 // k_blas.hip
 int launch_convert(const void *in, void *out, long long n, bool in_f32, bool out_f32, hipStream_t s);
+// the Arnoldi step's fused pair: partial dot products, then the axpy (or the
+// normalisation) that finishes their sum itself and stores it
+int launch_dot_partial(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx,
+                       long long ldy, c64 *partial, hipStream_t s);
+int launch_axpy_partials(c64 *y, const c64 *x, const c64 *partial, c64 *coef, double sign,
+                         long long n, int nrhs, long long ldy, long long ldx, hipStream_t s);
+int launch_scale_partials(c64 *v, const c64 *partial, c64 *dot, long long n, int nrhs,
+                          long long ld, hipStream_t s);
 int launch_dot(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx, long long ldy,
                c64 *out, c64 *partial, hipStream_t s);
 int launch_axpy_dev(c64 *y, const c64 *x, const c64 *coef, double sign, long long n, int nrhs,

@@ -37,18 +37,102 @@ __global__ __launch_bounds__(256) void k_dot_partial(const c64 *__restrict__ x,
   if (threadIdx.x == 0) partial[rhs * RED_BLOCKS + blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(256) void k_dot_final(const c64 *__restrict__ partial,
+// out[rhs] = the sum of the rhs's nb partials (fixed order)
+__global__ __launch_bounds__(256) void k_dot_final(const c64 *__restrict__ partial, int nb,
                                                    c64 *__restrict__ out) {
   __shared__ c64 sh[256];
-  block_reduce(sh, partial[blockIdx.x * RED_BLOCKS + threadIdx.x]);
+  block_reduce(sh, (int)threadIdx.x < nb ? partial[blockIdx.x * RED_BLOCKS + threadIdx.x]
+                                         : c64{0, 0});
   if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+// Partial blocks per right-hand side: enough for 8 entries per thread, at most
+// RED_BLOCKS (short vectors with many right-hand sides, such as 64 of 16,641
+// entries, would otherwise launch mostly idle blocks)
+static int dot_blocks(long long n) {
+  return (int)std::max<long long>(1, std::min<long long>(RED_BLOCKS, ceil_div_ll(n, 256 * 8)));
 }
 
 int launch_dot(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx, long long ldy,
                c64 *out, c64 *partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS, nrhs), dim3(256), 0, s, x, y, n, ldx, ldy,
+  const int nb = dot_blocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb, nrhs), dim3(256), 0, s, x, y, n, ldx, ldy, partial);
+  hipLaunchKernelGGL(k_dot_final, dim3(nrhs), dim3(RED_BLOCKS), 0, s, (const c64 *)partial, nb, out);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+int launch_dot_partial(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx,
+                       long long ldy, c64 *partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(dot_blocks(n), nrhs), dim3(256), 0, s, x, y, n, ldx, ldy,
                      partial);
-  hipLaunchKernelGGL(k_dot_final, dim3(nrhs), dim3(RED_BLOCKS), 0, s, (const c64 *)partial, out);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// The dot product of right-hand side r from its partials, in the same fixed
+// order as k_dot_final (every block of the caller computes it)
+__device__ __forceinline__ c64 dot_from_partials(const c64 *__restrict__ partial, int nb, int r,
+                                                 c64 *sh) {
+  block_reduce(sh, (int)threadIdx.x < nb ? partial[r * RED_BLOCKS + threadIdx.x] : c64{0, 0});
+  return sh[0];
+}
+
+// y[rhs] += sign * a x[rhs] with a = conj(x_i) . y from the partials of
+// k_dot_partial; block 0 stores a in coef[rhs]
+__global__ __launch_bounds__(256) void k_axpy_partials(c64 *__restrict__ y,
+                                                       const c64 *__restrict__ x,
+                                                       const c64 *__restrict__ partial, int nb,
+                                                       c64 *__restrict__ coef, double sign,
+                                                       long long n, long long ldy, long long ldx) {
+  __shared__ c64 sh[256];
+  const long long rhs = blockIdx.y;
+  const c64 a = dot_from_partials(partial, nb, (int)rhs, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) coef[rhs] = a;
+  const c64 sa = {sign * a.re, sign * a.im};
+  y += rhs * ldy;
+  x += rhs * ldx;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    c64 v = y[i];
+    cmac(v, sa, x[i]);
+    y[i] = v;
+  }
+}
+
+int launch_axpy_partials(c64 *y, const c64 *x, const c64 *partial, c64 *coef, double sign,
+                         long long n, int nrhs, long long ldy, long long ldx, hipStream_t s) {
+  const int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 4096);
+  hipLaunchKernelGGL(k_axpy_partials, dim3(blocks, nrhs), dim3(256), 0, s, y, x, partial,
+                     dot_blocks(n), coef, sign, n, ldy, ldx);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
+// v[rhs] /= ||v[rhs]|| with ||v||^2 from the partials of k_dot_partial (0 when
+// the norm is zero or not finite, as k_inv_norm); block 0 stores ||v||^2 in
+// dot[rhs]
+__global__ __launch_bounds__(256) void k_scale_partials(c64 *__restrict__ v,
+                                                        const c64 *__restrict__ partial, int nb,
+                                                        c64 *__restrict__ dot, long long n,
+                                                        long long ld) {
+  __shared__ c64 sh[256];
+  const long long rhs = blockIdx.y;
+  const c64 a = dot_from_partials(partial, nb, (int)rhs, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) dot[rhs] = a;
+  const double nrm = sqrt(a.re > 0.0 ? a.re : 0.0);
+  const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+  v += rhs * ld;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const c64 e = v[i];
+    v[i] = c64{inv * e.re, inv * e.im};
+  }
+}
+
+int launch_scale_partials(c64 *v, const c64 *partial, c64 *dot, long long n, int nrhs,
+                          long long ld, hipStream_t s) {
+  const int blocks = (int)std::min<long long>(ceil_div_ll(n, 256), 4096);
+  hipLaunchKernelGGL(k_scale_partials, dim3(blocks, nrhs), dim3(256), 0, s, v, partial,
+                     dot_blocks(n), dot, n, ld);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
