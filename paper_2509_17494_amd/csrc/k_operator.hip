@@ -13,7 +13,9 @@
 //           K1 W + M1 (Z - kappa h^2 W) along y -- a fixed-order gather, so the
 //           result is deterministic (no atomics).
 // A workgroup owns the nodes of a TC x TC cell tile (low edges included) and
-// reads one extra cell layer on the low sides.
+// reads one extra cell layer on the low sides; TC is picked per launch so
+// that small meshes with few right-hand sides still give the chip enough
+// workgroups.
 //
 // Dirichlet sides (op.dir): their nodes are eliminated with unit rows and
 // columns, so u is read as zero there and the row of such a node is u itself.
@@ -21,25 +23,81 @@
 
 namespace th {
 
-template <int P> struct TileOf;
-template <> struct TileOf<2> { static constexpr int TC = 16; };
-template <> struct TileOf<4> { static constexpr int TC = 8; };
-template <> struct TileOf<6> { static constexpr int TC = 5; };
-template <> struct TileOf<8> { static constexpr int TC = 4; };
+// Shape of a 2-D tile of TC x TC cells: node rows and cell columns staged by
+// the x pass; the y pass gives each local node row ay in [0, P) of the owned
+// cells its own whole wavefronts (CW threads, one per cell), so ay is uniform
+// per wavefront; threads and x-pass items per thread.
+template <int P, int TC>
+struct Tile2 {
+  static constexpr int NP = P + 1;
+  static constexpr int NROW = (TC + 1) * P + 1;
+  static constexpr int NCC = TC + 1;
+  static constexpr int CW = (TC * TC + 63) / 64 * 64;
+  static constexpr int NT = P * CW;
+  static constexpr int XI = (NROW * NCC + NT - 1) / NT;
+};
 
+// Robin term of node (ix, iy) on an absorbing side: -i k h (M1 along the side) u.
 template <int P, typename T>
-__global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<T> *__restrict__ u,
-                                                 const cx<T> *__restrict__ f,
-                                                 cx<T> *__restrict__ out, T sgn) {
-  constexpr int TC = TileOf<P>::TC;
+__device__ __forceinline__ void robin_add(const FineOp &op, const Ref1D &ref,
+                                          const cx<T> *__restrict__ u, int ix, int iy,
+                                          cx<T> &acc) {
   constexpr int NP = P + 1;
-  constexpr int NROW = (TC + 1) * P + 1;
-  constexpr int NCC = TC + 1;
-  __shared__ cx<T> WX[NROW * NCC * NP];
-  __shared__ cx<T> ZX[NROW * NCC * NP];
-  __shared__ T sK[NP * NP], sM[NP * NP];
+  const int N = op.N, n1 = op.n1, NPn = N * P;
+  const int chx = min(ix / P, N - 1), chy = min(iy / P, N - 1);
+  const int ncellx = (ix % P == 0 && ix > 0 && ix < NPn) ? 2 : 1;
+  const int ncelly = (iy % P == 0 && iy > 0 && iy < NPn) ? 2 : 1;
+  cx<T> s = {0, 0};
+  if ((ix == 0 && (op.robin & 1)) || (ix == NPn && (op.robin & 2))) {
+    const int cxq = (ix == 0) ? 0 : N - 1;
+    for (int qy = ncelly - 1; qy >= 0; --qy) {
+      const int cyq = chy - qy, ay = iy - cyq * P;
+      const T kk = (T)op.kr[(long long)cyq * N + cxq];
+      cx<T> m = {0, 0};
+      for (int by = 0; by < NP; ++by)
+        if (!on_dir(op.dir, 1, cyq * P + by, NPn))
+          rmac(m, (T)ref.M[ay * NP + by], u[(long long)(cyq * P + by) * n1 + ix]);
+      rmac(s, kk, m);
+    }
+  }
+  if ((iy == 0 && (op.robin & 4)) || (iy == NPn && (op.robin & 8))) {
+    const int cyq = (iy == 0) ? 0 : N - 1;
+    for (int qx = ncellx - 1; qx >= 0; --qx) {
+      const int cxq = chx - qx, ax = ix - cxq * P;
+      const T kk = (T)op.kr[(long long)cyq * N + cxq];
+      cx<T> m = {0, 0};
+      for (int bx = 0; bx < NP; ++bx)
+        if (!on_dir(op.dir, 0, cxq * P + bx, NPn))
+          rmac(m, (T)ref.M[ax * NP + bx], u[(long long)iy * n1 + cxq * P + bx]);
+      rmac(s, kk, m);
+    }
+  }
+  // -i h s = (h s.im, -h s.re)
+  const T h = (T)op.h;
+  acc.re += h * s.im;
+  acc.im -= h * s.re;
+}
 
-  const int N = op.N, n1 = op.n1;
+// x pass: one item per (staged node row, staged cell column), its u row
+// segment loaded by every thread at once before any compute; y pass: thread
+// (ay, cell) sums the nodes of the cell's local row ay on its low edges (and
+// on its high edges at the domain's last node column; the ay = 0 wavefronts
+// also take the last node row) over the cells that contain them --
+// below-left, below, left, own, a fixed order that keeps the result
+// deterministic.  ax is unrolled and ay uniform per wavefront, so the LDS
+// offsets are per-lane bases plus constants and the K1 / M1 entries scalars.
+template <int P, int TC, typename T>
+__global__ __launch_bounds__((Tile2<P, TC>::NT)) void k_apply2d(FineOp op, Ref1D ref,
+                                                               const cx<T> *__restrict__ u,
+                                                               const cx<T> *__restrict__ f,
+                                                               cx<T> *__restrict__ out, T sgn) {
+  using S = Tile2<P, TC>;
+  constexpr int NP = P + 1, NCC = S::NCC, NT = S::NT;
+  __shared__ cx<T> WX[S::NROW * NCC * NP];
+  __shared__ cx<T> ZX[S::NROW * NCC * NP];
+  __shared__ cx<T> KH[NCC * NCC];
+
+  const int N = op.N, n1 = op.n1, NPn = N * P;
   const long long rb = (long long)blockIdx.z * op.nf;
   u += rb;
   out += rb;
@@ -48,35 +106,63 @@ __global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<
   const int cx0 = blockIdx.x * TC, cy0 = blockIdx.y * TC;
   const int cxs = max(cx0 - 1, 0), cxe = min(cx0 + TC, N);
   const int cys = max(cy0 - 1, 0), cye = min(cy0 + TC, N);
-  const int ncx = cxe - cxs;
-  const int nrow = (cye - cys) * P + 1;
+  const int ncx = cxe - cxs, ncy = cye - cys;
+  const int nrow = ncy * P + 1;
+  const T h2 = (T)(op.h * op.h);
 
-  for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) {
-    sK[i] = (T)ref.K[i];
-    sM[i] = (T)ref.M[i];
+  cx<T> uv[S::XI][NP];
+#pragma unroll
+  for (int k = 0; k < S::XI; ++k) {
+    const int it = threadIdx.x + k * NT;
+    const int jr = min(it / NCC, nrow - 1), cc = min(it % NCC, ncx - 1);
+    const cx<T> *urow = u + (long long)(cys * P + jr) * n1 + (cxs + cc) * P;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) uv[k][b] = urow[b];
+  }
+  // the y pass's cell and node row, and its f values, loaded with the rest
+  const int ay0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x / S::CW);
+  const int ci = threadIdx.x % S::CW;
+  const int cxo = cx0 + ci % TC, cyo = cy0 + ci / TC;
+  const bool owner = ci < TC * TC && cxo < N && cyo < N;
+  const bool lastx = cxo == N - 1, lasty = cyo == N - 1;
+  cx<T> fv[2][NP];
+  {
+    const int gx = min(cxo, N - 1) * P, gy = min(cyo, N - 1) * P;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int ax = 0; ax < NP; ++ax) {
+        fv[r][ax] = cx<T>{0, 0};
+        const bool need = (r == 0 || (ay0 == 0 && lasty)) && (ax < P || lastx);
+        if (f && need) fv[r][ax] = f[(long long)(gy + (r ? P : ay0)) * n1 + gx + ax];
+      }
+  }
+  for (int i = threadIdx.x; i < ncx * ncy; i += NT) {
+    const int ly = i / ncx, lx = i - ly * ncx;
+    const c64 kd = op.kap[(long long)(cys + ly) * N + cxs + lx];
+    KH[ly * NCC + lx] = cx<T>{(T)kd.re * h2, (T)kd.im * h2};
   }
 
   // x pass
-  for (int it = threadIdx.x; it < nrow * ncx; it += blockDim.x) {
-    const int jr = it / ncx, cc = it - jr * ncx;
-    const int jy = cys * P + jr, c = cxs + cc;
-    const cx<T> *urow = u + (long long)jy * n1 + c * P;
-    cx<T> uv[NP];
 #pragma unroll
-    for (int b = 0; b < NP; ++b) uv[b] = urow[b];
+  for (int k = 0; k < S::XI; ++k) {
+    const int it = threadIdx.x + k * NT;
+    const int jr = it / NCC, cc = it % NCC;
+    if (jr >= nrow || cc >= ncx) continue;
     if (op.dir) {
-      const bool rowd = on_dir(op.dir, 1, jy, N * P);
+      const int jy = cys * P + jr, c = cxs + cc;
+      const bool rowd = on_dir(op.dir, 1, jy, NPn);
 #pragma unroll
       for (int b = 0; b < NP; ++b)
-        if (rowd || on_dir(op.dir, 0, c * P + b, N * P)) uv[b] = cx<T>{0, 0};
+        if (rowd || on_dir(op.dir, 0, c * P + b, NPn)) uv[k][b] = cx<T>{0, 0};
     }
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
       cx<T> w = {0, 0}, z = {0, 0};
 #pragma unroll
       for (int b = 0; b < NP; ++b) {
-        rmac(w, (T)ref.M[a * NP + b], uv[b]);
-        rmac(z, (T)ref.K[a * NP + b], uv[b]);
+        rmac(w, (T)ref.M[a * NP + b], uv[k][b]);
+        rmac(z, (T)ref.K[a * NP + b], uv[k][b]);
       }
       WX[(jr * NCC + cc) * NP + a] = w;
       ZX[(jr * NCC + cc) * NP + a] = z;
@@ -84,79 +170,48 @@ __global__ __launch_bounds__(256) void k_apply2d(FineOp op, Ref1D ref, const cx<
   }
   __syncthreads();
 
-  // y pass over owned nodes
-  const int NPn = N * P;
-  const int ix0 = cx0 * P, iy0 = cy0 * P;
-  const int ix1 = (cx0 + TC >= N) ? NPn + 1 : (cx0 + TC) * P;
-  const int iy1 = (cy0 + TC >= N) ? NPn + 1 : (cy0 + TC) * P;
-  const int nox = ix1 - ix0, noy = iy1 - iy0;
-  const T h = (T)op.h, h2 = (T)(op.h * op.h);
-
-  for (int it = threadIdx.x; it < nox * noy; it += blockDim.x) {
-    const int jy = it / nox, jx = it - jy * nox;
-    const int ix = ix0 + jx, iy = iy0 + jy;
-    const int chx = min(ix / P, N - 1), chy = min(iy / P, N - 1);
-    const int ncellx = (ix % P == 0 && ix > 0 && ix < NPn) ? 2 : 1;
-    const int ncelly = (iy % P == 0 && iy > 0 && iy < NPn) ? 2 : 1;
-    cx<T> acc = {0, 0};
-    for (int qy = ncelly - 1; qy >= 0; --qy) {
-      const int cyq = chy - qy;
-      const int ay = iy - cyq * P;
-      const int rbase = (cyq - cys) * P;
-      for (int qx = ncellx - 1; qx >= 0; --qx) {
-        const int cxq = chx - qx;
-        const int ax = ix - cxq * P;
-        const int cc = cxq - cxs;
-        const c64 kd = op.kap[(long long)cyq * N + cxq];
-        const cx<T> kh = {(T)kd.re * h2, (T)kd.im * h2};
+  // y pass
+  if (!owner) return;
+  const int cc = cxo - cxs, cr = cyo - cys;
+  const bool left = cxo > 0, below = cyo > 0;
+  // one cell's contribution to local node (lx, ly) of that cell
+  auto cell = [&](int c, int r, int lx, int ly, cx<T> &acc) {
+    const cx<T> kh = KH[r * NCC + c];
+    const int rbase = r * P;
 #pragma unroll
-        for (int by = 0; by < NP; ++by) {
-          const cx<T> w = WX[((rbase + by) * NCC + cc) * NP + ax];
-          const cx<T> z = ZX[((rbase + by) * NCC + cc) * NP + ax];
-          const T ky = sK[ay * NP + by], my = sM[ay * NP + by];
-          rmac(acc, ky, w);
-          cx<T> t = z - kh * w;
-          rmac(acc, my, t);
-        }
-      }
+    for (int by = 0; by < NP; ++by) {
+      const cx<T> w = WX[((rbase + by) * NCC + c) * NP + lx];
+      const cx<T> z = ZX[((rbase + by) * NCC + c) * NP + lx];
+      rmac(acc, (T)ref.K[ly * NP + by], w);
+      cx<T> t = z - kh * w;
+      rmac(acc, (T)ref.M[ly * NP + by], t);
     }
-    // absorbing boundary terms: -i k h (M1 along the side) u
-    if (op.robin) {
-      cx<T> s = {0, 0};
-      if ((ix == 0 && (op.robin & 1)) || (ix == NPn && (op.robin & 2))) {
-        const int cxq = (ix == 0) ? 0 : N - 1;
-        for (int qy = ncelly - 1; qy >= 0; --qy) {
-          const int cyq = chy - qy, ay = iy - cyq * P;
-          const T kk = (T)op.kr[(long long)cyq * N + cxq];
-          cx<T> m = {0, 0};
-          for (int by = 0; by < NP; ++by)
-            if (!on_dir(op.dir, 1, cyq * P + by, NPn))
-              rmac(m, sM[ay * NP + by], u[(long long)(cyq * P + by) * n1 + ix]);
-          rmac(s, kk, m);
-        }
+  };
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    if (r && !(ay0 == 0 && lasty)) break;
+    const int ay = r ? P : ay0;
+    const int iy = cyo * P + ay;
+#pragma unroll
+    for (int ax = 0; ax < NP; ++ax) {
+      if (ax == P && !lastx) continue;
+      const int ix = cxo * P + ax;
+      const long long g = (long long)iy * n1 + ix;
+      cx<T> acc = {0, 0};
+      if (ay == 0 && below) {
+        if (ax == 0 && left) cell(cc - 1, cr - 1, P, P, acc);
+        cell(cc, cr - 1, ax, P, acc);
       }
-      if ((iy == 0 && (op.robin & 4)) || (iy == NPn && (op.robin & 8))) {
-        const int cyq = (iy == 0) ? 0 : N - 1;
-        for (int qx = ncellx - 1; qx >= 0; --qx) {
-          const int cxq = chx - qx, ax = ix - cxq * P;
-          const T kk = (T)op.kr[(long long)cyq * N + cxq];
-          cx<T> m = {0, 0};
-          for (int bx = 0; bx < NP; ++bx)
-            if (!on_dir(op.dir, 0, cxq * P + bx, NPn))
-              rmac(m, sM[ax * NP + bx], u[(long long)iy * n1 + cxq * P + bx]);
-          rmac(s, kk, m);
-        }
-      }
-      // -i h s = (h s.im, -h s.re)
-      acc.re += h * s.im;
-      acc.im -= h * s.re;
+      if (ax == 0 && left) cell(cc - 1, cr, P, ay, acc);
+      cell(cc, cr, ax, ay, acc);
+      if (op.robin && (ix == 0 || ix == NPn || iy == 0 || iy == NPn))
+        robin_add<P, T>(op, ref, u, ix, iy, acc);
+      if (op.dir && (on_dir(op.dir, 0, ix, NPn) || on_dir(op.dir, 1, iy, NPn))) acc = u[g];
+      cx<T> o = fv[r][ax];
+      o.re = fma(sgn, acc.re, o.re);
+      o.im = fma(sgn, acc.im, o.im);
+      out[g] = o;
     }
-    const long long g = (long long)iy * n1 + ix;
-    if (op.dir && (on_dir(op.dir, 0, ix, NPn) || on_dir(op.dir, 1, iy, NPn))) acc = u[g];
-    cx<T> o = f ? f[g] : cx<T>{0, 0};
-    o.re = fma(sgn, acc.re, o.re);
-    o.im = fma(sgn, acc.im, o.im);
-    out[g] = o;
   }
 }
 
@@ -363,13 +418,36 @@ static int launch_apply3_t(const FineOp &op, const Ref1D &ref, const void *u, co
   return 0;
 }
 
+template <int P, int TC, typename T>
+static void launch_apply2(const FineOp &op, const Ref1D &ref, const void *u, const void *f,
+                          void *out, int nrhs, double sgn, hipStream_t s) {
+  dim3 grid(ceil_div(op.N, TC), ceil_div(op.N, TC), nrhs);
+  hipLaunchKernelGGL((k_apply2d<P, TC, T>), grid, dim3(Tile2<P, TC>::NT), 0, s, op, ref,
+                     (const cx<T> *)u, (const cx<T> *)f, (cx<T> *)out, (T)sgn);
+}
+
+// Tile edge (cells) per order: the largest of three whose grid still has
+// kApplyWGs workgroups, else the smallest (small meshes with one RHS would
+// otherwise leave most of the chip idle; every workgroup's time is about one
+// memory round trip, so more and smaller tiles finish sooner).
+constexpr long long kApplyWGs = 256;
+template <int P> struct Tiles2;
+template <> struct Tiles2<2> { static constexpr int t[3] = {16, 8, 4}; };
+template <> struct Tiles2<4> { static constexpr int t[3] = {8, 4, 2}; };
+template <> struct Tiles2<6> { static constexpr int t[3] = {5, 3, 2}; };
+template <> struct Tiles2<8> { static constexpr int t[3] = {4, 2, 1}; };
+
 template <int P, typename T>
 static int launch_apply_t(const FineOp &op, const Ref1D &ref, const void *u, const void *f,
                           void *out, int nrhs, double sgn, hipStream_t s) {
-  constexpr int TC = TileOf<P>::TC;
-  dim3 grid(ceil_div(op.N, TC), ceil_div(op.N, TC), nrhs);
-  hipLaunchKernelGGL((k_apply2d<P, T>), grid, dim3(256), 0, s, op, ref, (const cx<T> *)u,
-                     (const cx<T> *)f, (cx<T> *)out, (T)sgn);
+  auto wgs = [&](int tc) { return (long long)ceil_div(op.N, tc) * ceil_div(op.N, tc) * nrhs; };
+  constexpr int T0 = Tiles2<P>::t[0], T1 = Tiles2<P>::t[1], T2 = Tiles2<P>::t[2];
+  if (wgs(T0) >= kApplyWGs)
+    launch_apply2<P, T0, T>(op, ref, u, f, out, nrhs, sgn, s);
+  else if (wgs(T1) >= kApplyWGs)
+    launch_apply2<P, T1, T>(op, ref, u, f, out, nrhs, sgn, s);
+  else
+    launch_apply2<P, T2, T>(op, ref, u, f, out, nrhs, sgn, s);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }

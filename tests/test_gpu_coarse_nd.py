@@ -136,3 +136,24 @@ def test_automatic_choice_follows_the_time_model():
         s.close()
     print(f"automatic coarse solver: {got}", flush=True)
     assert got == {"C1": 1, "C3": 2, "C2": 2}
+
+
+
+def test_nd_calls_of_changing_width():
+    """One context, calls of changing width: 64 right-hand sides (eight passes
+    of 8), then 3, 17, 1 and 64 again; every call matches sparse LU to 1e-11."""
+    from paper_2509_17494_amd import TwoGridSolver
+    N, p = 64, 2
+    k = hetero_k(N, 2, p, seed=77)
+    Ac = coarse_matrix(coarse_cell_values(k, p), robin=(True,) * 4, dirichlet=(False,) * 4)
+    lu = spla.splu(Ac.tocsc())
+    s = TwoGridSolver(k, order=p, l_dd=8, max_rhs=64, coarse_solver="nd")
+    assert s.info()["coarse_solver"] == 2
+    for i, nrhs in enumerate((64, 3, 17, 1, 64)):
+        print(f"case nd call {i} nrhs={nrhs}", flush=True)
+        rc = syn.random_complex((nrhs, Ac.shape[0]), seed=300 + i)
+        ref = np.stack([lu.solve(x) for x in rc])
+        err = rel(to_np(s.coarse_solve(to_dev(rc))), ref)
+        print(f"  rel err {err:.2e}", flush=True)
+        assert err < 1e-11
+    s.close()

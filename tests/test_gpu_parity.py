@@ -73,6 +73,45 @@ def test_residual(N, p, l_dd):
     assert rel(to_np(r32), ref) < 1e-5
 
 
+# tile edges (cells) of the 2-D operator kernel per order: the launch takes the
+# largest whose grid has at least 256 workgroups (tiles x RHS), else the smallest
+OPERATOR_TILES = {2: (16, 8, 4), 4: (8, 4, 2), 6: (5, 3, 2), 8: (4, 2, 1)}
+
+
+def tile_nrhs(N, p):
+    """Numbers of right-hand sides that make the launch pick each tile edge."""
+    tiles = [(-(-N // c)) ** 2 for c in OPERATOR_TILES[p]]
+    out = [-(-256 // tiles[0])]
+    lo, hi = -(-256 // tiles[1]), 255 // tiles[0]
+    if lo <= hi:
+        out.append(lo)
+    if tiles[1] < 256:
+        out.append(1)
+    return out
+
+
+@pytest.mark.parametrize("N,p,l_dd", [(37, 2, 8), (19, 4, 6), (7, 6, 3), (5, 8, 2)])
+def test_residual_every_tile_size(N, p, l_dd):
+    """The residual at widths that select each of the operator kernel's three
+    tile edges matches the oracle's sparse matrix (FP64 1e-12, complex64 1e-5)."""
+    k = hetero_k(N, p, seed=N + 1)
+    A = helmholtz_matrix(p, k)
+    widths = tile_nrhs(N, p)
+    assert len(widths) == 3
+    s = make_solver(k, p, l_dd, max_rhs=max(widths), coarse=None)
+    n = A.shape[0]
+    for nrhs in widths:
+        print(f"case residual tiles N={N} p={p} nrhs={nrhs}", flush=True)
+        u = syn.random_complex((nrhs, n), seed=10 + nrhs)
+        f = syn.random_complex((nrhs, n), seed=20 + nrhs)
+        ref = f - (A @ u.T).T
+        r = s.residual(to_dev(u), to_dev(f))
+        assert rel(to_np(r), ref) < 1e-12
+        r32 = s.residual(to_dev(u, torch.complex64), to_dev(f, torch.complex64))
+        assert rel(to_np(r32), ref) < 1e-5
+    s.close()
+
+
 @pytest.mark.parametrize("N,p,l_dd", CASES)
 def test_transfers(N, p, l_dd):
     print(f"case transfers N={N} p={p}", flush=True)
