@@ -1364,10 +1364,18 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
       // modified Gram-Schmidt: coefficients stay on the device (column j of
       // the Hessenberg matrix in w.hcol), the new vector is normalised by a
       // device-computed 1/norm, and one copy brings the column to the host;
-      // each projection is two launches (partial dot products, then the axpy
-      // that finishes their fixed-order sum itself)
+      // short vectors with many right-hand sides take the whole step in one
+      // launch (a workgroup per right-hand side), otherwise each projection
+      // is two launches (partial dot products, then the axpy that finishes
+      // their fixed-order sum itself)
       std::vector<std::vector<zc>> hcol(nrhs, std::vector<zc>(j + 2, 0.0));
-      {
+      if (mgs_step_fits(nf, nrhs, j + 1)) {
+        // short vectors, many right-hand sides: the whole step in one launch
+        KTimer kt(c, TH_KT_KRYLOV);
+        MgsBasis B{};
+        for (int i = 0; i <= j; ++i) B.v[i] = Vj(i);
+        rc = launch_mgs_step(B, j + 1, Vj(j + 1), w.hcol, nf, nrhs, nf, s);
+      } else {
         KTimer kt(c, TH_KT_KRYLOV);
         for (int i = 0; i <= j && rc == 0; ++i) {
           rc = launch_dot_partial(Vj(i), Vj(j + 1), nf, nrhs, nf, nf, w.partial, s);

@@ -378,6 +378,18 @@ int gj_ws_status(const c64 *ws, hipStream_t s, const char *what);
 int launch_convert(const void *in, void *out, long long n, bool in_f32, bool out_f32, hipStream_t s);
 // the Arnoldi step's fused pair: partial dot products, then the axpy (or the
 // normalisation) that finishes their sum itself and stores it
+// One modified Gram-Schmidt step of the Arnoldi process in one launch (one
+// workgroup per right-hand side): w -= sum_i h_i V_i in order with
+// h_i = conj(V_i) . w into hcol[i][rhs], ||w||^2 into hcol[nv][rhs], w
+// normalised.  For nrhs >= kMgsMinRhs, nv <= kMgsMax, n <= 18432 entries.
+constexpr int kMgsMax = 32;
+constexpr int kMgsMinRhs = 8;
+struct MgsBasis {
+  const c64 *v[kMgsMax];
+};
+bool mgs_step_fits(long long n, int nrhs, int nv);
+int launch_mgs_step(const MgsBasis &B, int nv, c64 *w, c64 *hcol, long long n, int nrhs,
+                    long long ld, hipStream_t s);
 int launch_dot_partial(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx,
                        long long ldy, c64 *partial, hipStream_t s);
 int launch_axpy_partials(c64 *y, const c64 *x, const c64 *partial, c64 *coef, double sign,

@@ -137,6 +137,119 @@ int launch_scale_partials(c64 *v, const c64 *partial, c64 *dot, long long n, int
   return 0;
 }
 
+// One whole modified Gram-Schmidt step of the Arnoldi process for vectors of
+// at most 1024 K entries: one workgroup per right-hand side keeps its new
+// vector w in registers (K entries per thread) and, for i = 0 .. nv - 1 in
+// order, forms h_i = conj(V_i) . w (a fixed-order workgroup sum), stores it in
+// hcol[i][rhs] and subtracts h_i V_i (V_i read a second time, from L2); then
+// ||w||^2 goes to hcol[nv][rhs] and w / ||w|| (0 when the norm is zero or
+// not finite, as k_scale_partials) back to w.  Every step is deterministic;
+// the vectors pass through memory about half as often as with a launch per
+// projection, and the step is one launch instead of 2 nv + 2.
+constexpr int kMgsThreads = 1024;
+
+__device__ __forceinline__ c64 mgs_block_sum(c64 v, c64 *red, c64 *out) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.re += __shfl_xor(v.re, o, 64);
+    v.im += __shfl_xor(v.im, o, 64);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c64 t = red[0];
+    for (int q = 1; q < kMgsThreads / 64; ++q) t = t + red[q];
+    *out = t;
+  }
+  __syncthreads();
+  return *out;
+}
+
+template <int K>
+__global__ __launch_bounds__(kMgsThreads) void k_mgs_step(MgsBasis B, int nv,
+                                                          c64 *__restrict__ w,
+                                                          c64 *__restrict__ hcol, long long n,
+                                                          long long ld, int nrhs) {
+  __shared__ c64 red[kMgsThreads / 64];
+  __shared__ c64 bc;
+  const int rhs = blockIdx.x;
+  const long long off = (long long)rhs * ld;
+  c64 x[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const long long i = threadIdx.x + (long long)k * kMgsThreads;
+    x[k] = i < n ? w[off + i] : c64{0, 0};
+  }
+  for (int p = 0; p < nv; ++p) {
+    const c64 *__restrict__ v = B.v[p] + off;
+    c64 acc = {0, 0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const long long i = threadIdx.x + (long long)k * kMgsThreads;
+      if (i < n) {
+        const c64 a = v[i], b = x[k];
+        acc.re = fma(a.re, b.re, acc.re);
+        acc.re = fma(a.im, b.im, acc.re);
+        acc.im = fma(a.re, b.im, acc.im);
+        acc.im = fma(-a.im, b.re, acc.im);
+      }
+    }
+    const c64 h = mgs_block_sum(acc, red, &bc);
+    if (threadIdx.x == 0) hcol[(long long)p * nrhs + rhs] = h;
+    const c64 sa = {-h.re, -h.im};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const long long i = threadIdx.x + (long long)k * kMgsThreads;
+      if (i < n) cmac(x[k], sa, v[i]);
+    }
+  }
+  c64 acc = {0, 0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const c64 b = x[k];
+    acc.re = fma(b.re, b.re, acc.re);
+    acc.re = fma(b.im, b.im, acc.re);
+    acc.im = fma(b.re, b.im, acc.im);
+    acc.im = fma(-b.im, b.re, acc.im);
+  }
+  const c64 a = mgs_block_sum(acc, red, &bc);
+  if (threadIdx.x == 0) hcol[(long long)nv * nrhs + rhs] = a;
+  const double nrm = sqrt(a.re > 0.0 ? a.re : 0.0);
+  const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const long long i = threadIdx.x + (long long)k * kMgsThreads;
+    if (i < n) w[off + i] = c64{inv * x[k].re, inv * x[k].im};
+  }
+}
+
+bool mgs_step_fits(long long n, int nrhs, int nv) {
+  return nrhs >= kMgsMinRhs && nv <= kMgsMax && n <= (long long)kMgsThreads * 18;
+}
+
+int launch_mgs_step(const MgsBasis &B, int nv, c64 *w, c64 *hcol, long long n, int nrhs,
+                     long long ld, hipStream_t s) {
+  if (!mgs_step_fits(n, nrhs, nv)) {
+    set_error("launch_mgs_step: vector too long, too few right-hand sides or too many projections");
+    return TH_EINVAL;
+  }
+  const int K = (int)ceil_div_ll(n, kMgsThreads);
+  const dim3 g(nrhs), b(kMgsThreads);
+  if (K <= 4)
+    hipLaunchKernelGGL(k_mgs_step<4>, g, b, 0, s, B, nv, w, hcol, n, ld, nrhs);
+  else if (K <= 8)
+    hipLaunchKernelGGL(k_mgs_step<8>, g, b, 0, s, B, nv, w, hcol, n, ld, nrhs);
+  else if (K <= 12)
+    hipLaunchKernelGGL(k_mgs_step<12>, g, b, 0, s, B, nv, w, hcol, n, ld, nrhs);
+  else if (K <= 16)
+    hipLaunchKernelGGL(k_mgs_step<16>, g, b, 0, s, B, nv, w, hcol, n, ld, nrhs);
+  else
+    hipLaunchKernelGGL(k_mgs_step<18>, g, b, 0, s, B, nv, w, hcol, n, ld, nrhs);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
 // y[rhs] += sign * coef[rhs] * x[rhs]
 __global__ __launch_bounds__(256) void k_axpy_dev(c64 *__restrict__ y, const c64 *__restrict__ x,
                                                   const c64 *__restrict__ coef, double sign,

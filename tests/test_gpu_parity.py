@@ -225,6 +225,33 @@ def test_solve_c1_fp64():
     assert st.rel_res <= 1e-6
 
 
+def test_solve_fp64_many_rhs_one_launch_arnoldi():
+    """Ten right-hand sides of 41^2 nodes take the Arnoldi step that runs one
+    workgroup per right-hand side: every one matches the oracle's GMRES
+    (modified Gram-Schmidt) to 1e-10 after the same iteration count, and the
+    first seven, solved again together (seven right-hand sides take the
+    launch-per-projection step), agree with them to 1e-10."""
+    N, p, l_dd = 20, 2, 5
+    k = hetero_k(N, p, seed=5)
+    tg = TwoGrid(p, k, alpha_s=0.5, l_dd=l_dd)
+    n = (N * p + 1) ** 2
+    f = syn.random_complex((10, n), seed=33)
+    s = make_solver(k, p, l_dd, alpha_s=0.5, max_rhs=10)
+    u, st = s.solve(to_dev(f))
+    x = to_np(u)
+    iters = []
+    for r in range(10):
+        x_ref, it_ref, _ = tg.gmres(f[r], 1e-6)
+        iters.append(it_ref)
+        assert rel(x[r], x_ref) < 1e-10
+    print(f"oracle iters {iters}, gpu iters {st.iters}", flush=True)
+    assert st.status == 0 and st.iters == max(iters)
+    u7, st7 = s.solve(to_dev(f[:7]))
+    assert st7.status == 0 and st7.iters == max(iters[:7])
+    assert rel(to_np(u7), x[:7]) < 1e-10
+    s.close()
+
+
 # ------------------------------------------------------------ mixed precision
 def bf16_round(x):
     """Round float64 values to bfloat16 (nearest even) via float32, back to float64."""
