@@ -119,7 +119,7 @@ static void free_graphs(th_ctx *c) {
 
 static void free_fine(th_ctx *c) {
   void *ptrs[] = {c->d_kap, c->d_kaps, c->d_k,  c->d_subs, c->d_nblk, c->d_B, c->w_r,
-                  c->w_v,   c->w_rr,   c->w_y,  c->w_rc,   c->w_uc,   c->w_t, c->w_rc32,
+                  c->w_v,   c->w_rr,   c->w_y,  c->w_rc,   c->w_uc,   c->w_t,
                   c->d_eidx, c->w_p, c->w_x, c->w_z, c->w_yc, c->w_xp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -127,7 +127,7 @@ static void free_fine(th_ctx *c) {
   c->d_k = nullptr;
   c->d_subs = nullptr;
   c->d_nblk = nullptr;
-  c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = c->w_rc32 = nullptr;
+  c->d_B = c->w_r = c->w_v = c->w_rr = c->w_y = c->w_rc = c->w_uc = c->w_t = nullptr;
   c->d_eidx = nullptr;
   c->w_p = c->w_x = c->w_z = c->w_yc = c->w_xp = nullptr;
   c->mfx_max_nrb = 0;
@@ -887,8 +887,7 @@ th_status th_setup_coarse(th_ctx *ctx, const th_coarse_desc *d) {
   const size_t R = (size_t)c->desc.max_rhs;
   if (!c->w_rc) {
     if (hipMalloc(&c->w_rc, R * c->nc * sizeof(c64)) != hipSuccess ||
-        hipMalloc(&c->w_uc, R * c->nc * sizeof(c64)) != hipSuccess ||
-        hipMalloc(&c->w_rc32, R * c->nc * sizeof(c64)) != hipSuccess) {
+        hipMalloc(&c->w_uc, R * c->nc * sizeof(c64)) != hipSuccess) {
       free_coarse(c);
       return fail(ctx, TH_ENOMEM, "device allocation failed in setup_coarse");
     }
@@ -984,17 +983,21 @@ static int twogrid_impl(th_ctx *c, void *u, const void *f, int nrhs, bool f32, b
     rc = launch_apply(make_op(c, false), c->ref, u, f, c->w_r, nrhs, f32, -1.0, s);
   }
   if (rc) return rc;
-  void *rcv = f32 ? c->w_rc32 : c->w_rc;
-  void *ucv = f32 ? c->w_rc32 : c->w_uc;
+  // the coarse vectors stay complex128 for the FP64 coarse solve: a complex64
+  // step restricts straight into them and prolongs straight from them
   {
     KTimer kt(c, TH_KT_RESTRICT);
-    rc = launch_restrict(c->dim, c->N, c->P, c->dir, c->ref, c->w_r, rcv, nrhs, f32, s);
+    rc = launch_restrict(c->dim, c->N, c->P, c->dir, c->ref, c->w_r, c->w_rc, nrhs, f32, s, true);
   }
-  if (!rc) rc = coarse_solve_impl(c, rcv, ucv, nrhs, f32, accuracy);
+  if (!rc) {
+    KTimer kt(c, TH_KT_COARSE);
+    rc = launch_coarse_solve(c, (const c64 *)c->w_rc, (c64 *)c->w_uc, nrhs, s,
+                             f32 ? kCoarseRounded : accuracy);
+  }
   if (!rc) {
     KTimer kt(c, TH_KT_PROLONG);
-    rc = launch_prolong(c->dim, c->N, c->P, c->dir, c->ref, ucv, u, c->desc.omega_c, nrhs, f32,
-                        s);
+    rc = launch_prolong(c->dim, c->N, c->P, c->dir, c->ref, c->w_uc, u, c->desc.omega_c, nrhs, f32,
+                        s, true);
   }
   for (int i = 0; i < c->desc.n_s && rc == 0; ++i) rc = smooth_impl(c, u, f, nrhs, f32, false);
   return rc;

@@ -208,7 +208,6 @@ struct th_ctx {
   void *w_rc = nullptr;        // coarse rhs (FP64)
   void *w_uc = nullptr;        // coarse solution (FP64)
   void *w_t = nullptr;         // coarse sweep temporaries
-  void *w_rc32 = nullptr;      // coarse rhs in working precision
   void *w_p = nullptr;         // transposed-tile partial sums (symmetric layout)
   void *w_x = nullptr;         // gathered patches X_i (symmetric layout)
   void *w_yc = nullptr;        // colour planes [2^d][rhs][n_fine] of the staged matrix-core kernel
@@ -283,11 +282,12 @@ void gll_points(int p, std::vector<double> &x, std::vector<double> &w);
 int launch_apply(const FineOp &op, const Ref1D &ref, const void *u, const void *f, void *out,
                  int nrhs, bool f32, double sgn, hipStream_t s);
 
-// k_transfer.hip
+// k_transfer.hip; f32: complex64 fine vectors; coarse64: the coarse vector is
+// complex128 even then (the two-grid step hands it to the FP64 coarse solve)
 int launch_restrict(int dim, int N, int P, int dir, const Ref1D &ref, const void *r, void *rc, int nrhs,
-                    bool f32, hipStream_t s);
+                    bool f32, hipStream_t s, bool coarse64 = false);
 int launch_prolong(int dim, int N, int P, int dir, const Ref1D &ref, const void *uc, void *u, double omega,
-                   int nrhs, bool f32, hipStream_t s);
+                   int nrhs, bool f32, hipStream_t s, bool coarse64 = false);
 
 // k_smoother.hip
 int launch_dd_apply(const th_ctx *c, const void *r, void *y, int nrhs, bool f32, hipStream_t s);

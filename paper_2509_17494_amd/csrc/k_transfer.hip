@@ -29,10 +29,14 @@ __device__ __forceinline__ double p1w(const double *L, int N, int i, int J) {
 }
 
 // The grids are n1^DIM (fine) and nc1^DIM (coarse), x fastest; in 2-D the z
-// loops collapse to one iteration with unit weight.
-template <int DIM, int P, typename T>
+// loops collapse to one iteration with unit weight.  The coarse vector has its
+// own type TV: a complex64 two-grid step reads and writes the FP64 coarse
+// solve's vectors directly, rounding each coarse value to T as it is read
+// (prolongation) or the T sum to FP64 as it is stored (restriction), which is
+// what a separate conversion would do.
+template <int DIM, int P, typename T, typename TV>
 __global__ __launch_bounds__(256) void k_prolong(int N, int dir, Ref1D ref,
-                                                 const cx<T> *__restrict__ uc,
+                                                 const cx<TV> *__restrict__ uc,
                                                  cx<T> *__restrict__ u, T omega, long long nf,
                                                  long long ncn) {
   constexpr int R = P / 2;
@@ -63,12 +67,12 @@ __global__ __launch_bounds__(256) void k_prolong(int N, int dir, Ref1D ref,
         const T wy = (T)ref.L[ay * (R + 1) + by];
         if (wy == (T)0 || on_dir(dir, 1, cyq * R + by, nc1 - 1)) continue;
         cx<T> row = {0, 0};
-        const cx<T> *ucr = uc + ((long long)(czq * R + bz) * nc1 + cyq * R + by) * nc1 + cxq * R;
+        const cx<TV> *ucr = uc + ((long long)(czq * R + bz) * nc1 + cyq * R + by) * nc1 + cxq * R;
 #pragma unroll
         for (int bx = 0; bx <= R; ++bx) {
           const T wx = (T)ref.L[ax * (R + 1) + bx];
           if (wx == (T)0 || on_dir(dir, 0, cxq * R + bx, nc1 - 1)) continue;
-          rmac(row, wx, ucr[bx]);
+          rmac(row, wx, ccast<T>(ucr[bx]));
         }
         rmac(pl, wy, row);
       }
@@ -82,10 +86,10 @@ __global__ __launch_bounds__(256) void k_prolong(int N, int dir, Ref1D ref,
   }
 }
 
-template <int DIM, int P, typename T>
+template <int DIM, int P, typename T, typename TV>
 __global__ __launch_bounds__(256) void k_restrict(int N, int dir, Ref1D ref,
                                                   const cx<T> *__restrict__ r,
-                                                  cx<T> *__restrict__ rc, long long nf,
+                                                  cx<TV> *__restrict__ rc, long long nf,
                                                   long long ncn) {
   constexpr int R = P / 2;
   const int n1 = N * P + 1, nc1 = N * R + 1;
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(256) void k_restrict(int N, int dir, Ref1D ref,
     const int Jy = (int)(t % nc1), Jz = (int)(t / nc1);
     if (on_dir(dir, 0, Jx, nc1 - 1) || on_dir(dir, 1, Jy, nc1 - 1) ||
         (DIM == 3 && on_dir(dir, 2, Jz, nc1 - 1))) {
-      rc[G] = cx<T>{0, 0};
+      rc[G] = cx<TV>{0, 0};
       continue;
     }
     // cells whose coarse points include J: c R <= J <= c R + R; fine node range of those cells
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(256) void k_restrict(int N, int dir, Ref1D ref,
       if (DIM == 3) rmac(acc, wz, pl);
       else acc = pl;
     }
-    rc[G] = acc;
+    rc[G] = ccast<TV>(acc);
   }
 }
 
@@ -139,24 +143,24 @@ static long long ipow(long long b, int e) {
   return r;
 }
 
-template <int DIM, int P, typename T>
+template <int DIM, int P, typename T, typename TV>
 static int prolong_t(int N, int dir, const Ref1D &ref, const void *uc, void *u, double omega,
                      int nrhs, hipStream_t s) {
   const long long nf = ipow(N * P + 1, DIM), ncn = ipow(N * (P / 2) + 1, DIM);
   int blocks = (int)std::min<long long>(ceil_div_ll(nf, 256), 65535);
-  hipLaunchKernelGGL((k_prolong<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, dir, ref,
-                     (const cx<T> *)uc, (cx<T> *)u, (T)omega, nf, ncn);
+  hipLaunchKernelGGL((k_prolong<DIM, P, T, TV>), dim3(blocks, nrhs), dim3(256), 0, s, N, dir, ref,
+                     (const cx<TV> *)uc, (cx<T> *)u, (T)omega, nf, ncn);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
 
-template <int DIM, int P, typename T>
+template <int DIM, int P, typename T, typename TV>
 static int restrict_t(int N, int dir, const Ref1D &ref, const void *r, void *rc, int nrhs,
                       hipStream_t s) {
   const long long nf = ipow(N * P + 1, DIM), ncn = ipow(N * (P / 2) + 1, DIM);
   int blocks = (int)std::min<long long>(ceil_div_ll(ncn, 256), 65535);
-  hipLaunchKernelGGL((k_restrict<DIM, P, T>), dim3(blocks, nrhs), dim3(256), 0, s, N, dir, ref,
-                     (const cx<T> *)r, (cx<T> *)rc, nf, ncn);
+  hipLaunchKernelGGL((k_restrict<DIM, P, T, TV>), dim3(blocks, nrhs), dim3(256), 0, s, N, dir, ref,
+                     (const cx<T> *)r, (cx<TV> *)rc, nf, ncn);
   TH_HIP_CHECK_RET(hipGetLastError());
   return 0;
 }
@@ -170,17 +174,18 @@ static int restrict_t(int N, int dir, const Ref1D &ref, const void *r, void *rc,
   }
 
 int launch_prolong(int dim, int N, int P, int dir, const Ref1D &ref, const void *uc, void *u,
-                   double omega,
-                   int nrhs, bool f32, hipStream_t s) {
+                   double omega, int nrhs, bool f32, hipStream_t s, bool coarse64) {
   if (dim == 3) {
-#define CF(p) prolong_t<3, p, float>(N, dir, ref, uc, u, omega, nrhs, s)
-#define CD(p) prolong_t<3, p, double>(N, dir, ref, uc, u, omega, nrhs, s)
+#define CF(p) (coarse64 ? prolong_t<3, p, float, double>(N, dir, ref, uc, u, omega, nrhs, s) \
+                        : prolong_t<3, p, float, float>(N, dir, ref, uc, u, omega, nrhs, s))
+#define CD(p) prolong_t<3, p, double, double>(N, dir, ref, uc, u, omega, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
   } else {
-#define CF(p) prolong_t<2, p, float>(N, dir, ref, uc, u, omega, nrhs, s)
-#define CD(p) prolong_t<2, p, double>(N, dir, ref, uc, u, omega, nrhs, s)
+#define CF(p) (coarse64 ? prolong_t<2, p, float, double>(N, dir, ref, uc, u, omega, nrhs, s) \
+                        : prolong_t<2, p, float, float>(N, dir, ref, uc, u, omega, nrhs, s))
+#define CD(p) prolong_t<2, p, double, double>(N, dir, ref, uc, u, omega, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
@@ -190,17 +195,18 @@ int launch_prolong(int dim, int N, int P, int dir, const Ref1D &ref, const void 
 }
 
 int launch_restrict(int dim, int N, int P, int dir, const Ref1D &ref, const void *r, void *rc,
-                    int nrhs,
-                    bool f32, hipStream_t s) {
+                    int nrhs, bool f32, hipStream_t s, bool coarse64) {
   if (dim == 3) {
-#define CF(p) restrict_t<3, p, float>(N, dir, ref, r, rc, nrhs, s)
-#define CD(p) restrict_t<3, p, double>(N, dir, ref, r, rc, nrhs, s)
+#define CF(p) (coarse64 ? restrict_t<3, p, float, double>(N, dir, ref, r, rc, nrhs, s) \
+                        : restrict_t<3, p, float, float>(N, dir, ref, r, rc, nrhs, s))
+#define CD(p) restrict_t<3, p, double, double>(N, dir, ref, r, rc, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
   } else {
-#define CF(p) restrict_t<2, p, float>(N, dir, ref, r, rc, nrhs, s)
-#define CD(p) restrict_t<2, p, double>(N, dir, ref, r, rc, nrhs, s)
+#define CF(p) (coarse64 ? restrict_t<2, p, float, double>(N, dir, ref, r, rc, nrhs, s) \
+                        : restrict_t<2, p, float, float>(N, dir, ref, r, rc, nrhs, s))
+#define CD(p) restrict_t<2, p, double, double>(N, dir, ref, r, rc, nrhs, s)
     TH_DISPATCH_P(P, f32, CF, CD)
 #undef CF
 #undef CD
