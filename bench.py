@@ -148,6 +148,15 @@ def slab_apply_bytes(N, p, l_dd, dim, nrhs, mat_bytes, vec_bytes, packed=False):
     return byts, 8.0 * (g_entries + mul_entries + band_entries) * nrhs
 
 
+def traffic_cfg(key):
+    """The matrix-core smoother configuration a counter entry was taken with
+    (None when the entry names none)."""
+    try:
+        return json.load(open(TRAFFIC_FILE)).get(key, {}).get("smoother_cfg")
+    except Exception:
+        return None
+
+
 def traffic_entry(key):
     """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE counter runs scaled by
     a device copy of known size) from the committed summary, or None when the
@@ -562,8 +571,8 @@ def main():
         variants["C3_mixed_bf16_batched64_graph"] = variant_entry(
             v_mixed, roofline_hbm(v_mixed, mfma_kernel_name(v_mixed["info"]["smoother_cfg"]),
                                   mfma_peak=BF16_PEAK_TFLOPS,
-                                  traffic_key="C3" if v_mixed["info"]["smoother_cfg"] == 12
-                                  else None))
+                                  traffic_key="C3" if v_mixed["info"]["smoother_cfg"] ==
+                                  traffic_cfg("C3") else None))
         v_fp64 = run_workload("C3", max(3, a.steps), 1, precond="c128", gemm="f64", graph=False,
                               timing=True, verbose=a.verbose)
         variants["C3_fp64_batched64_control"] = variant_entry(v_fp64, roofline_fp64(v_fp64))
