@@ -571,8 +571,9 @@ def main():
         variants["C3_mixed_bf16_batched64_graph"] = variant_entry(
             v_mixed, roofline_hbm(v_mixed, mfma_kernel_name(v_mixed["info"]["smoother_cfg"]),
                                   mfma_peak=BF16_PEAK_TFLOPS,
-                                  traffic_key="C3" if v_mixed["info"]["smoother_cfg"] ==
-                                  traffic_cfg("C3") else None))
+                                  traffic_key=next((k for k in ("C3", "C3_cfg12")
+                                                    if traffic_cfg(k) ==
+                                                    v_mixed["info"]["smoother_cfg"]), None)))
         v_fp64 = run_workload("C3", max(3, a.steps), 1, precond="c128", gemm="f64", graph=False,
                               timing=True, verbose=a.verbose)
         variants["C3_fp64_batched64_control"] = variant_entry(v_fp64, roofline_fp64(v_fp64))
