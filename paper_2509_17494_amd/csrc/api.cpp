@@ -1114,7 +1114,7 @@ namespace th {
 using zc = std::complex<double>;
 
 struct SolverWS {
-  c64 *partial, *hd, *tmp32a, *tmp32b, *coef, *res;
+  c64 *partial, *partial2, *hd, *tmp32a, *tmp32b, *coef, *res;
   double *scal;
   c64 *hcol;    // device: one Hessenberg column, (m + 2) x nrhs
   c64 *hcol_h;  // pinned host copy of it
@@ -1143,7 +1143,7 @@ static int basis_vec(th_ctx *c, std::vector<void *> &blocks, int j, c64 **out) {
 static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
   const size_t vec = (size_t)nrhs * c->nf * sizeof(c64);
   size_t need = 0;
-  need += (size_t)nrhs * 256 * sizeof(c64);                 // partial sums
+  need += 2 * (size_t)nrhs * 256 * sizeof(c64);             // partial sums (two sets)
   need += (size_t)nrhs * sizeof(c64) * 2;                   // dot outputs
   need += 2 * vec;                                          // preconditioner staging
   need += (size_t)nrhs * (m + 1) * sizeof(c64);             // lincomb coefficients
@@ -1179,6 +1179,7 @@ static int ensure_solver_ws(th_ctx *c, int m, int nrhs, bool f32, SolverWS &w) {
     return q;
   };
   w.partial = (c64 *)take((size_t)nrhs * 256 * sizeof(c64));
+  w.partial2 = (c64 *)take((size_t)nrhs * 256 * sizeof(c64));
   w.hd = (c64 *)take((size_t)nrhs * sizeof(c64) * 2);
   // staging of the preconditioner input/output (complex64 copies, or FP64
   // copies at fixed addresses for graph replay)
@@ -1368,9 +1369,10 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
       // the Hessenberg matrix in w.hcol), the new vector is normalised by a
       // device-computed 1/norm, and one copy brings the column to the host;
       // short vectors with many right-hand sides take the whole step in one
-      // launch (a workgroup per right-hand side), otherwise each projection
-      // is two launches (partial dot products, then the axpy that finishes
-      // their fixed-order sum itself)
+      // launch (a workgroup per right-hand side); otherwise each projection
+      // is one launch, the axpy that finishes the fixed-order sum of its
+      // partial dot products fused with the partial dot products of the next
+      // projection (after the last one: of the squared norm)
       std::vector<std::vector<zc>> hcol(nrhs, std::vector<zc>(j + 2, 0.0));
       if (mgs_step_fits(nf, nrhs, j + 1)) {
         // short vectors, many right-hand sides: the whole step in one launch
@@ -1380,16 +1382,16 @@ static int solve_gmres(th_ctx *c, const c64 *f, c64 *u, int nrhs, const th_solve
         rc = launch_mgs_step(B, j + 1, Vj(j + 1), w.hcol, nf, nrhs, nf, s);
       } else {
         KTimer kt(c, TH_KT_KRYLOV);
+        c64 *pin = w.partial, *pout = w.partial2;
+        rc = launch_dot_partial(Vj(0), Vj(j + 1), nf, nrhs, nf, nf, pin, s);
         for (int i = 0; i <= j && rc == 0; ++i) {
-          rc = launch_dot_partial(Vj(i), Vj(j + 1), nf, nrhs, nf, nf, w.partial, s);
-          if (!rc)
-            rc = launch_axpy_partials(Vj(j + 1), Vj(i), w.partial, w.hcol + (size_t)i * nrhs, -1.0,
-                                      nf, nrhs, nf, nf, s);
+          rc = launch_axpy_dot_partials(Vj(j + 1), Vj(i), i < j ? Vj(i + 1) : Vj(j + 1), pin,
+                                        w.hcol + (size_t)i * nrhs, -1.0, nf, nrhs, nf, pout, s);
+          std::swap(pin, pout);
         }
-        if (!rc) rc = launch_dot_partial(Vj(j + 1), Vj(j + 1), nf, nrhs, nf, nf, w.partial, s);
         if (!rc)
-          rc = launch_scale_partials(Vj(j + 1), w.partial, w.hcol + (size_t)(j + 1) * nrhs, nf,
-                                     nrhs, nf, s);
+          rc = launch_scale_partials(Vj(j + 1), pin, w.hcol + (size_t)(j + 1) * nrhs, nf, nrhs,
+                                     nf, s);
       }
       if (rc) return rc;
       TH_HIP_CHECK_RET(hipMemcpyAsync(w.hcol_h, w.hcol, (size_t)(j + 2) * nrhs * sizeof(c64),

@@ -396,6 +396,11 @@ int launch_axpy_partials(c64 *y, const c64 *x, const c64 *partial, c64 *coef, do
                          long long n, int nrhs, long long ldy, long long ldx, hipStream_t s);
 int launch_scale_partials(c64 *v, const c64 *partial, c64 *dot, long long n, int nrhs,
                           long long ld, hipStream_t s);
+// the axpy of one projection fused with the partial dot products of the next
+// (z = y: the squared norm); pin and pout are distinct partial buffers
+int launch_axpy_dot_partials(c64 *y, const c64 *x, const c64 *z, const c64 *pin, c64 *coef,
+                             double sign, long long n, int nrhs, long long ld, c64 *pout,
+                             hipStream_t s);
 int launch_dot(const c64 *x, const c64 *y, long long n, int nrhs, long long ldx, long long ldy,
                c64 *out, c64 *partial, hipStream_t s);
 int launch_axpy_dev(c64 *y, const c64 *x, const c64 *coef, double sign, long long n, int nrhs,

@@ -108,6 +108,52 @@ int launch_axpy_partials(c64 *y, const c64 *x, const c64 *partial, c64 *coef, do
   return 0;
 }
 
+// y[rhs] += sign * a x[rhs] as k_axpy_partials, then the partial dot products
+// conj(z) . y of the updated y for the next projection (z = y: its squared
+// norm), over k_dot_partial's block partition (grid dot_blocks(n) x nrhs) and
+// in its element order, so the partials are the bits a separate k_dot_partial
+// would give: one launch and one vector pass fewer per projection.
+__global__ __launch_bounds__(256) void k_axpy_dot_partials(c64 *__restrict__ y,
+                                                           const c64 *__restrict__ x,
+                                                           const c64 *z, int z_is_y,
+                                                           const c64 *__restrict__ pin, int nb,
+                                                           c64 *__restrict__ coef, double sign,
+                                                           long long n, long long ld,
+                                                           c64 *__restrict__ pout) {
+  __shared__ c64 sh[256];
+  const long long rhs = blockIdx.y;
+  const c64 a = dot_from_partials(pin, nb, (int)rhs, sh);
+  __syncthreads();  // every thread holds a before sh is reused
+  if (blockIdx.x == 0 && threadIdx.x == 0) coef[rhs] = a;
+  const c64 sa = {sign * a.re, sign * a.im};
+  y += rhs * ld;
+  x += rhs * ld;
+  z += rhs * ld;
+  c64 acc = {0, 0};
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    c64 v = y[i];
+    cmac(v, sa, x[i]);
+    y[i] = v;
+    const c64 q = z_is_y ? v : z[i];
+    acc.re = fma(q.re, v.re, acc.re);
+    acc.re = fma(q.im, v.im, acc.re);
+    acc.im = fma(q.re, v.im, acc.im);
+    acc.im = fma(-q.im, v.re, acc.im);
+  }
+  block_reduce(sh, acc);
+  if (threadIdx.x == 0) pout[rhs * RED_BLOCKS + blockIdx.x] = sh[0];
+}
+
+int launch_axpy_dot_partials(c64 *y, const c64 *x, const c64 *z, const c64 *pin, c64 *coef,
+                             double sign, long long n, int nrhs, long long ld, c64 *pout,
+                             hipStream_t s) {
+  const int nb = dot_blocks(n);
+  hipLaunchKernelGGL(k_axpy_dot_partials, dim3(nb, nrhs), dim3(256), 0, s, y, x, z,
+                     z == y ? 1 : 0, pin, nb, coef, sign, n, ld, pout);
+  TH_HIP_CHECK_RET(hipGetLastError());
+  return 0;
+}
+
 // v[rhs] /= ||v[rhs]|| with ||v||^2 from the partials of k_dot_partial (0 when
 // the norm is zero or not finite, as k_inv_norm); block 0 stores ||v||^2 in
 // dot[rhs]
